@@ -1,0 +1,203 @@
+"""Pins for the oracle's lattice permutation matrix P0 (CPU only).
+
+* Monte Carlo of the six-dimensional overlap <X_ij | P | X_i'j'> sampled in
+  Jacobi set 1 and mapped to sets 2 and 3 -- independent of the delta-function
+  reduction, the cosine clipping and the Gauss rule;
+* the s-wave cosine integral against its closed form
+  int dx/(pi1 pi2) = (2/(q q')) ln(pi1 + pi2) |_{x_lo}^{x_hi};
+* symmetry and non-negativity of the s-wave P0;
+* the pre-selection is a necessary condition: every pair it drops evaluates
+  to exactly zero under the rule;
+* the angular coupling G: 1 in the s-wave, the Legendre addition theorem for
+  L = 0, and the exchange symmetry G_ab(q,q',x) = G_ba(q',q,x).
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial.legendre import Legendre
+
+import oracle.wpcd as W
+from inputs import C1, TOY_P, TOY_Q
+
+
+def _mc_swave(p, q, i, j, i2, j2, n, rng):
+    """Estimator of <X_ij|P|X_i'j'>: sample p in D_i, q in D_j uniformly and
+    isotropic directions; map to the two other Jacobi sets."""
+    pa = rng.uniform(p[i], p[i + 1], n)
+    qa = rng.uniform(q[j], q[j + 1], n)
+
+    def unit(k):
+        v = rng.normal(size=(k, 3))
+        return v / np.linalg.norm(v, axis=1)[:, None]
+
+    pv = pa[:, None] * unit(n)
+    qv = qa[:, None] * unit(n)
+    total = np.zeros(n)
+    for p2v, q2v in ((-0.5 * pv - 0.75 * qv, pv - 0.5 * qv),     # set 2
+                     (-0.5 * pv + 0.75 * qv, -pv - 0.5 * qv)):   # set 3
+        p2 = np.linalg.norm(p2v, axis=1)
+        q2 = np.linalg.norm(q2v, axis=1)
+        inside = (p2 >= p[i2]) & (p2 < p[i2 + 1]) & (q2 >= q[j2]) & (q2 < q[j2 + 1])
+        total += np.where(inside, pa * qa / np.maximum(p2 * q2, 1e-300), 0.0)
+    di, dj = p[i + 1] - p[i], q[j + 1] - q[j]
+    d2i, d2j = p[i2 + 1] - p[i2], q[j2 + 1] - q[j2]
+    est = total * math.sqrt(di * dj / (d2i * d2j))
+    return est.mean(), est.std() / math.sqrt(n)
+
+
+def _elem(p, q, i, j, i2, j2, n_gq, n_gx):
+    np_ = p.size - 1
+    return W.p0_pairs(p, q, n_gq, n_gx, 0, [(0, 0)],
+                      np.array([j * np_ + i]), np.array([j2 * np_ + i2]))[0, 0, 0]
+
+
+@pytest.mark.parametrize("cells", [(1, 1, 1, 1), (2, 1, 1, 2), (0, 1, 1, 0), (2, 2, 1, 3), (2, 0, 0, 2),
+                                   (0, 0, 0, 0)])
+def test_p0_element_monte_carlo(cells):
+    p, q = np.array(TOY_P), np.array(TOY_Q)
+    i, j, i2, j2 = cells
+    rule = _elem(p, q, i, j, i2, j2, 8, 16)
+    fine = _elem(p, q, i, j, i2, j2, 64, 64)
+    rng = np.random.default_rng(1508 + 7 * i + 13 * j + 17 * i2 + 19 * j2)
+    est, err = 0.0, 0.0
+    batches = 8
+    vals = [_mc_swave(p, q, i, j, i2, j2, 500_000, rng) for _ in range(batches)]
+    est = np.mean([v[0] for v in vals])
+    err = math.sqrt(np.sum([v[1] ** 2 for v in vals])) / batches
+    assert fine > 0.0
+    assert abs(est - fine) < 4.5 * err + 1e-4 * fine, (est, err, fine)
+    # the 8 x 8 x 16 rule is a quadrature of the same integral
+    assert abs(rule - fine) < 2e-2 * fine, (rule, fine)
+
+
+def test_p0_rule_converges_with_nodes():
+    p, q = np.array(TOY_P), np.array(TOY_Q)
+    ref = _elem(p, q, 2, 1, 1, 2, 96, 96)
+    errs = [abs(_elem(p, q, 2, 1, 1, 2, n, n) - ref) for n in (4, 8, 16, 32)]
+    assert errs[-1] < errs[0] and errs[-1] < 1e-3 * ref
+
+
+def test_swave_cosine_integral_closed_form():
+    """With one Gauss point per q bin (the bin midpoints, weight 2) the element
+    is (dq dq')^(1/2) (d d')^(-1/2) q q' int dx/(pi1 pi2)."""
+    p = W.cheb_edges(12, 10.0)
+    q = W.cheb_edges(12, 10.0)
+    checked = 0
+    ptr, col = W.preselect(p, q)
+    cand = []
+    for r in (12 * 6 + 5, 12 * 4 + 7, 12 * 8 + 8, 12 * 9 + 3, 12 * 2 + 6):
+        for c in col[ptr[r]:ptr[r + 1]][::3]:
+            cand.append((r % 12, r // 12, int(c) % 12, int(c) // 12))
+    for (i, j, i2, j2) in cand:
+        if min(i, i2) < 2:
+            continue
+        qa = 0.5 * (q[j] + q[j + 1]); qb = 0.5 * (q[j2] + q[j2 + 1])
+        A = qb * qb + 0.25 * qa * qa; C = qa * qa + 0.25 * qb * qb; B = qa * qb
+        xlo = max(-1.0, (p[i] ** 2 - A) / B, (p[i2] ** 2 - C) / B)
+        xhi = min(1.0, (p[i + 1] ** 2 - A) / B, (p[i2 + 1] ** 2 - C) / B)
+        if xhi <= xlo:
+            continue
+        f = lambda x: math.log(math.sqrt(A + B * x) + math.sqrt(C + B * x))
+        exact = 2.0 / B * (f(xhi) - f(xlo))
+        pref = math.sqrt((q[j + 1] - q[j]) * (q[j2 + 1] - q[j2])
+                         / ((p[i + 1] - p[i]) * (p[i2 + 1] - p[i2]))) * qa * qb
+        for nx, tol in ((16, 1e-9), (40, 1e-13)):
+            got = _elem(p, q, i, j, i2, j2, 1, nx) / pref
+            assert abs(got - exact) <= tol * exact, (nx, got, exact)
+        checked += 1
+    assert checked >= 6
+
+
+def test_p0_symmetric_nonnegative_c1():
+    p = W.cheb_edges(C1["n_p"], C1["p_max"])
+    q = W.cheb_edges(C1["n_q"], C1["q_max"])
+    ptr, col = W.preselect(p, q)
+    rows = np.repeat(np.arange(p.size - 1 + 0, dtype=np.int64).repeat(0), 0)
+    ncell = (p.size - 1) * (q.size - 1)
+    rows = np.repeat(np.arange(ncell, dtype=np.int64), np.diff(ptr))
+    val = W.p0_pairs(p, q, C1["n_gq"], C1["n_gx"], 0, [(0, 0)], rows, col)[:, 0, 0]
+    import scipy.sparse as sp
+    P = sp.csr_matrix((val, col, ptr), shape=(ncell, ncell))
+    # structure symmetric exactly, values up to rounding order
+    S = (P != 0).astype(np.int8)
+    Sfull = sp.csr_matrix((np.ones_like(val), col, ptr), shape=(ncell, ncell))
+    assert (Sfull - Sfull.T).nnz == 0
+    assert abs(P - P.T).max() <= 1e-14 * abs(P).max()
+    assert val.min() >= 0.0
+    assert int(ptr[-1]) == 53105
+    # the selected pairs are mostly nonzero under the rule
+    assert np.count_nonzero(val) > 0.9 * val.size
+    del S
+
+
+@pytest.mark.parametrize("n", [6, 11])
+def test_preselection_is_necessary(n):
+    """Evaluate the rule on every cell pair of a small grid: nothing outside
+    the selected structure is nonzero."""
+    p = W.cheb_edges(n, 10.0)
+    q = W.cheb_edges(n + 1, 7.0)
+    ncell = n * (n + 1)
+    rows = np.repeat(np.arange(ncell, dtype=np.int64), ncell)
+    cols = np.tile(np.arange(ncell, dtype=np.int32), ncell)
+    val = W.p0_pairs(p, q, 8, 16, 0, [(0, 0)], rows, cols)[:, 0, 0].reshape(ncell, ncell)
+    ptr, col = W.preselect(p, q)
+    mask = np.zeros((ncell, ncell), dtype=bool)
+    for r in range(ncell):
+        mask[r, col[ptr[r]:ptr[r + 1]]] = True
+    assert np.all(val[~mask] == 0.0)
+    assert np.count_nonzero(val[mask]) > 0.8 * mask.sum()
+    # a single-pair query agrees with the brute-force structure
+    for r in (0, ncell // 2, ncell - 1):
+        i, j = r % n, r // n
+        for c in range(ncell):
+            assert W.lib().orc_is_selected(W._p(p, W.ctypes.c_double), W._p(q, W.ctypes.c_double),
+                                           i, j, c % n, c // n) == int(mask[r, c])
+
+
+def test_geom_G_swave_is_one():
+    for (q, q2, x) in [(0.3, 1.7, -0.4), (2.0, 0.1, 0.99), (1.0, 1.0, 0.0)]:
+        assert abs(W.geom_G(0, (0, 0), (0, 0), q, q2, x) - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("ll", [(0, 2), (2, 0), (2, 2), (4, 2)])
+def test_geom_G_L0_addition_theorem(ll):
+    """For L = 0 the bipolar harmonic is (-1)^l sqrt(2l+1)/(4 pi) P_l(a.b), so
+    G = (-1)^(l+l') sqrt((2l+1)(2l'+1)) P_l(pi1^.q^) P_l'(pi2^.q'^)."""
+    l, l2 = ll
+    for (q, q2, x) in [(0.3, 1.7, -0.4), (2.0, 0.7, 0.6), (1.0, 1.3, -0.9)]:
+        s = math.sqrt(1 - x * x)
+        qv = np.array([q * s, 0, q * x]); q2v = np.array([0, 0, q2])
+        pi1 = q2v + 0.5 * qv; pi2 = -(qv + 0.5 * q2v)
+        c1 = pi1 @ qv / (np.linalg.norm(pi1) * q)
+        c2 = pi2 @ q2v / (np.linalg.norm(pi2) * q2)
+        ref = (-1) ** (l + l2) * math.sqrt((2 * l + 1) * (2 * l2 + 1)) \
+            * Legendre.basis(l)(c1) * Legendre.basis(l2)(c2)
+        got = W.geom_G(0, (l, l), (l2, l2), q, q2, x)
+        assert abs(got - ref) < 1e-12 * max(1.0, abs(ref))
+
+
+def test_geom_G_exchange_symmetry():
+    chans = [(0, 2), (2, 0), (2, 2)]
+    for a in chans:
+        for b in chans:
+            for (q, q2, x) in [(0.3, 1.7, -0.4), (2.0, 0.7, 0.6)]:
+                g1 = W.geom_G(2, a, b, q, q2, x)
+                g2 = W.geom_G(2, b, a, q2, q, x)
+                assert abs(g1 - g2) < 1e-12 * max(1.0, abs(g1))
+
+
+def test_structure_regression_fixture():
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "structure.json")) as f:
+        gold = json.load(f)
+    g = gold["40x40"]
+    p = W.cheb_edges(g["n_p"], g["p_max"])
+    ptr, col = W.preselect(p, W.cheb_edges(g["n_q"], g["q_max"]))
+    h = hashlib.sha256()
+    h.update(ptr.astype("<i8").tobytes())
+    h.update(col.astype("<i4").tobytes())
+    assert int(ptr[-1]) == g["nnz_cells"]
+    assert h.hexdigest() == g["sha256_rowptr_i64_col_i32"]
