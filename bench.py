@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the WPCD hot path on one MI355X.
+
+Workload (the 150 x 150 s-wave configuration): three identical spinless
+bosons, two-range Yukawa-sum pair potential with ranges 1 and 2 and a common
+strength fitted once (at setup) so the lowest pair level is -0.1 in the
+150-packet basis; 150 p-bins x 150 q-bins, Chebyshev-spaced edges to 10,
+8 Gauss points per q bin, 20 on the cosine interval; 8 energies spanning
+below and above breakup.
+
+One step = the whole hot path: pair potential + FP64 diagonalisation,
+pre-selection + P0 elements (FP32 with compensated sums), resolvent + the
+batched GMRES solve at the 8 energies + amplitudes.  Inputs are synthetic
+and resident on the GPU when the timed region starts.
+
+Prints one JSON line.  value = P-matrix elements (selected cell pairs) per
+second of P-build wall time (pre-selection + elements); the whole-step time
+and the solve time per energy are reported beside it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 150
+NGQ, NGX = 8, 20
+RANGES = (1.0, 2.0)
+ENERGIES = (-0.08, -0.05, -0.02, 0.05, 0.2, 0.5, 1.0, 2.0)
+
+# MI355X published peaks used for the roofline fractions
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops_per_element(ngq, ngx):
+    """Inner cosine rule per (q, q') Gauss pair and node: s = h u_c (1 mul),
+    t = t0 + s, u = u0 + s (2 add), t*u (1 mul), rsqrt (1), w*r accumulated
+    (1 fma = 2) -> 7 flops; the per-pair limits (~20 flops) and weights
+    (3 flops) are added once per pair."""
+    return ngq * ngq * (7 * ngx + 23)
+
+
+def cpu_baseline(sample_stride, threads):
+    """The oracle (as it stands) on a bounded sample of the same workload:
+    every sample_stride-th cell row of the 150 x 150 grid, brute-force
+    pre-selection over all columns plus the FP64 elements of those rows."""
+    import numpy as np
+
+    import oracle.wpcd as O
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    p = O.cheb_edges(N, 10.0)
+    rows = np.arange(0, N * N, sample_stride, dtype=np.int64)
+    t0 = time.perf_counter()
+    ptr, col = O.preselect(p, p.copy(), rows)
+    rr = np.repeat(rows, np.diff(ptr))
+    O.p0_pairs(p, p.copy(), NGQ, NGX, 0, [(0, 0)], rr, col)
+    dt = time.perf_counter() - t0
+    n = int(ptr[-1])
+    return {"value": n / dt, "unit": "P-matrix elements/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {sample_stride}th of the {N*N} cell rows ({rows.size} rows, {n} "
+                      f"cell pairs): brute-force pre-selection + FP64 elements, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-stride", type=int, default=12)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import paper_1508_07441_amd as P
+
+    ctx = P.Context(0)
+    # setup (untimed): fit the common strength once
+    fit = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(RANGES), fit_e2=-0.1)
+    ctx.build_basis(N, N, 10.0, 10.0, NGQ, NGX, potential=fit)
+    _, _, scale = ctx.pair_spectrum(0, want_O=False)
+    pot = dict(kind="yukawa", strength=[-scale, -scale], range=list(RANGES))
+
+    pbuild = [0.0]
+
+    def step():
+        ctx.build_basis(N, N, 10.0, 10.0, NGQ, NGX, potential=pot)
+        t0 = time.perf_counter()
+        nnz = ctx.build_p(P.WPCD_MIXED)
+        pbuild[0] += time.perf_counter() - t0
+        res = ctx.solve(ENERGIES, P.WPCD_MIXED)
+        return nnz, res
+
+    for _ in range(args.warmup):
+        step()
+    ctx.synchronize()
+    ctx.set_timing(P.WPCD_TIME_P0)
+    ctx.reset_timing()
+    pbuild[0] = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nnz, res = step()
+    ctx.synchronize()
+    t1 = time.perf_counter()
+    tim = ctx.timing()
+    ctx.set_timing(0)
+    wall = t1 - t0
+
+    # solve-only timing (untimed for value): batched 8 energies, mixed and FP64
+    def solve_time(prec, reps=3):
+        ts = []
+        for _ in range(reps):
+            a = time.perf_counter()
+            r = ctx.solve(ENERGIES, prec)
+            ts.append(time.perf_counter() - a)
+        return min(ts) / len(ENERGIES), r
+
+    s_mixed, r_mixed = solve_time(P.WPCD_MIXED)
+    # FP64 P-build throughput and FP64 solve beside it
+    ctx.set_timing(P.WPCD_TIME_P0)
+    ctx.reset_timing()
+    a = time.perf_counter()
+    for _ in range(3):
+        ctx.build_p(P.WPCD_FP64)
+    fp64_build = (time.perf_counter() - a) / 3
+    tim64 = ctx.timing()
+    ctx.set_timing(0)
+    s_fp64, r_fp64 = solve_time(P.WPCD_FP64)
+    amp_err = max(abs(complex(x.U_re, x.U_im) - complex(y.U_re, y.U_im)) / abs(complex(y.U_re, y.U_im))
+                  for x, y in zip(r_mixed, r_fp64))
+
+    elem_ms, elem_n = tim.get("p0_elem_f32", (0.0, 1))
+    elem_avg_s = elem_ms / max(elem_n, 1) / 1e3
+    flops = algorithmic_flops_per_element(NGQ, NGX) * nnz
+    achieved = flops / elem_avg_s / 1e12
+    e64_ms, e64_n = tim64.get("p0_elem_f64", (0.0, 1))
+    out = {
+        "metric": "P-matrix elements/s; solve s/energy, mixed+learned vs FP64 at <=1e-6 amp err",
+        "value": nnz * args.steps / pbuild[0],
+        "unit": "P-matrix elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (P0 elements, compensated sums) + f64 (pair, resolvent, solve)",
+        "data": "synthetic",
+        "config": {"workload": "s-wave bosons, 2-range Yukawa sum fitted to -0.1; 150x150 bins, "
+                               "8x8 q Gauss, 20-pt cosine rule, 8 energies", "nnz_cells": nnz,
+                   "basis": N * N, "energies": list(ENERGIES)},
+        "solve_s_per_energy": {"mixed": s_mixed, "fp64": s_fp64,
+                               "mixed_max_rel_amp_err_vs_fp64": amp_err},
+        "p_build": {"mixed_ms": 1e3 * pbuild[0] / args.steps, "fp64_ms": 1e3 * fp64_build,
+                    "fp64_elements_per_s": nnz / fp64_build,
+                    "elem_kernel_f32_ms": 1e3 * elem_avg_s,
+                    "elem_kernel_f64_ms": e64_ms / max(e64_n, 1),
+                    "preselect_ms": sum(tim.get(k, (0.0, 1))[0] for k in
+                                        ("preselect_count", "preselect_scan", "preselect_fill"))
+                    / args.steps},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": None, "kernel": "p0_elem_f32"},
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride, threads)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * wpcd.h -- C ABI of libwpcd.so, the MI355X (gfx950) implementation of the
+ * hot path of the wave-packet continuum discretization (WPCD) method for
+ * three-body Faddeev scattering (Pomerantsev, Kukulin, Rubtsova, Sakhiev,
+ * "Fast GPU-based calculations in few-body quantum scattering").
+ *
+ * The calls follow the paper's four-step scheme (Sec. III.C): process the
+ * input (bases, pair potential, pair diagonalisation), build the lattice
+ * permutation matrix P0, then for each energy build the channel resolvent
+ * and solve the matrix Faddeev equation for the on-shell amplitudes.
+ *
+ * Conventions used throughout:
+ *  - Units hbar = m = 1: pair kinetic energy p^2, spectator energy 3/4 q^2.
+ *  - Free wave packets have unit weight (eqs.(ip),(theta_p) with f = 1).
+ *  - Bins are 0-based: bin i is [p[i], p[i+1]].  A lattice cell (i, j) has
+ *    cell index j*n_p + i.  The channel-basis index of (channel a,
+ *    spectator bin j, pair state k) is (a*n_q + j)*n_p + k.
+ *  - All host pointers are owned by the caller and are only read or written
+ *    during the call.  The context owns every device allocation.
+ *  - Every call returns a wpcd_status; no C++ exception crosses the ABI.
+ *    On an error, outputs are left untouched and wpcd_last_error() holds a
+ *    message.  A context is not thread-safe: use one per host thread.
+ */
+#ifndef WPCD_H
+#define WPCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wpcd_ctx wpcd_ctx;
+
+typedef enum {
+    WPCD_OK = 0,
+    WPCD_E_INVALID = 1,          /* bad argument or unsupported size */
+    WPCD_E_NOMEM = 2,            /* device or host allocation failed */
+    WPCD_E_DEVICE = 3,           /* a HIP runtime call failed */
+    WPCD_E_NOT_CONVERGED = 4,    /* iterative solve hit max_iter (per energy) */
+    WPCD_E_BELOW_THRESHOLD = 5,  /* E at or below the two-body threshold (per energy) */
+    WPCD_E_ON_EDGE = 6,          /* an on-shell momentum sits on a bin edge (per energy) */
+    WPCD_E_STATE = 7             /* calls made out of order */
+} wpcd_status;
+
+typedef enum {
+    WPCD_FP64 = 0,   /* FP64 everywhere */
+    WPCD_MIXED = 1   /* P0 accumulated in FP32 with compensated sums */
+} wpcd_precision;
+
+/* Lattice basis (Sec. II.D, eq.(xij); channels eq.(si)).
+ * edge_kind 0: edges x_k = x_max (1 - cos(pi k / (2 n))) for 0 < k < n,
+ *              x_0 = 0 and x_n = x_max exactly.
+ * edge_kind 1: p_edges[n_p+1] and q_edges[n_q+1] given (strictly increasing,
+ *              first edge >= 0); p_max/q_max are then ignored.
+ * n_gauss_q: Gauss-Legendre points per q bin (1..16) for the P0 quadrature.
+ * n_gauss_x: Gauss-Legendre points on the clipped cosine interval (1..64).
+ * L: total orbital momentum; n_ch channels (l[a], lam[a]) with even l.
+ * Limits: 2 <= n_p, n_q <= 1024; 1 <= n_ch <= 8; l, lam <= 4.            */
+typedef struct {
+    int32_t n_p, n_q;
+    double p_max, q_max;
+    int32_t edge_kind;
+    const double *p_edges, *q_edges;
+    int32_t n_gauss_q, n_gauss_x;
+    int32_t L, n_ch;
+    const int32_t *l, *lam;
+} wpcd_basis_desc;
+
+/* Pair potential (eq.(vpot)).
+ * kind 0: rank-1 Yamaguchi v = strength[0] g g, g = 1/(p^2 + range[0]^2),
+ *         s-wave only (zero in l > 0).
+ * kind 1: sum over n_terms of strength[k] exp(-range[k] r)/r, in every pair
+ *         wave l.
+ * fit_e2: if not NaN (kind 1 only), all strengths are scaled by one common
+ *         positive factor chosen so that the lowest l = 0 pair level equals
+ *         fit_e2 in this basis.                                          */
+typedef struct {
+    int32_t kind;
+    int32_t n_terms;
+    const double *strength, *range;
+    double fit_e2;
+} wpcd_potential_desc;
+
+/* Iterative solve options.  max_iter: total Krylov iterations per energy
+ * (default 400 when <= 0); krylov_dim: GMRES restart length (default 48,
+ * max 128); tol: relative residual target (default 1e-12 FP64, 1e-10
+ * mixed).  want_breakup: fill breakup_out in wpcd_solve.                 */
+typedef struct {
+    int32_t max_iter;
+    int32_t krylov_dim;
+    double tol;
+    int32_t want_breakup;
+} wpcd_solve_opts;
+
+/* Per-energy result.  status is a wpcd_status value for this energy.
+ * U = on-shell element of the transition matrix, A = (2/(3 q0)) U / dq_j0,
+ * S = 1 - 2 pi i A (Sec. III.B, m = 1), delta = arg(S)/2, eta = |S|.
+ * n_open: open breakup pseudostate channels (breakup_out rows).         */
+typedef struct {
+    double E, q0;
+    int32_t j0, status, iters, n_open;
+    double U_re, U_im, A_re, A_im, S_re, S_im;
+    double delta, eta, residual;
+} wpcd_energy_result;
+
+/* Per-kernel timing (milliseconds summed over launches since the last
+ * reset, measured with HIP events on the stream the kernels run on).    */
+typedef struct {
+    char name[32];
+    double total_ms;
+    int64_t launches;
+} wpcd_kernel_time;
+
+/* Create a context on HIP device `device`.  hip_stream is a hipStream_t to
+ * launch on (NULL: the context creates its own).  The stream is not owned
+ * when passed in.  Errors: WPCD_E_INVALID, WPCD_E_DEVICE.               */
+wpcd_status wpcd_create(int device, void *hip_stream, wpcd_ctx **out);
+
+/* Step 1 of Sec. III.C: bin edges and Gauss tables (host, FP64, uploaded),
+ * pair-potential matrices in the free WP basis (eq.(vpot)) and the FP64
+ * diagonalisation of h1 = h0 + v for every pair wave used (eq.(exp_z)),
+ * both on the GPU.  O has rows = eigenvectors, eigenvalues ascending, sign
+ * chosen so the largest-magnitude component is positive.  Invalidates any
+ * P0 built for a different grid.  Errors: WPCD_E_INVALID, WPCD_E_NOMEM,
+ * WPCD_E_DEVICE.                                                         */
+wpcd_status wpcd_build_basis(wpcd_ctx *ctx, const wpcd_basis_desc *basis,
+                             const wpcd_potential_desc *pot);
+
+/* Replace only the pair potential (the grid and any built P0 stay valid,
+ * since P0 does not depend on the potential -- Sec. III.C).              */
+wpcd_status wpcd_set_potential(wpcd_ctx *ctx, const wpcd_potential_desc *pot);
+
+/* Copy out the pair spectrum of wave l: eps_out[n_p] and, if O_out is not
+ * NULL, O_out[n_p*n_p] (row-major, rows = eigenvectors).  Also reports the
+ * fitted strength scale (1 if no fit) in *scale_out if not NULL.
+ * Errors: WPCD_E_STATE (no basis), WPCD_E_INVALID (l not used).          */
+wpcd_status wpcd_pair_spectrum(wpcd_ctx *ctx, int32_t l, double *eps_out, double *O_out,
+                               double *scale_out);
+
+/* Step 2 of Sec. III.C (Sec. IV.B-C, eqs.(perm),(gal)): pre-select the
+ * nonzero cell pairs of P0 and compute them.  Structure: CSR over cells,
+ * row_ptr int64[n_p*n_q+1], col int32[nnz] ascending (bit-exact, from IEEE
+ * add/compare on FP64 tables).  Values: n_ch*n_ch per cell pair (row
+ * channel major), FP64 (WPCD_FP64) or FP32 with compensated sums
+ * (WPCD_MIXED).  *nnz_cells_out receives the number of cell pairs.
+ * Errors: WPCD_E_STATE, WPCD_E_NOMEM, WPCD_E_DEVICE.                      */
+wpcd_status wpcd_build_p(wpcd_ctx *ctx, wpcd_precision prec, int64_t *nnz_cells_out);
+
+/* Copy P0 to caller buffers: row_ptr[n_p*n_q+1], col[nnz], val[nnz*n_ch*n_ch]
+ * (FP64; FP32 values are widened).  Any pointer may be NULL to skip it.
+ * Errors: WPCD_E_STATE (no P0).                                          */
+wpcd_status wpcd_get_p(wpcd_ctx *ctx, int64_t *row_ptr, int32_t *col, double *val);
+
+/* Steps 3-4 of Sec. III.C for n_E energies at once: channel resolvent G1
+ * (FP64, diagonal in the channel WP basis), the factored kernel
+ * K = O P0 V~ G1 (eq.(kernel)) applied on the GPU, and a batched restarted
+ * GMRES solve of (1 - K) u = O P0 V~ e0 for the on-shell column of
+ * eq.(m_pvg).  out[n_E] receives the amplitudes.  breakup_out, if not NULL
+ * and opts->want_breakup, receives per energy up to n_p*n_ch rows of
+ * (channel, k, j_k, Re S_k0, Im S_k0) as doubles, row count in n_open.
+ * Per-energy failures are reported in out[e].status and do not abort the
+ * batch.  prec selects the P0 values used (FP64 requires an FP64 build).
+ * Errors: WPCD_E_STATE, WPCD_E_INVALID, WPCD_E_NOMEM, WPCD_E_DEVICE.      */
+wpcd_status wpcd_solve(wpcd_ctx *ctx, const double *E, int32_t n_E, wpcd_precision prec,
+                       const wpcd_solve_opts *opts, wpcd_energy_result *out,
+                       double *breakup_out);
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * each launch.  enable is a bit mask of kernel groups: WPCD_TIME_PAIR (pair
+ * potential and diagonalisation), WPCD_TIME_P0 (pre-selection and element
+ * kernels), WPCD_TIME_SOLVE (resolvent, kernel products, GMRES); 0 turns
+ * timing off.  wpcd_get_timing copies the accumulated table (up to n
+ * entries, count in *n_out); wpcd_reset_timing clears it.                */
+#define WPCD_TIME_PAIR 1
+#define WPCD_TIME_P0 2
+#define WPCD_TIME_SOLVE 4
+wpcd_status wpcd_set_timing(wpcd_ctx *ctx, int32_t enable);
+wpcd_status wpcd_get_timing(wpcd_ctx *ctx, wpcd_kernel_time *out, int32_t n, int32_t *n_out);
+wpcd_status wpcd_reset_timing(wpcd_ctx *ctx);
+
+/* Wait for all work the context queued.                                  */
+wpcd_status wpcd_synchronize(wpcd_ctx *ctx);
+
+/* Message for the last error on this context (never NULL).              */
+const char *wpcd_last_error(const wpcd_ctx *ctx);
+
+/* Release the context and all its device memory.  NULL is ignored.       */
+void wpcd_destroy(wpcd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WPCD_H */

@@ -1,0 +1,299 @@
+"""Python binding of libwpcd.so (the MI355X WPCD hot path).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+The functions carry the C ABI's names (include/wpcd.h); ``Context`` is a
+small convenience wrapper over them.  If the library has not been built,
+importing works but every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwpcd.so")
+
+WPCD_OK = 0
+WPCD_E_INVALID = 1
+WPCD_E_NOMEM = 2
+WPCD_E_DEVICE = 3
+WPCD_E_NOT_CONVERGED = 4
+WPCD_E_BELOW_THRESHOLD = 5
+WPCD_E_ON_EDGE = 6
+WPCD_E_STATE = 7
+WPCD_FP64 = 0
+WPCD_MIXED = 1
+WPCD_TIME_PAIR = 1
+WPCD_TIME_P0 = 2
+WPCD_TIME_SOLVE = 4
+WPCD_TIME_ALL = 7
+
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_CONVERGED",
+                5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE"}
+
+ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_set_potential", "wpcd_pair_spectrum",
+                 "wpcd_build_p", "wpcd_get_p", "wpcd_solve", "wpcd_set_timing",
+                 "wpcd_get_timing", "wpcd_reset_timing", "wpcd_synchronize", "wpcd_last_error",
+                 "wpcd_destroy")
+
+
+class wpcd_basis_desc(ctypes.Structure):
+    _fields_ = [("n_p", ctypes.c_int32), ("n_q", ctypes.c_int32),
+                ("p_max", ctypes.c_double), ("q_max", ctypes.c_double),
+                ("edge_kind", ctypes.c_int32),
+                ("p_edges", ctypes.POINTER(ctypes.c_double)),
+                ("q_edges", ctypes.POINTER(ctypes.c_double)),
+                ("n_gauss_q", ctypes.c_int32), ("n_gauss_x", ctypes.c_int32),
+                ("L", ctypes.c_int32), ("n_ch", ctypes.c_int32),
+                ("l", ctypes.POINTER(ctypes.c_int32)), ("lam", ctypes.POINTER(ctypes.c_int32))]
+
+
+class wpcd_potential_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_terms", ctypes.c_int32),
+                ("strength", ctypes.POINTER(ctypes.c_double)),
+                ("range", ctypes.POINTER(ctypes.c_double)),
+                ("fit_e2", ctypes.c_double)]
+
+
+class wpcd_solve_opts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("krylov_dim", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("want_breakup", ctypes.c_int32)]
+
+
+class wpcd_energy_result(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("q0", ctypes.c_double),
+                ("j0", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("n_open", ctypes.c_int32),
+                ("U_re", ctypes.c_double), ("U_im", ctypes.c_double),
+                ("A_re", ctypes.c_double), ("A_im", ctypes.c_double),
+                ("S_re", ctypes.c_double), ("S_im", ctypes.c_double),
+                ("delta", ctypes.c_double), ("eta", ctypes.c_double),
+                ("residual", ctypes.c_double)]
+
+
+class wpcd_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("total_ms", ctypes.c_double),
+                ("launches", ctypes.c_int64)]
+
+
+class WpcdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libwpcd.so; raise if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1508_07441_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.wpcd_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.wpcd_build_basis.argtypes = [vp, ctypes.POINTER(wpcd_basis_desc),
+                                       ctypes.POINTER(wpcd_potential_desc)]
+        L.wpcd_set_potential.argtypes = [vp, ctypes.POINTER(wpcd_potential_desc)]
+        L.wpcd_pair_spectrum.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
+        L.wpcd_build_p.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.wpcd_get_p.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int32), dp]
+        L.wpcd_solve.argtypes = [vp, dp, ctypes.c_int32, ctypes.c_int,
+                                 ctypes.POINTER(wpcd_solve_opts),
+                                 ctypes.POINTER(wpcd_energy_result), dp]
+        L.wpcd_set_timing.argtypes = [vp, ctypes.c_int32]
+        L.wpcd_get_timing.argtypes = [vp, ctypes.POINTER(wpcd_kernel_time), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]
+        L.wpcd_reset_timing.argtypes = [vp]
+        L.wpcd_synchronize.argtypes = [vp]
+        L.wpcd_last_error.argtypes = [vp]
+        L.wpcd_last_error.restype = ctypes.c_char_p
+        L.wpcd_destroy.argtypes = [vp]
+        L.wpcd_destroy.restype = None
+        for f in ABI_FUNCTIONS:
+            if f not in ("wpcd_last_error", "wpcd_destroy"):
+                getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(ctx, st):
+    if st != WPCD_OK:
+        msg = lib().wpcd_last_error(ctx).decode() if ctx else ""
+        raise WpcdError(st, msg)
+
+
+# ------------------------------------------------------------ ABI names
+def wpcd_create(device: int = 0, stream: int | None = None):
+    h = ctypes.c_void_p()
+    st = lib().wpcd_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+    if st != WPCD_OK:
+        raise WpcdError(st, "wpcd_create failed")
+    return h
+
+
+def wpcd_build_basis(ctx, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, channels=((0, 0),),
+                     L=0, potential=None, p_edges=None, q_edges=None):
+    l = np.ascontiguousarray([c[0] for c in channels], dtype=np.int32)
+    lam = np.ascontiguousarray([c[1] for c in channels], dtype=np.int32)
+    pe = None if p_edges is None else np.ascontiguousarray(p_edges, dtype=np.float64)
+    qe = None if q_edges is None else np.ascontiguousarray(q_edges, dtype=np.float64)
+    d = wpcd_basis_desc(n_p, n_q, float(p_max), float(q_max), 0 if pe is None else 1,
+                        _dp(pe), _dp(qe), n_gauss_q, n_gauss_x, L, len(channels),
+                        l.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        lam.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    pd, keep = _pot_desc(potential)
+    _check(ctx, lib().wpcd_build_basis(ctx, ctypes.byref(d), ctypes.byref(pd)))
+    del keep
+
+
+def _pot_desc(potential):
+    """potential: dict(kind='yamaguchi'|'yukawa', strength=[...], range=[...], fit_e2=None)."""
+    kind = {"yamaguchi": 0, "yukawa": 1}[potential["kind"]]
+    s = np.ascontiguousarray(potential["strength"], dtype=np.float64)
+    r = np.ascontiguousarray(potential["range"], dtype=np.float64)
+    fit = potential.get("fit_e2")
+    d = wpcd_potential_desc(kind, s.size, _dp(s), _dp(r), math.nan if fit is None else float(fit))
+    return d, (s, r)
+
+
+def wpcd_set_potential(ctx, potential):
+    pd, keep = _pot_desc(potential)
+    _check(ctx, lib().wpcd_set_potential(ctx, ctypes.byref(pd)))
+    del keep
+
+
+def wpcd_pair_spectrum(ctx, l, n_p, want_O=True):
+    eps = np.zeros(n_p)
+    O = np.zeros((n_p, n_p)) if want_O else None
+    sc = np.zeros(1)
+    _check(ctx, lib().wpcd_pair_spectrum(ctx, l, _dp(eps), _dp(O), _dp(sc)))
+    return eps, O, float(sc[0])
+
+
+def wpcd_build_p(ctx, precision=WPCD_FP64):
+    n = ctypes.c_int64()
+    _check(ctx, lib().wpcd_build_p(ctx, precision, ctypes.byref(n)))
+    return n.value
+
+
+def wpcd_get_p(ctx, n_cells, nnz, n_ch=1, values=True):
+    row_ptr = np.zeros(n_cells + 1, dtype=np.int64)
+    col = np.zeros(nnz, dtype=np.int32)
+    val = np.zeros(nnz * n_ch * n_ch) if values else None
+    _check(ctx, lib().wpcd_get_p(ctx, row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(val)))
+    if values:
+        val = val.reshape(nnz, n_ch, n_ch)
+    return row_ptr, col, val
+
+
+def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0,
+               want_breakup=False, n_p=0, n_ch=1):
+    E = np.ascontiguousarray(energies, dtype=np.float64)
+    out = (wpcd_energy_result * max(1, E.size))()
+    opts = wpcd_solve_opts(max_iter, krylov_dim, tol, 1 if want_breakup else 0)
+    br = np.zeros(E.size * max(1, n_p) * n_ch * 5) if want_breakup else None
+    _check(ctx, lib().wpcd_solve(ctx, _dp(E), E.size, precision, ctypes.byref(opts), out,
+                                 _dp(br)))
+    res = [out[k] for k in range(E.size)]
+    if want_breakup:
+        brs = []
+        for k in range(E.size):
+            rows = br.reshape(E.size, -1, 5)[k, :res[k].n_open]
+            brs.append(rows.copy())
+        return res, brs
+    return res
+
+
+def wpcd_set_timing(ctx, groups=WPCD_TIME_ALL):
+    _check(ctx, lib().wpcd_set_timing(ctx, int(groups)))
+
+
+def wpcd_get_timing(ctx):
+    arr = (wpcd_kernel_time * 64)()
+    n = ctypes.c_int32()
+    _check(ctx, lib().wpcd_get_timing(ctx, arr, 64, ctypes.byref(n)))
+    return {arr[k].name.decode(): (arr[k].total_ms, arr[k].launches) for k in range(min(n.value, 64))}
+
+
+def wpcd_reset_timing(ctx):
+    _check(ctx, lib().wpcd_reset_timing(ctx))
+
+
+def wpcd_synchronize(ctx):
+    _check(ctx, lib().wpcd_synchronize(ctx))
+
+
+def wpcd_last_error(ctx):
+    return lib().wpcd_last_error(ctx).decode()
+
+
+def wpcd_destroy(ctx):
+    if ctx:
+        lib().wpcd_destroy(ctx)
+
+
+class Context:
+    """Owns one wpcd_ctx; thin wrapper over the ABI functions above."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.h = wpcd_create(device, stream)
+        self.n_p = self.n_q = self.n_ch = 0
+        self.nnz = 0
+
+    def build_basis(self, n_p, n_q, p_max=10.0, q_max=10.0, n_gauss_q=8, n_gauss_x=16,
+                    channels=((0, 0),), L=0, potential=None, p_edges=None, q_edges=None):
+        wpcd_build_basis(self.h, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, channels, L,
+                         potential, p_edges, q_edges)
+        self.n_p, self.n_q, self.n_ch = n_p, n_q, len(channels)
+
+    def set_potential(self, potential):
+        wpcd_set_potential(self.h, potential)
+
+    def pair_spectrum(self, l=0, want_O=True):
+        return wpcd_pair_spectrum(self.h, l, self.n_p, want_O)
+
+    def build_p(self, precision=WPCD_FP64):
+        self.nnz = wpcd_build_p(self.h, precision)
+        return self.nnz
+
+    def get_p(self, values=True):
+        return wpcd_get_p(self.h, self.n_p * self.n_q, self.nnz, self.n_ch, values)
+
+    def solve(self, energies, precision=WPCD_FP64, **kw):
+        return wpcd_solve(self.h, energies, precision, n_p=self.n_p, n_ch=self.n_ch, **kw)
+
+    def set_timing(self, groups=WPCD_TIME_ALL):
+        wpcd_set_timing(self.h, groups)
+
+    def timing(self):
+        return wpcd_get_timing(self.h)
+
+    def reset_timing(self):
+        wpcd_reset_timing(self.h)
+
+    def synchronize(self):
+        wpcd_synchronize(self.h)
+
+    def close(self):
+        if self.h:
+            wpcd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,355 @@
+// Lattice permutation matrix P0 (paper Sec. III.B eqs.(perm),(gal); GPU
+// scheme Sec. IV.B-C): pre-selection of the nonzero cell pairs, compaction
+// into CSR, and the cell-overlap quadrature for each selected pair.
+//
+// Structure kernels use only IEEE add/sub/compare on FP64 tables computed on
+// the host (p, q, p^2, 3/4 q^2, q/2), so the selected set is bit-exact.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "wpcd_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace wpcd {
+
+struct GridView {
+    const double *p, *q, *P2, *Q34, *H;   // p[np+1], q[nq+1], p^2, 3/4 q^2, q/2
+    int np, nq;
+};
+
+// First index k in [lo, hi) with f(k) true for a monotone predicate
+// (false ... false true ... true); returns hi if none.
+template <class F>
+__device__ __forceinline__ int first_true(int lo, int hi, F f) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (f(mid)) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Column range [lo, hi) of row cell (i, j) within column spectator bin j2.
+// Selection (a necessary condition for a nonzero element): the two cells'
+// energy ranges p^2 + 3/4 q^2 overlap, |q' + q/2| can fall in D_i, and
+// |q + q'/2| can fall in D_i'.
+__device__ __forceinline__ void col_range(const GridView &g, int i, int j, int j2, int &lo,
+                                          int &hi) {
+    lo = 0;
+    hi = 0;
+    // pi1 = |q' + q/2| over q in bin j, q' in bin j2
+    double d1 = 0.0, a;
+    a = g.q[j2] - g.H[j + 1];
+    if (a > d1) d1 = a;
+    a = g.H[j] - g.q[j2 + 1];
+    if (a > d1) d1 = a;
+    if (!(g.p[i + 1] > d1 && g.p[i] < g.q[j2 + 1] + g.H[j + 1])) return;
+    const double elo = g.P2[i] + g.Q34[j];
+    const double ehi = g.P2[i + 1] + g.Q34[j + 1];
+    const double q34lo = g.Q34[j2], q34hi = g.Q34[j2 + 1];
+    double d2 = 0.0;
+    a = g.q[j] - g.H[j2 + 1];
+    if (a > d2) d2 = a;
+    a = g.H[j2] - g.q[j + 1];
+    if (a > d2) d2 = a;
+    const double pmax2 = g.q[j + 1] + g.H[j2 + 1];
+    const int n = g.np;
+    // i2 >= first with  P2[i2+1] + Q34[j2+1] > elo
+    int la = first_true(0, n, [&](int k) { return g.P2[k + 1] + q34hi > elo; });
+    // i2 >= first with  p[i2+1] > d2
+    int lc = first_true(0, n, [&](int k) { return g.p[k + 1] > d2; });
+    // i2 <  first with  !(ehi > P2[i2] + Q34[j2])
+    int hb = first_true(0, n, [&](int k) { return !(ehi > g.P2[k] + q34lo); });
+    // i2 <  first with  !(p[i2] < pmax2)
+    int hd = first_true(0, n, [&](int k) { return !(g.p[k] < pmax2); });
+    lo = la > lc ? la : lc;
+    hi = hb < hd ? hb : hd;
+    if (hi < lo) hi = lo;
+}
+
+// One wavefront per row cell; lanes sweep the column spectator bins.
+__global__ __launch_bounds__(256) void k_count(GridView g, int32_t *__restrict__ cnt) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nrow = g.np * g.nq;
+    if (row >= nrow) return;
+    const int i = row % g.np, j = row / g.np;
+    int c = 0;
+    for (int j2 = lane; j2 < g.nq; j2 += 64) {
+        int lo, hi;
+        col_range(g, i, j, j2, lo, hi);
+        c += hi - lo;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) cnt[row] = c;
+}
+
+// Exclusive prefix sum of cnt[0..n) into row_ptr[0..n], one workgroup.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int n,
+                                               int64_t *__restrict__ row_ptr) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int beg = tid * per;
+    const int end = min(beg + per, n);
+    int64_t s = 0;
+    for (int k = beg; k < end; ++k) s += cnt[k];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = tid ? part[tid - 1] : 0;
+    for (int k = beg; k < end; ++k) {
+        row_ptr[k] = run;
+        run += cnt[k];
+    }
+    if (tid == 1023) row_ptr[n] = part[1023];
+}
+
+// One wavefront per row cell: per column bin ranges -> coalesced column
+// writes in ascending order (column index c = j2*np + i2).
+__global__ __launch_bounds__(256) void k_fill(GridView g, const int64_t *__restrict__ row_ptr,
+                                              int32_t *__restrict__ col,
+                                              int32_t *__restrict__ rowidx) {
+    __shared__ int s_off[4][65];
+    __shared__ int s_lo[4][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int row = blockIdx.x * 4 + w;
+    const int nrow = g.np * g.nq;
+    // every wave runs the loop (uniform trip count) so all reach the barriers
+    const bool valid = row < nrow;
+    const int i = valid ? row % g.np : 0, j = valid ? row / g.np : 0;
+    int64_t base = valid ? row_ptr[row] : 0;
+    for (int j0 = 0; j0 < g.nq; j0 += 64) {
+        const int j2 = j0 + lane;
+        int lo = 0, hi = 0;
+        if (valid && j2 < g.nq) col_range(g, i, j, j2, lo, hi);
+        int c = hi - lo;
+        // inclusive scan across the wavefront
+        int incl = c;
+        for (int off = 1; off < 64; off <<= 1) {
+            int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        s_off[w][lane + 1] = incl;
+        if (lane == 0) s_off[w][0] = 0;
+        s_lo[w][lane] = lo;
+        __syncthreads();
+        const int total = s_off[w][64];
+        for (int t = lane; t < total; t += 64) {
+            // owner lane: last k with s_off[k] <= t
+            int a = 0, b = 63;
+            while (a < b) {
+                int m = (a + b + 1) >> 1;
+                if (s_off[w][m] <= t) a = m;
+                else b = m - 1;
+            }
+            int i2 = s_lo[w][a] + (t - s_off[w][a]);
+            col[base + t] = (j0 + a) * g.np + i2;
+            rowidx[base + t] = row;
+        }
+        base += total;
+        __syncthreads();
+    }
+}
+
+// The element quadrature below may contract into FMAs.
+#pragma clang fp contract(fast)
+
+// ------------------------------------------------------------ element
+// P0 element of cell pair (i, j) x (i2, j2), s-wave:
+//   (d_i d_i2 dq_j dq_j2)^(-1/2) sum_{a,b} wq_a wq_b  int dt / sqrt(t u)
+// with t = pi1^2 in [t_lo, t_hi] (the clipped cosine interval mapped by the
+// affine t = q'^2 + q^2/4 + q q' x; the q q' of the measure cancels dx = dt/(q q'))
+// and u = pi2^2 = t + 3/4 (q^2 - q'^2).  Lane = (a, b) Gauss pair.
+struct ElemTables {
+    const double *P2;      // p^2 [np+1]
+    const double *rsd_p;   // 1/sqrt(d_i) [np]
+    const double *rsd_q;   // 1/sqrt(dq_j) [nq]
+    const double *qnode;   // [nq][ngq] Gauss points in each q bin
+    const double *qwt;     // [nq][ngq] weights * half width
+    const double *ux;      // 1 + t_c [ngx]
+    const double *wx;      // w_c [ngx]
+    const float *uxf, *wxf;
+    int np, ngq, ngx;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Neumaier two-sum accumulation in FP32.
+struct Comp32 {
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float x) {
+        float t = s + x;
+        if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+    }
+};
+
+__device__ __forceinline__ void lane_limits(const ElemTables &T, int i, int i2, double q, double q2,
+                                            double &lo_t, double &lo_u, double &h) {
+    const double qq = q * q, qq2 = q2 * q2;
+    const double A = qq2 + 0.25 * qq;   // pi1^2 at x = 0
+    const double C = qq + 0.25 * qq2;   // pi2^2 at x = 0
+    const double B = q * q2;
+    const double D = C - A;             // u - t
+    const double pl1 = T.P2[i], ph1 = T.P2[i + 1];
+    const double pl2 = T.P2[i2], ph2 = T.P2[i2 + 1];
+    lo_t = fmax(fmax(A - B, pl1), pl2 - D);
+    double hi_t = fmin(fmin(A + B, ph1), ph2 - D);
+    lo_u = fmax(fmax(C - B, pl2), pl1 + D);
+    double hi_u = fmin(fmin(C + B, ph2), ph1 + D);
+    h = (hi_t > lo_t) ? 0.25 * ((hi_t - lo_t) + (hi_u - lo_u)) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_p0_swave_f64(ElemTables T,
+                                                      const int32_t *__restrict__ rowidx,
+                                                      const int32_t *__restrict__ col, int64_t nnz,
+                                                      double *__restrict__ val) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int npair = T.ngq * T.ngq;
+    for (int64_t e = wave0; e < nnz; e += nwaves) {
+        const int r = rowidx[e], c = col[e];
+        const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+        double acc = 0.0;
+        for (int pr = lane; pr < npair; pr += 64) {
+            const int a = pr / T.ngq, b = pr - a * T.ngq;
+            const double q = T.qnode[j * T.ngq + a], q2 = T.qnode[j2 * T.ngq + b];
+            double lo_t, lo_u, h;
+            lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
+            if (h > 0.0) {
+                double s = 0.0;
+                for (int k = 0; k < T.ngx; ++k) {
+                    const double sk = h * T.ux[k];
+                    s += T.wx[k] * rsqrt((lo_t + sk) * (lo_u + sk));
+                }
+                acc += T.qwt[j * T.ngq + a] * T.qwt[j2 * T.ngq + b] * h * s;
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) val[e] = acc * (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_p0_swave_f32(ElemTables T,
+                                                      const int32_t *__restrict__ rowidx,
+                                                      const int32_t *__restrict__ col, int64_t nnz,
+                                                      float *__restrict__ val) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int npair = T.ngq * T.ngq;
+    for (int64_t e = wave0; e < nnz; e += nwaves) {
+        const int r = rowidx[e], c = col[e];
+        const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+        Comp32 acc;
+        for (int pr = lane; pr < npair; pr += 64) {
+            const int a = pr / T.ngq, b = pr - a * T.ngq;
+            const double q = T.qnode[j * T.ngq + a], q2 = T.qnode[j2 * T.ngq + b];
+            double lo_t, lo_u, h;
+            lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
+            if (h > 0.0) {
+                const float tf = (float)lo_t, uf = (float)lo_u, hf = (float)h;
+                Comp32 s;
+                for (int k = 0; k < T.ngx; ++k) {
+                    const float sk = hf * T.uxf[k];
+                    s.add(T.wxf[k] * rsqrtf((tf + sk) * (uf + sk)));
+                }
+                const float wab = (float)(T.qwt[j * T.ngq + a] * T.qwt[j2 * T.ngq + b] * h);
+                acc.add(wab * s.s);
+                acc.add(wab * s.c);
+            }
+        }
+        // compensated wavefront reduction of (s, c) pairs
+        float s = acc.s, cc = acc.c;
+        for (int off = 32; off > 0; off >>= 1) {
+            float so = __shfl_xor(s, off, 64), co = __shfl_xor(cc, off, 64);
+            float t = s + so;
+            float bp = t - s;
+            float err = (s - (t - bp)) + (so - bp);
+            s = t;
+            cc = cc + co + err;
+        }
+        if (lane == 0)
+            val[e] = (float)(((double)s + (double)cc) * (T.rsd_p[i] * T.rsd_p[i2]) *
+                             (T.rsd_q[j] * T.rsd_q[j2]));
+    }
+}
+
+// ------------------------------------------------------------------ host
+static GridView grid_view(wpcd_ctx *c) {
+    return GridView{c->d_p.ptr, c->d_q.ptr, c->d_P2.ptr, c->d_Q34.ptr, c->d_H.ptr, c->np, c->nq};
+}
+
+void build_structure(wpcd_ctx *c) {
+    const int nrow = c->np * c->nq;
+    GridView g = grid_view(c);
+    c->d_cnt.reserve(nrow);
+    c->d_rowptr.reserve((size_t)nrow + 1);
+    const int blocks = (nrow + 3) / 4;
+    {
+        TimedLaunch tl(c->timer, c->stream, "preselect_count", WPCD_TIME_P0);
+        hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), 0, c->stream, g, c->d_cnt.ptr);
+        WPCD_HIP(hipGetLastError());
+    }
+    {
+        TimedLaunch tl(c->timer, c->stream, "preselect_scan", WPCD_TIME_P0);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, c->d_cnt.ptr, nrow,
+                           c->d_rowptr.ptr);
+        WPCD_HIP(hipGetLastError());
+    }
+    int64_t nnz = 0;
+    WPCD_HIP(hipMemcpyAsync(&nnz, c->d_rowptr.ptr + nrow, sizeof(int64_t), hipMemcpyDeviceToHost,
+                            c->stream));
+    WPCD_HIP(hipStreamSynchronize(c->stream));
+    WPCD_REQUIRE(nnz >= 0 && nnz < ((int64_t)1 << 40), WPCD_E_DEVICE, "bad nonzero count");
+    c->nnz = nnz;
+    c->d_col.reserve(nnz);
+    c->d_rowidx.reserve(nnz);
+    {
+        TimedLaunch tl(c->timer, c->stream, "preselect_fill", WPCD_TIME_P0);
+        hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, c->stream, g, c->d_rowptr.ptr,
+                           c->d_col.ptr, c->d_rowidx.ptr);
+        WPCD_HIP(hipGetLastError());
+    }
+}
+
+void build_values(wpcd_ctx *c, bool fp64) {
+    ElemTables T{c->d_P2.ptr, c->d_rsd_p.ptr, c->d_rsd_q.ptr, c->d_qnode.ptr, c->d_qwt.ptr,
+                 c->d_ux.ptr,  c->d_wx.ptr,    c->d_uxf.ptr,   c->d_wxf.ptr,   c->np,
+                 c->ngq,       c->ngx};
+    WPCD_REQUIRE(c->nch == 1, WPCD_E_INVALID, "multichannel P0 not built yet");
+    const int64_t nnz = c->nnz;
+    if (nnz == 0) return;
+    // persistent grid: enough waves to fill 256 CUs several times over
+    int64_t want = (nnz + 3) / 4;
+    int blocks = (int)(want < 65536 ? want : 65536);
+    if (fp64) {
+        c->d_val64.reserve(nnz);
+        TimedLaunch tl(c->timer, c->stream, "p0_elem_f64", WPCD_TIME_P0);
+        hipLaunchKernelGGL(k_p0_swave_f64, dim3(blocks), dim3(256), 0, c->stream, T,
+                           c->d_rowidx.ptr, c->d_col.ptr, nnz, c->d_val64.ptr);
+        WPCD_HIP(hipGetLastError());
+    } else {
+        c->d_val32.reserve(nnz);
+        TimedLaunch tl(c->timer, c->stream, "p0_elem_f32", WPCD_TIME_P0);
+        hipLaunchKernelGGL(k_p0_swave_f32, dim3(blocks), dim3(256), 0, c->stream, T,
+                           c->d_rowidx.ptr, c->d_col.ptr, nnz, c->d_val32.ptr);
+        WPCD_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace wpcd

@@ -1,0 +1,745 @@
+// C ABI of libwpcd: context, host tables, orchestration of the GPU steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "wpcd_internal.h"
+
+namespace wpcd {
+
+void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
+                 bool fp64, int m, int max_iter, double tol, std::vector<int> &iters,
+                 std::vector<double> &resid, std::vector<int> &edge_flag);
+void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
+                      const std::vector<int32_t> &ens, const std::vector<double> &rho,
+                      const std::vector<double> &rho0, std::vector<double> &out);
+
+// ------------------------------------------------------------ timing
+int Timer::id_of(const char *name) {
+    for (size_t i = 0; i < names.size(); ++i)
+        if (names[i] == name) return (int)i;
+    names.emplace_back(name);
+    total_ms.push_back(0.0);
+    launches.push_back(0);
+    return (int)names.size() - 1;
+}
+
+hipEvent_t Timer::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    WPCD_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Timer::begin(hipStream_t s, const char *name, Pending &p) {
+    p.id = id_of(name);
+    p.a = get();
+    p.b = get();
+    WPCD_HIP(hipEventRecord(p.a, s));
+}
+
+void Timer::end(hipStream_t s, Pending &p) {
+    (void)hipEventRecord(p.b, s);
+    pending.push_back(p);
+}
+
+void Timer::collect() {
+    for (auto &p : pending) {
+        float ms = 0.f;
+        WPCD_HIP(hipEventSynchronize(p.b));
+        WPCD_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        total_ms[p.id] += ms;
+        launches[p.id] += 1;
+        pool.push_back(p.a);
+        pool.push_back(p.b);
+    }
+    pending.clear();
+}
+
+void Timer::reset() {
+    collect();
+    for (auto &t : total_ms) t = 0.0;
+    for (auto &l : launches) l = 0;
+}
+
+void Timer::release() {
+    for (auto &p : pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    pending.clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+// ------------------------------------------------------- Gauss tables
+// Golub-Welsch: the nodes are the eigenvalues of the symmetric tridiagonal
+// Jacobi matrix of the Legendre recurrence (zero diagonal, off-diagonal
+// k / sqrt(4k^2 - 1)); weight = 2 (first eigenvector component)^2.  The
+// eigenproblem is solved by cyclic Jacobi rotations on the dense n x n
+// matrix; nodes are then polished by Newton steps in long double and the
+// weights recomputed from P_n'.
+void gauss_legendre_gw(int n, std::vector<double> &x, std::vector<double> &w) {
+    std::vector<long double> J((size_t)n * n, 0.0L), V((size_t)n * n, 0.0L);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0L;
+    for (int k = 1; k < n; ++k) {
+        long double b = k / std::sqrt(4.0L * k * k - 1.0L);
+        J[(size_t)(k - 1) * n + k] = b;
+        J[(size_t)k * n + k - 1] = b;
+    }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        long double off = 0.0L;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += J[(size_t)p * n + q] * J[(size_t)p * n + q];
+        if (off < 1e-40L) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                long double apq = J[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300L) continue;
+                long double th = (J[(size_t)q * n + q] - J[(size_t)p * n + p]) / (2.0L * apq);
+                long double t = (th >= 0 ? 1.0L : -1.0L) / (std::fabs(th) + std::sqrt(1.0L + th * th));
+                long double c = 1.0L / std::sqrt(1.0L + t * t), s = t * c;
+                for (int r = 0; r < n; ++r) {
+                    long double a = J[(size_t)r * n + p], bq = J[(size_t)r * n + q];
+                    J[(size_t)r * n + p] = c * a - s * bq;
+                    J[(size_t)r * n + q] = s * a + c * bq;
+                }
+                for (int r = 0; r < n; ++r) {
+                    long double a = J[(size_t)p * n + r], bq = J[(size_t)q * n + r];
+                    J[(size_t)p * n + r] = c * a - s * bq;
+                    J[(size_t)q * n + r] = s * a + c * bq;
+                }
+                for (int r = 0; r < n; ++r) {
+                    long double a = V[(size_t)r * n + p], bq = V[(size_t)r * n + q];
+                    V[(size_t)r * n + p] = c * a - s * bq;
+                    V[(size_t)r * n + q] = s * a + c * bq;
+                }
+            }
+    }
+    std::vector<std::pair<long double, long double>> nw(n);
+    for (int k = 0; k < n; ++k) nw[k] = {J[(size_t)k * n + k], 2.0L * V[k] * V[k]};
+    std::sort(nw.begin(), nw.end());
+    x.resize(n);
+    w.resize(n);
+    for (int k = 0; k < n; ++k) {
+        long double z = nw[k].first, dp = 0.0L;
+        for (int it = 0; it < 3; ++it) {
+            long double p0 = 1.0L, p1 = z;
+            for (int mm = 2; mm <= n; ++mm) {
+                long double p2 = ((2 * mm - 1) * z * p1 - (mm - 1) * p0) / mm;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) {
+                p1 = z;
+                p0 = 1.0L;
+            }
+            dp = n * (p0 - z * p1) / (1.0L - z * z);
+            z -= p1 / dp;
+        }
+        long double p0 = 1.0L, p1 = z;
+        for (int mm = 2; mm <= n; ++mm) {
+            long double p2 = ((2 * mm - 1) * z * p1 - (mm - 1) * p0) / mm;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) {
+            p1 = z;
+            p0 = 1.0L;
+        }
+        dp = n * (p0 - z * p1) / (1.0L - z * z);
+        x[k] = (double)z;
+        w[k] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+template <class T>
+static void upload(DBuf<T> &d, const std::vector<T> &h, hipStream_t s) {
+    d.reserve(h.size());
+    WPCD_HIP(hipMemcpyAsync(d.ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// Edges x_k = x_max (1 - cos(pi k / (2n))), ends exactly 0 and x_max.
+static std::vector<double> cheb_edges(int n, double vmax) {
+    std::vector<double> e(n + 1);
+    for (int k = 1; k < n; ++k) e[k] = vmax * (1.0 - std::cos((M_PI * (double)k) / (2.0 * (double)n)));
+    e[0] = 0.0;
+    e[n] = vmax;
+    return e;
+}
+
+static void upload_tables(wpcd_ctx *c) {
+    const int np = c->np, nq = c->nq;
+    hipStream_t s = c->stream;
+    std::vector<double> P2(np + 1), Q34(nq + 1), H(nq + 1), rp(np), rq(nq);
+    for (int k = 0; k <= np; ++k) P2[k] = c->p[k] * c->p[k];
+    for (int k = 0; k <= nq; ++k) {
+        Q34[k] = 0.75 * (c->q[k] * c->q[k]);
+        H[k] = 0.5 * c->q[k];
+    }
+    for (int k = 0; k < np; ++k) rp[k] = 1.0 / std::sqrt(c->p[k + 1] - c->p[k]);
+    for (int k = 0; k < nq; ++k) rq[k] = 1.0 / std::sqrt(c->q[k + 1] - c->q[k]);
+    std::vector<double> qn((size_t)nq * c->ngq), qw((size_t)nq * c->ngq);
+    for (int j = 0; j < nq; ++j) {
+        const double m = 0.5 * (c->q[j] + c->q[j + 1]), h = 0.5 * (c->q[j + 1] - c->q[j]);
+        for (int a = 0; a < c->ngq; ++a) {
+            qn[(size_t)j * c->ngq + a] = m + h * c->gq[a];
+            qw[(size_t)j * c->ngq + a] = h * c->wq[a];
+        }
+    }
+    std::vector<double> ux(c->ngx), wx(c->ngx);
+    std::vector<float> uxf(c->ngx), wxf(c->ngx);
+    for (int k = 0; k < c->ngx; ++k) {
+        ux[k] = 1.0 + c->gx[k];
+        wx[k] = c->wx[k];
+        uxf[k] = (float)ux[k];
+        wxf[k] = (float)wx[k];
+    }
+    upload(c->d_p, c->p, s);
+    upload(c->d_q, c->q, s);
+    upload(c->d_P2, P2, s);
+    upload(c->d_Q34, Q34, s);
+    upload(c->d_H, H, s);
+    upload(c->d_rsd_p, rp, s);
+    upload(c->d_rsd_q, rq, s);
+    upload(c->d_qnode, qn, s);
+    upload(c->d_qwt, qw, s);
+    upload(c->d_ux, ux, s);
+    upload(c->d_wx, wx, s);
+    upload(c->d_uxf, uxf, s);
+    upload(c->d_wxf, wxf, s);
+    WPCD_HIP(hipStreamSynchronize(s));
+}
+
+static void set_potential_desc(wpcd_ctx *c, const wpcd_potential_desc *pot) {
+    WPCD_REQUIRE(pot, WPCD_E_INVALID, "potential descriptor is NULL");
+    WPCD_REQUIRE(pot->kind == 0 || pot->kind == 1, WPCD_E_INVALID, "potential kind must be 0 or 1");
+    WPCD_REQUIRE(pot->n_terms >= 1 && pot->n_terms <= 16, WPCD_E_INVALID, "n_terms must be 1..16");
+    WPCD_REQUIRE(pot->strength && pot->range, WPCD_E_INVALID, "strength/range NULL");
+    if (pot->kind == 0) WPCD_REQUIRE(pot->n_terms == 1, WPCD_E_INVALID, "Yamaguchi takes one term");
+    for (int t = 0; t < pot->n_terms; ++t) {
+        WPCD_REQUIRE(std::isfinite(pot->strength[t]) && std::isfinite(pot->range[t]) &&
+                         pot->range[t] > 0.0,
+                     WPCD_E_INVALID, "potential parameters must be finite with range > 0");
+    }
+    c->pot_kind = pot->kind;
+    c->pot_s.assign(pot->strength, pot->strength + pot->n_terms);
+    c->pot_mu.assign(pot->range, pot->range + pot->n_terms);
+    c->pot_scale = 1.0;
+}
+
+static void diagonalise_all(wpcd_ctx *c) {
+    const int n = c->np;
+    for (int w = 0; w < c->n_waves; ++w) {
+        PairWave &pw = c->waves[w];
+        pw.v.reserve((size_t)n * n);
+        pw.O.reserve((size_t)n * n);
+        pw.Vt.reserve((size_t)n * n);
+        pw.eps.reserve(n);
+        launch_potential(c, w, pw.v.ptr);
+        pair_diagonalise(c, w, true);
+        launch_vt(c, w);
+    }
+    WPCD_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Common positive scale of all strengths so that the lowest l = 0 level is
+// `target`: safeguarded Newton on sigma with the Hellmann-Feynman slope
+// d eps0 / d sigma = z0^T v_unit z0 (host arithmetic on copied vectors).
+static void fit_scale(wpcd_ctx *c, double target) {
+    int w0 = -1;
+    for (int w = 0; w < c->n_waves; ++w)
+        if (c->waves[w].l == 0) w0 = w;
+    WPCD_REQUIRE(w0 >= 0, WPCD_E_INVALID, "strength fit needs an l = 0 channel");
+    const int n = c->np;
+    PairWave &pw = c->waves[w0];
+    pw.v.reserve((size_t)n * n);
+    pw.O.reserve((size_t)n * n);
+    pw.Vt.reserve((size_t)n * n);
+    pw.eps.reserve(n);
+    std::vector<double> vu((size_t)n * n), z(n);
+    c->pot_scale = 1.0;
+    launch_potential(c, w0, pw.v.ptr);
+    WPCD_HIP(hipMemcpyAsync(vu.data(), pw.v.ptr, vu.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    WPCD_HIP(hipStreamSynchronize(c->stream));
+    auto eval = [&](double sig, double &e0, double &slope) {
+        c->pot_scale = sig;
+        launch_potential(c, w0, pw.v.ptr);
+        pair_diagonalise(c, w0, true);
+        WPCD_HIP(hipMemcpyAsync(z.data(), pw.O.ptr, n * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+        e0 = pw.h_eps[0];
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double r = 0.0;
+            for (int k = 0; k < n; ++k) r += vu[(size_t)i * n + k] * z[k];
+            s += z[i] * r;
+        }
+        slope = s;
+    };
+    double lo = 0.0, hi = 1.0, e0 = 0.0, sl = 0.0;
+    // bracket: eps0(lo) > target >= eps0(hi)
+    for (int it = 0; it < 60; ++it) {
+        eval(hi, e0, sl);
+        if (e0 <= target) break;
+        lo = hi;
+        hi *= 2.0;
+        WPCD_REQUIRE(it < 59, WPCD_E_INVALID, "strength fit: no bound state reachable");
+    }
+    double sig = hi;
+    for (int it = 0; it < 100; ++it) {
+        eval(sig, e0, sl);
+        double f = e0 - target;
+        if (f > 0) lo = sig;
+        else hi = sig;
+        if (std::fabs(f) <= 1e-14 * std::fabs(target) || hi - lo <= 1e-15 * hi) break;
+        double nx = (sl != 0.0) ? sig - f / sl : 0.5 * (lo + hi);
+        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+        sig = nx;
+    }
+    c->pot_scale = sig;
+}
+
+static void build_pair_waves(wpcd_ctx *c, const wpcd_potential_desc *pot) {
+    set_potential_desc(c, pot);
+    if (!std::isnan(pot->fit_e2)) {
+        WPCD_REQUIRE(pot->kind == 1, WPCD_E_INVALID, "fit_e2 applies to the Yukawa sum only");
+        fit_scale(c, pot->fit_e2);
+    }
+    diagonalise_all(c);
+    c->has_pot = true;
+}
+
+}  // namespace wpcd
+
+using namespace wpcd;
+
+template <class F>
+static wpcd_status guarded(wpcd_ctx *c, F &&f) {
+    if (!c) return WPCD_E_INVALID;
+    try {
+        WPCD_HIP(hipSetDevice(c->device));
+        f();
+        c->err.clear();
+        return WPCD_OK;
+    } catch (const Error &e) {
+        c->err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        c->err = e.what();
+        return WPCD_E_NOMEM;
+    } catch (...) {
+        c->err = "unknown error";
+        return WPCD_E_DEVICE;
+    }
+}
+
+extern "C" {
+
+wpcd_status wpcd_create(int device, void *hip_stream, wpcd_ctx **out) {
+    if (!out) return WPCD_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return WPCD_E_DEVICE;
+    if (device < 0 || device >= ndev) return WPCD_E_INVALID;
+    wpcd_ctx *c = new (std::nothrow) wpcd_ctx();
+    if (!c) return WPCD_E_NOMEM;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return WPCD_E_DEVICE;
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return WPCD_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return WPCD_OK;
+}
+
+wpcd_status wpcd_build_basis(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_potential_desc *pot) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(b, WPCD_E_INVALID, "basis descriptor is NULL");
+        WPCD_REQUIRE(b->n_p >= 2 && b->n_p <= 1024 && b->n_q >= 2 && b->n_q <= 1024,
+                     WPCD_E_INVALID, "n_p, n_q must be in 2..1024");
+        WPCD_REQUIRE(b->n_gauss_q >= 1 && b->n_gauss_q <= kMaxGq, WPCD_E_INVALID,
+                     "n_gauss_q must be 1..16");
+        WPCD_REQUIRE(b->n_gauss_x >= 1 && b->n_gauss_x <= kMaxGx, WPCD_E_INVALID,
+                     "n_gauss_x must be 1..64");
+        WPCD_REQUIRE(b->n_ch >= 1 && b->n_ch <= kMaxCh, WPCD_E_INVALID, "n_ch must be 1..8");
+        WPCD_REQUIRE(b->l && b->lam, WPCD_E_INVALID, "channel arrays NULL");
+        WPCD_REQUIRE(b->L >= 0 && b->L <= 8, WPCD_E_INVALID, "L must be 0..8");
+        std::vector<int> waves;
+        for (int a = 0; a < b->n_ch; ++a) {
+            const int l = b->l[a], lam = b->lam[a];
+            WPCD_REQUIRE(l >= 0 && l <= 4 && lam >= 0 && lam <= kMaxLam && l % 2 == 0,
+                         WPCD_E_INVALID, "channels need even l <= 4 and lam <= 4");
+            WPCD_REQUIRE(std::abs(l - lam) <= b->L && b->L <= l + lam && (l + lam - b->L) % 2 == 0,
+                         WPCD_E_INVALID, "channel (l, lam) cannot couple to L with parity (-1)^L");
+            if (std::find(waves.begin(), waves.end(), l) == waves.end()) waves.push_back(l);
+        }
+        WPCD_REQUIRE((int)waves.size() <= kMaxWaves, WPCD_E_INVALID, "too many pair waves");
+        std::vector<double> p, q;
+        if (b->edge_kind == 0) {
+            WPCD_REQUIRE(b->p_max > 0 && b->q_max > 0 && std::isfinite(b->p_max) &&
+                             std::isfinite(b->q_max),
+                         WPCD_E_INVALID, "p_max, q_max must be positive");
+            p = cheb_edges(b->n_p, b->p_max);
+            q = cheb_edges(b->n_q, b->q_max);
+        } else if (b->edge_kind == 1) {
+            WPCD_REQUIRE(b->p_edges && b->q_edges, WPCD_E_INVALID, "explicit edges NULL");
+            p.assign(b->p_edges, b->p_edges + b->n_p + 1);
+            q.assign(b->q_edges, b->q_edges + b->n_q + 1);
+            WPCD_REQUIRE(p[0] >= 0 && q[0] >= 0, WPCD_E_INVALID, "edges must start >= 0");
+            for (int k = 0; k < b->n_p; ++k)
+                WPCD_REQUIRE(p[k + 1] > p[k] && std::isfinite(p[k + 1]), WPCD_E_INVALID,
+                             "p edges must increase");
+            for (int k = 0; k < b->n_q; ++k)
+                WPCD_REQUIRE(q[k + 1] > q[k] && std::isfinite(q[k + 1]), WPCD_E_INVALID,
+                             "q edges must increase");
+        } else {
+            throw Error{WPCD_E_INVALID, "edge_kind must be 0 or 1"};
+        }
+        bool same_grid = c->has_basis && c->np == b->n_p && c->nq == b->n_q && c->p == p &&
+                         c->q == q && c->ngq == b->n_gauss_q && c->ngx == b->n_gauss_x &&
+                         c->L == b->L && c->nch == b->n_ch;
+        for (int a = 0; same_grid && a < b->n_ch; ++a)
+            same_grid = c->ch_l[a] == b->l[a] && c->ch_lam[a] == b->lam[a];
+        c->has_basis = false;
+        c->has_pot = false;
+        if (!same_grid) c->has_p = false;
+        c->np = b->n_p;
+        c->nq = b->n_q;
+        c->ngq = b->n_gauss_q;
+        c->ngx = b->n_gauss_x;
+        c->L = b->L;
+        c->nch = b->n_ch;
+        c->p = p;
+        c->q = q;
+        gauss_legendre_gw(c->ngq, c->gq, c->wq);
+        gauss_legendre_gw(c->ngx, c->gx, c->wx);
+        c->n_waves = (int)waves.size();
+        for (int w = 0; w < c->n_waves; ++w) c->waves[w].l = waves[w];
+        for (int a = 0; a < c->nch; ++a) {
+            c->ch_l[a] = b->l[a];
+            c->ch_lam[a] = b->lam[a];
+            c->ch_wave[a] = (int)(std::find(waves.begin(), waves.end(), b->l[a]) - waves.begin());
+        }
+        upload_tables(c);
+        c->has_basis = true;
+        build_pair_waves(c, pot);
+    });
+}
+
+wpcd_status wpcd_set_potential(wpcd_ctx *c, const wpcd_potential_desc *pot) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        c->has_pot = false;
+        build_pair_waves(c, pot);
+    });
+}
+
+wpcd_status wpcd_pair_spectrum(wpcd_ctx *c, int32_t l, double *eps_out, double *O_out,
+                               double *scale_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(c->has_basis && c->has_pot, WPCD_E_STATE, "no basis/potential");
+        int w = -1;
+        for (int k = 0; k < c->n_waves; ++k)
+            if (c->waves[k].l == l) w = k;
+        WPCD_REQUIRE(w >= 0, WPCD_E_INVALID, "pair wave l not used by the channels");
+        const int n = c->np;
+        if (eps_out)
+            WPCD_HIP(hipMemcpyAsync(eps_out, c->waves[w].eps.ptr, n * sizeof(double),
+                                    hipMemcpyDeviceToHost, c->stream));
+        if (O_out)
+            WPCD_HIP(hipMemcpyAsync(O_out, c->waves[w].O.ptr, (size_t)n * n * sizeof(double),
+                                    hipMemcpyDeviceToHost, c->stream));
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+        if (scale_out) *scale_out = c->pot_scale;
+    });
+}
+
+wpcd_status wpcd_build_p(wpcd_ctx *c, wpcd_precision prec, int64_t *nnz_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
+        c->has_p = false;
+        build_structure(c);
+        build_values(c, prec == WPCD_FP64);
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+        c->has_p = true;
+        c->p_fp64 = prec == WPCD_FP64;
+        if (nnz_out) *nnz_out = c->nnz;
+    });
+}
+
+wpcd_status wpcd_get_p(wpcd_ctx *c, int64_t *row_ptr, int32_t *col, double *val) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(c->has_p, WPCD_E_STATE, "no P0 built");
+        const int64_t nrow = (int64_t)c->np * c->nq;
+        const int64_t nv = c->nnz * c->nch * c->nch;
+        if (row_ptr)
+            WPCD_HIP(hipMemcpyAsync(row_ptr, c->d_rowptr.ptr, (nrow + 1) * sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, c->stream));
+        if (col)
+            WPCD_HIP(hipMemcpyAsync(col, c->d_col.ptr, c->nnz * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, c->stream));
+        if (val) {
+            if (c->p_fp64) {
+                WPCD_HIP(hipMemcpyAsync(val, c->d_val64.ptr, nv * sizeof(double),
+                                        hipMemcpyDeviceToHost, c->stream));
+            } else {
+                std::vector<float> tmp(nv);
+                WPCD_HIP(hipMemcpyAsync(tmp.data(), c->d_val32.ptr, nv * sizeof(float),
+                                        hipMemcpyDeviceToHost, c->stream));
+                WPCD_HIP(hipStreamSynchronize(c->stream));
+                for (int64_t k = 0; k < nv; ++k) val[k] = tmp[k];
+            }
+        }
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+wpcd_status wpcd_solve(wpcd_ctx *c, const double *E, int32_t n_E, wpcd_precision prec,
+                       const wpcd_solve_opts *opts, wpcd_energy_result *out, double *breakup_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
+                     "build_basis and build_p must come first");
+        WPCD_REQUIRE(E && out && n_E >= 0, WPCD_E_INVALID, "E/out NULL or n_E < 0");
+        WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
+        WPCD_REQUIRE(prec == WPCD_MIXED || c->p_fp64, WPCD_E_STATE,
+                     "FP64 solve needs an FP64 P0 build");
+        WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE,
+                     "mixed solve needs a mixed P0 build");
+        int m = 48, max_iter = 400;
+        double tol = 1e-12;
+        int want_breakup = 0;
+        if (opts) {
+            if (opts->krylov_dim > 0) m = opts->krylov_dim;
+            if (opts->max_iter > 0) max_iter = opts->max_iter;
+            if (opts->tol > 0) tol = opts->tol;
+            want_breakup = opts->want_breakup;
+        }
+        WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
+        // entrance channel: l = 0, lam = L
+        int a0 = -1;
+        for (int a = 0; a < c->nch; ++a)
+            if (c->ch_l[a] == 0 && c->ch_lam[a] == c->L) {
+                a0 = a;
+                break;
+            }
+        WPCD_REQUIRE(a0 >= 0, WPCD_E_INVALID, "no entrance channel (l = 0, lam = L)");
+        const double eb = c->waves[c->ch_wave[a0]].h_eps[0];
+        const double qmax = c->q[c->nq];
+        std::vector<wpcd_energy_result> res(n_E);
+        std::vector<int> active;
+        std::vector<int64_t> idx0v;
+        std::vector<double> rho0v;
+        for (int e = 0; e < n_E; ++e) {
+            wpcd_energy_result &r = res[e];
+            std::memset(&r, 0, sizeof(r));
+            r.E = E[e];
+            r.status = WPCD_OK;
+            if (!std::isfinite(E[e])) {
+                r.status = WPCD_E_INVALID;
+                continue;
+            }
+            if (E[e] <= eb) {
+                r.status = WPCD_E_BELOW_THRESHOLD;
+                continue;
+            }
+            const double q0 = std::sqrt(4.0 * (E[e] - eb) / 3.0);
+            r.q0 = q0;
+            if (q0 >= qmax) {
+                r.status = WPCD_E_INVALID;
+                continue;
+            }
+            const int j0 = (int)(std::upper_bound(c->q.begin(), c->q.end(), q0) - c->q.begin()) - 1;
+            r.j0 = j0;
+            active.push_back(e);
+            idx0v.push_back(((int64_t)a0 * c->nq + j0) * c->np);
+            rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
+        }
+        const int kBatch = 32;
+        for (size_t b0 = 0; b0 < active.size(); b0 += kBatch) {
+            const int nb = (int)std::min(active.size() - b0, (size_t)kBatch);
+            std::vector<double> Eb(nb), rho0(nb);
+            std::vector<int64_t> idx0(nb);
+            for (int t = 0; t < nb; ++t) {
+                Eb[t] = E[active[b0 + t]];
+                idx0[t] = idx0v[b0 + t];
+                rho0[t] = rho0v[b0 + t];
+            }
+            std::vector<int> iters, edge;
+            std::vector<double> resid;
+            gmres_batch(c, Eb, idx0, prec == WPCD_FP64, m, max_iter, tol, iters, resid, edge);
+            // amplitude list: elastic first, then open breakup pseudostates
+            std::vector<int64_t> rows;
+            std::vector<int32_t> ens;
+            std::vector<double> rho;
+            std::vector<int> first_br(nb), n_br(nb);
+            for (int t = 0; t < nb; ++t) {
+                rows.push_back(idx0[t]);
+                ens.push_back(t);
+                rho.push_back(rho0[t]);
+            }
+            for (int t = 0; t < nb; ++t) {
+                first_br[t] = (int)rows.size();
+                n_br[t] = 0;
+                for (int a = 0; a < c->nch; ++a) {
+                    const std::vector<double> &ev = c->waves[c->ch_wave[a]].h_eps;
+                    for (int k = 0; k < c->np; ++k) {
+                        if ((a == a0 && k == 0) || !(ev[k] < Eb[t])) continue;
+                        const double qk = std::sqrt(4.0 * (Eb[t] - ev[k]) / 3.0);
+                        if (qk >= qmax) continue;
+                        const int jk = (int)(std::upper_bound(c->q.begin(), c->q.end(), qk) -
+                                             c->q.begin()) - 1;
+                        rows.push_back(((int64_t)a * c->nq + jk) * c->np + k);
+                        ens.push_back(t);
+                        rho.push_back(2.0 / (3.0 * qk * (c->q[jk + 1] - c->q[jk])));
+                        ++n_br[t];
+                    }
+                }
+            }
+            std::vector<double> amp;
+            amplitudes_batch(c, nb, rows, ens, rho, rho0, amp);
+            for (int t = 0; t < nb; ++t) {
+                const int e = active[b0 + t];
+                wpcd_energy_result &r = res[e];
+                r.iters = iters[t];
+                r.residual = resid[t];
+                if (edge[t]) {
+                    r.status = WPCD_E_ON_EDGE;
+                    continue;
+                }
+                if (!(resid[t] <= tol * 10.0)) r.status = WPCD_E_NOT_CONVERGED;
+                r.U_re = amp[4 * t];
+                r.U_im = amp[4 * t + 1];
+                r.A_re = rho0[t] * r.U_re;
+                r.A_im = rho0[t] * r.U_im;
+                r.S_re = 1.0 + amp[4 * t + 2];
+                r.S_im = amp[4 * t + 3];
+                r.delta = 0.5 * std::atan2(r.S_im, r.S_re);
+                r.eta = std::hypot(r.S_re, r.S_im);
+                r.n_open = n_br[t];
+                if (breakup_out && want_breakup) {
+                    double *dst = breakup_out + (size_t)e * c->np * c->nch * 5;
+                    for (int u = 0; u < n_br[t]; ++u) {
+                        const int row = first_br[t] + u;
+                        const int64_t rr = rows[row];
+                        const int a = (int)(rr / ((int64_t)c->nq * c->np));
+                        const int jk = (int)((rr / c->np) % c->nq);
+                        const int k = (int)(rr % c->np);
+                        dst[5 * u + 0] = a;
+                        dst[5 * u + 1] = k;
+                        dst[5 * u + 2] = jk;
+                        dst[5 * u + 3] = amp[4 * row + 2];
+                        dst[5 * u + 4] = amp[4 * row + 3];
+                    }
+                }
+            }
+        }
+        for (int e = 0; e < n_E; ++e) out[e] = res[e];
+    });
+}
+
+wpcd_status wpcd_set_timing(wpcd_ctx *c, int32_t enable) {
+    return guarded(c, [&] {
+        c->timer.collect();
+        c->timer.enabled = enable;
+    });
+}
+
+wpcd_status wpcd_get_timing(wpcd_ctx *c, wpcd_kernel_time *out, int32_t n, int32_t *n_out) {
+    return guarded(c, [&] {
+        c->timer.collect();
+        const int cnt = (int)c->timer.names.size();
+        for (int k = 0; k < cnt && k < n; ++k) {
+            std::memset(&out[k], 0, sizeof(out[k]));
+            std::snprintf(out[k].name, sizeof(out[k].name), "%s", c->timer.names[k].c_str());
+            out[k].total_ms = c->timer.total_ms[k];
+            out[k].launches = c->timer.launches[k];
+        }
+        if (n_out) *n_out = cnt;
+    });
+}
+
+wpcd_status wpcd_reset_timing(wpcd_ctx *c) {
+    return guarded(c, [&] { c->timer.reset(); });
+}
+
+wpcd_status wpcd_synchronize(wpcd_ctx *c) {
+    return guarded(c, [&] { WPCD_HIP(hipStreamSynchronize(c->stream)); });
+}
+
+const char *wpcd_last_error(const wpcd_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+void wpcd_destroy(wpcd_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    c->timer.release();
+    c->d_p.release();
+    c->d_q.release();
+    c->d_P2.release();
+    c->d_Q34.release();
+    c->d_H.release();
+    c->d_rsd_p.release();
+    c->d_rsd_q.release();
+    c->d_qnode.release();
+    c->d_qwt.release();
+    c->d_ux.release();
+    c->d_wx.release();
+    c->d_uxf.release();
+    c->d_wxf.release();
+    for (auto &w : c->waves) {
+        w.v.release();
+        w.O.release();
+        w.eps.release();
+        w.Vt.release();
+    }
+    c->d_rowptr.release();
+    c->d_col.release();
+    c->d_rowidx.release();
+    c->d_cnt.release();
+    c->d_val64.release();
+    c->d_val32.release();
+    c->d_G.release();
+    c->d_X.release();
+    c->d_B.release();
+    c->d_W.release();
+    c->d_T1.release();
+    c->d_T2.release();
+    c->d_V.release();
+    c->d_Hess.release();
+    c->d_partial.release();
+    c->d_misc.release();
+    c->d_idx.release();
+    c->d_jac.release();
+    c->d_flag.release();
+    c->d_pot.release();
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations of libwpcd (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wpcd.h"
+
+namespace wpcd {
+
+constexpr int kMaxCh = 8;
+constexpr int kMaxWaves = 3;      // distinct even pair waves l = 0, 2, 4
+constexpr int kMaxGq = 16;
+constexpr int kMaxGx = 64;
+constexpr int kMaxLam = 4;
+
+struct Error {
+    wpcd_status code;
+    std::string msg;
+};
+
+#define WPCD_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw ::wpcd::Error{WPCD_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define WPCD_REQUIRE(cond, code, msg)                                                    \
+    do {                                                                                 \
+        if (!(cond)) throw ::wpcd::Error{(code), (msg)};                                 \
+    } while (0)
+
+// Device buffer that grows on demand and is freed with the context.
+template <class T>
+struct DBuf {
+    T *ptr = nullptr;
+    size_t cap = 0;
+    void reserve(size_t n) {
+        if (n <= cap) return;
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc(&ptr, sizeof(T) * (n ? n : 1));
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            throw Error{WPCD_E_NOMEM, "hipMalloc of " + std::to_string(sizeof(T) * n) + " bytes failed"};
+        }
+        cap = n;
+    }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+    }
+};
+
+struct Timer {
+    struct Pending {
+        int id;
+        hipEvent_t a, b;
+    };
+    int enabled = 0;   // bit mask of WPCD_TIME_* groups
+    std::vector<std::string> names;
+    std::vector<double> total_ms;
+    std::vector<int64_t> launches;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int id_of(const char *name);
+    hipEvent_t get();
+    void begin(hipStream_t s, const char *name, Pending &p);
+    void end(hipStream_t s, Pending &p);
+    void collect();
+    void reset();
+    void release();
+};
+
+// Scope guard that brackets one kernel launch with timing events.
+struct TimedLaunch {
+    Timer &t;
+    hipStream_t s;
+    Timer::Pending p{};
+    bool on;
+    TimedLaunch(Timer &t_, hipStream_t s_, const char *name, int group)
+        : t(t_), s(s_), on((t_.enabled & group) != 0) {
+        if (on) t.begin(s, name, p);
+    }
+    ~TimedLaunch() {
+        if (on) t.end(s, p);
+    }
+};
+
+struct PairWave {
+    int l = 0;
+    DBuf<double> v, O, eps, Vt;   // v, O (rows eigenvectors), eps* ascending, Vt = v O^T
+    std::vector<double> h_eps;    // host copy of eps*
+};
+
+}  // namespace wpcd
+
+struct wpcd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    wpcd::Timer timer;
+
+    // ---- basis
+    bool has_basis = false;
+    int np = 0, nq = 0, ngq = 0, ngx = 0, L = 0, nch = 0;
+    int ch_l[wpcd::kMaxCh] = {}, ch_lam[wpcd::kMaxCh] = {};
+    int ch_wave[wpcd::kMaxCh] = {};     // channel -> index into waves
+    std::vector<double> p, q;           // host edges
+    std::vector<double> gq, wq, gx, wx; // host Gauss tables on [-1, 1]
+    wpcd::DBuf<double> d_p, d_q, d_P2, d_Q34, d_H, d_rsd_p, d_rsd_q;
+    wpcd::DBuf<double> d_qnode, d_qwt, d_ux, d_wx;
+    wpcd::DBuf<float> d_uxf, d_wxf;
+
+    // ---- potential / pair waves
+    bool has_pot = false;
+    int pot_kind = 0;
+    std::vector<double> pot_s, pot_mu;
+    wpcd::DBuf<double> d_pot;           // strengths [16] | ranges [16]
+    double pot_scale = 1.0;
+    int n_waves = 0;
+    wpcd::PairWave waves[wpcd::kMaxWaves];
+
+    // ---- P0
+    bool has_p = false;
+    bool p_fp64 = false;
+    int64_t nnz = 0;
+    wpcd::DBuf<int64_t> d_rowptr;
+    wpcd::DBuf<int32_t> d_col, d_rowidx, d_cnt;
+    wpcd::DBuf<double> d_val64;
+    wpcd::DBuf<float> d_val32;
+
+    // ---- solve workspace
+    wpcd::DBuf<double> d_G, d_X, d_B, d_W, d_T1, d_T2, d_V, d_Hess, d_partial, d_misc;
+    wpcd::DBuf<int64_t> d_idx;
+    wpcd::DBuf<double> d_jac;   // Jacobi workspace (A and V per wave)
+    wpcd::DBuf<int32_t> d_flag;
+};
+
+namespace wpcd {
+
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1] by the Golub-Welsch
+// eigenvalue method, polished by Newton steps in long double (host).
+void gauss_legendre_gw(int n, std::vector<double> &x, std::vector<double> &w);
+
+// ---- kernel launchers (defined in the .hip files)
+void launch_potential(wpcd_ctx *c, int wave, double *v_out);
+void pair_diagonalise(wpcd_ctx *c, int wave, bool want_vectors);
+void launch_vt(wpcd_ctx *c, int wave);
+
+void build_structure(wpcd_ctx *c);   // a3: counts, scan, fill (sets c->nnz)
+void build_values(wpcd_ctx *c, bool fp64);
+
+}  // namespace wpcd

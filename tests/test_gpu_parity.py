@@ -1,0 +1,244 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: structure (row_ptr, col) bit-exact; FP64 values and amplitudes within
+1e-10 relative; FP32-compensated values within the bound derived in the
+design notes (a few FP32 ulps on every element); run-to-run determinism.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.wpcd as O
+from inputs import C1, C2, TOY_P, TOY_Q, YAM_BETA, YAM_LAMBDA, YUK_RANGES
+
+pytestmark = pytest.mark.gpu
+
+YAM = dict(kind="yamaguchi", strength=[YAM_LAMBDA], range=[YAM_BETA])
+ENERGIES = (-0.08, -0.05, -0.02, 0.05, 0.2, 0.5, 1.0, 2.0)
+FP32_REL = 2e-6     # per-element relative bound for the FP32-compensated path
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1508_07441_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle_values(p, q, ngq, ngx, ptr, col):
+    rows = np.repeat(np.arange(ptr.size - 1, dtype=np.int64), np.diff(ptr))
+    return O.p0_pairs(p, q, ngq, ngx, 0, [(0, 0)], rows, col)[:, 0, 0]
+
+
+def _check_structure_and_values(ctx, P, p, q, ngq, ngx, label):
+    say(f"[{label}] build_p FP64 n_p={p.size-1} n_q={q.size-1} ngq={ngq} ngx={ngx}")
+    nnz = ctx.build_p(P.WPCD_FP64)
+    rp, col, val = ctx.get_p()
+    ptr_o, col_o = O.preselect(p, q)
+    assert nnz == int(ptr_o[-1])
+    assert np.array_equal(rp, ptr_o)
+    assert np.array_equal(col, col_o)
+    vo = _oracle_values(p, q, ngq, ngx, ptr_o, col_o)
+    v = val[:, 0, 0]
+    scale = np.abs(vo).max() if vo.size else 1.0
+    err = np.abs(v - vo)
+    assert np.all(err <= 1e-10 * np.abs(vo) + 1e-14 * scale), float(np.max(err / (np.abs(vo) + scale * 1e-14)))
+    say(f"[{label}] FP64 max rel err {np.max(err / np.maximum(np.abs(vo), 1e-300 + 1e-14 * scale)):.2e}")
+    say(f"[{label}] build_p MIXED")
+    ctx.build_p(P.WPCD_MIXED)
+    rp2, col2, val2 = ctx.get_p()
+    assert np.array_equal(rp2, ptr_o) and np.array_equal(col2, col_o)
+    e32 = np.abs(val2[:, 0, 0] - vo)
+    rel32 = np.max(e32 / np.maximum(np.abs(vo), 1e-30 + 1e-7 * scale)) if vo.size else 0.0
+    say(f"[{label}] FP32 max rel err {rel32:.2e}")
+    assert np.all(e32 <= FP32_REL * np.abs(vo) + 1e-7 * scale * 1e-3)
+    return vo
+
+
+def test_c1_p0_parity(ctx, P):
+    n = C1["n_p"]
+    ctx.build_basis(n, n, 10.0, 10.0, C1["n_gq"], C1["n_gx"], potential=YAM)
+    p = O.cheb_edges(n, 10.0)
+    _check_structure_and_values(ctx, P, p, p.copy(), C1["n_gq"], C1["n_gx"], "C1")
+
+
+@pytest.mark.parametrize("shape", [(37, 23, 8.0, 6.0, 5, 7), (2, 2, 1.0, 1.0, 8, 16),
+                                   (64, 65, 10.0, 10.0, 3, 20), (17, 40, 10.0, 10.0, 9, 4)])
+def test_ragged_grids_p0_parity(ctx, P, shape):
+    n_p, n_q, pm, qm, ngq, ngx = shape
+    ctx.build_basis(n_p, n_q, pm, qm, ngq, ngx, potential=YAM)
+    p, q = O.cheb_edges(n_p, pm), O.cheb_edges(n_q, qm)
+    _check_structure_and_values(ctx, P, p, q, ngq, ngx, f"ragged{shape}")
+
+
+def test_explicit_edges_p0_parity(ctx, P):
+    p, q = np.array(TOY_P), np.array(TOY_Q)
+    ctx.build_basis(4, 4, 0, 0, 8, 16, potential=YAM, p_edges=p, q_edges=q)
+    _check_structure_and_values(ctx, P, p, q, 8, 16, "toy")
+
+
+def test_c2_structure_full_size(ctx, P):
+    """Full 150 x 150 structure against the oracle's committed digest."""
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "structure.json")) as f:
+        g = json.load(f)["150x150"]
+    say("[C2] structure")
+    ctx.build_basis(150, 150, 10.0, 10.0, 8, 20, potential=YAM)
+    nnz = ctx.build_p(P.WPCD_FP64)
+    rp, col, val = ctx.get_p()
+    h = hashlib.sha256()
+    h.update(rp.astype("<i8").tobytes())
+    h.update(col.astype("<i4").tobytes())
+    assert nnz == g["nnz_cells"]
+    assert h.hexdigest() == g["sha256_rowptr_i64_col_i32"]
+    # sampled rows of values, oracle element by element
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(150 * 150, 120, replace=False))
+    p = O.cheb_edges(150, 10.0)
+    for r in rows[:120]:
+        cols = col[rp[r]:rp[r + 1]]
+        vo = O.p0_pairs(p, p, 8, 20, 0, [(0, 0)], np.full(cols.size, r, dtype=np.int64), cols)[:, 0, 0]
+        v = val[rp[r]:rp[r + 1], 0, 0]
+        sc = max(np.abs(vo).max(), 1e-300) if vo.size else 1.0
+        assert np.all(np.abs(v - vo) <= 1e-10 * np.abs(vo) + 1e-14 * sc)
+
+
+def test_determinism(ctx, P):
+    ctx.build_basis(40, 40, 10.0, 10.0, 8, 16, potential=YAM)
+    for prec in (P.WPCD_FP64, P.WPCD_MIXED):
+        say(f"[det] prec={prec}")
+        ctx.build_p(prec)
+        a = ctx.get_p()
+        ctx.build_p(prec)
+        b = ctx.get_p()
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_pair_spectrum_parity(ctx, P):
+    n = 40
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    eps, Og, _ = ctx.pair_spectrum(0)
+    p = O.cheb_edges(n, 10.0)
+    e_o, O_o = O.pair_diag(p, O.yamaguchi_v(p, YAM_LAMBDA, YAM_BETA))
+    assert np.max(np.abs(eps - e_o)) <= 1e-12 * np.abs(e_o).max()
+    # rows are eigenvectors with the same sign rule; compare up to FP64 noise
+    assert np.max(np.abs(Og - O_o)) < 1e-9
+    np.testing.assert_allclose(Og @ Og.T, np.eye(n), atol=1e-12)
+
+
+def _oracle_system_yam(n, ngx):
+    p = O.cheb_edges(n, 10.0)
+    pot = O.Potential("yamaguchi", (YAM_LAMBDA,), (YAM_BETA,))
+    return O.build_system(p, p.copy(), 0, [(0, 0)], 8, ngx, pot)
+
+
+def test_c1_amplitudes_fp64(ctx, P):
+    n = C1["n_p"]
+    ctx.build_basis(n, n, 10.0, 10.0, 8, C1["n_gx"], potential=YAM)
+    ctx.build_p(P.WPCD_FP64)
+    say("[C1] solve FP64")
+    res = ctx.solve(ENERGIES, P.WPCD_FP64)
+    sysm = _oracle_system_yam(n, C1["n_gx"])
+    for r, E in zip(res, ENERGIES):
+        assert r.status == P.WPCD_OK, (E, P.STATUS_NAMES[r.status])
+        u, _, _ = O.solve_gmres(sysm, E)
+        a = O.amplitudes(sysm, E, u)
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
+        assert abs(complex(r.S_re, r.S_im) - a.S) <= 1e-10
+        if E < 0:
+            assert abs(math.hypot(r.S_re, r.S_im) - 1.0) < 1e-12
+        else:
+            assert r.eta <= 1.0 + 1e-12
+        assert r.residual < 1e-11
+
+
+def test_c1_breakup_parity(ctx, P):
+    n = C1["n_p"]
+    ctx.build_basis(n, n, 10.0, 10.0, 8, C1["n_gx"], potential=YAM)
+    ctx.build_p(P.WPCD_FP64)
+    E = 0.5
+    res, br = ctx.solve([E], P.WPCD_FP64, want_breakup=True)
+    sysm = _oracle_system_yam(n, C1["n_gx"])
+    u, _, _ = O.solve_gmres(sysm, E)
+    a = O.amplitudes(sysm, E, u)
+    assert res[0].n_open == len(a.breakup)
+    got = {(int(r[0]), int(r[1]), int(r[2])): complex(r[3], r[4]) for r in br[0]}
+    for (ch, k, jk, S) in a.breakup:
+        assert abs(got[(ch, k, jk)] - S) <= 1e-10 * max(abs(S), 1e-3)
+
+
+def test_status_codes(ctx, P):
+    n = 40
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    ctx.build_p(P.WPCD_FP64)
+    eps, _, _ = ctx.pair_spectrum(0, want_O=False)
+    q = O.cheb_edges(n, 10.0)
+    e_edge = eps[0] + 0.75 * q[10] ** 2
+    res = ctx.solve([eps[0] - 0.01, eps[0], float("nan"), 80.0, e_edge, 0.5], P.WPCD_FP64)
+    st = [r.status for r in res]
+    assert st[0] == P.WPCD_E_BELOW_THRESHOLD
+    assert st[1] == P.WPCD_E_BELOW_THRESHOLD
+    assert st[2] == P.WPCD_E_INVALID
+    assert st[3] == P.WPCD_E_INVALID
+    assert st[4] == P.WPCD_E_ON_EDGE
+    assert st[5] == P.WPCD_OK
+    # state errors
+    c2 = P.Context(0)
+    with pytest.raises(P.WpcdError) as ei:
+        c2.build_p(P.WPCD_FP64)
+    assert ei.value.status == P.WPCD_E_STATE
+    c2.close()
+
+
+def test_c2_full_fp64_and_mixed(ctx, P):
+    """Bench configuration: Yukawa sum fitted to a pair level at -0.1,
+    150 x 150 bins, 20-point cosine rule, 8 energies."""
+    n = C2["n_p"]
+    pot = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+    say("[C2] build_basis with fit")
+    ctx.build_basis(n, n, 10.0, 10.0, 8, C2["n_gx"], potential=pot)
+    eps, _, scale = ctx.pair_spectrum(0, want_O=False)
+    p = O.cheb_edges(n, 10.0)
+    s_o = O.fit_strength(p, YUK_RANGES, -0.1)
+    assert abs(scale - s_o) <= 1e-10 * s_o
+    assert abs(eps[0] + 0.1) < 1e-12
+    opot = O.Potential("yukawa", (-s_o, -s_o), YUK_RANGES)
+    sysm = O.build_system(p, p.copy(), 0, [(0, 0)], 8, C2["n_gx"], opot)
+    ctx.build_p(P.WPCD_FP64)
+    say("[C2] solve FP64")
+    res = ctx.solve(C2["energies"], P.WPCD_FP64)
+    ref = {}
+    for r, E in zip(res, C2["energies"]):
+        assert r.status == P.WPCD_OK, (E, P.STATUS_NAMES[r.status])
+        u, _, _ = O.solve_gmres(sysm, E)
+        a = O.amplitudes(sysm, E, u)
+        ref[E] = a.U00
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
+    say("[C2] build_p MIXED + solve")
+    ctx.build_p(P.WPCD_MIXED)
+    res2 = ctx.solve(C2["energies"], P.WPCD_MIXED)
+    worst = 0.0
+    for r, E in zip(res2, C2["energies"]):
+        assert r.status == P.WPCD_OK
+        U = complex(r.U_re, r.U_im)
+        worst = max(worst, abs(U - ref[E]) / abs(ref[E]))
+    say(f"[C2] mixed max rel amplitude error vs FP64 oracle: {worst:.3e}")
+    assert worst < 1e-4
