@@ -61,37 +61,39 @@
 
 /* ------------------------------------------------------------------ */
 /* Legendre P_n(z) and P_{n-1}(z) by the three-term recurrence. */
-static void orc_legendre(int n, double z, double *pn, double *pnm1)
+static void orc_legendre(int n, long double z, long double *pn, long double *pnm1)
 {
-    double a = 1.0, b = z; /* P_0, P_1 */
-    if (n == 0) { *pn = 1.0; *pnm1 = 0.0; return; }
+    long double a = 1.0L, b = z; /* P_0, P_1 */
+    if (n == 0) { *pn = 1.0L; *pnm1 = 0.0L; return; }
     for (int m = 2; m <= n; ++m) {
-        double c = ((2.0 * m - 1.0) * z * b - (m - 1.0) * a) / m;
+        long double c = ((2.0L * m - 1.0L) * z * b - (m - 1.0L) * a) / m;
         a = b; b = c;
     }
     *pn = b; *pnm1 = a;
 }
 
 /* Gauss-Legendre nodes and weights on [-1,1] by Newton iteration on P_n,
- * w = 2 / ((1 - z^2) P_n'(z)^2).  Nodes ascending.  Returns 0 on success. */
+ * w = 2 / ((1 - z^2) P_n'(z)^2), carried out in long double so that the
+ * values rounded to double are (almost always) the correctly rounded ones.
+ * Nodes ascending.  Returns 0 on success. */
 int orc_gauss_legendre(int n, double *x, double *w)
 {
     if (n < 1 || n > 256) return 1;
     for (int k = 0; k < (n + 1) / 2; ++k) {
-        double z = cos(M_PI * (k + 0.75) / (n + 0.5)); /* k-th largest root */
-        double pn, pm, dp;
+        long double z = cosl(3.14159265358979323846264338327950288L * (k + 0.75L) / (n + 0.5L));
+        long double pn, pm, dp;
         for (int it = 0; it < 100; ++it) {
             orc_legendre(n, z, &pn, &pm);
-            dp = n * (pm - z * pn) / (1.0 - z * z);
-            double dz = pn / dp;
+            dp = n * (pm - z * pn) / (1.0L - z * z);
+            long double dz = pn / dp;
             z -= dz;
-            if (fabs(dz) < 1e-16) break;
+            if (fabsl(dz) < 1e-19L) break;
         }
         orc_legendre(n, z, &pn, &pm);
-        dp = n * (pm - z * pn) / (1.0 - z * z);
-        double wk = 2.0 / ((1.0 - z * z) * dp * dp);
-        x[n - 1 - k] = z;  w[n - 1 - k] = wk;
-        x[k] = -z;         w[k] = wk;
+        dp = n * (pm - z * pn) / (1.0L - z * z);
+        long double wk = 2.0L / ((1.0L - z * z) * dp * dp);
+        x[n - 1 - k] = (double)z;  w[n - 1 - k] = (double)wk;
+        x[k] = -(double)z;         w[k] = (double)wk;
     }
     if (n % 2 == 1) x[n / 2] = 0.0;
     return 0;
@@ -293,16 +295,16 @@ void orc_p0_block(const double *p, const double *q, int i, int j, int i2, int j2
             double wb = qh2 * wq[b];
             /* pi1^2 = A + B x, pi2^2 = C + B x, x in [-1, 1] */
             double A = qb * qb + 0.25 * qa * qa;
-            double C = qa * qa + 0.25 * qb * qb;
             double B = qa * qb;
-            /* clipped range of t = pi1^2 and u = pi2^2 (u - t = C - A) */
-            double tlo = A - B, thi = A + B;
-            double ulo = C - B, uhi = C + B;
+            /* at x = -1 and x = +1: pi1 = |q' -+ q/2|, pi2 = |q -+ q'/2|; the
+             * squares are formed directly (no cancellation near q' = q/2) */
+            double tlo = (qb - 0.5 * qa) * (qb - 0.5 * qa), thi = (qb + 0.5 * qa) * (qb + 0.5 * qa);
+            double ulo = (qa - 0.5 * qb) * (qa - 0.5 * qb), uhi = (qa + 0.5 * qb) * (qa + 0.5 * qb);
             /* pi1 in [p_i, p_{i+1}] */
             double p1l = p[i] * p[i], p1h = p[i + 1] * p[i + 1];
             double p2l = p[i2] * p[i2], p2h = p[i2 + 1] * p[i2 + 1];
-            /* convert each constraint to both variables */
-            double D = C - A; /* = 3/4 (q^2 - q'^2) */
+            /* convert each constraint to both variables: u - t = D */
+            double D = 0.75 * (qa - qb) * (qa + qb); /* = 3/4 (q^2 - q'^2) */
             double lo_t = tlo, hi_t = thi;
             if (p1l > lo_t) lo_t = p1l;
             if (p2l - D > lo_t) lo_t = p2l - D;
