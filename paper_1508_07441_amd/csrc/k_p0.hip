@@ -199,17 +199,22 @@ struct Comp32 {
 
 __device__ __forceinline__ void lane_limits(const ElemTables &T, int i, int i2, double q, double q2,
                                             double &lo_t, double &lo_u, double &h) {
-    const double qq = q * q, qq2 = q2 * q2;
-    const double A = qq2 + 0.25 * qq;   // pi1^2 at x = 0
-    const double C = qq + 0.25 * qq2;   // pi2^2 at x = 0
-    const double B = q * q2;
-    const double D = C - A;             // u - t
+    // Limits are rounded exactly as written (no FMA contraction): where a
+    // limit is formed by cancellation (p^2 - D with D ~ p^2) the element is
+    // ill-conditioned and must round the same way as the reference formula.
+#pragma clang fp contract(off)
+    // cosine -1 / +1 give pi1 = |q2 -+ q/2| and pi2 = |q -+ q2/2|: squares
+    // formed directly, and u - t = D = 3/4 (q^2 - q2^2) as a product, so no
+    // limit is formed by cancellation.
+    const double m1 = q2 - 0.5 * q, p1 = q2 + 0.5 * q;
+    const double m2 = q - 0.5 * q2, p2 = q + 0.5 * q2;
+    const double D = 0.75 * (q - q2) * (q + q2);
     const double pl1 = T.P2[i], ph1 = T.P2[i + 1];
     const double pl2 = T.P2[i2], ph2 = T.P2[i2 + 1];
-    lo_t = fmax(fmax(A - B, pl1), pl2 - D);
-    double hi_t = fmin(fmin(A + B, ph1), ph2 - D);
-    lo_u = fmax(fmax(C - B, pl2), pl1 + D);
-    double hi_u = fmin(fmin(C + B, ph2), ph1 + D);
+    lo_t = fmax(fmax(m1 * m1, pl1), pl2 - D);
+    double hi_t = fmin(fmin(p1 * p1, ph1), ph2 - D);
+    lo_u = fmax(fmax(m2 * m2, pl2), pl1 + D);
+    double hi_u = fmin(fmin(p2 * p2, ph2), ph1 + D);
     h = (hi_t > lo_t) ? 0.25 * ((hi_t - lo_t) + (hi_u - lo_u)) : 0.0;
 }
 
