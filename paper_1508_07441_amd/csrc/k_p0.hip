@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "wpcd_internal.h"
 
@@ -294,6 +295,179 @@ __global__ __launch_bounds__(256) void k_p0_swave_f32(ElemTables T,
     }
 }
 
+// ------------------------------------------------- compacted element kernel
+// For the 8-point q rule (64 Gauss pairs per cell pair).  About half of the
+// (q, q') pairs of a cell pair have an empty cosine interval, so a wavefront
+// first evaluates the limits of kEC cell pairs x 64 Gauss pairs, compacts
+// the non-empty ones into an LDS queue (ballot + popcount, order preserved),
+// then every lane integrates one queued interval at a time with the cosine
+// rule fully unrolled, and finally each cell pair is reduced over its slots
+// (FP32: (hi, lo) pairs combined with TwoSum).  Deterministic: the queue
+// order and the reduction order depend only on the inputs.
+constexpr int kEC = 4;   // cell pairs per wavefront per round
+
+struct NodeTab {
+    double ux[kMaxGx], wx[kMaxGx];
+    float uxf[kMaxGx], wxf[kMaxGx];
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+template <int NGX>
+__device__ __forceinline__ void inner_f32(const NodeTab &N, int ngx, float lt, float lu, float h,
+                                          float &s0, float &s1) {
+    s0 = 0.f;
+    s1 = 0.f;
+    if (NGX > 0) {
+#pragma unroll
+        for (int k = 0; k < NGX; k += 2) {
+            const float sa = h * N.uxf[k];
+            s0 = fmaf(N.wxf[k], __builtin_amdgcn_rsqf((lt + sa) * (lu + sa)), s0);
+            if (k + 1 < NGX) {
+                const float sb = h * N.uxf[k + 1];
+                s1 = fmaf(N.wxf[k + 1], __builtin_amdgcn_rsqf((lt + sb) * (lu + sb)), s1);
+            }
+        }
+    } else {
+        for (int k = 0; k < ngx; ++k) {
+            const float sa = h * N.uxf[k];
+            const float v = N.wxf[k] * __builtin_amdgcn_rsqf((lt + sa) * (lu + sa));
+            if (k & 1) s1 += v;
+            else s0 += v;
+        }
+    }
+}
+
+template <int NGX>
+__device__ __forceinline__ double inner_f64(const NodeTab &N, int ngx, double lt, double lu,
+                                            double h) {
+    double s = 0.0;
+    if (NGX > 0) {
+#pragma unroll
+        for (int k = 0; k < NGX; ++k) {
+            const double sk = h * N.ux[k];
+            s = fma(N.wx[k], rsqrt((lt + sk) * (lu + sk)), s);
+        }
+    } else {
+        for (int k = 0; k < ngx; ++k) {
+            const double sk = h * N.ux[k];
+            s = fma(N.wx[k], rsqrt((lt + sk) * (lu + sk)), s);
+        }
+    }
+    return s;
+}
+
+template <bool F32, int NGX>
+__global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
+                                                    const int32_t *__restrict__ rowidx,
+                                                    const int32_t *__restrict__ col, int64_t nnz,
+                                                    double *__restrict__ val64,
+                                                    float *__restrict__ val32) {
+    using R = typename std::conditional<F32, float, double>::type;
+    constexpr int QN = kEC * 64;
+    __shared__ R q_lt[4][QN], q_lu[4][QN], q_h[4][QN], q_w[4][QN];
+    __shared__ unsigned char q_k[4][QN], q_r[4][QN];
+    __shared__ R s_hi[4][kEC][64];
+    __shared__ float s_lo[4][kEC][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int a = lane >> 3, b = lane & 7;
+    const int64_t nch = (nnz + kEC - 1) / kEC;
+    for (int64_t it = 0;; ++it) {
+        const int64_t cbase = (it * gridDim.x + blockIdx.x) * 4;
+        if (cbase >= nch) break;   // uniform across the workgroup
+        const int64_t chunk = cbase + w;
+        // phase 1: limits of kEC cell pairs, compaction into the queue
+        int total = 0;
+#pragma unroll
+        for (int k = 0; k < kEC; ++k) {
+            const int64_t e = chunk * kEC + k;
+            bool act = false;
+            double lo_t = 0.0, lo_u = 0.0, h = 0.0, wab = 0.0;
+            if (chunk < nch && e < nnz) {
+                const int r = rowidx[e], c = col[e];
+                const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+                const double q = T.qnode[j * 8 + a], q2 = T.qnode[j2 * 8 + b];
+                lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
+                act = h > 0.0;
+                wab = T.qwt[j * 8 + a] * T.qwt[j2 * 8 + b] * h;
+            }
+            const unsigned long long m = __ballot(act);
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            if (act) {
+                const int slot = total + rank;
+                q_lt[w][slot] = (R)lo_t;
+                q_lu[w][slot] = (R)lo_u;
+                q_h[w][slot] = (R)h;
+                q_w[w][slot] = (R)wab;
+                q_k[w][slot] = (unsigned char)k;
+                q_r[w][slot] = (unsigned char)rank;
+            }
+            total += __popcll(m);
+            s_hi[w][k][lane] = (R)0;
+            s_lo[w][k][lane] = 0.f;
+        }
+        __syncthreads();
+        // phase 2: one queued interval per lane
+        for (int base = 0; base < total; base += 64) {
+            const int t = base + lane;
+            if (t < total) {
+                const int k = q_k[w][t], rk = q_r[w][t];
+                if (F32) {
+                    float s0, s1, hi, lo;
+                    inner_f32<NGX>(N, T.ngx, (float)q_lt[w][t], (float)q_lu[w][t], (float)q_h[w][t],
+                                   s0, s1);
+                    two_sum(s0, s1, hi, lo);
+                    const float wf = (float)q_w[w][t];
+                    const float p = hi * wf;
+                    const float ep = fmaf(hi, wf, -p);
+                    s_hi[w][k][rk] = (R)p;
+                    s_lo[w][k][rk] = fmaf(lo, wf, ep);
+                } else {
+                    s_hi[w][k][rk] = (R)(q_w[w][t] *
+                                         inner_f64<NGX>(N, T.ngx, (double)q_lt[w][t],
+                                                        (double)q_lu[w][t], (double)q_h[w][t]));
+                }
+            }
+        }
+        __syncthreads();
+        // phase 3: reduce each cell pair over its 64 slots
+#pragma unroll
+        for (int k = 0; k < kEC; ++k) {
+            const int64_t e = chunk * kEC + k;
+            if (F32) {
+                float s = (float)s_hi[w][k][lane], cc = s_lo[w][k][lane];
+                for (int off = 32; off > 0; off >>= 1) {
+                    const float so = __shfl_xor(s, off, 64), co = __shfl_xor(cc, off, 64);
+                    float t2, err;
+                    two_sum(s, so, t2, err);
+                    s = t2;
+                    cc = cc + co + err;
+                }
+                if (lane == 0 && chunk < nch && e < nnz) {
+                    const int r = rowidx[e], c = col[e];
+                    const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+                    val32[e] = (float)(((double)s + (double)cc) * (T.rsd_p[i] * T.rsd_p[i2]) *
+                                       (T.rsd_q[j] * T.rsd_q[j2]));
+                }
+            } else {
+                double s = (double)s_hi[w][k][lane];
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+                if (lane == 0 && chunk < nch && e < nnz) {
+                    const int r = rowidx[e], c = col[e];
+                    const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+                    val64[e] = s * (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ host
 static GridView grid_view(wpcd_ctx *c) {
     return GridView{c->d_p.ptr, c->d_q.ptr, c->d_P2.ptr, c->d_Q34.ptr, c->d_H.ptr, c->np, c->nq};
@@ -332,24 +506,60 @@ void build_structure(wpcd_ctx *c) {
     }
 }
 
+template <bool F32>
+static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N, int blocks) {
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, c->stream, T, N, c->d_rowidx.ptr,
+                           c->d_col.ptr, c->nnz, c->d_val64.ptr, c->d_val32.ptr);
+    };
+    switch (c->ngx) {
+        case 16: go(k_p0_swave_c<F32, 16>); break;
+        case 20: go(k_p0_swave_c<F32, 20>); break;
+        case 24: go(k_p0_swave_c<F32, 24>); break;
+        case 32: go(k_p0_swave_c<F32, 32>); break;
+        default: go(k_p0_swave_c<F32, 0>); break;
+    }
+}
+
 void build_values(wpcd_ctx *c, bool fp64) {
     ElemTables T{c->d_P2.ptr, c->d_rsd_p.ptr, c->d_rsd_q.ptr, c->d_qnode.ptr, c->d_qwt.ptr,
                  c->d_ux.ptr,  c->d_wx.ptr,    c->d_uxf.ptr,   c->d_wxf.ptr,   c->np,
                  c->ngq,       c->ngx};
     WPCD_REQUIRE(c->nch == 1, WPCD_E_INVALID, "multichannel P0 not built yet");
     const int64_t nnz = c->nnz;
+    if (fp64) c->d_val64.reserve(nnz);
+    else c->d_val32.reserve(nnz);
     if (nnz == 0) return;
-    // persistent grid: enough waves to fill 256 CUs several times over
+    if (c->ngq == 8) {
+        NodeTab N{};
+        for (int k = 0; k < c->ngx; ++k) {
+            N.ux[k] = 1.0 + c->gx[k];
+            N.wx[k] = c->wx[k];
+            N.uxf[k] = (float)N.ux[k];
+            N.wxf[k] = (float)N.wx[k];
+        }
+        const int64_t nchunk = (nnz + kEC - 1) / kEC;
+        const int64_t want = (nchunk + 3) / 4;
+        const int blocks = (int)(want < 8192 ? want : 8192);
+        if (fp64) {
+            TimedLaunch tl(c->timer, c->stream, "p0_elem_f64", WPCD_TIME_P0);
+            launch_compacted<false>(c, T, N, blocks);
+        } else {
+            TimedLaunch tl(c->timer, c->stream, "p0_elem_f32", WPCD_TIME_P0);
+            launch_compacted<true>(c, T, N, blocks);
+        }
+        WPCD_HIP(hipGetLastError());
+        return;
+    }
+    // general Gauss order: one wavefront per cell pair, lanes = (a, b)
     int64_t want = (nnz + 3) / 4;
     int blocks = (int)(want < 65536 ? want : 65536);
     if (fp64) {
-        c->d_val64.reserve(nnz);
         TimedLaunch tl(c->timer, c->stream, "p0_elem_f64", WPCD_TIME_P0);
         hipLaunchKernelGGL(k_p0_swave_f64, dim3(blocks), dim3(256), 0, c->stream, T,
                            c->d_rowidx.ptr, c->d_col.ptr, nnz, c->d_val64.ptr);
         WPCD_HIP(hipGetLastError());
     } else {
-        c->d_val32.reserve(nnz);
         TimedLaunch tl(c->timer, c->stream, "p0_elem_f32", WPCD_TIME_P0);
         hipLaunchKernelGGL(k_p0_swave_f32, dim3(blocks), dim3(256), 0, c->stream, T,
                            c->d_rowidx.ptr, c->d_col.ptr, nnz, c->d_val32.ptr);

@@ -94,139 +94,182 @@ __global__ void k_potential(const double *__restrict__ p, int n, int l, int kind
     v[idx] = scale * acc / sqrt((bi - ai) * (bk - ak));
 }
 
-// Parallel-ordered cyclic Jacobi on one workgroup.  A (n x n, row-major,
-// symmetric) is overwritten: on exit its diagonal holds the eigenvalues and
-// V (n x n) the eigenvectors as columns (A0 = V diag V^T).  Each round of the
-// round-robin tournament rotates n/2 disjoint index pairs at once: the
-// columns of A and V are rotated first, then the rows of A.
-constexpr int kJacThreads = 1024;
+// ---------------------------------------------------------- eigensolver
+// h1 is made positive definite by a shift sigma (Gershgorin), then
+// diagonalised by one-sided (Hestenes) Jacobi: the columns of W = h1 + sigma
+// are rotated pairwise until mutually orthogonal.  Since W = Q Lambda' Q^T,
+// the final columns are Q Lambda': eigenvalue = column norm - sigma,
+// eigenvector = normalised column.  Column pairs are visited block-cyclically:
+// each workgroup holds two blocks of b columns in LDS and sweeps every pair
+// among them; one launch per round of a round-robin tournament over blocks.
 
-__global__ __launch_bounds__(kJacThreads) void k_jacobi(double *__restrict__ A,
-                                                         double *__restrict__ V, int n,
-                                                         int want_vectors, int max_sweeps,
-                                                         int *__restrict__ sweeps_out) {
-    const int nn = n + (n & 1);   // even number of tournament players
-    const int npairs = nn / 2;
-    __shared__ int s_p[512], s_q[512];
-    __shared__ double s_c[512], s_s[512];
-    __shared__ int s_rot;
-    const int tid = threadIdx.x;
-    if (want_vectors)
-        for (int idx = tid; idx < n * n; idx += blockDim.x) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
-    __syncthreads();
-    int sweep = 0;
-    for (; sweep < max_sweeps; ++sweep) {
-        if (tid == 0) s_rot = 0;
-        __syncthreads();
-        for (int r = 0; r < nn - 1; ++r) {
-            for (int k = tid; k < npairs; k += blockDim.x) {
-                int a, b;
-                if (k == 0) {
-                    a = r;
-                    b = nn - 1;
-                } else {
-                    a = (r + k) % (nn - 1);
-                    b = (r - k + (nn - 1)) % (nn - 1);
-                }
-                int pp = a < b ? a : b, qq = a < b ? b : a;
-                double c = 1.0, sn = 0.0;
-                if (qq < n) {
-                    double app = A[pp * n + pp], aqq = A[qq * n + qq], apq = A[pp * n + qq];
-                    if (fabs(apq) > 1e-280 && fabs(apq) > 2.2e-16 * sqrt(fabs(app * aqq))) {
-                        double th = (aqq - app) / (2.0 * apq);
-                        double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        sn = t * c;
-                        s_rot = 1;
-                    }
-                }
-                s_p[k] = pp;
-                s_q[k] = qq;
-                s_c[k] = c;
-                s_s[k] = sn;
-            }
-            __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int idx = tid; idx < npairs * n; idx += blockDim.x) {
-                int k = idx / n, row = idx % n;
-                double c = s_c[k], sn = s_s[k];
-                if (sn == 0.0) continue;
-                int pp = s_p[k], qq = s_q[k];
-                double x = A[row * n + pp], y = A[row * n + qq];
-                A[row * n + pp] = c * x - sn * y;
-                A[row * n + qq] = sn * x + c * y;
-                if (want_vectors) {
-                    x = V[row * n + pp];
-                    y = V[row * n + qq];
-                    V[row * n + pp] = c * x - sn * y;
-                    V[row * n + qq] = sn * x + c * y;
-                }
-            }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int idx = tid; idx < npairs * n; idx += blockDim.x) {
-                int k = idx / n, col = idx % n;
-                double c = s_c[k], sn = s_s[k];
-                if (sn == 0.0) continue;
-                int pp = s_p[k], qq = s_q[k];
-                double x = A[pp * n + col], y = A[qq * n + col];
-                A[pp * n + col] = c * x - sn * y;
-                A[qq * n + col] = sn * x + c * y;
-            }
-            __syncthreads();
-            for (int k = tid; k < npairs; k += blockDim.x) {
-                if (s_s[k] != 0.0) {
-                    int pp = s_p[k], qq = s_q[k];
-                    A[pp * n + qq] = 0.0;
-                    A[qq * n + pp] = 0.0;
-                }
-            }
-            __syncthreads();
-        }
-        int done = (s_rot == 0);
-        __syncthreads();
-        if (done) break;
+// Tournament pairing of P players (P even) in round r: pair k.
+__device__ __forceinline__ void tourney(int P, int r, int k, int &a, int &b) {
+    if (k == 0) {
+        a = r;
+        b = P - 1;
+    } else {
+        a = (r + k) % (P - 1);
+        b = (r - k + (P - 1)) % (P - 1);
     }
-    if (tid == 0) *sweeps_out = sweep;
 }
 
-// Ascending order + sign rule: eps[rank] = A[k][k]; O[rank][:] = V[:, k]
+// W = h1 (symmetric, so row- and column-major coincide); rowlo[i] =
+// Gershgorin lower bound of row i.
+__global__ void k_h1_gersh(const double *__restrict__ p, const double *__restrict__ v, int n,
+                           double *__restrict__ W, double *__restrict__ rowlo) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = p[i], b = p[i + 1];
+    double off = 0.0, d = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double x = v[(int64_t)i * n + k];
+        if (k == i) {
+            x += (a * a + a * b + b * b) / 3.0;
+            d = x;
+        } else {
+            off += fabs(x);
+        }
+        W[(int64_t)i * n + k] = x;
+    }
+    rowlo[i] = d - off;
+}
+
+// sigma = max(0, 1 - min_i rowlo[i]); W += sigma I.  One workgroup.
+__global__ __launch_bounds__(256) void k_shift(double *__restrict__ W, int n,
+                                               const double *__restrict__ rowlo,
+                                               double *__restrict__ sigma_out) {
+    __shared__ double red[256];
+    double m = 1e300;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmin(m, rowlo[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    const double sigma = red[0] < 1.0 ? 1.0 - red[0] : 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) W[(int64_t)i * n + i] += sigma;
+    if (threadIdx.x == 0) *sigma_out = sigma;
+}
+
+__device__ __forceinline__ double wsum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One tournament round over blocks: workgroup s takes block pair (I, J),
+// loads the 2b columns into LDS, rotates every pair among them once (2b - 1
+// inner rounds of b disjoint pairs, one wavefront per pair, the pair's
+// columns held in registers: NPL elements per lane), writes them back.
+// rotated[sweep] is set if any pair was rotated (|w_x.w_y| > tol |w_x||w_y|).
+template <int NPL>
+__global__ __launch_bounds__(1024) void k_jacobi_blocks(double *__restrict__ W, int n, int b,
+                                                        int NB, int r, double tol,
+                                                        int *__restrict__ rotated, int sweep) {
+    extern __shared__ double sW[];   // [2b][n]
+    int I, J;
+    tourney(NB, r, blockIdx.x, I, J);
+    const int P = 2 * b;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int idx = tid; idx < P * n; idx += blockDim.x) {
+        const int lc = idx / n, e = idx % n;
+        const int gc = lc < b ? I * b + lc : J * b + (lc - b);
+        sW[idx] = gc < n ? W[(int64_t)gc * n + e] : 0.0;
+    }
+    __syncthreads();
+    int any = 0;
+    for (int rr = 0; rr < P - 1; ++rr) {
+        if (wave < b) {
+            int x, y;
+            tourney(P, rr, wave, x, y);
+            const int gx = x < b ? I * b + x : J * b + (x - b);
+            const int gy = y < b ? I * b + y : J * b + (y - b);
+            if (gx < n && gy < n) {
+                double wx[NPL], wy[NPL];
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int u = 0; u < NPL; ++u) {
+                    const int e = lane + 64 * u;
+                    wx[u] = e < n ? sW[x * n + e] : 0.0;
+                    wy[u] = e < n ? sW[y * n + e] : 0.0;
+                    al += wx[u] * wx[u];
+                    be += wy[u] * wy[u];
+                    ga += wx[u] * wy[u];
+                }
+                al = wsum(al);
+                be = wsum(be);
+                ga = wsum(ga);
+                if (fabs(ga) > tol * sqrt(al * be)) {
+                    const double ze = (be - al) / (2.0 * ga);
+                    const double t = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                    const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+#pragma unroll
+                    for (int u = 0; u < NPL; ++u) {
+                        const int e = lane + 64 * u;
+                        if (e < n) {
+                            sW[x * n + e] = c * wx[u] - sn * wy[u];
+                            sW[y * n + e] = sn * wx[u] + c * wy[u];
+                        }
+                    }
+                    any = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < P * n; idx += blockDim.x) {
+        const int lc = idx / n, e = idx % n;
+        const int gc = lc < b ? I * b + lc : J * b + (lc - b);
+        if (gc < n) W[(int64_t)gc * n + e] = sW[idx];
+    }
+    if (any) rotated[sweep] = 1;
+}
+
+// Column norms: lam'[k] = |w_k|, eps[k] = lam'[k] - sigma.
+__global__ void k_colnorm(const double *__restrict__ W, int n, const double *__restrict__ sigma,
+                          double *__restrict__ nrm, double *__restrict__ ev) {
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (k >= n) return;
+    double s = 0.0;
+    for (int e = lane; e < n; e += 64) {
+        const double x = W[(int64_t)k * n + e];
+        s += x * x;
+    }
+    s = wsum(s);
+    if (lane == 0) {
+        nrm[k] = sqrt(s);
+        ev[k] = sqrt(s) - sigma[0];
+    }
+}
+
+// Ascending order + sign rule: eps[rank] = ev[k]; O[rank][:] = w_k / |w_k|
 // with the largest-magnitude component made positive (lowest index on ties).
-__global__ void k_eig_sort(const double *__restrict__ A, const double *__restrict__ V, int n,
-                           int want_vectors, double *__restrict__ eps, double *__restrict__ O) {
+__global__ void k_eig_sort(const double *__restrict__ W, const double *__restrict__ nrm,
+                           const double *__restrict__ ev, int n, int want_vectors,
+                           double *__restrict__ eps, double *__restrict__ O) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    double ek = A[k * n + k];
+    const double ek = ev[k];
     int rank = 0;
     for (int m = 0; m < n; ++m) {
-        double em = A[m * n + m];
+        const double em = ev[m];
         rank += (em < ek) || (em == ek && m < k);
     }
     eps[rank] = ek;
     if (!want_vectors) return;
     double big = -1.0, sgn = 1.0;
+    const double *w = W + (int64_t)k * n;
     for (int r = 0; r < n; ++r) {
-        double x = V[r * n + k];
+        const double x = w[r];
         if (fabs(x) > big) {
             big = fabs(x);
             sgn = x < 0 ? -1.0 : 1.0;
         }
     }
-    for (int r = 0; r < n; ++r) O[(int64_t)rank * n + r] = sgn * V[r * n + k];
-}
-
-// A = diag(eps0) + v
-__global__ void k_h1(const double *__restrict__ p, const double *__restrict__ v, int n,
-                     double *__restrict__ A) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n) return;
-    int i = idx / n, k = idx % n;
-    double x = v[idx];
-    if (i == k) {
-        double a = p[i], b = p[i + 1];
-        x += (a * a + a * b + b * b) / 3.0;
-    }
-    A[idx] = x;
+    const double f = sgn / nrm[k];
+    for (int r = 0; r < n; ++r) O[(int64_t)rank * n + r] = f * w[r];
 }
 
 // Vt = v O^T  (Vt[i][k] = sum_m v[i][m] O[k][m])
@@ -276,37 +319,62 @@ void launch_potential(wpcd_ctx *c, int wave, double *v_out) {
 }
 
 void pair_diagonalise(wpcd_ctx *c, int wave, bool want_vectors) {
-    int n = c->np;
+    const int n = c->np;
     PairWave &pw = c->waves[wave];
-    c->d_jac.reserve((size_t)2 * n * n);
-    c->d_flag.reserve(4);
-    double *A = c->d_jac.ptr, *V = c->d_jac.ptr + (size_t)n * n;
-    int threads = 256, blocks = (n * n + threads - 1) / threads;
+    constexpr int kMaxSweeps = 40;
+    const int b = (2 * 16 * n * (int)sizeof(double) <= 150 * 1024) ? 16 : 8;
+    const int nbr = (n + b - 1) / b;
+    const int NB = nbr + (nbr & 1);
+    const size_t lds = (size_t)2 * b * n * sizeof(double);
+    // workspace: W [n*n] | rowlo [n] | nrm [n] | ev [n] | sigma [1]
+    c->d_jac.reserve((size_t)n * n + 3 * (size_t)n + 8);
+    c->d_flag.reserve(kMaxSweeps + 4);
+    double *W = c->d_jac.ptr, *rowlo = W + (size_t)n * n, *nrm = rowlo + n, *ev = nrm + n,
+           *sigma = ev + n;
+    int *rot = c->d_flag.ptr;
+    hipStream_t s = c->stream;
     {
-        TimedLaunch tl(c->timer, c->stream, "h1", WPCD_TIME_PAIR);
-        hipLaunchKernelGGL(k_h1, dim3(blocks), dim3(threads), 0, c->stream, c->d_p.ptr, pw.v.ptr,
-                           n, A);
+        TimedLaunch tl(c->timer, s, "h1", WPCD_TIME_PAIR);
+        hipLaunchKernelGGL(k_h1_gersh, dim3((n + 255) / 256), dim3(256), 0, s, c->d_p.ptr, pw.v.ptr,
+                           n, W, rowlo);
+        hipLaunchKernelGGL(k_shift, dim3(1), dim3(256), 0, s, W, n, rowlo, sigma);
         WPCD_HIP(hipGetLastError());
     }
-    {
-        TimedLaunch tl(c->timer, c->stream, "jacobi", WPCD_TIME_PAIR);
-        hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), 0, c->stream, A, V, n,
-                           want_vectors ? 1 : 0, 40, c->d_flag.ptr);
-        WPCD_HIP(hipGetLastError());
+    WPCD_HIP(hipMemsetAsync(rot, 0, kMaxSweeps * sizeof(int), s));
+    const int npl = (n + 63) / 64;
+    auto kern = npl <= 2 ? k_jacobi_blocks<2>
+              : npl <= 4 ? k_jacobi_blocks<4>
+              : npl <= 8 ? k_jacobi_blocks<8>
+                         : k_jacobi_blocks<16>;
+    WPCD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 160 * 1024));
+    const double tol = 2.2e-16 * (double)n;
+    int sweep = 0;
+    bool converged = false;
+    for (; sweep < kMaxSweeps && !converged; ++sweep) {
+        {
+            TimedLaunch tl(c->timer, s, "jacobi_sweep", WPCD_TIME_PAIR);
+            for (int r = 0; r < NB - 1; ++r)
+                hipLaunchKernelGGL(kern, dim3(NB / 2), dim3(64 * b), lds, s, W, n, b, NB, r, tol,
+                                   rot, sweep);
+            WPCD_HIP(hipGetLastError());
+        }
+        int flag = 1;
+        WPCD_HIP(hipMemcpyAsync(&flag, rot + sweep, sizeof(int), hipMemcpyDeviceToHost, s));
+        WPCD_HIP(hipStreamSynchronize(s));
+        converged = (flag == 0);
     }
+    WPCD_REQUIRE(converged, WPCD_E_NOT_CONVERGED, "pair diagonalisation did not converge");
     {
-        TimedLaunch tl(c->timer, c->stream, "eig_sort", WPCD_TIME_PAIR);
-        hipLaunchKernelGGL(k_eig_sort, dim3((n + 255) / 256), dim3(256), 0, c->stream, A, V, n,
+        TimedLaunch tl(c->timer, s, "eig_finish", WPCD_TIME_PAIR);
+        hipLaunchKernelGGL(k_colnorm, dim3((n + 3) / 4), dim3(256), 0, s, W, n, sigma, nrm, ev);
+        hipLaunchKernelGGL(k_eig_sort, dim3((n + 255) / 256), dim3(256), 0, s, W, nrm, ev, n,
                            want_vectors ? 1 : 0, pw.eps.ptr, pw.O.ptr);
         WPCD_HIP(hipGetLastError());
     }
     pw.h_eps.resize(n);
-    WPCD_HIP(hipMemcpyAsync(pw.h_eps.data(), pw.eps.ptr, n * sizeof(double),
-                            hipMemcpyDeviceToHost, c->stream));
-    int sweeps = 0;
-    WPCD_HIP(hipMemcpyAsync(&sweeps, c->d_flag.ptr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    WPCD_HIP(hipStreamSynchronize(c->stream));
-    WPCD_REQUIRE(sweeps < 40, WPCD_E_NOT_CONVERGED, "pair diagonalisation did not converge");
+    WPCD_HIP(hipMemcpyAsync(pw.h_eps.data(), pw.eps.ptr, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    WPCD_HIP(hipStreamSynchronize(s));
 }
 
 void launch_vt(wpcd_ctx *c, int wave) {

@@ -184,19 +184,26 @@ __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ Vb, int
     }
 }
 
-// h[p] = sum_chunks partial[chunk][p]; optionally accumulate into the
-// Hessenberg column H[e][i][k] (layout [nE][m+1][m] complex).
-__global__ void k_dots_reduce(const double *__restrict__ partial, int nchunk, int nvec, int nE,
-                              double *__restrict__ h, double *__restrict__ H, int m, int kcol,
-                              int accumulate) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// h[p] = sum_chunks partial[chunk][p] (one wavefront per pair p); also
+// written/accumulated into the Hessenberg column H[e][i][k] (layout
+// [nE][m+1][m] complex) when H is given.
+__global__ __launch_bounds__(256) void k_dots_reduce(const double *__restrict__ partial, int nchunk,
+                                                     int nvec, int nE, double *__restrict__ h,
+                                                     double *__restrict__ H, int m, int kcol,
+                                                     int accumulate) {
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int npair = nvec * nE;
     if (p >= npair) return;
     double sr = 0.0, si = 0.0;
-    for (int c = 0; c < nchunk; ++c) {
+    for (int c = lane; c < nchunk; c += 64) {
         sr += partial[((int64_t)c * npair + p) * 2];
         si += partial[((int64_t)c * npair + p) * 2 + 1];
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off, 64);
+        si += __shfl_xor(si, off, 64);
+    }
+    if (lane != 0) return;
     h[2 * p] = sr;
     h[2 * p + 1] = si;
     if (H) {
@@ -478,7 +485,7 @@ void dots(Batch &b, const double *Vb, int nvec, const double *w, double *h, doub
     }
     {
         TimedLaunch tl(c->timer, c->stream, "gmres_reduce", WPCD_TIME_SOLVE);
-        hipLaunchKernelGGL(k_dots_reduce, dim3(cdiv(nvec * b.nE, 256)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL(k_dots_reduce, dim3(cdiv(nvec * b.nE, 4)), dim3(256), 0, c->stream,
                            b.partial, b.nchunk, nvec, b.nE, h, H, b.m, kcol, accumulate);
         WPCD_HIP(hipGetLastError());
     }
