@@ -342,6 +342,18 @@ __device__ __forceinline__ void inner_f32(const NodeTab &N, int ngx, float lt, f
     }
 }
 
+// 1/sqrt(x) in FP64: FP32 seed (v_rsq_f32, ~1 ulp of FP32) refined by two
+// Newton-Raphson steps y <- y (3 - x y^2) / 2, each squaring the relative
+// error (2^-23 -> 2^-45 -> below FP64 rounding).  Arguments here are
+// products of squared momenta, well inside the FP32 normal range.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
 template <int NGX>
 __device__ __forceinline__ double inner_f64(const NodeTab &N, int ngx, double lt, double lu,
                                             double h) {
@@ -350,12 +362,12 @@ __device__ __forceinline__ double inner_f64(const NodeTab &N, int ngx, double lt
 #pragma unroll
         for (int k = 0; k < NGX; ++k) {
             const double sk = h * N.ux[k];
-            s = fma(N.wx[k], rsqrt((lt + sk) * (lu + sk)), s);
+            s = fma(N.wx[k], rsqrt_nr((lt + sk) * (lu + sk)), s);
         }
     } else {
         for (int k = 0; k < ngx; ++k) {
             const double sk = h * N.ux[k];
-            s = fma(N.wx[k], rsqrt((lt + sk) * (lu + sk)), s);
+            s = fma(N.wx[k], rsqrt_nr((lt + sk) * (lu + sk)), s);
         }
     }
     return s;

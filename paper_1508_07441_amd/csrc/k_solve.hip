@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "wpcd_internal.h"
 
@@ -65,7 +66,9 @@ __global__ void k_resolvent(const double *__restrict__ q, int np, int nq, int nc
 // ------------------------------------------------------- block products
 // out[(b, r)][c] = sum_k Mat_b[r][k] y[(b, k)][c],  b = a*nq + j, Mat_b = mats[a]
 // y = G (.) in (complex product, USE_G) or in; out = that (SUB false) or
-// add - that (SUB true).  Tiles of 32 rows x W columns, k in steps of 32.
+// add - that (SUB true).  Tiles of 32 rows x W columns, k in steps of 32
+// (small tiles: at these sizes the product is latency-bound, so many
+// workgroups in flight matter more than register reuse).
 constexpr int kTR = 32, kTK = 32;
 
 template <bool USE_G, bool SUB>
@@ -138,7 +141,8 @@ __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq,
 
 // --------------------------------------------------------------- P0 SpMM
 // y[r][c] = sum_t val[t] x[col[t]][c]; one wavefront per cell row, lanes =
-// (nonzero slot g, column c) with Wp = pow2 >= W columns per slot.
+// (nonzero slot g, column c) with Wp = pow2 >= W columns per slot; four
+// independent gathers in flight per lane.
 template <class V>
 __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ rowptr,
                                               const int32_t *__restrict__ col,
@@ -151,36 +155,178 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ rowptr
     const int G = 64 / Wp;
     const int g = lane / Wp, c = lane % Wp;
     const int64_t b = rowptr[r], e = rowptr[r + 1];
-    double acc = 0.0;
-    if (c < W)
-        for (int64_t t = b + g; t < e; t += G) acc += (double)val[t] * x[(int64_t)col[t] * W + c];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (c < W) {
+        int64_t t = b + g;
+        for (; t + 3 * G < e; t += 4 * G) {
+            const int64_t c0 = col[t], c1 = col[t + G], c2 = col[t + 2 * G], c3 = col[t + 3 * G];
+            const double v0 = (double)val[t], v1 = (double)val[t + G];
+            const double v2 = (double)val[t + 2 * G], v3 = (double)val[t + 3 * G];
+            a0 += v0 * x[c0 * W + c];
+            a1 += v1 * x[c1 * W + c];
+            a2 += v2 * x[c2 * W + c];
+            a3 += v3 * x[c3 * W + c];
+        }
+        for (; t < e; t += G) a0 += (double)val[t] * x[(int64_t)col[t] * W + c];
+    }
+    double acc = (a0 + a1) + (a2 + a3);
     for (int off = Wp; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
     if (g == 0 && c < W) y[(int64_t)r * W + c] = acc;
 }
 
-// ----------------------------------------------------------- GMRES parts
-// partial[chunk][i][e] = sum_{rows in chunk} conj(V_i[row][e]) w[row][e]
-constexpr int kDotRows = 64;
+// ------------------------------------------------------ Krylov vector ops
+// Rows are processed in chunks of kRB per workgroup.  Thread t handles
+// energy e = t % nEp (nEp = pow2 >= nE) and rows r0 + t / nEp + k (256/nEp),
+// k < NR = kRB nEp / 256, so loads of one row are contiguous across threads
+// and each thread keeps one energy.
+constexpr int kRB = 32;
 
-__global__ __launch_bounds__(256) void k_dots(const double *__restrict__ Vb, int64_t vstride,
-                                              int nvec, const double *__restrict__ w, int64_t M,
-                                              int nE, double *__restrict__ partial) {
-    const int t = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * kDotRows;
-    const int64_t r1 = r0 + kDotRows < M ? r0 + kDotRows : M;
-    const int npair = nvec * nE;
-    for (int p = t; p < npair; p += 256) {
-        const int i = p / nE, e = p % nE;
-        const double *v = Vb + i * vstride;
-        double sr = 0.0, si = 0.0;
-        for (int64_t r = r0; r < r1; ++r) {
-            const int64_t o = (r * nE + e) * 2;
-            const double vr = v[o], vi = v[o + 1], wr = w[o], wi = w[o + 1];
-            sr += vr * wr + vi * wi;
-            si += vr * wi - vi * wr;
+// Reduce (sr, si) over the lanes of a wavefront that share the same energy
+// (lane offsets nEp, 2 nEp, ...).
+__device__ __forceinline__ void reduce_rows(double &sr, double &si, int nEp) {
+    for (int off = nEp; off < 64; off <<= 1) {
+        sr += __shfl_xor(sr, off, 64);
+        si += __shfl_xor(si, off, 64);
+    }
+}
+
+// Partial dot products of vectors V_0..V_{nvec-1} with the thread's rows of
+// w (held in wr/wi): partial[blk][i][e] = sum conj(V_i) w over the chunk.
+template <int NR>
+__device__ __forceinline__ void chunk_dots(const double *__restrict__ Vb, int64_t vstride, int nvec,
+                                           const double (&wr)[NR], const double (&wi)[NR],
+                                           const int64_t (&off)[NR], bool valid_e, int nE, int nEp,
+                                           double *__restrict__ partial,
+                                           double (*red)[8][32][2]) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, e = t % nEp;
+    for (int i0 = 0; i0 < nvec; i0 += 8) {
+        double ar[8], ai[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            ar[g] = 0.0;
+            ai[g] = 0.0;
         }
-        partial[((int64_t)blockIdx.x * npair + p) * 2] = sr;
-        partial[((int64_t)blockIdx.x * npair + p) * 2 + 1] = si;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (off[k] < 0 || !valid_e) continue;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                if (i0 + g < nvec) {
+                    const double *v = Vb + (int64_t)(i0 + g) * vstride + off[k];
+                    const double vr = v[0], vi = v[1];
+                    ar[g] += vr * wr[k] + vi * wi[k];
+                    ai[g] += vr * wi[k] - vi * wr[k];
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 8; ++g) reduce_rows(ar[g], ai[g], nEp);
+        if (lane < nEp) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                red[wave][g][lane][0] = ar[g];
+                red[wave][g][lane][1] = ai[g];
+            }
+        }
+        __syncthreads();
+        if (t < 8 * nE) {
+            const int g = t / nE, ee = t % nE;
+            if (i0 + g < nvec) {
+                const double sr = (red[0][g][ee][0] + red[1][g][ee][0]) + (red[2][g][ee][0] + red[3][g][ee][0]);
+                const double si = (red[0][g][ee][1] + red[1][g][ee][1]) + (red[2][g][ee][1] + red[3][g][ee][1]);
+                const int64_t p = ((int64_t)blockIdx.x * nvec + (i0 + g)) * nE + ee;
+                partial[2 * p] = sr;
+                partial[2 * p + 1] = si;
+            }
+        }
+        __syncthreads();
+        (void)e;
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void chunk_rows(int64_t M, int nE, int nEp, int64_t (&off)[NR],
+                                           bool &valid_e) {
+    const int t = threadIdx.x, e = t % nEp, rs = t / nEp, rstep = 256 / nEp;
+    const int64_t r0 = (int64_t)blockIdx.x * kRB;
+    valid_e = e < nE;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int64_t row = r0 + rs + (int64_t)k * rstep;
+        off[k] = (rs + k * rstep < kRB && row < M) ? (row * nE + e) * 2 : -1;
+    }
+}
+
+// partial[blk][i][e] = sum_{rows of blk} conj(V_i[row][e]) w[row][e]
+template <int NR>
+__global__ __launch_bounds__(256) void k_vdots(const double *__restrict__ Vb, int64_t vstride,
+                                               int nvec, const double *__restrict__ w, int64_t M,
+                                               int nE, int nEp, double *__restrict__ partial) {
+    __shared__ double red[4][8][32][2];
+    int64_t off[NR];
+    bool valid_e;
+    chunk_rows<NR>(M, nE, nEp, off, valid_e);
+    double wr[NR], wi[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        wr[k] = (off[k] >= 0 && valid_e) ? w[off[k]] : 0.0;
+        wi[k] = (off[k] >= 0 && valid_e) ? w[off[k] + 1] : 0.0;
+    }
+    chunk_dots<NR>(Vb, vstride, nvec, wr, wi, off, valid_e, nE, nEp, partial, red);
+}
+
+// w -= sum_i h[i][e] V_i; then either the partial dots of V_0.. with the new
+// w (DOTS, second Gram-Schmidt pass) or the partial |w|^2 per energy (NORM:
+// npart[blk][e]).  h layout [nvec][nE] complex.
+template <int NR, bool DOTS, bool NORM>
+__global__ __launch_bounds__(256) void k_vupdate(const double *__restrict__ Vb, int64_t vstride,
+                                                 int nvec, const double *__restrict__ h, int64_t M,
+                                                 int nE, int nEp, double *__restrict__ w,
+                                                 double *__restrict__ partial) {
+    __shared__ double red[4][8][32][2];
+    int64_t off[NR];
+    bool valid_e;
+    chunk_rows<NR>(M, nE, nEp, off, valid_e);
+    const int t = threadIdx.x, e = t % nEp;
+    double wr[NR], wi[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        wr[k] = (off[k] >= 0 && valid_e) ? w[off[k]] : 0.0;
+        wi[k] = (off[k] >= 0 && valid_e) ? w[off[k] + 1] : 0.0;
+    }
+    if (valid_e) {
+        for (int i = 0; i < nvec; ++i) {
+            const double hr = h[2 * (i * nE + e)], hi = h[2 * (i * nE + e) + 1];
+            const double *v = Vb + (int64_t)i * vstride;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (off[k] < 0) continue;
+                const double vr = v[off[k]], vi = v[off[k] + 1];
+                wr[k] -= hr * vr - hi * vi;
+                wi[k] -= hr * vi + hi * vr;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (off[k] < 0) continue;
+            w[off[k]] = wr[k];
+            w[off[k] + 1] = wi[k];
+        }
+    }
+    if (DOTS) chunk_dots<NR>(Vb, vstride, nvec, wr, wi, off, valid_e, nE, nEp, partial, red);
+    if (NORM) {
+        double s = 0.0, z = 0.0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s += wr[k] * wr[k] + wi[k] * wi[k];
+        reduce_rows(s, z, nEp);
+        const int lane = t & 63, wave = t >> 6;
+        if (lane < nEp) red[wave][0][lane][0] = s;
+        __syncthreads();
+        if (t < nE) {
+            const double v = (red[0][0][t][0] + red[1][0][t][0]) + (red[2][0][t][0] + red[3][0][t][0]);
+            partial[2 * ((int64_t)blockIdx.x * nE + t)] = v;
+            partial[2 * ((int64_t)blockIdx.x * nE + t) + 1] = 0.0;
+        }
     }
 }
 
@@ -217,24 +363,6 @@ __global__ __launch_bounds__(256) void k_dots_reduce(const double *__restrict__ 
             hh[1] = si;
         }
     }
-}
-
-// w[row][e] -= sum_i h[i][e] V_i[row][e]
-__global__ void k_update(const double *__restrict__ Vb, int64_t vstride, int nvec,
-                         const double *__restrict__ h, int64_t M, int nE,
-                         double *__restrict__ w) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= M * nE) return;
-    const int e = (int)(idx % nE);
-    double wr = w[2 * idx], wi = w[2 * idx + 1];
-    for (int i = 0; i < nvec; ++i) {
-        const double hr = h[2 * (i * nE + e)], hi = h[2 * (i * nE + e) + 1];
-        const double vr = Vb[i * vstride + 2 * idx], vi = Vb[i * vstride + 2 * idx + 1];
-        wr -= hr * vr - hi * vi;
-        wi -= hr * vi + hi * vr;
-    }
-    w[2 * idx] = wr;
-    w[2 * idx + 1] = wi;
 }
 
 // w[row][e] *= scale[e] (scale[e] = 1/norm, or 0 after breakdown)
@@ -296,16 +424,29 @@ __global__ void k_cycle_start(const double *__restrict__ nrm2, int nE, int m, do
     inv[e] = beta > 1e-300 ? 1.0 / beta : 0.0;
 }
 
-// After orthogonalising w = K v_k: H[k+1][k] = ||w||; inv = 1/||w||; Givens.
-__global__ void k_givens(const double *__restrict__ nrm2, double *__restrict__ H, int nE, int m,
-                         int k, double tol, GState S, double *__restrict__ inv) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// After orthogonalising w = K v_k: reduce the per-chunk |w|^2 partials
+// (npart[chunk][e], one workgroup), then per energy H[k+1][k] = ||w||,
+// inv = 1/||w||, apply the previous Givens rotations to column k, form the
+// new one and update the residual estimate.
+__global__ __launch_bounds__(256) void k_givens(const double *__restrict__ npart, int nchunk,
+                                                double *__restrict__ H, int nE, int m, int k,
+                                                double tol, GState S, double *__restrict__ inv) {
+    __shared__ double nr2[32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int ee = wave; ee < nE; ee += 4) {
+        double v = 0.0;
+        for (int cch = lane; cch < nchunk; cch += 64) v += npart[2 * ((int64_t)cch * nE + ee)];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) nr2[ee] = v;
+    }
+    __syncthreads();
+    const int e = threadIdx.x;
     if (e >= nE) return;
     double *st = S.st + e * kSt;
     double *He = H + (int64_t)e * (m + 1) * m * 2;
     auto Hr = [&](int i) -> double & { return He[(i * m + k) * 2]; };
     auto Hi = [&](int i) -> double & { return He[(i * m + k) * 2 + 1]; };
-    const double hn = sqrt(nrm2[2 * e]);
+    const double hn = sqrt(nr2[e]);
     Hr(k + 1) = hn;
     Hi(k + 1) = 0.0;
     const double beta = st[0];
@@ -419,7 +560,7 @@ inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 struct Batch {
     wpcd_ctx *c;
-    int nE, W, Wp, m;
+    int nE, nEp, W, Wp, m;
     int64_t M;
     bool fp64;
     double *G, *X, *B, *T1, *T2, *R, *Vb, *H, *partial, *h, *inv, *y;
@@ -429,6 +570,14 @@ struct Batch {
     int nchunk;
 };
 
+template <bool USE_G, bool SUB>
+void launch_block_apply(Batch &b, dim3 grid, ChPtrs mats, const double *in, const double *add,
+                        double *out) {
+    wpcd_ctx *c = b.c;
+    hipLaunchKernelGGL((k_block_apply<USE_G, SUB>), grid, dim3(256), 0, c->stream, mats, c->np,
+                       c->nq, b.W, in, b.G, add, out);
+}
+
 void op_apply(Batch &b, const double *x, double *out, bool with_g, bool sub) {
     wpcd_ctx *c = b.c;
     ChPtrs vt{}, oo{};
@@ -436,16 +585,11 @@ void op_apply(Batch &b, const double *x, double *out, bool with_g, bool sub) {
         vt.p[a] = c->waves[c->ch_wave[a]].Vt.ptr;
         oo.p[a] = c->waves[c->ch_wave[a]].O.ptr;
     }
-    const int n = c->np;
-    dim3 grid(cdiv(n, kTR), c->nch * c->nq);
+    dim3 grid(cdiv(c->np, kTR), c->nch * c->nq);
     {
         TimedLaunch tl(c->timer, c->stream, "apply_vt", WPCD_TIME_SOLVE);
-        if (with_g)
-            hipLaunchKernelGGL((k_block_apply<true, false>), grid, dim3(256), 0, c->stream, vt, n,
-                               c->nq, b.W, x, b.G, nullptr, b.T1);
-        else
-            hipLaunchKernelGGL((k_block_apply<false, false>), grid, dim3(256), 0, c->stream, vt, n,
-                               c->nq, b.W, x, nullptr, nullptr, b.T1);
+        if (with_g) launch_block_apply<true, false>(b, grid, vt, x, nullptr, b.T1);
+        else launch_block_apply<false, false>(b, grid, vt, x, nullptr, b.T1);
         WPCD_HIP(hipGetLastError());
     }
     {
@@ -463,32 +607,57 @@ void op_apply(Batch &b, const double *x, double *out, bool with_g, bool sub) {
     }
     {
         TimedLaunch tl(c->timer, c->stream, "apply_o", WPCD_TIME_SOLVE);
-        if (sub)
-            hipLaunchKernelGGL((k_block_apply<false, true>), grid, dim3(256), 0, c->stream, oo, n,
-                               c->nq, b.W, b.T2, nullptr, x, out);
-        else
-            hipLaunchKernelGGL((k_block_apply<false, false>), grid, dim3(256), 0, c->stream, oo, n,
-                               c->nq, b.W, b.T2, nullptr, nullptr, out);
+        if (sub) launch_block_apply<false, true>(b, grid, oo, b.T2, x, out);
+        else launch_block_apply<false, false>(b, grid, oo, b.T2, nullptr, out);
         WPCD_HIP(hipGetLastError());
     }
 }
 
-// nrm2/dots of w against nvec vectors starting at Vb -> h (reduced), optional H column.
+// Dispatch on NR = rows per thread in a kRB-row chunk = max(1, kRB nEp / 256).
+template <class F>
+void with_nr(int nEp, F &&f) {
+    switch (nEp) {
+        case 1: case 2: case 4: case 8: f(std::integral_constant<int, 1>{}); break;
+        case 16: f(std::integral_constant<int, 2>{}); break;
+        default: f(std::integral_constant<int, 4>{}); break;
+    }
+}
+
+void reduce_partials(Batch &b, int nvec, double *h, double *H, int kcol, int accumulate) {
+    wpcd_ctx *c = b.c;
+    TimedLaunch tl(c->timer, c->stream, "gmres_reduce", WPCD_TIME_SOLVE);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(cdiv(nvec * b.nE, 4)), dim3(256), 0, c->stream,
+                       b.partial, b.nchunk, nvec, b.nE, h, H, b.m, kcol, accumulate);
+    WPCD_HIP(hipGetLastError());
+}
+
+// dots of w against nvec vectors starting at Vb -> h (reduced), optional H column.
 void dots(Batch &b, const double *Vb, int nvec, const double *w, double *h, double *H, int kcol,
           int accumulate) {
     wpcd_ctx *c = b.c;
     {
         TimedLaunch tl(c->timer, c->stream, "gmres_dots", WPCD_TIME_SOLVE);
-        hipLaunchKernelGGL(k_dots, dim3(b.nchunk), dim3(256), 0, c->stream, Vb, b.vstride, nvec, w,
-                           b.M, b.nE, b.partial);
+        with_nr(b.nEp, [&](auto nr) {
+            hipLaunchKernelGGL(k_vdots<decltype(nr)::value>, dim3(b.nchunk), dim3(256), 0,
+                               c->stream, Vb, b.vstride, nvec, w, b.M, b.nE, b.nEp, b.partial);
+        });
         WPCD_HIP(hipGetLastError());
     }
-    {
-        TimedLaunch tl(c->timer, c->stream, "gmres_reduce", WPCD_TIME_SOLVE);
-        hipLaunchKernelGGL(k_dots_reduce, dim3(cdiv(nvec * b.nE, 4)), dim3(256), 0, c->stream,
-                           b.partial, b.nchunk, nvec, b.nE, h, H, b.m, kcol, accumulate);
-        WPCD_HIP(hipGetLastError());
-    }
+    reduce_partials(b, nvec, h, H, kcol, accumulate);
+}
+
+// w -= sum h V over nvec vectors, then DOTS: second-pass partial dots, or
+// NORM: |w|^2 partials.
+template <bool DOTS, bool NORM>
+void vupdate(Batch &b, int nvec, double *w) {
+    wpcd_ctx *c = b.c;
+    TimedLaunch tl(c->timer, c->stream, "gmres_update", WPCD_TIME_SOLVE);
+    with_nr(b.nEp, [&](auto nr) {
+        hipLaunchKernelGGL((k_vupdate<decltype(nr)::value, DOTS, NORM>), dim3(b.nchunk), dim3(256),
+                           0, c->stream, b.Vb, b.vstride, nvec, b.h, b.M, b.nE, b.nEp, w,
+                           b.partial);
+    });
+    WPCD_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -504,14 +673,15 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     b.c = c;
     b.nE = nE;
     b.W = 2 * nE;
-    b.Wp = 1;
-    while (b.Wp < b.W) b.Wp <<= 1;
+    b.nEp = 1;
+    while (b.nEp < nE) b.nEp <<= 1;
+    b.Wp = 2 * b.nEp;
     b.m = m;
     b.M = (int64_t)c->nch * c->nq * c->np;
     b.fp64 = fp64;
     const int64_t vec = b.M * b.W;   // doubles per batched vector
     b.vstride = vec;
-    b.nchunk = cdiv(b.M, kDotRows);
+    b.nchunk = cdiv(b.M, kRB);
     c->d_G.reserve(vec);
     c->d_X.reserve(vec);
     c->d_B.reserve(vec);
@@ -604,18 +774,20 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
             double *vk = b.Vb + (int64_t)k * vec;
             double *w = b.Vb + (int64_t)(k + 1) * vec;
             op_apply(b, vk, w, true, true);
-            for (int pass = 0; pass < 2; ++pass) {
-                dots(b, b.Vb, k + 1, w, b.h, b.H, k, pass);
-                TimedLaunch tl(c->timer, s, "gmres_update", WPCD_TIME_SOLVE);
-                hipLaunchKernelGGL(k_update, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.Vb,
-                                   b.vstride, k + 1, b.h, b.M, nE, w);
+            // classical Gram-Schmidt, two passes; the second pass's dots are
+            // fused into the first update, |w|^2 into the second
+            dots(b, b.Vb, k + 1, w, b.h, b.H, k, 0);
+            vupdate<true, false>(b, k + 1, w);
+            reduce_partials(b, k + 1, b.h, b.H, k, 1);
+            vupdate<false, true>(b, k + 1, w);
+            {
+                TimedLaunch tl(c->timer, s, "gmres_givens", WPCD_TIME_SOLVE);
+                hipLaunchKernelGGL(k_givens, dim3(1), dim3(256), 0, s, b.partial, b.nchunk, b.H, nE,
+                                   m, k, tol, b.S, b.inv);
+                hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.inv, b.M,
+                                   nE, w);
                 WPCD_HIP(hipGetLastError());
             }
-            dots(b, w, 1, w, b.h, nullptr, 0, 0);
-            hipLaunchKernelGGL(k_givens, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.h, b.H, nE, m, k, tol,
-                               b.S, b.inv);
-            hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.inv, b.M, nE, w);
-            WPCD_HIP(hipGetLastError());
             ++total;
             if ((k + 1) % check_every == 0 || k + 1 == m) {
                 WPCD_HIP(hipMemcpyAsync(sth.data(), b.S.st, sth.size() * sizeof(double),
