@@ -270,6 +270,50 @@ double orc_geom_G(int L, int l, int lam, int l2, int lam2, double q, double q2, 
     return 16.0 * M_PI * M_PI / (2.0 * L + 1.0) * creal(acc);
 }
 
+/* All channel pairs of G at one node: G[a*nch + a2].  Same formula as
+ * orc_geom_G; the spherical harmonics of the four directions are computed
+ * once per node and shared by the pairs, the Clebsch-Gordan coefficients
+ * come from the caller's table cg[a][M+L][m+l] = <l m lam M-m | L M>.    */
+#define ORC_LMAX 4
+static void orc_geom_G_all(int L, int nch, const int *l, const int *lam, const double *cg,
+                           double q, double q2, double x, double *G)
+{
+    double s = sqrt((1.0 - x) * (1.0 + x));
+    double qv[3] = { q * s, 0.0, q * x };
+    double q2v[3] = { 0.0, 0.0, q2 };
+    double pi1[3] = { q2v[0] + 0.5 * qv[0], 0.0, q2v[2] + 0.5 * qv[2] };
+    double pi2[3] = { -(qv[0] + 0.5 * q2v[0]), 0.0, -(qv[2] + 0.5 * q2v[2]) };
+    /* Y[dir][l][m + ORC_LMAX] for dir = pi1, q, pi2, q2 */
+    double complex Y[4][ORC_LMAX + 1][2 * ORC_LMAX + 1];
+    const double *dirs[4] = { pi1, qv, pi2, q2v };
+    for (int d = 0; d < 4; ++d)
+        for (int ll = 0; ll <= ORC_LMAX; ++ll)
+            for (int m = -ll; m <= ll; ++m)
+                Y[d][ll][m + ORC_LMAX] = orc_ylm(ll, m, dirs[d][0], dirs[d][1], dirs[d][2]);
+    const int W = 2 * ORC_LMAX + 1, WM = 2 * 8 + 1;
+    for (int a = 0; a < nch; ++a)
+        for (int a2 = 0; a2 < nch; ++a2) {
+            double complex acc = 0.0;
+            for (int M = -L; M <= L; ++M) {
+                double complex b1 = 0.0, b2 = 0.0;
+                for (int m = -l[a]; m <= l[a]; ++m) {
+                    int mu = M - m;
+                    if (abs(mu) > lam[a]) continue;
+                    b1 += cg[(a * WM + (M + L)) * W + (m + ORC_LMAX)] *
+                          Y[0][l[a]][m + ORC_LMAX] * Y[1][lam[a]][mu + ORC_LMAX];
+                }
+                for (int m = -l[a2]; m <= l[a2]; ++m) {
+                    int mu = M - m;
+                    if (abs(mu) > lam[a2]) continue;
+                    b2 += cg[(a2 * WM + (M + L)) * W + (m + ORC_LMAX)] *
+                          Y[2][l[a2]][m + ORC_LMAX] * Y[3][lam[a2]][mu + ORC_LMAX];
+                }
+                acc += conj(b1) * b2;
+            }
+            G[a * nch + a2] = 16.0 * M_PI * M_PI / (2.0 * L + 1.0) * creal(acc);
+        }
+}
+
 /* ------------------------------------------------------------------ */
 /* One cell-pair block of P0: out[a*nch + a2] for channel rows a, columns a2.
  * i, j: row cell; i2, j2: column cell (0-based bins).
@@ -286,6 +330,16 @@ void orc_p0_block(const double *p, const double *q, int i, int j, int i2, int j2
     double qm2 = 0.5 * (q[j2 + 1] + q[j2]), qh2 = 0.5 * dq2;
     int swave = (nch == 1 && L == 0 && l[0] == 0 && lam[0] == 0);
     for (int c = 0; c < nch * nch; ++c) out[c] = 0.0;
+    /* Clebsch-Gordan table per channel: cg[a][M + L][m + LMAX] */
+    double cg[8 * 17 * (2 * ORC_LMAX + 1)];
+    double Gn[64];
+    if (!swave) {
+        for (int a = 0; a < nch; ++a)
+            for (int M = -L; M <= L; ++M)
+                for (int m = -ORC_LMAX; m <= ORC_LMAX; ++m)
+                    cg[(a * 17 + (M + L)) * (2 * ORC_LMAX + 1) + (m + ORC_LMAX)] =
+                        (abs(m) <= l[a]) ? orc_cg(l[a], m, lam[a], M - m, L, M) : 0.0;
+    }
 
     for (int a = 0; a < nq_pts; ++a) {
         double qa = qm1 + qh1 * gq[a];
@@ -331,10 +385,9 @@ void orc_p0_block(const double *p, const double *q, int i, int j, int i2, int j2
                     double x = (t - A) / B;
                     if (x > 1.0) x = 1.0;
                     if (x < -1.0) x = -1.0;
-                    for (int ca = 0; ca < nch; ++ca)
-                        for (int cb = 0; cb < nch; ++cb)
-                            out[ca * nch + cb] += wa * wb * f *
-                                orc_geom_G(L, l[ca], lam[ca], l[cb], lam[cb], qa, qb, x);
+                    orc_geom_G_all(L, nch, l, lam, cg, qa, qb, x, Gn);
+                    for (int cab = 0; cab < nch * nch; ++cab)
+                        out[cab] += wa * wb * f * Gn[cab];
                 }
             }
         }

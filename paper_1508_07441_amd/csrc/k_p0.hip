@@ -480,6 +480,184 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
     }
 }
 
+// ------------------------------------------------ multichannel elements
+// Cell pair block of P0 for n_ch channels: the s-wave integrand 1/(pi1 pi2)
+// times the angular coupling G_aa'(q, q', x) = N_aa'(q^2, q'^2, y) /
+// (t^(l/2) u^(l'/2) (q^2)^(lam/2) (q'^2)^(lam'/2)), y = q q' x = t - q'^2 - q^2/4,
+// with N the coupling polynomial (coefficients from coupling_tables).
+// One wavefront per cell pair, lanes = (q, q') Gauss pairs; FP64 arithmetic
+// (the polynomial cancels near pi1 -> 0 and needs the range); values are
+// stored in FP64 or rounded once to FP32.
+struct McTab {
+    McPair p[kMaxCh * kMaxCh];
+    int npair;
+};
+
+__device__ __forceinline__ double ipow_h(double v, int h) {
+    return h == 0 ? 1.0 : (h == 1 ? v : (h == 2 ? v * v : v * v * v * v));
+}
+
+template <int NP, int DEG>
+__device__ __forceinline__ void mc_lane_fast(const McTab &Mt, const double *__restrict__ coef,
+                                             const NodeTab &N, int ngx, double q, double q2,
+                                             double lo_t, double lo_u, double h, double (&acc)[NP]) {
+    const double a2 = q * q, b2 = q2 * q2, A = b2 + 0.25 * a2;
+    double Dc[NP][DEG + 1];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const McPair P = Mt.p[p];
+        const double den = ipow_h(a2, P.hlam) * ipow_h(b2, P.hlam2);
+        int o = P.off;
+#pragma unroll
+        for (int c = 0; c <= DEG; ++c) {
+            double s = 0.0;
+            if (c <= P.d) {
+                double pa = 1.0;
+                for (int a = 0; a <= P.d - c; ++a) {
+                    double pb = 1.0;
+                    for (int bb = 0; bb < P.d - c - a; ++bb) pb *= b2;
+                    s += coef[o++] * pa * pb;
+                    pa *= a2;
+                }
+            }
+            Dc[p][c] = s / den;
+        }
+        acc[p] = 0.0;
+    }
+    for (int k = 0; k < ngx; ++k) {
+        const double sk = h * N.ux[k];
+        const double t = lo_t + sk, u = lo_u + sk;
+        const double rt = rsqrt_nr(t), ru = rsqrt_nr(u);
+        const double base = N.wx[k] * rt * ru, it = rt * rt, iu = ru * ru;
+        const double y = t - A;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            double nv = Dc[p][DEG];
+#pragma unroll
+            for (int c = DEG - 1; c >= 0; --c) nv = fma(nv, y, Dc[p][c]);
+            acc[p] = fma(base * ipow_h(it, Mt.p[p].hl) * ipow_h(iu, Mt.p[p].hl2), nv, acc[p]);
+        }
+    }
+}
+
+template <int NP, int DEG>
+__global__ __launch_bounds__(256) void k_p0_mc(ElemTables T, NodeTab N, McTab Mt,
+                                               const double *__restrict__ coef,
+                                               const int32_t *__restrict__ rowidx,
+                                               const int32_t *__restrict__ col, int64_t nnz,
+                                               double *__restrict__ val64, float *__restrict__ val32) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int npair_q = T.ngq * T.ngq;
+    for (int64_t e = wave0; e < nnz; e += nwaves) {
+        const int r = rowidx[e], c = col[e];
+        const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+        double tot[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) tot[p] = 0.0;
+        for (int pr = lane; pr < npair_q; pr += 64) {
+            const int a = pr / T.ngq, b = pr - a * T.ngq;
+            const double q = T.qnode[j * T.ngq + a], q2 = T.qnode[j2 * T.ngq + b];
+            double lo_t, lo_u, h;
+            lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
+            if (h > 0.0) {
+                double acc[NP];
+                mc_lane_fast<NP, DEG>(Mt, coef, N, T.ngx, q, q2, lo_t, lo_u, h, acc);
+                const double wab = T.qwt[j * T.ngq + a] * T.qwt[j2 * T.ngq + b] * h;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) tot[p] = fma(wab, acc[p], tot[p]);
+            }
+        }
+        const double nrm = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const double v = wave_sum(tot[p]);
+            if (lane == 0) {
+                if (val64) val64[e * NP + p] = v * nrm;
+                else val32[e * NP + p] = (float)(v * nrm);
+            }
+        }
+    }
+}
+
+// General channel sets: pairs processed in chunks of 16, the coupling
+// polynomial evaluated in full at every node.
+__global__ __launch_bounds__(256) void k_p0_mc_gen(ElemTables T, NodeTab N, McTab Mt,
+                                                   const double *__restrict__ coef,
+                                                   const int32_t *__restrict__ rowidx,
+                                                   const int32_t *__restrict__ col, int64_t nnz,
+                                                   double *__restrict__ val64,
+                                                   float *__restrict__ val32) {
+    constexpr int PC = 16;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int npair_q = T.ngq * T.ngq;
+    const int NP = Mt.npair;
+    for (int64_t e = wave0; e < nnz; e += nwaves) {
+        const int r = rowidx[e], c = col[e];
+        const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+        const double nrm = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
+        for (int p0 = 0; p0 < NP; p0 += PC) {
+            double tot[PC];
+#pragma unroll
+            for (int s = 0; s < PC; ++s) tot[s] = 0.0;
+            for (int pr = lane; pr < npair_q; pr += 64) {
+                const int a = pr / T.ngq, b = pr - a * T.ngq;
+                const double q = T.qnode[j * T.ngq + a], q2 = T.qnode[j2 * T.ngq + b];
+                double lo_t, lo_u, h;
+                lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
+                if (!(h > 0.0)) continue;
+                const double a2 = q * q, b2 = q2 * q2, A = b2 + 0.25 * a2;
+                const double wab = T.qwt[j * T.ngq + a] * T.qwt[j2 * T.ngq + b] * h;
+                double acc[PC];
+#pragma unroll
+                for (int s = 0; s < PC; ++s) acc[s] = 0.0;
+                for (int k = 0; k < T.ngx; ++k) {
+                    const double sk = h * N.ux[k];
+                    const double t = lo_t + sk, u = lo_u + sk;
+                    const double rt = rsqrt_nr(t), ru = rsqrt_nr(u);
+                    const double base = N.wx[k] * rt * ru, it = rt * rt, iu = ru * ru;
+                    const double y = t - A;
+#pragma unroll
+                    for (int s = 0; s < PC; ++s) {
+                        const int p = p0 + s;
+                        if (p >= NP) break;
+                        const McPair P = Mt.p[p];
+                        double nv = 0.0, yc = 1.0;
+                        int o = P.off;
+                        for (int cc = 0; cc <= P.d; ++cc) {
+                            double sa = 0.0, pa = 1.0;
+                            for (int aa = 0; aa <= P.d - cc; ++aa) {
+                                double pb = 1.0;
+                                for (int bb = 0; bb < P.d - cc - aa; ++bb) pb *= b2;
+                                sa += coef[o++] * pa * pb;
+                                pa *= a2;
+                            }
+                            nv += sa * yc;
+                            yc *= y;
+                        }
+                        const double den = ipow_h(a2, P.hlam) * ipow_h(b2, P.hlam2);
+                        acc[s] += base * ipow_h(it, P.hl) * ipow_h(iu, P.hl2) * nv / den;
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < PC; ++s) tot[s] = fma(wab, acc[s], tot[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < PC; ++s) {
+                const int p = p0 + s;
+                const double v = wave_sum(tot[s]);
+                if (lane == 0 && p < NP) {
+                    if (val64) val64[e * NP + p] = v * nrm;
+                    else val32[e * NP + p] = (float)(v * nrm);
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host
 static GridView grid_view(wpcd_ctx *c) {
     return GridView{c->d_p.ptr, c->d_q.ptr, c->d_P2.ptr, c->d_Q34.ptr, c->d_H.ptr, c->np, c->nq};
@@ -537,11 +715,37 @@ void build_values(wpcd_ctx *c, bool fp64) {
     ElemTables T{c->d_P2.ptr, c->d_rsd_p.ptr, c->d_rsd_q.ptr, c->d_qnode.ptr, c->d_qwt.ptr,
                  c->d_ux.ptr,  c->d_wx.ptr,    c->d_uxf.ptr,   c->d_wxf.ptr,   c->np,
                  c->ngq,       c->ngx};
-    WPCD_REQUIRE(c->nch == 1, WPCD_E_INVALID, "multichannel P0 not built yet");
     const int64_t nnz = c->nnz;
-    if (fp64) c->d_val64.reserve(nnz);
-    else c->d_val32.reserve(nnz);
+    const int NP = c->nch * c->nch;
+    if (fp64) c->d_val64.reserve(nnz * NP);
+    else c->d_val32.reserve(nnz * NP);
     if (nnz == 0) return;
+    if (!c->swave) {
+        NodeTab N{};
+        for (int k = 0; k < c->ngx; ++k) {
+            N.ux[k] = 1.0 + c->gx[k];
+            N.wx[k] = c->wx[k];
+        }
+        McTab Mt{};
+        Mt.npair = NP;
+        for (int p = 0; p < NP; ++p) Mt.p[p] = c->mc_pairs[p];
+        const int64_t want = (nnz + 3) / 4;
+        const int blocks = (int)(want < 65536 ? want : 65536);
+        double *v64 = fp64 ? c->d_val64.ptr : nullptr;
+        float *v32 = fp64 ? nullptr : c->d_val32.ptr;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, c->stream, T, N, Mt,
+                               c->d_mcoef.ptr, c->d_rowidx.ptr, c->d_col.ptr, nnz, v64, v32);
+        };
+        TimedLaunch tl(c->timer, c->stream, fp64 ? "p0_elem_mc_f64" : "p0_elem_mc_f32",
+                       WPCD_TIME_P0);
+        if (c->mc_deg <= 4 && NP == 1) go(k_p0_mc<1, 4>);
+        else if (c->mc_deg <= 4 && NP == 4) go(k_p0_mc<4, 4>);
+        else if (c->mc_deg <= 4 && NP == 9) go(k_p0_mc<9, 4>);
+        else go(k_p0_mc_gen);
+        WPCD_HIP(hipGetLastError());
+        return;
+    }
     if (c->ngq == 8) {
         NodeTab N{};
         for (int k = 0; k < c->ngx; ++k) {

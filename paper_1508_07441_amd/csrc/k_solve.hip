@@ -174,6 +174,43 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ rowptr
     if (g == 0 && c < W) y[(int64_t)r * W + c] = acc;
 }
 
+// Block SpMM for n_ch channels: y[(a, r)][c] = sum_t sum_a2 val[t][a][a2]
+// x[(a2, col[t])][c]; one wavefront per cell row, all NCH output rows.
+template <class V, int NCH>
+__global__ __launch_bounds__(256) void k_spmm_bsr(const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const V *__restrict__ val, int ncell, int W,
+                                                  int Wp, const double *__restrict__ x,
+                                                  double *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= ncell) return;
+    const int G = 64 / Wp;
+    const int g = lane / Wp, c = lane % Wp;
+    const int64_t b = rowptr[r], e = rowptr[r + 1];
+    double acc[NCH];
+#pragma unroll
+    for (int a = 0; a < NCH; ++a) acc[a] = 0.0;
+    if (c < W) {
+        for (int64_t t = b + g; t < e; t += G) {
+            const int64_t cc = col[t];
+            const V *vb = val + t * NCH * NCH;
+#pragma unroll
+            for (int a2 = 0; a2 < NCH; ++a2) {
+                const double xv = x[((int64_t)a2 * ncell + cc) * W + c];
+#pragma unroll
+                for (int a = 0; a < NCH; ++a) acc[a] += (double)vb[a * NCH + a2] * xv;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NCH; ++a) {
+        double v = acc[a];
+        for (int off = Wp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        if (g == 0 && c < W) y[((int64_t)a * ncell + r) * W + c] = v;
+    }
+}
+
 // ------------------------------------------------------ Krylov vector ops
 // Rows are processed in chunks of kRB per workgroup.  Thread t handles
 // energy e = t % nEp (nEp = pow2 >= nE) and rows r0 + t / nEp + k (256/nEp),
@@ -592,7 +629,28 @@ void op_apply(Batch &b, const double *x, double *out, bool with_g, bool sub) {
         else launch_block_apply<false, false>(b, grid, vt, x, nullptr, b.T1);
         WPCD_HIP(hipGetLastError());
     }
-    {
+    if (c->nch > 1) {
+        const int nrow = c->np * c->nq;
+        TimedLaunch tl(c->timer, c->stream, "spmm", WPCD_TIME_SOLVE);
+        auto go = [&](auto kd, auto kf) {
+            if (b.fp64)
+                hipLaunchKernelGGL(kd, dim3(cdiv(nrow, 4)), dim3(256), 0, c->stream, c->d_rowptr.ptr,
+                                   c->d_col.ptr, c->d_val64.ptr, nrow, b.W, b.Wp, b.T1, b.T2);
+            else
+                hipLaunchKernelGGL(kf, dim3(cdiv(nrow, 4)), dim3(256), 0, c->stream, c->d_rowptr.ptr,
+                                   c->d_col.ptr, c->d_val32.ptr, nrow, b.W, b.Wp, b.T1, b.T2);
+        };
+        switch (c->nch) {
+            case 2: go(k_spmm_bsr<double, 2>, k_spmm_bsr<float, 2>); break;
+            case 3: go(k_spmm_bsr<double, 3>, k_spmm_bsr<float, 3>); break;
+            case 4: go(k_spmm_bsr<double, 4>, k_spmm_bsr<float, 4>); break;
+            case 5: go(k_spmm_bsr<double, 5>, k_spmm_bsr<float, 5>); break;
+            case 6: go(k_spmm_bsr<double, 6>, k_spmm_bsr<float, 6>); break;
+            case 7: go(k_spmm_bsr<double, 7>, k_spmm_bsr<float, 7>); break;
+            default: go(k_spmm_bsr<double, 8>, k_spmm_bsr<float, 8>); break;
+        }
+        WPCD_HIP(hipGetLastError());
+    } else {
         const int nrow = c->np * c->nq;
         TimedLaunch tl(c->timer, c->stream, "spmm", WPCD_TIME_SOLVE);
         if (b.fp64)

@@ -443,6 +443,15 @@ wpcd_status wpcd_build_basis(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_p
             c->ch_wave[a] = (int)(std::find(waves.begin(), waves.end(), b->l[a]) - waves.begin());
         }
         upload_tables(c);
+        c->swave = (c->nch == 1 && c->L == 0 && c->ch_l[0] == 0 && c->ch_lam[0] == 0);
+        {
+            std::vector<double> coef;
+            coupling_tables(c->L, c->nch, c->ch_l, c->ch_lam, c->mc_pairs, coef);
+            c->mc_deg = 0;
+            for (auto &pp : c->mc_pairs) c->mc_deg = std::max(c->mc_deg, pp.d);
+            upload(c->d_mcoef, coef, c->stream);
+            WPCD_HIP(hipStreamSynchronize(c->stream));
+        }
         c->has_basis = true;
         build_pair_waves(c, pot);
     });
@@ -738,6 +747,7 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->d_jac.release();
     c->d_flag.release();
     c->d_pot.release();
+    c->d_mcoef.release();
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

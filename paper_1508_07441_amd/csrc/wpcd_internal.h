@@ -93,6 +93,13 @@ struct TimedLaunch {
     }
 };
 
+// Coupling polynomial of one channel pair: degree d = (l+lam+l'+lam')/2,
+// half powers of the divisor t^(l/2) u^(l'/2) (q^2)^(lam/2) (q'^2)^(lam'/2),
+// offset of its coefficients (c major, then a) in the coefficient table.
+struct McPair {
+    int d, hl, hl2, hlam, hlam2, off;
+};
+
 struct PairWave {
     int l = 0;
     DBuf<double> v, O, eps, Vt;   // v, O (rows eigenvectors), eps* ascending, Vt = v O^T
@@ -118,6 +125,11 @@ struct wpcd_ctx {
     wpcd::DBuf<double> d_p, d_q, d_P2, d_Q34, d_H, d_rsd_p, d_rsd_q;
     wpcd::DBuf<double> d_qnode, d_qwt, d_ux, d_wx;
     wpcd::DBuf<float> d_uxf, d_wxf;
+
+    bool swave = true;                  // single (0,0) channel with L = 0: G = 1
+    std::vector<wpcd::McPair> mc_pairs; // coupling polynomials per channel pair
+    int mc_deg = 0;                     // largest d over the pairs
+    wpcd::DBuf<double> d_mcoef;
 
     // ---- potential / pair waves
     bool has_pot = false;
@@ -149,6 +161,10 @@ namespace wpcd {
 // Gauss-Legendre nodes (ascending) and weights on [-1, 1] by the Golub-Welsch
 // eigenvalue method, polished by Newton steps in long double (host).
 void gauss_legendre_gw(int n, std::vector<double> &x, std::vector<double> &w);
+
+// Coupling polynomial coefficients for all channel pairs (host, long double fit).
+void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<McPair> &pairs,
+                     std::vector<double> &coef);
 
 // ---- kernel launchers (defined in the .hip files)
 void launch_potential(wpcd_ctx *c, int wave, double *v_out);

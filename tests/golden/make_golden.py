@@ -4,7 +4,7 @@ The paper prints no matrix elements, amplitudes or counts for any worked
 example (its figures carry no data and its only table holds run times), so
 no stored value here is the paper's.  This file records the oracle's own
 pre-selected structure (nonzero cell-pair counts and a SHA-256 of the CSR
-arrays) for the 40 x 40 and 150 x 150 grids, as a regression fixture.  It is
+arrays) for the 40 x 40, 150 x 150 and 300 x 300 grids, as a regression fixture.  It is
 produced by this script, which calls only oracle/.
 """
 import hashlib
@@ -29,7 +29,7 @@ def digest(ptr, col):
 
 def main():
     out = {}
-    for n in (40, 150):
+    for n in (40, 150, 300):
         p = W.cheb_edges(n, 10.0)
         ptr, col = W.preselect(p, p.copy())
         out[f"{n}x{n}"] = {"n_p": n, "n_q": n, "p_max": 10.0, "q_max": 10.0,

