@@ -82,27 +82,86 @@ typedef struct {
     double fit_e2;
 } wpcd_potential_desc;
 
+/* Initial vector of the iterative solve.  The paper starts from zero (or
+ * sums the Neumann series); the warm starts are an addition of this library
+ * and never change what the solve converges to: the proposed vector x0 is
+ * replaced by alpha x0 with the complex alpha that minimises the initial
+ * residual |b - alpha (1 - K) x0| (alpha = 0, i.e. the zero start, when the
+ * proposal is useless or not finite), and the usual residual test ends the
+ * solve.                                                                 */
+#define WPCD_WARM_NONE 0     /* zero initial vector */
+#define WPCD_WARM_LEARNED 1  /* reduced-basis vector proposed by the network of wpcd_learn_train */
+#define WPCD_WARM_GIVEN 2    /* caller's x0 */
+
 /* Iterative solve options.  max_iter: total Krylov iterations per energy
  * (default 400 when <= 0); krylov_dim: GMRES restart length (default 48,
- * max 128); tol: relative residual target (default 1e-12 FP64, 1e-10
- * mixed).  want_breakup: fill breakup_out in wpcd_solve.                 */
+ * max 128); tol: relative residual target (default 1e-12 for WPCD_FP64,
+ * 1e-9 for WPCD_MIXED, whose FP32 P0 values already perturb the operator at
+ * the 1e-7 level).  want_breakup:
+ * fill breakup_out in wpcd_solve.  warm_start: a WPCD_WARM_* value; x0
+ * (WPCD_WARM_GIVEN only): host array [n_E][M][2] of (re, im) doubles in
+ * channel-basis order, M = n_ch*n_q*n_p.                                 */
 typedef struct {
     int32_t max_iter;
     int32_t krylov_dim;
     double tol;
     int32_t want_breakup;
+    int32_t warm_start;
+    const double *x0;
 } wpcd_solve_opts;
 
 /* Per-energy result.  status is a wpcd_status value for this energy.
  * U = on-shell element of the transition matrix, A = (2/(3 q0)) U / dq_j0,
  * S = 1 - 2 pi i A (Sec. III.B, m = 1), delta = arg(S)/2, eta = |S|.
- * n_open: open breakup pseudostate channels (breakup_out rows).         */
+ * n_open: open breakup pseudostate channels (breakup_out rows).
+ * warm: 1 if a warm start was kept (alpha != 0); r0: relative residual of
+ * the initial vector (1 for the zero start).                             */
 typedef struct {
     double E, q0;
     int32_t j0, status, iters, n_open;
     double U_re, U_im, A_re, A_im, S_re, S_im;
     double delta, eta, residual;
+    int32_t warm, pad_;
+    double r0;
 } wpcd_energy_result;
+
+/* Training of the learned warm start (not part of the paper's method).
+ * For each of n_var potential variants the strengths of the current
+ * potential are multiplied term by term by mult[v][0..n_mult) (n_mult =
+ * the potential's n_terms), the pair waves are re-diagonalised (P0 is
+ * potential independent and is kept), and the energies E[v][0..n_E) are
+ * solved from the zero start in `precision` with `solve` options.  The
+ * converged solutions are snapshots: a greedy reduced basis of n_basis
+ * orthonormal vectors is built from them, and a multilayer perceptron
+ * (three tanh hidden layers of `hidden` units, BF16 weights, FP32
+ * accumulation, Adam) is trained to map the features (E, on-shell
+ * momentum and its position on the spectator grid, entrance channel,
+ * multipliers) to the snapshot coefficients.
+ * The multipliers are restored to 1 at the end.  Limits: n_basis 1..128,
+ * hidden 16..512, n_mult = n_terms, all multipliers finite and > 0.      */
+typedef struct {
+    int32_t n_var, n_mult;
+    const double *mult;      /* [n_var][n_mult] */
+    int32_t n_E;
+    const double *E;         /* [n_var][n_E] */
+    int32_t precision;       /* wpcd_precision of the training solves */
+    int32_t n_basis;         /* reduced-basis size */
+    int32_t hidden;          /* hidden width (default 256 when <= 0) */
+    int32_t epochs;          /* passes over the samples (default 400) */
+    int32_t batch;           /* minibatch size (default 64) */
+    double lr;               /* Adam step size (default 2e-3), cosine decay to lr/20 */
+    uint64_t seed;           /* weight initialisation and minibatch order */
+    const wpcd_solve_opts *solve;   /* may be NULL */
+} wpcd_learn_desc;
+
+typedef struct {
+    int32_t n_samples;       /* converged solves that entered the training set */
+    int32_t plain_iters;     /* Krylov iterations of those solves, summed */
+    double basis_max_rel_err;   /* max over samples of |u - Phi Phi^H u| / |u| */
+    double basis_mean_rel_err;
+    double loss_first, loss_last;   /* training loss of the first / last epoch */
+    double solve_ms, basis_ms, train_ms;
+} wpcd_learn_report;
 
 /* Per-kernel timing (milliseconds summed over launches since the last
  * reset, measured with HIP events on the stream the kernels run on).    */
@@ -165,6 +224,30 @@ wpcd_status wpcd_get_p(wpcd_ctx *ctx, int64_t *row_ptr, int32_t *col, double *va
 wpcd_status wpcd_solve(wpcd_ctx *ctx, const double *E, int32_t n_E, wpcd_precision prec,
                        const wpcd_solve_opts *opts, wpcd_energy_result *out,
                        double *breakup_out);
+
+/* Multiply the strengths of the current potential term by term by
+ * mult[0..n_mult) (n_mult = n_terms; the multipliers are relative to the
+ * potential given last) and re-diagonalise the pair waves; P0 stays valid.
+ * These multipliers are features of the learned warm start.
+ * Errors: WPCD_E_STATE, WPCD_E_INVALID.                                   */
+wpcd_status wpcd_set_multipliers(wpcd_ctx *ctx, const double *mult, int32_t n_mult);
+
+/* Build the learned warm start (see wpcd_learn_desc); report may be NULL.
+ * Errors: WPCD_E_STATE (no P0), WPCD_E_INVALID, WPCD_E_NOMEM (snapshots
+ * take n_var*n_E*M*8 bytes of device memory), WPCD_E_DEVICE.             */
+wpcd_status wpcd_learn_train(wpcd_ctx *ctx, const wpcd_learn_desc *desc,
+                             wpcd_learn_report *report);
+
+/* One forward and backward pass of the warm-start network's kernels on
+ * caller data, for checking them.  params: FP32 [W1 b1 W2 b2 W3 b3 W4 b4],
+ * W_l row-major (out x in), layer widths n_in -> n_hidden (x3) -> n_out;
+ * the weights are rounded to BF16 as in training (biases stay FP32).
+ * X[batch][n_in], T[batch][n_out].  Outputs (any may be NULL): Y[batch]
+ * [n_out], grad (same layout as params) of loss = sum (Y - T)^2 / batch,
+ * *loss_out.  Does not touch a trained model.  Errors: WPCD_E_INVALID.   */
+wpcd_status wpcd_mlp_eval(wpcd_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                          const float *params, int32_t batch, const float *X, const float *T,
+                          float *Y_out, float *grad_out, double *loss_out);
 
 /* Kernel timing with HIP events recorded on the context's stream around
  * each launch.  enable is a bit mask of kernel groups: WPCD_TIME_PAIR (pair

@@ -30,12 +30,16 @@ WPCD_TIME_PAIR = 1
 WPCD_TIME_P0 = 2
 WPCD_TIME_SOLVE = 4
 WPCD_TIME_ALL = 7
+WPCD_WARM_NONE = 0
+WPCD_WARM_LEARNED = 1
+WPCD_WARM_GIVEN = 2
 
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_CONVERGED",
                 5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE"}
 
 ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_set_potential", "wpcd_pair_spectrum",
-                 "wpcd_build_p", "wpcd_get_p", "wpcd_solve", "wpcd_set_timing",
+                 "wpcd_build_p", "wpcd_get_p", "wpcd_solve", "wpcd_set_multipliers",
+                 "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_timing",
                  "wpcd_get_timing", "wpcd_reset_timing", "wpcd_synchronize", "wpcd_last_error",
                  "wpcd_destroy")
 
@@ -60,7 +64,8 @@ class wpcd_potential_desc(ctypes.Structure):
 
 class wpcd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("krylov_dim", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("want_breakup", ctypes.c_int32)]
+                ("tol", ctypes.c_double), ("want_breakup", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("x0", ctypes.POINTER(ctypes.c_double))]
 
 
 class wpcd_energy_result(ctypes.Structure):
@@ -71,7 +76,25 @@ class wpcd_energy_result(ctypes.Structure):
                 ("A_re", ctypes.c_double), ("A_im", ctypes.c_double),
                 ("S_re", ctypes.c_double), ("S_im", ctypes.c_double),
                 ("delta", ctypes.c_double), ("eta", ctypes.c_double),
-                ("residual", ctypes.c_double)]
+                ("residual", ctypes.c_double), ("warm", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("r0", ctypes.c_double)]
+
+
+class wpcd_learn_desc(ctypes.Structure):
+    _fields_ = [("n_var", ctypes.c_int32), ("n_mult", ctypes.c_int32),
+                ("mult", ctypes.POINTER(ctypes.c_double)), ("n_E", ctypes.c_int32),
+                ("E", ctypes.POINTER(ctypes.c_double)), ("precision", ctypes.c_int32),
+                ("n_basis", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("solve", ctypes.POINTER(wpcd_solve_opts))]
+
+
+class wpcd_learn_report(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int32), ("plain_iters", ctypes.c_int32),
+                ("basis_max_rel_err", ctypes.c_double), ("basis_mean_rel_err", ctypes.c_double),
+                ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("basis_ms", ctypes.c_double),
+                ("train_ms", ctypes.c_double)]
 
 
 class wpcd_kernel_time(ctypes.Structure):
@@ -108,6 +131,12 @@ def lib():
         L.wpcd_solve.argtypes = [vp, dp, ctypes.c_int32, ctypes.c_int,
                                  ctypes.POINTER(wpcd_solve_opts),
                                  ctypes.POINTER(wpcd_energy_result), dp]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.wpcd_set_multipliers.argtypes = [vp, dp, ctypes.c_int32]
+        L.wpcd_learn_train.argtypes = [vp, ctypes.POINTER(wpcd_learn_desc),
+                                       ctypes.POINTER(wpcd_learn_report)]
+        L.wpcd_mlp_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, fp,
+                                    ctypes.c_int32, fp, fp, fp, fp, dp]
         L.wpcd_set_timing.argtypes = [vp, ctypes.c_int32]
         L.wpcd_get_timing.argtypes = [vp, ctypes.POINTER(wpcd_kernel_time), ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int32)]
@@ -199,11 +228,24 @@ def wpcd_get_p(ctx, n_cells, nnz, n_ch=1, values=True):
     return row_ptr, col, val
 
 
+def _opts(max_iter=0, krylov_dim=0, tol=0.0, want_breakup=False, warm_start=WPCD_WARM_NONE,
+          x0=None):
+    return wpcd_solve_opts(max_iter, krylov_dim, tol, 1 if want_breakup else 0, warm_start,
+                           _dp(x0))
+
+
 def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0,
-               want_breakup=False, n_p=0, n_ch=1):
+               want_breakup=False, n_p=0, n_ch=1, warm_start=WPCD_WARM_NONE, x0=None):
+    """x0 (warm_start=WPCD_WARM_GIVEN): complex array [n_E][M]."""
     E = np.ascontiguousarray(energies, dtype=np.float64)
     out = (wpcd_energy_result * max(1, E.size))()
-    opts = wpcd_solve_opts(max_iter, krylov_dim, tol, 1 if want_breakup else 0)
+    x0r = None
+    if x0 is not None:
+        x0c = np.ascontiguousarray(x0, dtype=np.complex128)
+        if x0c.ndim != 2 or x0c.shape[0] != E.size:
+            raise ValueError("x0 must be [n_E][M] complex")
+        x0r = x0c.view(np.float64).reshape(-1)
+    opts = _opts(max_iter, krylov_dim, tol, want_breakup, warm_start, x0r)
     br = np.zeros(E.size * max(1, n_p) * n_ch * 5) if want_breakup else None
     _check(ctx, lib().wpcd_solve(ctx, _dp(E), E.size, precision, ctypes.byref(opts), out,
                                  _dp(br)))
@@ -215,6 +257,44 @@ def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol
             brs.append(rows.copy())
         return res, brs
     return res
+
+
+def wpcd_set_multipliers(ctx, mult):
+    m = np.ascontiguousarray(mult, dtype=np.float64)
+    _check(ctx, lib().wpcd_set_multipliers(ctx, _dp(m), m.size))
+
+
+def wpcd_learn_train(ctx, mult, energies, precision=WPCD_FP64, n_basis=32, hidden=256,
+                     epochs=400, batch=64, lr=2e-3, seed=1508074410, solve_opts=None):
+    """mult: [n_var][n_mult]; energies: [n_var][n_E].  Returns the report as a dict."""
+    m = np.ascontiguousarray(mult, dtype=np.float64)
+    E = np.ascontiguousarray(energies, dtype=np.float64)
+    if m.ndim != 2 or E.ndim != 2 or m.shape[0] != E.shape[0]:
+        raise ValueError("mult [n_var][n_mult] and energies [n_var][n_E] expected")
+    so = _opts(**(solve_opts or {}))
+    d = wpcd_learn_desc(m.shape[0], m.shape[1], _dp(m), E.shape[1], _dp(E), precision, n_basis,
+                        hidden, epochs, batch, lr, seed, ctypes.pointer(so))
+    r = wpcd_learn_report()
+    _check(ctx, lib().wpcd_learn_train(ctx, ctypes.byref(d), ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in r._fields_}
+
+
+def wpcd_mlp_eval(ctx, n_in, n_hidden, n_out, params, X, T=None, want_grad=True):
+    """One forward/backward of the network kernels; returns (Y, grad, loss)."""
+    fp = ctypes.POINTER(ctypes.c_float)
+    P = np.ascontiguousarray(params, dtype=np.float32)
+    Xa = np.ascontiguousarray(X, dtype=np.float32)
+    B = Xa.shape[0]
+    Ta = None if T is None else np.ascontiguousarray(T, dtype=np.float32)
+    Y = np.zeros((B, n_out), dtype=np.float32)
+    G = np.zeros(P.size, dtype=np.float32) if (Ta is not None and want_grad) else None
+    loss = np.zeros(1) if Ta is not None else None
+
+    def f(a):
+        return None if a is None else a.ctypes.data_as(fp)
+    _check(ctx, lib().wpcd_mlp_eval(ctx, n_in, n_hidden, n_out, f(P), B, f(Xa), f(Ta), f(Y), f(G),
+                                    _dp(loss)))
+    return Y, G, (None if loss is None else float(loss[0]))
 
 
 def wpcd_set_timing(ctx, groups=WPCD_TIME_ALL):
@@ -274,6 +354,15 @@ class Context:
 
     def solve(self, energies, precision=WPCD_FP64, **kw):
         return wpcd_solve(self.h, energies, precision, n_p=self.n_p, n_ch=self.n_ch, **kw)
+
+    def set_multipliers(self, mult):
+        wpcd_set_multipliers(self.h, mult)
+
+    def learn_train(self, mult, energies, **kw):
+        return wpcd_learn_train(self.h, mult, energies, **kw)
+
+    def mlp_eval(self, n_in, n_hidden, n_out, params, X, T=None, want_grad=True):
+        return wpcd_mlp_eval(self.h, n_in, n_hidden, n_out, params, X, T, want_grad)
 
     def set_timing(self, groups=WPCD_TIME_ALL):
         wpcd_set_timing(self.h, groups)

@@ -5,7 +5,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["wpcd_api.hip", "wpcd_coupling.hip", "k_pair.hip", "k_p0.hip", "k_solve.hip"]
+SRC = ["wpcd_api.hip", "wpcd_coupling.hip", "k_pair.hip", "k_p0.hip", "k_solve.hip",
+       "k_mlp.hip", "wpcd_learn.hip"]
 OUT = os.path.join(HERE, "libwpcd.so")
 
 

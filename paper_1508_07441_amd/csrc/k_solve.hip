@@ -590,6 +590,44 @@ __global__ void k_amplitudes(const double *__restrict__ x, int nE, const int64_t
     out[4 * t + 3] = -2.0 * M_PI * f * ur;
 }
 
+// Warm-start judge: alpha[e] = <r, b> / |r|^2 with r = (1 - K) x0, the
+// scaling of x0 that minimises |b - alpha r|; 0 when |r|^2 is zero or
+// anything is not finite.  rb: <r, b> (complex), rr: |r|^2 (real part).
+__global__ void k_warm_alpha(const double *__restrict__ rb, const double *__restrict__ rr, int nE,
+                             double *__restrict__ alpha) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nE) return;
+    const double n2 = rr[2 * e];
+    const double ar = rb[2 * e] / n2, ai = rb[2 * e + 1] / n2;
+    const bool ok = n2 > 0.0 && isfinite(n2) && isfinite(ar) && isfinite(ai);
+    alpha[2 * e] = ok ? ar : 0.0;
+    alpha[2 * e + 1] = ok ? ai : 0.0;
+}
+
+// x = alpha x, r = b - alpha r; alpha = 0 gives x = 0 and r = b exactly,
+// whatever x and r held (NaN included).
+__global__ void k_warm_apply(const double *__restrict__ alpha, int64_t M, int nE,
+                             const double *__restrict__ b, double *__restrict__ x,
+                             double *__restrict__ r) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * nE) return;
+    const int e = (int)(idx % nE);
+    const double ar = alpha[2 * e], ai = alpha[2 * e + 1];
+    if (ar == 0.0 && ai == 0.0) {
+        x[2 * idx] = 0.0;
+        x[2 * idx + 1] = 0.0;
+        r[2 * idx] = b[2 * idx];
+        r[2 * idx + 1] = b[2 * idx + 1];
+        return;
+    }
+    const double xr = x[2 * idx], xi = x[2 * idx + 1];
+    x[2 * idx] = ar * xr - ai * xi;
+    x[2 * idx + 1] = ar * xi + ai * xr;
+    const double rr = r[2 * idx], ri = r[2 * idx + 1];
+    r[2 * idx] = b[2 * idx] - (ar * rr - ai * ri);
+    r[2 * idx + 1] = b[2 * idx + 1] - (ar * ri + ai * rr);
+}
+
 // ----------------------------------------------------------------- host
 namespace {
 
@@ -721,11 +759,12 @@ void vupdate(Batch &b, int nvec, double *w) {
 }  // namespace
 
 // Solve the batch of energies already validated by the caller.
-// idx0/rho0: entrance row and flux factor per energy.  Returns iterations
-// and relative residual per energy in iters/resid.
+// idx0: entrance row per energy.
 void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
-                 bool fp64, int m, int max_iter, double tol, std::vector<int> &iters,
-                 std::vector<double> &resid, std::vector<int> &edge_flag) {
+                 bool fp64, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
+                 GmresOut &out) {
+    std::vector<int> &iters = out.iters, &edge_flag = out.edge;
+    std::vector<double> &resid = out.resid;
     const int nE = (int)E.size();
     Batch b{};
     b.c = c;
@@ -809,9 +848,37 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     std::vector<double> st(nE * kSt, 0.0);
     for (int e = 0; e < nE; ++e) st[e * kSt + 1] = std::sqrt(h0[2 * e]);
     WPCD_HIP(hipMemcpyAsync(b.S.st, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    // x = 0, r = b
-    WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
-    WPCD_HIP(hipMemcpyAsync(b.R, b.B, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+    out.warm.assign(nE, 0);
+    out.r0.assign(nE, 1.0);
+    if (warm) {
+        // proposed x0, judged by the minimal initial residual over its scalings
+        warm(c, warm_user, b.X, nE);
+        op_apply(b, b.X, b.R, true, true);
+        dots(b, b.R, 1, b.B, b.h, nullptr, 0, 0);
+        dots(b, b.R, 1, b.R, b.h + 2 * nE, nullptr, 0, 0);
+        {
+            TimedLaunch tl(c->timer, s, "warm_judge", WPCD_TIME_SOLVE);
+            hipLaunchKernelGGL(k_warm_alpha, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.h, b.h + 2 * nE,
+                               nE, b.y);
+            hipLaunchKernelGGL(k_warm_apply, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.y, b.M,
+                               nE, b.B, b.X, b.R);
+            WPCD_HIP(hipGetLastError());
+        }
+        dots(b, b.R, 1, b.R, b.h, nullptr, 0, 0);
+        std::vector<double> al(2 * nE), rr(2 * nE);
+        WPCD_HIP(hipMemcpyAsync(al.data(), b.y, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
+        WPCD_HIP(hipMemcpyAsync(rr.data(), b.h, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
+        WPCD_HIP(hipStreamSynchronize(s));
+        for (int e = 0; e < nE; ++e) {
+            out.warm[e] = (al[2 * e] != 0.0 || al[2 * e + 1] != 0.0) ? 1 : 0;
+            const double bn = st[e * kSt + 1];
+            out.r0[e] = bn > 0 ? std::sqrt(std::max(rr[2 * e], 0.0)) / bn : 0.0;
+        }
+    } else {
+        // x = 0, r = b
+        WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
+        WPCD_HIP(hipMemcpyAsync(b.R, b.B, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
 
     iters.assign(nE, 0);
     resid.assign(nE, 1.0);

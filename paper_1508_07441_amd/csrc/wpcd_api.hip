@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -11,13 +12,6 @@
 #include "wpcd_internal.h"
 
 namespace wpcd {
-
-void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
-                 bool fp64, int m, int max_iter, double tol, std::vector<int> &iters,
-                 std::vector<double> &resid, std::vector<int> &edge_flag);
-void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
-                      const std::vector<int32_t> &ens, const std::vector<double> &rho,
-                      const std::vector<double> &rho0, std::vector<double> &out);
 
 // ------------------------------------------------------------ timing
 int Timer::id_of(const char *name) {
@@ -234,6 +228,8 @@ static void set_potential_desc(wpcd_ctx *c, const wpcd_potential_desc *pot) {
     }
     c->pot_kind = pot->kind;
     c->pot_s.assign(pot->strength, pot->strength + pot->n_terms);
+    c->pot_base = c->pot_s;
+    c->pot_mult.assign(pot->n_terms, 1.0);
     c->pot_mu.assign(pot->range, pot->range + pot->n_terms);
     c->pot_scale = 1.0;
 }
@@ -312,6 +308,22 @@ static void fit_scale(wpcd_ctx *c, double target) {
     c->pot_scale = sig;
 }
 
+static void set_multipliers(wpcd_ctx *c, const double *mult, int n) {
+    WPCD_REQUIRE(mult, WPCD_E_INVALID, "multipliers NULL");
+    WPCD_REQUIRE(n == (int)c->pot_base.size(), WPCD_E_INVALID,
+                 "one multiplier per potential term is required");
+    for (int k = 0; k < n; ++k)
+        WPCD_REQUIRE(std::isfinite(mult[k]) && mult[k] > 0.0, WPCD_E_INVALID,
+                     "multipliers must be finite and > 0");
+    for (int k = 0; k < n; ++k) {
+        c->pot_mult[k] = mult[k];
+        c->pot_s[k] = c->pot_base[k] * mult[k];
+    }
+    c->has_pot = false;
+    diagonalise_all(c);
+    c->has_pot = true;
+}
+
 static void build_pair_waves(wpcd_ctx *c, const wpcd_potential_desc *pot) {
     set_potential_desc(c, pot);
     if (!std::isnan(pot->fit_e2)) {
@@ -320,6 +332,456 @@ static void build_pair_waves(wpcd_ctx *c, const wpcd_potential_desc *pot) {
     }
     diagonalise_all(c);
     c->has_pot = true;
+}
+
+// Features of one energy for the warm-start network: E, on-shell momentum,
+// its position on the spectator grid (bin index plus fraction, and the
+// fraction alone: the driving term changes with the bin), the entrance
+// channel and the potential multipliers.
+static int learn_features(const wpcd_ctx *c, double E, double q0, int j0, int a0, double *f) {
+    const double frac = (q0 - c->q[j0]) / (c->q[j0 + 1] - c->q[j0]);
+    f[0] = E;
+    f[1] = q0;
+    f[2] = j0 + frac;
+    f[3] = frac;
+    f[4] = a0;
+    const int nm = (int)c->pot_mult.size();
+    for (int k = 0; k < nm; ++k) f[5 + k] = c->pot_mult[k];
+    return 5 + nm;
+}
+
+// Converged solutions collected for training.
+struct Collect {
+    float *snaps = nullptr;
+    int64_t n = 0, cap = 0;
+    std::vector<double> feat;   // [n][nfeat]
+    int nfeat = 0;
+    int64_t iters = 0;
+};
+
+// Initial vectors for one GMRES batch.
+struct WarmCtx {
+    int kind = WPCD_WARM_NONE;
+    std::vector<float> feat;               // learned: normalised features [nb][nfeat]
+    std::vector<const double *> given;     // given: caller vector per energy
+};
+
+static void warm_fill(wpcd_ctx *c, void *user, double *x, int nE) {
+    WarmCtx &w = *(WarmCtx *)user;
+    const int64_t M = (int64_t)c->nch * c->nq * c->np;
+    if (w.kind == WPCD_WARM_LEARNED) {
+        Learned &L = c->learned;
+        L.feat.reserve(w.feat.size());
+        WPCD_HIP(hipMemcpyAsync(L.feat.ptr, w.feat.data(), w.feat.size() * sizeof(float),
+                                hipMemcpyHostToDevice, c->stream));
+        const float *y = mlp_forward(L.mlp, c->stream, c->timer, L.feat.ptr, nE);
+        learn_lift(c, y, nE, x);
+    } else {
+        // stage the caller's vectors in the residual buffer (free until the
+        // judge overwrites it), then interleave them into the batch layout
+        double *stage = c->d_W.ptr;
+        for (int e = 0; e < nE; ++e)
+            WPCD_HIP(hipMemcpyAsync(stage + (int64_t)e * M * 2, w.given[e], M * 2 * sizeof(double),
+                                    hipMemcpyHostToDevice, c->stream));
+        learn_interleave(c, stage, nE, M, x);
+    }
+}
+
+// Steps 3-4 for a list of energies; collect, if given, receives the
+// converged solutions and their features.
+static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision prec,
+                       const wpcd_solve_opts *opts, wpcd_energy_result *out, double *breakup_out,
+                       Collect *collect) {
+    WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
+                 "build_basis and build_p must come first");
+    WPCD_REQUIRE(E && out && n_E >= 0, WPCD_E_INVALID, "E/out NULL or n_E < 0");
+    WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
+    WPCD_REQUIRE(prec == WPCD_MIXED || c->p_fp64, WPCD_E_STATE, "FP64 solve needs an FP64 P0 build");
+    WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE, "mixed solve needs a mixed P0 build");
+    int m = 48, max_iter = 400;
+    // FP32 storage of P0 perturbs the operator at the 1e-7 level: a mixed
+    // solve gains nothing below 1e-9
+    double tol = prec == WPCD_MIXED ? 1e-9 : 1e-12;
+    int want_breakup = 0, warm_kind = WPCD_WARM_NONE;
+    if (opts) {
+        if (opts->krylov_dim > 0) m = opts->krylov_dim;
+        if (opts->max_iter > 0) max_iter = opts->max_iter;
+        if (opts->tol > 0) tol = opts->tol;
+        want_breakup = opts->want_breakup;
+        warm_kind = opts->warm_start;
+    }
+    WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
+    WPCD_REQUIRE(warm_kind >= WPCD_WARM_NONE && warm_kind <= WPCD_WARM_GIVEN, WPCD_E_INVALID,
+                 "warm_start must be a WPCD_WARM_* value");
+    const int64_t M = (int64_t)c->nch * c->nq * c->np;
+    if (warm_kind == WPCD_WARM_GIVEN) WPCD_REQUIRE(opts->x0, WPCD_E_INVALID, "x0 is NULL");
+    if (warm_kind == WPCD_WARM_LEARNED)
+        WPCD_REQUIRE(c->learned.ready && c->learned.M == M &&
+                         c->learned.n_mult == (int)c->pot_mult.size(),
+                     WPCD_E_STATE, "no learned warm start for this basis and potential");
+    // entrance channel: l = 0, lam = L
+    int a0 = -1;
+    for (int a = 0; a < c->nch; ++a)
+        if (c->ch_l[a] == 0 && c->ch_lam[a] == c->L) {
+            a0 = a;
+            break;
+        }
+    WPCD_REQUIRE(a0 >= 0, WPCD_E_INVALID, "no entrance channel (l = 0, lam = L)");
+    const double eb = c->waves[c->ch_wave[a0]].h_eps[0];
+    const double qmax = c->q[c->nq];
+    std::vector<wpcd_energy_result> res(n_E);
+    std::vector<int> active;
+    std::vector<int64_t> idx0v;
+    std::vector<double> rho0v;
+    for (int e = 0; e < n_E; ++e) {
+        wpcd_energy_result &r = res[e];
+        std::memset(&r, 0, sizeof(r));
+        r.E = E[e];
+        r.status = WPCD_OK;
+        r.r0 = 1.0;
+        if (!std::isfinite(E[e])) {
+            r.status = WPCD_E_INVALID;
+            continue;
+        }
+        if (E[e] <= eb) {
+            r.status = WPCD_E_BELOW_THRESHOLD;
+            continue;
+        }
+        const double q0 = std::sqrt(4.0 * (E[e] - eb) / 3.0);
+        r.q0 = q0;
+        if (q0 >= qmax) {
+            r.status = WPCD_E_INVALID;
+            continue;
+        }
+        const int j0 = (int)(std::upper_bound(c->q.begin(), c->q.end(), q0) - c->q.begin()) - 1;
+        r.j0 = j0;
+        active.push_back(e);
+        idx0v.push_back(((int64_t)a0 * c->nq + j0) * c->np);
+        rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
+    }
+    const int kBatch = 32;
+    for (size_t b0 = 0; b0 < active.size(); b0 += kBatch) {
+        const int nb = (int)std::min(active.size() - b0, (size_t)kBatch);
+        std::vector<double> Eb(nb), rho0(nb);
+        std::vector<int64_t> idx0(nb);
+        for (int t = 0; t < nb; ++t) {
+            Eb[t] = E[active[b0 + t]];
+            idx0[t] = idx0v[b0 + t];
+            rho0[t] = rho0v[b0 + t];
+        }
+        WarmCtx wc;
+        wc.kind = warm_kind;
+        if (warm_kind == WPCD_WARM_LEARNED) {
+            const Learned &L = c->learned;
+            double f[kMaxFeat];
+            for (int t = 0; t < nb; ++t) {
+                const int e = active[b0 + t];
+                learn_features(c, Eb[t], res[e].q0, res[e].j0, a0, f);
+                for (int k = 0; k < L.nfeat; ++k)
+                    wc.feat.push_back((float)((f[k] - L.feat_mu[k]) / L.feat_sd[k]));
+            }
+        } else if (warm_kind == WPCD_WARM_GIVEN) {
+            for (int t = 0; t < nb; ++t) wc.given.push_back(opts->x0 + (size_t)active[b0 + t] * M * 2);
+        }
+        GmresOut go;
+        gmres_batch(c, Eb, idx0, prec == WPCD_FP64, m, max_iter, tol,
+                    warm_kind == WPCD_WARM_NONE ? nullptr : warm_fill, &wc, go);
+        // amplitude list: elastic first, then open breakup pseudostates
+        std::vector<int64_t> rows;
+        std::vector<int32_t> ens;
+        std::vector<double> rho;
+        std::vector<int> first_br(nb), n_br(nb);
+        for (int t = 0; t < nb; ++t) {
+            rows.push_back(idx0[t]);
+            ens.push_back(t);
+            rho.push_back(rho0[t]);
+        }
+        for (int t = 0; t < nb; ++t) {
+            first_br[t] = (int)rows.size();
+            n_br[t] = 0;
+            for (int a = 0; a < c->nch; ++a) {
+                const std::vector<double> &ev = c->waves[c->ch_wave[a]].h_eps;
+                for (int k = 0; k < c->np; ++k) {
+                    if ((a == a0 && k == 0) || !(ev[k] < Eb[t])) continue;
+                    const double qk = std::sqrt(4.0 * (Eb[t] - ev[k]) / 3.0);
+                    if (qk >= qmax) continue;
+                    const int jk =
+                        (int)(std::upper_bound(c->q.begin(), c->q.end(), qk) - c->q.begin()) - 1;
+                    rows.push_back(((int64_t)a * c->nq + jk) * c->np + k);
+                    ens.push_back(t);
+                    rho.push_back(2.0 / (3.0 * qk * (c->q[jk + 1] - c->q[jk])));
+                    ++n_br[t];
+                }
+            }
+        }
+        std::vector<double> amp;
+        amplitudes_batch(c, nb, rows, ens, rho, rho0, amp);
+        std::vector<int> ok;
+        for (int t = 0; t < nb; ++t) {
+            const int e = active[b0 + t];
+            wpcd_energy_result &r = res[e];
+            r.iters = go.iters[t];
+            r.residual = go.resid[t];
+            r.warm = go.warm[t];
+            r.r0 = go.r0[t];
+            if (go.edge[t]) {
+                r.status = WPCD_E_ON_EDGE;
+                continue;
+            }
+            if (!(go.resid[t] <= tol * 10.0)) r.status = WPCD_E_NOT_CONVERGED;
+            r.U_re = amp[4 * t];
+            r.U_im = amp[4 * t + 1];
+            r.A_re = rho0[t] * r.U_re;
+            r.A_im = rho0[t] * r.U_im;
+            r.S_re = 1.0 + amp[4 * t + 2];
+            r.S_im = amp[4 * t + 3];
+            r.delta = 0.5 * std::atan2(r.S_im, r.S_re);
+            r.eta = std::hypot(r.S_re, r.S_im);
+            r.n_open = n_br[t];
+            if (r.status == WPCD_OK) ok.push_back(t);
+            if (breakup_out && want_breakup) {
+                double *dst = breakup_out + (size_t)e * c->np * c->nch * 5;
+                for (int u = 0; u < n_br[t]; ++u) {
+                    const int row = first_br[t] + u;
+                    const int64_t rr = rows[row];
+                    const int a = (int)(rr / ((int64_t)c->nq * c->np));
+                    const int jk = (int)((rr / c->np) % c->nq);
+                    const int k = (int)(rr % c->np);
+                    dst[5 * u + 0] = a;
+                    dst[5 * u + 1] = k;
+                    dst[5 * u + 2] = jk;
+                    dst[5 * u + 3] = amp[4 * row + 2];
+                    dst[5 * u + 4] = amp[4 * row + 3];
+                }
+            }
+        }
+        if (collect && !ok.empty()) {
+            WPCD_REQUIRE(collect->n + (int64_t)ok.size() <= collect->cap, WPCD_E_INVALID,
+                         "snapshot store full");
+            learn_snap_store(c, collect->snaps, collect->n, c->d_X.ptr, nb, ok);
+            double f[kMaxFeat];
+            for (int t : ok) {
+                const int e = active[b0 + t];
+                collect->nfeat = learn_features(c, Eb[t], res[e].q0, res[e].j0, a0, f);
+                collect->feat.insert(collect->feat.end(), f, f + collect->nfeat);
+                collect->iters += go.iters[t];
+            }
+            collect->n += (int64_t)ok.size();
+        }
+    }
+    for (int e = 0; e < n_E; ++e) out[e] = res[e];
+}
+
+static uint64_t splitmix_next(uint64_t &st) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Training of the learned warm start (see wpcd_learn_desc).
+static void learn_train(wpcd_ctx *c, const wpcd_learn_desc *d, wpcd_learn_report *rep) {
+    WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
+                 "build_basis and build_p must come first");
+    WPCD_REQUIRE(d, WPCD_E_INVALID, "learn descriptor is NULL");
+    const int nm = (int)c->pot_base.size();
+    WPCD_REQUIRE(d->n_var >= 1 && d->n_E >= 1 && d->mult && d->E, WPCD_E_INVALID,
+                 "need n_var >= 1, n_E >= 1, mult and E");
+    WPCD_REQUIRE(d->n_mult == nm, WPCD_E_INVALID, "n_mult must equal the potential's n_terms");
+    WPCD_REQUIRE(d->n_basis >= 1 && d->n_basis <= 128, WPCD_E_INVALID, "n_basis must be 1..128");
+    const int hidden = d->hidden > 0 ? d->hidden : 256;
+    WPCD_REQUIRE(hidden >= 16 && hidden <= 512, WPCD_E_INVALID, "hidden must be 16..512");
+    const int epochs = d->epochs > 0 ? d->epochs : 400;
+    const int bsz_req = d->batch > 0 ? d->batch : 64;
+    const double lr = d->lr > 0 ? d->lr : 2e-3;
+    WPCD_REQUIRE(std::isfinite(lr), WPCD_E_INVALID, "lr must be finite");
+    WPCD_REQUIRE(d->precision == WPCD_FP64 || d->precision == WPCD_MIXED, WPCD_E_INVALID,
+                 "bad precision");
+    for (int64_t k = 0; k < (int64_t)d->n_var * nm; ++k)
+        WPCD_REQUIRE(std::isfinite(d->mult[k]) && d->mult[k] > 0.0, WPCD_E_INVALID,
+                     "multipliers must be finite and > 0");
+    hipStream_t s = c->stream;
+    Learned &L = c->learned;
+    L.release();
+    const int64_t M = (int64_t)c->nch * c->nq * c->np;
+    wpcd_solve_opts so{};
+    if (d->solve) so = *d->solve;
+    so.warm_start = WPCD_WARM_NONE;
+    so.x0 = nullptr;
+    so.want_breakup = 0;
+
+    // 1. plain solves over the variants; converged solutions become snapshots
+    auto t0 = std::chrono::steady_clock::now();
+    DBuf<float> snaps;
+    Collect col;
+    col.cap = (int64_t)d->n_var * d->n_E;
+    snaps.reserve((size_t)col.cap * M * 2);
+    col.snaps = snaps.ptr;
+    std::vector<wpcd_energy_result> res(d->n_E);
+    const std::vector<double> ones(nm, 1.0);
+    try {
+        for (int v = 0; v < d->n_var; ++v) {
+            set_multipliers(c, d->mult + (size_t)v * nm, nm);
+            solve_impl(c, d->E + (size_t)v * d->n_E, d->n_E, (wpcd_precision)d->precision, &so,
+                       res.data(), nullptr, &col);
+        }
+    } catch (...) {
+        set_multipliers(c, ones.data(), nm);
+        throw;
+    }
+    set_multipliers(c, ones.data(), nm);
+    const double solve_ms = ms_since(t0);
+    const int n = (int)col.n;
+    WPCD_REQUIRE(n >= 1, WPCD_E_INVALID, "no training solve converged");
+
+    // 2. greedy reduced basis and the coefficient targets
+    t0 = std::chrono::steady_clock::now();
+    std::vector<double> coef;
+    double max_err = 0.0, mean_err = 0.0;
+    learn_build_basis(c, snaps.ptr, n, std::min(d->n_basis, n), coef, max_err, mean_err);
+    snaps.release();
+    const int K = L.K;
+    WPCD_REQUIRE(K >= 1, WPCD_E_INVALID, "empty reduced basis");
+    const double basis_ms = ms_since(t0);
+
+    // 3. network: normalised features -> coefficients / coef_scale
+    t0 = std::chrono::steady_clock::now();
+    const int nf = col.nfeat;
+    L.nfeat = nf;
+    L.n_mult = nm;
+    for (int k = 0; k < nf; ++k) {
+        double mu = 0.0, sd = 0.0;
+        for (int i = 0; i < n; ++i) mu += col.feat[(size_t)i * nf + k] / n;
+        for (int i = 0; i < n; ++i) {
+            const double dv = col.feat[(size_t)i * nf + k] - mu;
+            sd += dv * dv / n;
+        }
+        sd = std::sqrt(sd);
+        L.feat_mu[k] = mu;
+        L.feat_sd[k] = sd > 1e-12 * std::max(1.0, std::fabs(mu)) ? sd : 1.0;
+    }
+    double c2 = 0.0;
+    for (double x : coef) c2 += x * x;
+    L.coef_scale = c2 > 0 ? std::sqrt(c2 / coef.size()) : 1.0;
+    const int nout = 2 * K;
+    std::vector<float> Xh((size_t)n * nf), Th((size_t)n * nout);
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < nf; ++k)
+            Xh[(size_t)i * nf + k] = (float)((col.feat[(size_t)i * nf + k] - L.feat_mu[k]) / L.feat_sd[k]);
+        for (int k = 0; k < K; ++k) {
+            Th[(size_t)i * nout + 2 * k] = (float)(coef[2 * ((size_t)k * n + i)] / L.coef_scale);
+            Th[(size_t)i * nout + 2 * k + 1] = (float)(coef[2 * ((size_t)k * n + i) + 1] / L.coef_scale);
+        }
+    }
+    DBuf<float> dX, dT, bX, bT;
+    DBuf<int32_t> dperm;
+    dX.reserve(Xh.size());
+    dT.reserve(Th.size());
+    const int bsz = std::min(bsz_req, n);
+    bX.reserve((size_t)bsz * nf);
+    bT.reserve((size_t)bsz * nout);
+    dperm.reserve(n);
+    WPCD_HIP(hipMemcpyAsync(dX.ptr, Xh.data(), Xh.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    WPCD_HIP(hipMemcpyAsync(dT.ptr, Th.data(), Th.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    Mlp &net = L.mlp;
+    mlp_init(net, s, nf, hidden, nout, d->seed);
+    const double loss_first = mlp_loss_grad(net, s, c->timer, dX.ptr, dT.ptr, n, true);
+    std::vector<int32_t> perm(n);
+    uint64_t st = d->seed ^ 0x5DEECE66Dull;
+    const int nbatch = (n + bsz - 1) / bsz;
+    const int64_t total_steps = (int64_t)epochs * nbatch;
+    int64_t step = 0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = n - 1; i > 0; --i) {
+            const int j = (int)(splitmix_next(st) % (uint64_t)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        WPCD_HIP(hipMemcpyAsync(dperm.ptr, perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        for (int bi = 0; bi < nbatch; ++bi, ++step) {
+            const int first = bi * bsz, cnt = std::min(bsz, n - first);
+            mlp_gather(s, dX.ptr, nf, dperm.ptr + first, cnt, bX.ptr);
+            mlp_gather(s, dT.ptr, nout, dperm.ptr + first, cnt, bT.ptr);
+            mlp_loss_grad(net, s, c->timer, bX.ptr, bT.ptr, cnt, false);
+            const double lr_min = lr / 20.0;
+            const double lr_t =
+                lr_min + 0.5 * (lr - lr_min) * (1.0 + std::cos(M_PI * (double)step / (double)total_steps));
+            mlp_adam_step(net, s, c->timer, (float)lr_t);
+        }
+        // the minibatch order of the next epoch is uploaded only after this
+        // epoch's gathers have run
+        WPCD_HIP(hipStreamSynchronize(s));
+    }
+    const double loss_last = mlp_loss_grad(net, s, c->timer, dX.ptr, dT.ptr, n, true);
+    dX.release();
+    dT.release();
+    bX.release();
+    bT.release();
+    dperm.release();
+    L.ready = true;
+    const double train_ms = ms_since(t0);
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->n_samples = n;
+        rep->plain_iters = (int32_t)col.iters;
+        rep->basis_max_rel_err = max_err;
+        rep->basis_mean_rel_err = mean_err;
+        rep->loss_first = loss_first;
+        rep->loss_last = loss_last;
+        rep->solve_ms = solve_ms;
+        rep->basis_ms = basis_ms;
+        rep->train_ms = train_ms;
+    }
+}
+
+// One forward and backward pass on caller data with a temporary network.
+static void mlp_eval(wpcd_ctx *c, int nin, int nh, int nout, const float *params, int B,
+                     const float *X, const float *T, float *Y_out, float *grad_out,
+                     double *loss_out) {
+    WPCD_REQUIRE(nin >= 1 && nin <= 4096 && nh >= 1 && nh <= 4096 && nout >= 1 && nout <= 4096 &&
+                     B >= 1 && B <= 65536,
+                 WPCD_E_INVALID, "network sizes out of range");
+    WPCD_REQUIRE(params && X, WPCD_E_INVALID, "params/X NULL");
+    WPCD_REQUIRE(T || (!grad_out && !loss_out), WPCD_E_INVALID, "gradients and loss need T");
+    hipStream_t s = c->stream;
+    Mlp net;
+    net.nin = nin;
+    net.nh = nh;
+    net.nout = nout;
+    DBuf<float> dX, dT;
+    try {
+        mlp_set_weights(net, s, params);
+        dX.reserve((size_t)B * nin);
+        WPCD_HIP(hipMemcpyAsync(dX.ptr, X, (size_t)B * nin * sizeof(float), hipMemcpyHostToDevice, s));
+        const float *Y = mlp_forward(net, s, c->timer, dX.ptr, B);
+        if (Y_out)
+            WPCD_HIP(hipMemcpyAsync(Y_out, Y, (size_t)B * nout * sizeof(float), hipMemcpyDeviceToHost, s));
+        WPCD_HIP(hipStreamSynchronize(s));
+        if (T) {
+            dT.reserve((size_t)B * nout);
+            WPCD_HIP(hipMemcpyAsync(dT.ptr, T, (size_t)B * nout * sizeof(float), hipMemcpyHostToDevice, s));
+            const double loss = mlp_loss_grad(net, s, c->timer, dX.ptr, dT.ptr, B, true);
+            if (grad_out)
+                WPCD_HIP(hipMemcpyAsync(grad_out, net.grad.ptr, net.n_params() * sizeof(float),
+                                        hipMemcpyDeviceToHost, s));
+            WPCD_HIP(hipStreamSynchronize(s));
+            if (loss_out) *loss_out = loss;
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        net.release();
+        dX.release();
+        dT.release();
+        throw;
+    }
+    net.release();
+    dX.release();
+    dT.release();
 }
 
 }  // namespace wpcd
@@ -423,6 +885,7 @@ wpcd_status wpcd_build_basis(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_p
         for (int a = 0; same_grid && a < b->n_ch; ++a)
             same_grid = c->ch_l[a] == b->l[a] && c->ch_lam[a] == b->lam[a];
         c->has_basis = false;
+        c->learned.release();
         c->has_pot = false;
         if (!same_grid) c->has_p = false;
         c->np = b->n_p;
@@ -528,145 +991,24 @@ wpcd_status wpcd_get_p(wpcd_ctx *c, int64_t *row_ptr, int32_t *col, double *val)
 
 wpcd_status wpcd_solve(wpcd_ctx *c, const double *E, int32_t n_E, wpcd_precision prec,
                        const wpcd_solve_opts *opts, wpcd_energy_result *out, double *breakup_out) {
+    return guarded(c, [&] { solve_impl(c, E, n_E, prec, opts, out, breakup_out, nullptr); });
+}
+
+wpcd_status wpcd_set_multipliers(wpcd_ctx *c, const double *mult, int32_t n_mult) {
     return guarded(c, [&] {
-        WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
-                     "build_basis and build_p must come first");
-        WPCD_REQUIRE(E && out && n_E >= 0, WPCD_E_INVALID, "E/out NULL or n_E < 0");
-        WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
-        WPCD_REQUIRE(prec == WPCD_MIXED || c->p_fp64, WPCD_E_STATE,
-                     "FP64 solve needs an FP64 P0 build");
-        WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE,
-                     "mixed solve needs a mixed P0 build");
-        int m = 48, max_iter = 400;
-        double tol = 1e-12;
-        int want_breakup = 0;
-        if (opts) {
-            if (opts->krylov_dim > 0) m = opts->krylov_dim;
-            if (opts->max_iter > 0) max_iter = opts->max_iter;
-            if (opts->tol > 0) tol = opts->tol;
-            want_breakup = opts->want_breakup;
-        }
-        WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
-        // entrance channel: l = 0, lam = L
-        int a0 = -1;
-        for (int a = 0; a < c->nch; ++a)
-            if (c->ch_l[a] == 0 && c->ch_lam[a] == c->L) {
-                a0 = a;
-                break;
-            }
-        WPCD_REQUIRE(a0 >= 0, WPCD_E_INVALID, "no entrance channel (l = 0, lam = L)");
-        const double eb = c->waves[c->ch_wave[a0]].h_eps[0];
-        const double qmax = c->q[c->nq];
-        std::vector<wpcd_energy_result> res(n_E);
-        std::vector<int> active;
-        std::vector<int64_t> idx0v;
-        std::vector<double> rho0v;
-        for (int e = 0; e < n_E; ++e) {
-            wpcd_energy_result &r = res[e];
-            std::memset(&r, 0, sizeof(r));
-            r.E = E[e];
-            r.status = WPCD_OK;
-            if (!std::isfinite(E[e])) {
-                r.status = WPCD_E_INVALID;
-                continue;
-            }
-            if (E[e] <= eb) {
-                r.status = WPCD_E_BELOW_THRESHOLD;
-                continue;
-            }
-            const double q0 = std::sqrt(4.0 * (E[e] - eb) / 3.0);
-            r.q0 = q0;
-            if (q0 >= qmax) {
-                r.status = WPCD_E_INVALID;
-                continue;
-            }
-            const int j0 = (int)(std::upper_bound(c->q.begin(), c->q.end(), q0) - c->q.begin()) - 1;
-            r.j0 = j0;
-            active.push_back(e);
-            idx0v.push_back(((int64_t)a0 * c->nq + j0) * c->np);
-            rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
-        }
-        const int kBatch = 32;
-        for (size_t b0 = 0; b0 < active.size(); b0 += kBatch) {
-            const int nb = (int)std::min(active.size() - b0, (size_t)kBatch);
-            std::vector<double> Eb(nb), rho0(nb);
-            std::vector<int64_t> idx0(nb);
-            for (int t = 0; t < nb; ++t) {
-                Eb[t] = E[active[b0 + t]];
-                idx0[t] = idx0v[b0 + t];
-                rho0[t] = rho0v[b0 + t];
-            }
-            std::vector<int> iters, edge;
-            std::vector<double> resid;
-            gmres_batch(c, Eb, idx0, prec == WPCD_FP64, m, max_iter, tol, iters, resid, edge);
-            // amplitude list: elastic first, then open breakup pseudostates
-            std::vector<int64_t> rows;
-            std::vector<int32_t> ens;
-            std::vector<double> rho;
-            std::vector<int> first_br(nb), n_br(nb);
-            for (int t = 0; t < nb; ++t) {
-                rows.push_back(idx0[t]);
-                ens.push_back(t);
-                rho.push_back(rho0[t]);
-            }
-            for (int t = 0; t < nb; ++t) {
-                first_br[t] = (int)rows.size();
-                n_br[t] = 0;
-                for (int a = 0; a < c->nch; ++a) {
-                    const std::vector<double> &ev = c->waves[c->ch_wave[a]].h_eps;
-                    for (int k = 0; k < c->np; ++k) {
-                        if ((a == a0 && k == 0) || !(ev[k] < Eb[t])) continue;
-                        const double qk = std::sqrt(4.0 * (Eb[t] - ev[k]) / 3.0);
-                        if (qk >= qmax) continue;
-                        const int jk = (int)(std::upper_bound(c->q.begin(), c->q.end(), qk) -
-                                             c->q.begin()) - 1;
-                        rows.push_back(((int64_t)a * c->nq + jk) * c->np + k);
-                        ens.push_back(t);
-                        rho.push_back(2.0 / (3.0 * qk * (c->q[jk + 1] - c->q[jk])));
-                        ++n_br[t];
-                    }
-                }
-            }
-            std::vector<double> amp;
-            amplitudes_batch(c, nb, rows, ens, rho, rho0, amp);
-            for (int t = 0; t < nb; ++t) {
-                const int e = active[b0 + t];
-                wpcd_energy_result &r = res[e];
-                r.iters = iters[t];
-                r.residual = resid[t];
-                if (edge[t]) {
-                    r.status = WPCD_E_ON_EDGE;
-                    continue;
-                }
-                if (!(resid[t] <= tol * 10.0)) r.status = WPCD_E_NOT_CONVERGED;
-                r.U_re = amp[4 * t];
-                r.U_im = amp[4 * t + 1];
-                r.A_re = rho0[t] * r.U_re;
-                r.A_im = rho0[t] * r.U_im;
-                r.S_re = 1.0 + amp[4 * t + 2];
-                r.S_im = amp[4 * t + 3];
-                r.delta = 0.5 * std::atan2(r.S_im, r.S_re);
-                r.eta = std::hypot(r.S_re, r.S_im);
-                r.n_open = n_br[t];
-                if (breakup_out && want_breakup) {
-                    double *dst = breakup_out + (size_t)e * c->np * c->nch * 5;
-                    for (int u = 0; u < n_br[t]; ++u) {
-                        const int row = first_br[t] + u;
-                        const int64_t rr = rows[row];
-                        const int a = (int)(rr / ((int64_t)c->nq * c->np));
-                        const int jk = (int)((rr / c->np) % c->nq);
-                        const int k = (int)(rr % c->np);
-                        dst[5 * u + 0] = a;
-                        dst[5 * u + 1] = k;
-                        dst[5 * u + 2] = jk;
-                        dst[5 * u + 3] = amp[4 * row + 2];
-                        dst[5 * u + 4] = amp[4 * row + 3];
-                    }
-                }
-            }
-        }
-        for (int e = 0; e < n_E; ++e) out[e] = res[e];
+        WPCD_REQUIRE(c->has_basis && c->has_pot, WPCD_E_STATE, "no basis/potential");
+        set_multipliers(c, mult, n_mult);
     });
+}
+
+wpcd_status wpcd_learn_train(wpcd_ctx *c, const wpcd_learn_desc *desc, wpcd_learn_report *report) {
+    return guarded(c, [&] { learn_train(c, desc, report); });
+}
+
+wpcd_status wpcd_mlp_eval(wpcd_ctx *c, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                          const float *params, int32_t batch, const float *X, const float *T,
+                          float *Y_out, float *grad_out, double *loss_out) {
+    return guarded(c, [&] { mlp_eval(c, n_in, n_hidden, n_out, params, batch, X, T, Y_out, grad_out, loss_out); });
 }
 
 wpcd_status wpcd_set_timing(wpcd_ctx *c, int32_t enable) {
@@ -746,6 +1088,7 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->d_idx.release();
     c->d_jac.release();
     c->d_flag.release();
+    c->learned.release();
     c->d_pot.release();
     c->d_mcoef.release();
     if (c->own_stream) (void)hipStreamDestroy(c->stream);

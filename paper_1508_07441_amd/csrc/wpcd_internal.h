@@ -106,6 +106,56 @@ struct PairWave {
     std::vector<double> h_eps;    // host copy of eps*
 };
 
+// Multilayer perceptron x -> tanh(W1 x + b1) -> tanh(W2 . + b2) ->
+// tanh(W3 . + b3) -> W4 . + b4.  FP32 master parameters [W1 b1 .. W4 b4]
+// (W row-major out x in), BF16 copies of the weights for the products.
+struct Mlp {
+    int nin = 0, nh = 0, nout = 0;
+    int step = 0;
+    bool ready = false;
+    int din(int l) const { return l == 0 ? nin : nh; }
+    int dout(int l) const { return l == 3 ? nout : nh; }
+    int64_t n_params() const;
+    int64_t w_off(int l) const;
+    DBuf<float> w32, am, av, grad, act, dact, rowloss;
+    DBuf<uint16_t> w16;
+    void release() {
+        w32.release();
+        am.release();
+        av.release();
+        grad.release();
+        act.release();
+        dact.release();
+        rowloss.release();
+        w16.release();
+        ready = false;
+    }
+};
+
+// Learned warm start: reduced basis Phi (K orthonormal complex FP32 vectors
+// of length M, [K][M][2]) and the network mapping normalised features to
+// coefficients in Phi (scaled by 1/coef_scale).
+constexpr int kMaxFeat = 5 + 16;
+struct Learned {
+    bool ready = false;
+    int K = 0, nfeat = 0, n_mult = 0;
+    int64_t M = 0;
+    double feat_mu[kMaxFeat] = {}, feat_sd[kMaxFeat] = {};
+    double coef_scale = 1.0;
+    DBuf<float> phi;
+    Mlp mlp;
+    DBuf<float> feat, y;   // inference scratch
+    DBuf<int32_t> sel;     // snapshot selection list
+    void release() {
+        phi.release();
+        mlp.release();
+        feat.release();
+        y.release();
+        sel.release();
+        ready = false;
+    }
+};
+
 }  // namespace wpcd
 
 struct wpcd_ctx {
@@ -137,6 +187,8 @@ struct wpcd_ctx {
     std::vector<double> pot_s, pot_mu;
     wpcd::DBuf<double> d_pot;           // strengths [16] | ranges [16]
     double pot_scale = 1.0;
+    std::vector<double> pot_base;       // strengths as given; pot_s = pot_base * mult
+    std::vector<double> pot_mult;
     int n_waves = 0;
     wpcd::PairWave waves[wpcd::kMaxWaves];
 
@@ -154,6 +206,9 @@ struct wpcd_ctx {
     wpcd::DBuf<int64_t> d_idx;
     wpcd::DBuf<double> d_jac;   // Jacobi workspace (A and V per wave)
     wpcd::DBuf<int32_t> d_flag;
+
+    // ---- learned warm start
+    wpcd::Learned learned;
 };
 
 namespace wpcd {
@@ -173,5 +228,39 @@ void launch_vt(wpcd_ctx *c, int wave);
 
 void build_structure(wpcd_ctx *c);   // a3: counts, scan, fill (sets c->nnz)
 void build_values(wpcd_ctx *c, bool fp64);
+
+// Batched GMRES over energies (k_solve.hip).  warm: fills the initial
+// vector in the batch layout x[row][e][2] (called after b is formed), or
+// empty for the zero start.  Per energy: iterations, final relative
+// residual, resolvent edge flag, warm start kept, initial relative residual.
+struct GmresOut {
+    std::vector<int> iters, edge, warm;
+    std::vector<double> resid, r0;
+};
+using WarmFill = void (*)(wpcd_ctx *c, void *user, double *x, int nE);
+void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
+                 bool fp64, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
+                 GmresOut &out);
+void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
+                      const std::vector<int32_t> &ens, const std::vector<double> &rho,
+                      const std::vector<double> &rho0, std::vector<double> &out);
+
+// Network kernels (k_mlp.hip).  X, T, Y on the device; parameters in m.
+void mlp_init(Mlp &m, hipStream_t s, int nin, int nh, int nout, uint64_t seed);
+void mlp_set_weights(Mlp &m, hipStream_t s, const float *w_host);
+float *mlp_forward(Mlp &m, hipStream_t s, Timer &t, const float *X, int B);
+// Gradients into m.grad; returns the loss if want_loss (synchronises), else 0.
+double mlp_loss_grad(Mlp &m, hipStream_t s, Timer &t, const float *X, const float *T, int B,
+                     bool want_loss);
+void mlp_adam_step(Mlp &m, hipStream_t s, Timer &t, float lr);
+void mlp_gather(hipStream_t s, const float *src, int ncol, const int32_t *idx, int n, float *dst);
+
+// Learned warm start (wpcd_learn.hip).
+void learn_snap_store(wpcd_ctx *c, float *snaps, int64_t first, const double *x, int nE,
+                      const std::vector<int> &which);
+void learn_build_basis(wpcd_ctx *c, const float *snaps, int n, int K, std::vector<double> &coef,
+                       double &max_err, double &mean_err);
+void learn_lift(wpcd_ctx *c, const float *y, int nE, double *x);
+void learn_interleave(wpcd_ctx *c, const double *src, int nE, int64_t M, double *x);
 
 }  // namespace wpcd

@@ -44,3 +44,34 @@ C2 = dict(n_p=150, n_q=150, p_max=10.0, q_max=10.0, n_gq=8, n_gx=20,
 # Toy grid for single-element checks.
 TOY_P = (0.0, 0.4, 0.9, 1.5, 2.2)
 TOY_Q = (0.0, 0.5, 1.0, 1.6, 2.3)
+
+
+def mlp_case(seed: int, nin: int, nh: int, nout: int, batch: int):
+    """Parameters [W1 b1 .. W4 b4] (Glorot-uniform weights, small biases),
+    inputs in [-2, 2) and targets in [-1, 1) for a 3-hidden-layer network."""
+    dims = [(nh, nin), (nh, nh), (nh, nh), (nout, nh)]
+    n_par = sum(o * i + o for o, i in dims)
+    u = uniforms(seed, n_par + batch * (nin + nout))
+    params, k = [], 0
+    for o, i in dims:
+        a = math.sqrt(6.0 / (o + i))
+        params += [(2.0 * x - 1.0) * a for x in u[k:k + o * i]]
+        k += o * i
+        params += [0.1 * (2.0 * x - 1.0) for x in u[k:k + o]]
+        k += o
+    X = [4.0 * x - 2.0 for x in u[k:k + batch * nin]]
+    k += batch * nin
+    T = [2.0 * x - 1.0 for x in u[k:k + batch * nout]]
+    return dims, params, X, T
+
+
+def learn_draws(seed: int, n_var: int, n_mult: int, n_E: int, e_lo: float, e_hi: float):
+    """Potential multipliers U[0.8, 1.2] (n_mult per variant, drawn first)
+    and energies U[e_lo, e_hi] (n_E per variant), variant by variant."""
+    u = uniforms(seed, n_var * (n_mult + n_E))
+    mult, E = [], []
+    for v in range(n_var):
+        row = u[v * (n_mult + n_E):(v + 1) * (n_mult + n_E)]
+        mult.append([0.8 + 0.4 * x for x in row[:n_mult]])
+        E.append([e_lo + (e_hi - e_lo) * x for x in row[n_mult:]])
+    return mult, E

@@ -38,18 +38,43 @@ def test_null_arguments_rejected_without_device():
     assert L.wpcd_build_basis(None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_build_p(None, 0, None) == P.WPCD_E_INVALID
     assert L.wpcd_solve(None, None, 0, 0, None, None, None) == P.WPCD_E_INVALID
+    assert L.wpcd_set_multipliers(None, None, 0) == P.WPCD_E_INVALID
+    assert L.wpcd_learn_train(None, None, None) == P.WPCD_E_INVALID
+    assert L.wpcd_mlp_eval(None, 1, 1, 1, None, 1, None, None, None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_last_error(None) == b"null context"
     L.wpcd_destroy(None)
 
 
-def test_struct_layouts_match_header():
+STRUCTS = ("wpcd_basis_desc", "wpcd_potential_desc", "wpcd_solve_opts", "wpcd_energy_result",
+           "wpcd_learn_desc", "wpcd_learn_report", "wpcd_kernel_time")
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes mirrors equal what the C
+    compiler lays out from include/wpcd.h."""
+    import shutil
+    import subprocess
     import paper_1508_07441_amd as P
-    # sizes follow from the C declarations with natural alignment
-    assert ctypes.sizeof(P.wpcd_basis_desc) == 4 * 2 + 8 * 2 + 8 + 8 * 2 + 4 * 4 + 8 * 2
-    assert ctypes.sizeof(P.wpcd_potential_desc) == 8 + 8 * 2 + 8
-    assert ctypes.sizeof(P.wpcd_solve_opts) == 4 * 2 + 8 + 8
-    assert ctypes.sizeof(P.wpcd_energy_result) == 8 * 2 + 4 * 4 + 8 * 9
-    assert ctypes.sizeof(P.wpcd_kernel_time) == 32 + 8 + 8
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for st in STRUCTS:
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for f, _ in getattr(P, st)._fields_:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in STRUCTS:
+        T = getattr(P, st)
+        assert got[(st, "size")] == ctypes.sizeof(T), st
+        for f, _ in T._fields_:
+            assert got[(st, f)] == getattr(T, f).offset, (st, f)
 
 
 def test_create_without_gpu_reports_device_error():

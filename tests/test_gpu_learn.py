@@ -1,0 +1,143 @@
+"""GPU tests of the warm starts of the solve: the network kernels against the
+FP64 reference of oracle/mlp.py, the residual judge on given initial vectors
+(useless, huge and exact ones), and the learned warm start against the plain
+solve at equal residual."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.mlp as OM
+import oracle.wpcd as O
+from inputs import SEED, YAM_BETA, YAM_LAMBDA, YUK_RANGES, learn_draws, mlp_case, uniforms
+
+pytestmark = pytest.mark.gpu
+
+YAM = dict(kind="yamaguchi", strength=[YAM_LAMBDA], range=[YAM_BETA])
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1508_07441_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _unpack(dims, flat):
+    out, k = [], 0
+    for o, i in dims:
+        W = flat[k:k + o * i].reshape(o, i)
+        k += o * i
+        out.append((W, flat[k:k + o]))
+        k += o
+    return out
+
+
+@pytest.mark.parametrize("nin,nh,nout,B", [(5, 70, 18, 37), (19, 256, 128, 256), (3, 16, 2, 1)])
+def test_mlp_kernels_match_fp64_reference(ctx, P, nin, nh, nout, B):
+    say(f"[mlp] nin={nin} nh={nh} nout={nout} B={B}")
+    dims, flat, X, T = mlp_case(SEED + nh, nin, nh, nout, B)
+    flat32 = np.array(flat, dtype=np.float32)
+    X = np.array(X, dtype=np.float32).reshape(B, nin)
+    T = np.array(T, dtype=np.float32).reshape(B, nout)
+    Y, G, loss = ctx.mlp_eval(nin, nh, nout, flat32, X, T)
+    # reference: weights rounded to BF16 as the kernels use them, biases FP32
+    ref = [(OM.bf16_round(W), b.astype(np.float64)) for W, b in _unpack(dims, flat32)]
+    acts = OM.forward(ref, X.astype(np.float64))
+    l_ref, g_ref = OM.loss_and_grads(ref, X.astype(np.float64), T.astype(np.float64))
+    # FP32 accumulation over at most 256 terms per product, four layers deep:
+    # relative error below 256 * 2^-24 per layer on O(1) activations
+    ytol = 2e-4 * max(1.0, np.abs(acts[-1]).max())
+    assert np.abs(Y - acts[-1]).max() <= ytol
+    assert abs(loss - l_ref) <= 2e-4 * l_ref
+    gg = _unpack(dims, G.astype(np.float64))
+    for (dW, db), (rW, rb) in zip(gg, g_ref):
+        for a, r in ((dW, rW), (db, rb)):
+            assert np.abs(a - r).max() <= 5e-4 * np.abs(r).max() + 1e-7
+
+
+def _c1(ctx, P):
+    n = 40
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    ctx.build_p(P.WPCD_FP64)
+    return n
+
+
+def test_given_warm_start_residual_judge(ctx, P):
+    n = _c1(ctx, P)
+    M = n * n
+    E = [0.05, 0.5, 1.0]
+    base = ctx.solve(E, P.WPCD_FP64)
+    say("[warm] NaN start")
+    bad = np.full((3, M), np.nan + 1j * np.nan)
+    r_nan = ctx.solve(E, P.WPCD_FP64, warm_start=P.WPCD_WARM_GIVEN, x0=bad)
+    say("[warm] huge start")
+    u = np.array(uniforms(SEED + 5, 2 * 3 * M)).reshape(3, M, 2)
+    huge = 1e200 * ((u[..., 0] - 0.5) + 1j * (u[..., 1] - 0.5))
+    r_huge = ctx.solve(E, P.WPCD_FP64, warm_start=P.WPCD_WARM_GIVEN, x0=huge)
+    say("[warm] oracle-solution start")
+    sysm = O.build_system(O.cheb_edges(n, 10.0), O.cheb_edges(n, 10.0), 0, [(0, 0)], 8, 16,
+                          O.Potential("yamaguchi", (YAM_LAMBDA,), (YAM_BETA,)))
+    good = np.array([O.solve_gmres(sysm, e)[0] for e in E])
+    r_good = ctx.solve(E, P.WPCD_FP64, warm_start=P.WPCD_WARM_GIVEN, x0=good)
+    for b, a, h, g in zip(base, r_nan, r_huge, r_good):
+        for r in (a, h, g):
+            assert r.status == P.WPCD_OK
+            U0, U = complex(b.U_re, b.U_im), complex(r.U_re, r.U_im)
+            assert abs(U - U0) <= 1e-10 * abs(U0)
+            assert r.residual < 1e-11
+        assert a.warm == 0 and a.r0 == 1.0 and a.iters == b.iters
+        assert h.r0 <= 1.0 + 1e-12
+        assert g.warm == 1 and g.r0 < 1e-9 and g.iters < b.iters
+        say(f"[warm] E={b.E}: plain {b.iters} it, exact start r0={g.r0:.1e} {g.iters} it")
+
+
+def test_learned_warm_start_gain(ctx, P):
+    """Training on plain solves of potential variants, then a held-out
+    variant: the same amplitudes as the plain solve at the same residual,
+    an initial residual well below that of the zero start; the iteration
+    counts of both are printed (the gain measured, not assumed)."""
+    n = 40
+    pot = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=pot)
+    ctx.build_p(P.WPCD_FP64)
+    mult, E = learn_draws(SEED + 11, 8, 2, 24, -0.05, 2.0)
+    say("[learn] training 8 variants x 24 energies")
+    rep = ctx.learn_train(mult, E, precision=P.WPCD_FP64, n_basis=32, hidden=256, epochs=300,
+                          batch=32, seed=SEED)
+    say(f"[learn] report {rep}")
+    assert 0 < rep["n_samples"] <= 8 * 24
+    assert 0.0 <= rep["basis_mean_rel_err"] <= rep["basis_max_rel_err"] < 1.0
+    assert rep["loss_last"] < rep["loss_first"]
+    held = [1.07, 0.93]
+    Eh = list(np.linspace(-0.05, 2.0, 24))
+    ctx.set_multipliers(held)
+    plain = ctx.solve(Eh, P.WPCD_FP64)
+    learned = ctx.solve(Eh, P.WPCD_FP64, warm_start=P.WPCD_WARM_LEARNED)
+    ctx.set_multipliers([1.0, 1.0])
+    it_p = it_l = 0
+    r0 = []
+    for a, b in zip(plain, learned):
+        assert a.status == b.status
+        if a.status != P.WPCD_OK:
+            continue
+        U0, U = complex(a.U_re, a.U_im), complex(b.U_re, b.U_im)
+        assert abs(U - U0) <= 1e-10 * abs(U0)
+        assert a.residual < 1e-11 and b.residual < 1e-11
+        it_p += a.iters
+        it_l += b.iters
+        r0.append(b.r0)
+    say(f"[learn] held-out: plain {it_p} it, learned {it_l} it, median r0 {np.median(r0):.2e}")
+    assert max(r0) <= 1.0
+    assert np.median(r0) < 0.5

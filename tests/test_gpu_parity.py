@@ -241,7 +241,7 @@ def test_c2_full_fp64_and_mixed(ctx, P):
         U = complex(r.U_re, r.U_im)
         worst = max(worst, abs(U - ref[E]) / abs(ref[E]))
     say(f"[C2] mixed max rel amplitude error vs FP64 oracle: {worst:.3e}")
-    assert worst < 1e-4
+    assert worst <= 1e-6     # the mixed tier's amplitude gate
 
 
 # ------------------------------------------------------------ multichannel
