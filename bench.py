@@ -13,6 +13,12 @@ pre-selection + P0 elements (FP32 with compensated sums), resolvent + the
 batched GMRES solve at the 8 energies + amplitudes.  Inputs are synthetic
 and resident on the GPU when the timed region starts.
 
+Beside the timed steps: the solve per energy in the mixed tier, in the
+mixed tier with the learned warm start (trained at setup on 16 potential
+variants x 32 energies drawn with splitmix64: strength multipliers
+U[0.8, 1.2], energies U[-0.05, 2.0]) and in FP64, with iterations and the
+amplitude errors against the FP64 solve.
+
 Prints one JSON line.  value = P-matrix elements (selected cell pairs) per
 second of P-build wall time (pre-selection + elements); the whole-step time
 and the solve time per energy are reported beside it.
@@ -26,11 +32,14 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+from inputs import SEED, learn_draws  # noqa: E402  (seeded draws only)
 
 N = 150
 NGQ, NGX = 8, 20
 RANGES = (1.0, 2.0)
 ENERGIES = (-0.08, -0.05, -0.02, 0.05, 0.2, 0.5, 1.0, 2.0)
+LEARN_VARIANTS, LEARN_ENERGIES = 16, 32
 
 # MI355X published peaks used for the roofline fractions
 PEAK_FP32_VECTOR_TFLOPS = 157.3
@@ -67,6 +76,97 @@ def cpu_baseline(sample_stride, threads):
                       f"cell pairs): brute-force pre-selection + FP64 elements, {dt:.1f} s"}
 
 
+def c3_measure(P):
+    """The 270k-basis case beside the main line: L = 2+ channels (0,2), (2,0),
+    (2,2), 300 x 300 bins, the same Yukawa sum fitted to -0.1, 8 energies.
+    P build (pre-selection + elements) in the mixed tier, and the batched
+    solve per energy in the three tiers with their amplitude error against
+    the FP64 solve."""
+    ctx = P.Context(0)
+    ctx.set_autotune(P.WPCD_TUNE_MEASURE)
+    fit = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(RANGES), fit_e2=-0.1)
+    chans = [(0, 2), (2, 0), (2, 2)]
+    ctx.build_basis(300, 300, 10.0, 10.0, NGQ, NGX, channels=chans, L=2, potential=fit)
+    ctx.build_p(P.WPCD_MIXED)
+    ctx.synchronize()
+    t = time.perf_counter()
+    nnz = ctx.build_p(P.WPCD_MIXED)
+    ctx.synchronize()
+    t_build = time.perf_counter() - t
+
+    def solve(prec):
+        ctx.solve(ENERGIES, prec)            # tune + capture
+        best, res = 1e30, None
+        for _ in range(2):
+            a = time.perf_counter()
+            res = ctx.solve(ENERGIES, prec)
+            best = min(best, time.perf_counter() - a)
+        return best / len(ENERGIES), res
+
+    s_mixed, r_mixed = solve(P.WPCD_MIXED)
+    s_refine, r_refine = solve(P.WPCD_MIXED_REFINE)
+    ctx.build_p(P.WPCD_FP64)
+    s_fp64, r_fp64 = solve(P.WPCD_FP64)
+    ok = [k for k, r in enumerate(r_fp64) if r.status == P.WPCD_OK]
+
+    def err(ra):
+        return max(abs(complex(ra[k].U_re, ra[k].U_im) - complex(r_fp64[k].U_re, r_fp64[k].U_im))
+                   / abs(complex(r_fp64[k].U_re, r_fp64[k].U_im)) for k in ok)
+    ctx.close()
+    return {"workload": "L=2+ channels (0,2),(2,0),(2,2); 300x300 bins; Yukawa sum fitted to "
+                        "-0.1; 8 energies", "basis": 3 * 300 * 300, "nnz_cells": nnz,
+            "p_build_mixed_ms": 1e3 * t_build, "p_elements_per_s": nnz / t_build,
+            "channel_values_per_s": 9 * nnz / t_build,
+            "solve_s_per_energy": {"mixed": s_mixed, "mixed_refine": s_refine, "fp64": s_fp64},
+            "iters_per_energy": {"mixed": sum(r.iters for r in r_mixed) / len(r_mixed),
+                                 "mixed_refine": sum(r.iters for r in r_refine) / len(r_refine),
+                                 "fp64": sum(r.iters for r in r_fp64) / len(r_fp64)},
+            "max_rel_amp_err_vs_fp64": {"mixed": err(r_mixed), "mixed_refine": err(r_refine)}}
+
+
+def c5_measure(P, n_var, n_e, sweep):
+    """Learned warm start on the 270k basis: plain mixed solves of n_var x n_e
+    (potential variant, energy) pairs train the network (multipliers
+    U[0.8, 1.2], energies U[-0.05, 2.0], splitmix64), then a sweep of `sweep`
+    energies uniform in [-0.05, 2.0] at the base potential is solved plainly
+    and with the warm start: iterations, time and amplitude agreement."""
+    ctx = P.Context(0)
+    ctx.set_autotune(P.WPCD_TUNE_MEASURE)
+    fit = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(RANGES), fit_e2=-0.1)
+    ctx.build_basis(300, 300, 10.0, 10.0, NGQ, NGX, channels=[(0, 2), (2, 0), (2, 2)], L=2,
+                    potential=fit)
+    ctx.build_p(P.WPCD_MIXED)
+    mult, e_train = learn_draws(SEED + 5, n_var, 2, n_e, -0.05, 2.0)
+    t = time.perf_counter()
+    rep = ctx.learn_train(mult, e_train, precision=P.WPCD_MIXED, n_basis=128, hidden=256,
+                          epochs=200, batch=128, seed=SEED)
+    t_train = time.perf_counter() - t
+    E = [-0.05 + 2.05 * k / (sweep - 1) for k in range(sweep)]
+    ctx.solve(E[:32], P.WPCD_MIXED)
+    ctx.solve(E[:32], P.WPCD_MIXED, warm_start=P.WPCD_WARM_LEARNED)
+    t = time.perf_counter()
+    plain = ctx.solve(E, P.WPCD_MIXED)
+    t_plain = time.perf_counter() - t
+    t = time.perf_counter()
+    learned = ctx.solve(E, P.WPCD_MIXED, warm_start=P.WPCD_WARM_LEARNED)
+    t_learned = time.perf_counter() - t
+    ok = [k for k in range(sweep) if plain[k].status == P.WPCD_OK]
+    err = max(abs(complex(learned[k].U_re, learned[k].U_im) - complex(plain[k].U_re, plain[k].U_im))
+              / abs(complex(plain[k].U_re, plain[k].U_im)) for k in ok)
+    r0 = sorted(learned[k].r0 for k in ok)
+    ctx.close()
+    return {"workload": f"270k basis (300x300, L=2+ 3 channels); training {n_var} variants x "
+                        f"{n_e} energies, sweep of {sweep} energies",
+            "train": {k: rep[k] for k in ("n_samples", "plain_iters", "basis_mean_rel_err",
+                                          "basis_max_rel_err", "loss_first", "loss_last")},
+            "train_s": t_train, "train_solve_s": rep["solve_ms"] / 1e3,
+            "sweep_iters": {"plain": sum(plain[k].iters for k in ok),
+                            "learned": sum(learned[k].iters for k in ok)},
+            "sweep_s_per_energy": {"plain": t_plain / sweep, "learned": t_learned / sweep},
+            "learned_initial_residual_median": r0[len(r0) // 2],
+            "max_rel_amp_diff_learned_vs_plain": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +174,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-stride", type=int, default=1)
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="after the run, one plain device copy y = x * 1 of this many MiB "
+                         "(float32, torch elementwise kernel) to calibrate HBM byte counters")
+    ap.add_argument("--c5", type=str, default="",
+                    help="learned warm start on the 270k basis: VARIANTS,ENERGIES,SWEEP "
+                         "(e.g. 64,64,256); off by default (about a minute)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
@@ -90,6 +197,8 @@ def main():
     _, _, scale = ctx.pair_spectrum(0, want_O=False)
     pot = dict(kind="yukawa", strength=[-scale, -scale], range=list(RANGES))
 
+    # launch shapes: time the candidates once per shape (cached in the context)
+    ctx.set_autotune(P.WPCD_TUNE_MEASURE)
     pbuild = [0.0]
 
     def step():
@@ -116,15 +225,25 @@ def main():
     wall = t1 - t0
 
     # solve-only timing (untimed for value): batched 8 energies, mixed and FP64
-    def solve_time(prec, reps=3):
+    def solve_time(prec, reps=3, **kw):
         ts = []
         for _ in range(reps):
             a = time.perf_counter()
-            r = ctx.solve(ENERGIES, prec)
+            r = ctx.solve(ENERGIES, prec, **kw)
             ts.append(time.perf_counter() - a)
         return min(ts) / len(ENERGIES), r
 
     s_mixed, r_mixed = solve_time(P.WPCD_MIXED)
+    solve_time(P.WPCD_MIXED_REFINE, reps=1)     # tune + capture
+    s_refine, r_refine = solve_time(P.WPCD_MIXED_REFINE)
+    # learned warm start (mixed): trained on plain mixed solves of potential
+    # variants, then the 8 energies at the base potential (a held-out point)
+    mult, e_train = learn_draws(SEED, LEARN_VARIANTS, 2, LEARN_ENERGIES, -0.05, 2.0)
+    t_learn = time.perf_counter()
+    rep = ctx.learn_train(mult, e_train, precision=P.WPCD_MIXED, n_basis=64, hidden=256,
+                          epochs=300, batch=64, seed=SEED)
+    t_learn = time.perf_counter() - t_learn
+    s_learned, r_learned = solve_time(P.WPCD_MIXED, warm_start=P.WPCD_WARM_LEARNED)
     # FP64 P-build throughput and FP64 solve beside it
     ctx.set_timing(P.WPCD_TIME_P0)
     ctx.reset_timing()
@@ -135,8 +254,13 @@ def main():
     tim64 = ctx.timing()
     ctx.set_timing(0)
     s_fp64, r_fp64 = solve_time(P.WPCD_FP64)
-    amp_err = max(abs(complex(x.U_re, x.U_im) - complex(y.U_re, y.U_im)) / abs(complex(y.U_re, y.U_im))
-                  for x, y in zip(r_mixed, r_fp64))
+
+    def amp_err(ra):
+        return max(abs(complex(x.U_re, x.U_im) - complex(y.U_re, y.U_im)) / abs(complex(y.U_re, y.U_im))
+                   for x, y in zip(ra, r_fp64))
+
+    def mean_iters(ra):
+        return sum(x.iters for x in ra) / len(ra)
 
     elem_ms, elem_n = tim.get("p0_elem_f32", (0.0, 1))
     elem_avg_s = elem_ms / max(elem_n, 1) / 1e3
@@ -159,8 +283,22 @@ def main():
         "config": {"workload": "s-wave bosons, 2-range Yukawa sum fitted to -0.1; 150x150 bins, "
                                "8x8 q Gauss, 20-pt cosine rule, 8 energies", "nnz_cells": nnz,
                    "basis": N * N, "energies": list(ENERGIES)},
-        "solve_s_per_energy": {"mixed": s_mixed, "fp64": s_fp64,
-                               "mixed_max_rel_amp_err_vs_fp64": amp_err},
+        "solve_s_per_energy": {"mixed": s_mixed, "mixed_learned": s_learned,
+                               "mixed_refine": s_refine, "fp64": s_fp64,
+                               "mixed_max_rel_amp_err_vs_fp64": amp_err(r_mixed),
+                               "mixed_refine_max_rel_amp_err_vs_fp64": amp_err(r_refine),
+                               "mixed_learned_max_rel_amp_err_vs_fp64": amp_err(r_learned),
+                               "iters_per_energy": {"mixed": mean_iters(r_mixed),
+                                                    "mixed_learned": mean_iters(r_learned),
+                                                    "mixed_refine": mean_iters(r_refine),
+                                                    "fp64": mean_iters(r_fp64)},
+                               "learned_initial_residual_median":
+                                   sorted(x.r0 for x in r_learned)[len(r_learned) // 2],
+                               "fp64_over_mixed_learned": s_fp64 / s_learned},
+        "learn": {"train_solves": rep["n_samples"], "basis": 64,
+                  "basis_mean_rel_err": rep["basis_mean_rel_err"],
+                  "loss_first": rep["loss_first"], "loss_last": rep["loss_last"],
+                  "train_s": t_learn},
         "p_build": {"mixed_ms": 1e3 * pbuild[0] / args.steps, "fp64_ms": 1e3 * fp64_build,
                     "fp64_elements_per_s": nnz / fp64_build,
                     "elem_kernel_f32_ms": 1e3 * elem_avg_s,
@@ -172,10 +310,24 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": None, "kernel": "p0_elem_f32"},
     }
+    out["autotune"] = {f'{e["name"]} [{e["key"]}]': e["choice"] for e in ctx.autotune()}
+    if not args.no_c3:
+        out["c3"] = c3_measure(P)
+    if args.c5:
+        nv, ne, sw = (int(x) for x in args.c5.split(","))
+        out["c5"] = c5_measure(P, nv, ne, sw)
     if rank == 0 and not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride, threads)
     ctx.close()
+    if args.copy_calib_mb:
+        import torch
+        n = args.copy_calib_mb * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = {"read": 4 * n, "write": 4 * n}
     print(json.dumps(out), flush=True)
 
 

@@ -44,8 +44,13 @@ typedef enum {
 } wpcd_status;
 
 typedef enum {
-    WPCD_FP64 = 0,   /* FP64 everywhere */
-    WPCD_MIXED = 1   /* P0 accumulated in FP32 with compensated sums */
+    WPCD_FP64 = 0,          /* FP64 everywhere */
+    WPCD_MIXED = 1,         /* P0 accumulated in FP32 with compensated sums */
+    WPCD_MIXED_REFINE = 2   /* wpcd_solve only, on a WPCD_MIXED P0: the two
+                               intermediate panels of the kernel product are
+                               FP32 inside the Krylov iterations; each restart
+                               forms the true residual with FP64 panels
+                               (iterative refinement) */
 } wpcd_precision;
 
 /* Lattice basis (Sec. II.D, eq.(xij); channels eq.(si)).
@@ -96,8 +101,8 @@ typedef struct {
 /* Iterative solve options.  max_iter: total Krylov iterations per energy
  * (default 400 when <= 0); krylov_dim: GMRES restart length (default 48,
  * max 128); tol: relative residual target (default 1e-12 for WPCD_FP64,
- * 1e-9 for WPCD_MIXED, whose FP32 P0 values already perturb the operator at
- * the 1e-7 level).  want_breakup:
+ * 1e-9 for the mixed tiers, whose FP32 P0 values already perturb the
+ * operator at the 1e-7 level).  want_breakup:
  * fill breakup_out in wpcd_solve.  warm_start: a WPCD_WARM_* value; x0
  * (WPCD_WARM_GIVEN only): host array [n_E][M][2] of (re, im) doubles in
  * channel-basis order, M = n_ch*n_q*n_p.                                 */
@@ -219,11 +224,24 @@ wpcd_status wpcd_get_p(wpcd_ctx *ctx, int64_t *row_ptr, int32_t *col, double *va
  * and opts->want_breakup, receives per energy up to n_p*n_ch rows of
  * (channel, k, j_k, Re S_k0, Im S_k0) as doubles, row count in n_open.
  * Per-energy failures are reported in out[e].status and do not abort the
- * batch.  prec selects the P0 values used (FP64 requires an FP64 build).
+ * batch.  prec selects the P0 values used (FP64 requires an FP64 build,
+ * WPCD_MIXED and WPCD_MIXED_REFINE a mixed one).
  * Errors: WPCD_E_STATE, WPCD_E_INVALID, WPCD_E_NOMEM, WPCD_E_DEVICE.      */
 wpcd_status wpcd_solve(wpcd_ctx *ctx, const double *E, int32_t n_E, wpcd_precision prec,
                        const wpcd_solve_opts *opts, wpcd_energy_result *out,
                        double *breakup_out);
+
+/* wpcd_solve for n_sys independent systems at once (uneven sizes and
+ * channel sets allowed): system i is solved in context ctxs[i] at energies
+ * E[i][0..n_E[i]) into out[i][0..n_E[i]) (no breakup rows).  Each system is
+ * driven by its own host thread on its context's stream, so the systems'
+ * kernels share the device.  The contexts must be distinct (a context is
+ * not thread-safe) and on the same device or not.  status_out[i] (may be
+ * NULL) receives each system's call status; the return value is the first
+ * non-OK one.  Errors: WPCD_E_INVALID (NULL arrays, repeated context).   */
+wpcd_status wpcd_solve_multi(wpcd_ctx *const *ctxs, int32_t n_sys, const double *const *E,
+                             const int32_t *n_E, wpcd_precision prec, const wpcd_solve_opts *opts,
+                             wpcd_energy_result *const *out, wpcd_status *status_out);
 
 /* Multiply the strengths of the current potential term by term by
  * mult[0..n_mult) (n_mult = n_terms; the multipliers are relative to the
@@ -248,6 +266,34 @@ wpcd_status wpcd_learn_train(wpcd_ctx *ctx, const wpcd_learn_desc *desc,
 wpcd_status wpcd_mlp_eval(wpcd_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out,
                           const float *params, int32_t batch, const float *X, const float *T,
                           float *Y_out, float *grad_out, double *loss_out);
+
+/* Launch shapes (tile sizes of the block products, rows per workgroup of
+ * the Krylov vector kernels) are chosen per problem shape:
+ * WPCD_TUNE_HEURISTIC (default): fixed rules from the number of workgroups;
+ * WPCD_TUNE_MEASURE: the first solve of each shape times every candidate on
+ * the live buffers (a few launches) and keeps the fastest for the life of
+ * the context; WPCD_TUNE_FORCE + i: candidate i everywhere (clamped), for
+ * tests.  Changing the mode clears the decisions.  wpcd_get_autotune lists
+ * them (up to n entries, count in *n_out).  Results agree between choices
+ * to rounding (the block products bit for bit).                          */
+#define WPCD_TUNE_HEURISTIC 0
+#define WPCD_TUNE_MEASURE 1
+#define WPCD_TUNE_FORCE 16
+typedef struct {
+    char name[32];
+    char key[64];
+    int32_t choice, n_candidates;
+    double us;   /* measured time of the choice, 0 when not measured */
+} wpcd_tune_entry;
+wpcd_status wpcd_set_autotune(wpcd_ctx *ctx, int32_t mode);
+wpcd_status wpcd_get_autotune(wpcd_ctx *ctx, wpcd_tune_entry *out, int32_t n, int32_t *n_out);
+
+/* Replay of captured HIP graphs for the solve's iterations (default on):
+ * each group of four GMRES iterations of a batch shape is captured once
+ * and then launched as one graph; results are identical to the eager
+ * launches, which are used instead while solve-kernel timing is on or
+ * after wpcd_set_graphs(ctx, 0).  Clears the captured graphs.            */
+wpcd_status wpcd_set_graphs(wpcd_ctx *ctx, int32_t enable);
 
 /* Kernel timing with HIP events recorded on the context's stream around
  * each launch.  enable is a bit mask of kernel groups: WPCD_TIME_PAIR (pair

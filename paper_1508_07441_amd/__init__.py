@@ -26,6 +26,7 @@ WPCD_E_ON_EDGE = 6
 WPCD_E_STATE = 7
 WPCD_FP64 = 0
 WPCD_MIXED = 1
+WPCD_MIXED_REFINE = 2
 WPCD_TIME_PAIR = 1
 WPCD_TIME_P0 = 2
 WPCD_TIME_SOLVE = 4
@@ -33,13 +34,18 @@ WPCD_TIME_ALL = 7
 WPCD_WARM_NONE = 0
 WPCD_WARM_LEARNED = 1
 WPCD_WARM_GIVEN = 2
+WPCD_TUNE_HEURISTIC = 0
+WPCD_TUNE_MEASURE = 1
+WPCD_TUNE_FORCE = 16
 
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_CONVERGED",
                 5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE"}
 
 ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_set_potential", "wpcd_pair_spectrum",
-                 "wpcd_build_p", "wpcd_get_p", "wpcd_solve", "wpcd_set_multipliers",
-                 "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_timing",
+                 "wpcd_build_p", "wpcd_get_p", "wpcd_solve", "wpcd_solve_multi",
+                 "wpcd_set_multipliers",
+                 "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_autotune",
+                 "wpcd_get_autotune", "wpcd_set_graphs", "wpcd_set_timing",
                  "wpcd_get_timing", "wpcd_reset_timing", "wpcd_synchronize", "wpcd_last_error",
                  "wpcd_destroy")
 
@@ -97,6 +103,12 @@ class wpcd_learn_report(ctypes.Structure):
                 ("train_ms", ctypes.c_double)]
 
 
+class wpcd_tune_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("key", ctypes.c_char * 64),
+                ("choice", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("us", ctypes.c_double)]
+
+
 class wpcd_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("total_ms", ctypes.c_double),
                 ("launches", ctypes.c_int64)]
@@ -132,11 +144,20 @@ def lib():
                                  ctypes.POINTER(wpcd_solve_opts),
                                  ctypes.POINTER(wpcd_energy_result), dp]
         fp = ctypes.POINTER(ctypes.c_float)
+        L.wpcd_solve_multi.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(dp),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                       ctypes.POINTER(wpcd_solve_opts),
+                                       ctypes.POINTER(ctypes.POINTER(wpcd_energy_result)),
+                                       ctypes.POINTER(ctypes.c_int)]
         L.wpcd_set_multipliers.argtypes = [vp, dp, ctypes.c_int32]
         L.wpcd_learn_train.argtypes = [vp, ctypes.POINTER(wpcd_learn_desc),
                                        ctypes.POINTER(wpcd_learn_report)]
         L.wpcd_mlp_eval.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, fp,
                                     ctypes.c_int32, fp, fp, fp, fp, dp]
+        L.wpcd_set_autotune.argtypes = [vp, ctypes.c_int32]
+        L.wpcd_get_autotune.argtypes = [vp, ctypes.POINTER(wpcd_tune_entry), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]
+        L.wpcd_set_graphs.argtypes = [vp, ctypes.c_int32]
         L.wpcd_set_timing.argtypes = [vp, ctypes.c_int32]
         L.wpcd_get_timing.argtypes = [vp, ctypes.POINTER(wpcd_kernel_time), ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int32)]
@@ -259,6 +280,27 @@ def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol
     return res
 
 
+def wpcd_solve_multi(ctxs, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0):
+    """Solve several systems at once: ctxs[i] (handles) at energies[i]."""
+    n = len(ctxs)
+    Es = [np.ascontiguousarray(e, dtype=np.float64) for e in energies]
+    outs = [(wpcd_energy_result * max(1, e.size))() for e in Es]
+    H = (ctypes.c_void_p * n)(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    dp = ctypes.POINTER(ctypes.c_double)
+    EP = (dp * n)(*[_dp(e) for e in Es])
+    NE = (ctypes.c_int32 * n)(*[e.size for e in Es])
+    OP = (ctypes.POINTER(wpcd_energy_result) * n)(
+        *[ctypes.cast(o, ctypes.POINTER(wpcd_energy_result)) for o in outs])
+    st = (ctypes.c_int * n)()
+    opts = _opts(max_iter, krylov_dim, tol)
+    rc = lib().wpcd_solve_multi(H, n, EP, NE, precision, ctypes.byref(opts), OP, st)
+    if rc != WPCD_OK:
+        bad = [i for i in range(n) if st[i] != WPCD_OK]
+        msg = lib().wpcd_last_error(H[bad[0]]).decode() if bad else ""
+        raise WpcdError(rc, msg)
+    return [[outs[i][k] for k in range(Es[i].size)] for i in range(n)]
+
+
 def wpcd_set_multipliers(ctx, mult):
     m = np.ascontiguousarray(mult, dtype=np.float64)
     _check(ctx, lib().wpcd_set_multipliers(ctx, _dp(m), m.size))
@@ -295,6 +337,22 @@ def wpcd_mlp_eval(ctx, n_in, n_hidden, n_out, params, X, T=None, want_grad=True)
     _check(ctx, lib().wpcd_mlp_eval(ctx, n_in, n_hidden, n_out, f(P), B, f(Xa), f(Ta), f(Y), f(G),
                                     _dp(loss)))
     return Y, G, (None if loss is None else float(loss[0]))
+
+
+def wpcd_set_autotune(ctx, mode=WPCD_TUNE_MEASURE):
+    _check(ctx, lib().wpcd_set_autotune(ctx, int(mode)))
+
+
+def wpcd_get_autotune(ctx):
+    arr = (wpcd_tune_entry * 64)()
+    n = ctypes.c_int32()
+    _check(ctx, lib().wpcd_get_autotune(ctx, arr, 64, ctypes.byref(n)))
+    return [dict(name=arr[k].name.decode(), key=arr[k].key.decode(), choice=arr[k].choice,
+                 n_candidates=arr[k].n_candidates, us=arr[k].us) for k in range(min(n.value, 64))]
+
+
+def wpcd_set_graphs(ctx, enable=True):
+    _check(ctx, lib().wpcd_set_graphs(ctx, 1 if enable else 0))
 
 
 def wpcd_set_timing(ctx, groups=WPCD_TIME_ALL):
@@ -363,6 +421,15 @@ class Context:
 
     def mlp_eval(self, n_in, n_hidden, n_out, params, X, T=None, want_grad=True):
         return wpcd_mlp_eval(self.h, n_in, n_hidden, n_out, params, X, T, want_grad)
+
+    def set_autotune(self, mode=WPCD_TUNE_MEASURE):
+        wpcd_set_autotune(self.h, mode)
+
+    def autotune(self):
+        return wpcd_get_autotune(self.h)
+
+    def set_graphs(self, enable=True):
+        wpcd_set_graphs(self.h, enable)
 
     def set_timing(self, groups=WPCD_TIME_ALL):
         wpcd_set_timing(self.h, groups)

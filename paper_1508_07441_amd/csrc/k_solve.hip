@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <type_traits>
 
@@ -66,91 +67,116 @@ __global__ void k_resolvent(const double *__restrict__ q, int np, int nq, int nc
 // ------------------------------------------------------- block products
 // out[(b, r)][c] = sum_k Mat_b[r][k] y[(b, k)][c],  b = a*nq + j, Mat_b = mats[a]
 // y = G (.) in (complex product, USE_G) or in; out = that (SUB false) or
-// add - that (SUB true).  Tiles of 32 rows x W columns, k in steps of 32
-// (small tiles: at these sizes the product is latency-bound, so many
-// workgroups in flight matter more than register reuse).
-constexpr int kTR = 32, kTK = 32;
-
-template <bool USE_G, bool SUB>
+// add - that (SUB true).  Per channel a this is one GEMM
+//   C_a[r][(j, c)] = sum_k Mat_a[r][k] Y_a[k][(j, c)]
+// over all spectator bins j at once: tiles of TM rows x TN panel columns
+// (a panel column is (j, c), c < W), k in steps of 16 staged in LDS, each of
+// the 256 threads accumulating (TM/16) x (TN/16) outputs in registers.
+// Panels in and out are FP64, or FP32 (TI/TO float) for the inner
+// iterations of the mixed tier; the arithmetic is FP64 throughout.
+template <bool USE_G, bool SUB, int TM, int TN, class TI, class TO>
 __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq, int W,
-                                                     const double *__restrict__ in,
+                                                     const TI *__restrict__ in,
                                                      const double *__restrict__ G,
                                                      const double *__restrict__ add,
-                                                     double *__restrict__ out) {
-    __shared__ double sM[kTR][kTK + 1];
-    __shared__ double sX[kTK][64 + 1];
-    const int t = threadIdx.x;
-    const int blk = blockIdx.y;
-    const int row0 = blockIdx.x * kTR;
-    const double *Mt = mats.p[blk / nq];
-    const int64_t base = (int64_t)blk * n;   // first channel-basis row of this block
-    const int nout = kTR * W;
-    double acc[8];
+                                                     TO *__restrict__ out) {
+    constexpr int KS = 16, UM = TM / 16, UN = TN / 16;
+    __shared__ double sA[KS][TM + 1];
+    __shared__ double sB[KS][TN + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int a = blockIdx.z;
+    const int row0 = blockIdx.y * TM;
+    const int64_t q0 = (int64_t)blockIdx.x * TN;
+    const int64_t ncol = (int64_t)nq * W;
+    const double *Mt = mats.p[a];
+    const int64_t chbase = (int64_t)a * nq * n;   // first channel-basis row of channel a
+    double acc[UM][UN];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[s] = 0.0;
-    for (int k0 = 0; k0 < n; k0 += kTK) {
-        for (int idx = t; idx < kTR * kTK; idx += 256) {
-            int rr = idx / kTK, kk = idx % kTK;
-            int r = row0 + rr, k = k0 + kk;
-            sM[rr][kk] = (r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0;
+    for (int u = 0; u < UM; ++u)
+#pragma unroll
+        for (int v = 0; v < UN; ++v) acc[u][v] = 0.0;
+    for (int k0 = 0; k0 < n; k0 += KS) {
+        // A tile, transposed: sA[kk][rr] = Mat[row0 + rr][k0 + kk]
+        for (int idx = t; idx < TM * KS; idx += 256) {
+            const int rr = idx / KS, kk = idx % KS;
+            const int r = row0 + rr, k = k0 + kk;
+            sA[kk][rr] = (r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0;
         }
-        for (int idx = t; idx < kTK * W; idx += 256) {
-            int kk = idx / W, cc = idx % W;
-            int k = k0 + kk;
+        // B tile: sB[kk][qq] = Y[k0 + kk][q0 + qq]
+        for (int idx = t; idx < KS * TN; idx += 256) {
+            const int kk = idx / TN, qq = idx % TN;
+            const int k = k0 + kk;
+            const int64_t q = q0 + qq;
             double v = 0.0;
-            if (k < n) {
-                const int64_t o = (base + k) * W;
+            if (k < n && q < ncol) {
+                const int64_t j = q / W;
+                const int c = (int)(q - j * W);
+                const int64_t o = (chbase + j * n + k) * W;
                 if (USE_G) {
-                    const int c0 = cc & ~1;
+                    const int c0 = c & ~1;
                     const double gr = G[o + c0], gi = G[o + c0 + 1];
-                    const double xr = in[o + c0], xi = in[o + c0 + 1];
-                    v = (cc & 1) ? (gr * xi + gi * xr) : (gr * xr - gi * xi);
+                    const double xr = (double)in[o + c0], xi = (double)in[o + c0 + 1];
+                    v = (c & 1) ? (gr * xi + gi * xr) : (gr * xr - gi * xi);
                 } else {
-                    v = in[o + cc];
+                    v = (double)in[o + c];
                 }
             }
-            sX[kk][cc] = v;
+            sB[kk][qq] = v;
         }
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const int o = t + 256 * s;
-            if (o < nout) {
-                const int rr = o / W, cc = o % W;
-                double a = acc[s];
-#pragma unroll 8
-                for (int kk = 0; kk < kTK; ++kk) a += sM[rr][kk] * sX[kk][cc];
-                acc[s] = a;
-            }
+        for (int kk = 0; kk < KS; ++kk) {
+            double av[UM], bv[UN];
+#pragma unroll
+            for (int u = 0; u < UM; ++u) av[u] = sA[kk][ty + 16 * u];
+#pragma unroll
+            for (int v = 0; v < UN; ++v) bv[v] = sB[kk][tx + 16 * v];
+#pragma unroll
+            for (int u = 0; u < UM; ++u)
+#pragma unroll
+                for (int v = 0; v < UN; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int o = t + 256 * s;
-        if (o < nout) {
-            const int rr = o / W, cc = o % W;
-            const int r = row0 + rr;
-            if (r < n) {
-                const int64_t gi = (base + r) * W + cc;
-                out[gi] = SUB ? add[gi] - acc[s] : acc[s];
-            }
+    for (int u = 0; u < UM; ++u) {
+        const int r = row0 + ty + 16 * u;
+        if (r >= n) continue;
+#pragma unroll
+        for (int v = 0; v < UN; ++v) {
+            const int64_t q = q0 + tx + 16 * v;
+            if (q >= ncol) continue;
+            const int64_t j = q / W;
+            const int c = (int)(q - j * W);
+            const int64_t gi = (chbase + j * n + r) * W + c;
+            out[gi] = (TO)(SUB ? add[gi] - acc[u][v] : acc[u][v]);
         }
     }
 }
 
 // --------------------------------------------------------------- P0 SpMM
+// Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD
+// b % 8), each XCD with its own L2.  Neighbouring cell rows share most of
+// their columns, so the row range is remapped to give every XCD one
+// contiguous run of rows: XCD x takes logical blocks [start_x, start_x +
+// count_x) in order.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int x = b % 8, i = b / 8;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // y[r][c] = sum_t val[t] x[col[t]][c]; one wavefront per cell row, lanes =
 // (nonzero slot g, column c) with Wp = pow2 >= W columns per slot; four
 // independent gathers in flight per lane.
-template <class V>
+template <class V, class XT, class YT, bool XCD>
 __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ rowptr,
                                               const int32_t *__restrict__ col,
                                               const V *__restrict__ val, int nrow, int W, int Wp,
-                                              const double *__restrict__ x,
-                                              double *__restrict__ y) {
+                                              const XT *__restrict__ x,
+                                              YT *__restrict__ y) {
     const int lane = threadIdx.x & 63;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int r = (XCD ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (r >= nrow) return;
     const int G = 64 / Wp;
     const int g = lane / Wp, c = lane % Wp;
@@ -162,28 +188,28 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ rowptr
             const int64_t c0 = col[t], c1 = col[t + G], c2 = col[t + 2 * G], c3 = col[t + 3 * G];
             const double v0 = (double)val[t], v1 = (double)val[t + G];
             const double v2 = (double)val[t + 2 * G], v3 = (double)val[t + 3 * G];
-            a0 += v0 * x[c0 * W + c];
-            a1 += v1 * x[c1 * W + c];
-            a2 += v2 * x[c2 * W + c];
-            a3 += v3 * x[c3 * W + c];
+            a0 += v0 * (double)x[c0 * W + c];
+            a1 += v1 * (double)x[c1 * W + c];
+            a2 += v2 * (double)x[c2 * W + c];
+            a3 += v3 * (double)x[c3 * W + c];
         }
-        for (; t < e; t += G) a0 += (double)val[t] * x[(int64_t)col[t] * W + c];
+        for (; t < e; t += G) a0 += (double)val[t] * (double)x[(int64_t)col[t] * W + c];
     }
     double acc = (a0 + a1) + (a2 + a3);
     for (int off = Wp; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
-    if (g == 0 && c < W) y[(int64_t)r * W + c] = acc;
+    if (g == 0 && c < W) y[(int64_t)r * W + c] = (YT)acc;
 }
 
 // Block SpMM for n_ch channels: y[(a, r)][c] = sum_t sum_a2 val[t][a][a2]
 // x[(a2, col[t])][c]; one wavefront per cell row, all NCH output rows.
-template <class V, int NCH>
+template <class V, int NCH, class XT, class YT, bool XCD, int U>
 __global__ __launch_bounds__(256) void k_spmm_bsr(const int64_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col,
                                                   const V *__restrict__ val, int ncell, int W,
-                                                  int Wp, const double *__restrict__ x,
-                                                  double *__restrict__ y) {
+                                                  int Wp, const XT *__restrict__ x,
+                                                  YT *__restrict__ y) {
     const int lane = threadIdx.x & 63;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int r = (XCD ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (r >= ncell) return;
     const int G = 64 / Wp;
     const int g = lane / Wp, c = lane % Wp;
@@ -191,13 +217,35 @@ __global__ __launch_bounds__(256) void k_spmm_bsr(const int64_t *__restrict__ ro
     double acc[NCH];
 #pragma unroll
     for (int a = 0; a < NCH; ++a) acc[a] = 0.0;
+    // U > 1: U nonzeros per lane in flight (their column indices, then all
+    // their gathers, issued before any is used)
     if (c < W) {
-        for (int64_t t = b + g; t < e; t += G) {
+        int64_t t = b + g;
+        for (; U > 1 && t + (U - 1) * G < e; t += U * G) {
+            int64_t cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cc[u] = col[t + u * G];
+            double xv[U][NCH];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int a2 = 0; a2 < NCH; ++a2)
+                    xv[u][a2] = (double)x[((int64_t)a2 * ncell + cc[u]) * W + c];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const V *vb = val + (t + u * G) * NCH * NCH;
+#pragma unroll
+                for (int a2 = 0; a2 < NCH; ++a2)
+#pragma unroll
+                    for (int a = 0; a < NCH; ++a) acc[a] += (double)vb[a * NCH + a2] * xv[u][a2];
+            }
+        }
+        for (; t < e; t += G) {
             const int64_t cc = col[t];
             const V *vb = val + t * NCH * NCH;
 #pragma unroll
             for (int a2 = 0; a2 < NCH; ++a2) {
-                const double xv = x[((int64_t)a2 * ncell + cc) * W + c];
+                const double xv = (double)x[((int64_t)a2 * ncell + cc) * W + c];
 #pragma unroll
                 for (int a = 0; a < NCH; ++a) acc[a] += (double)vb[a * NCH + a2] * xv;
             }
@@ -207,16 +255,67 @@ __global__ __launch_bounds__(256) void k_spmm_bsr(const int64_t *__restrict__ ro
     for (int a = 0; a < NCH; ++a) {
         double v = acc[a];
         for (int off = Wp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-        if (g == 0 && c < W) y[((int64_t)a * ncell + r) * W + c] = v;
+        if (g == 0 && c < W) y[((int64_t)a * ncell + r) * W + c] = (YT)v;
+    }
+}
+
+// LDS-staged SpMM for any n_ch (n_ch = 1 is the s-wave case): one
+// wavefront (= workgroup) per cell row; the row's column indices and value
+// blocks are loaded a tile at a time with coalesced loads into LDS, then
+// every lane slot (nonzero slot g, column c) reads them as LDS broadcasts,
+// so global memory sees each value once instead of once per column lane.
+template <class V, int NCH, class XT, class YT>
+__global__ __launch_bounds__(64) void k_spmm_lds(const int64_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const V *__restrict__ val, int ncell, int W,
+                                                 int Wp, const XT *__restrict__ x,
+                                                 YT *__restrict__ y) {
+    constexpr int NV = NCH * NCH;
+    constexpr int T = NV <= 16 ? 64 : 32;   // nonzeros per tile
+    __shared__ int32_t cs[T];
+    __shared__ V vs[T * NV];
+    const int lane = threadIdx.x;
+    const int r = blockIdx.x;
+    const int G = 64 / Wp, g = lane / Wp, c = lane % Wp;
+    const int64_t b = rowptr[r], e = rowptr[r + 1];
+    double acc[NCH];
+#pragma unroll
+    for (int a = 0; a < NCH; ++a) acc[a] = 0.0;
+    for (int64_t t0 = b; t0 < e; t0 += T) {
+        const int n = (int)(e - t0 < T ? e - t0 : T);
+        __syncthreads();   // the previous tile has been consumed
+        for (int k = lane; k < n; k += 64) cs[k] = col[t0 + k];
+        for (int k = lane; k < n * NV; k += 64) vs[k] = val[t0 * NV + k];
+        __syncthreads();
+        if (c < W) {
+#pragma unroll 4
+            for (int k = g; k < n; k += G) {
+                const int64_t cc = cs[k];
+                const V *vb = vs + k * NV;
+#pragma unroll
+                for (int a2 = 0; a2 < NCH; ++a2) {
+                    const double xv = (double)x[((int64_t)a2 * ncell + cc) * W + c];
+#pragma unroll
+                    for (int a = 0; a < NCH; ++a) acc[a] += (double)vb[a * NCH + a2] * xv;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NCH; ++a) {
+        double v = acc[a];
+        for (int off = Wp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        if (g == 0 && c < W) y[((int64_t)a * ncell + r) * W + c] = (YT)v;
     }
 }
 
 // ------------------------------------------------------ Krylov vector ops
-// Rows are processed in chunks of kRB per workgroup.  Thread t handles
-// energy e = t % nEp (nEp = pow2 >= nE) and rows r0 + t / nEp + k (256/nEp),
-// k < NR = kRB nEp / 256, so loads of one row are contiguous across threads
-// and each thread keeps one energy.
-constexpr int kRB = 32;
+// Rows are processed in chunks of NR * (256 / nEp) per workgroup (nEp =
+// pow2 >= nE).  Thread t handles energy e = t % nEp and rows r0 + t / nEp +
+// k (256 / nEp), k < NR, so loads of one row are contiguous across threads
+// and each thread keeps one energy.  Larger NR means fewer per-chunk partial
+// sums to reduce, smaller NR more workgroups in flight.
+inline int chunk_rows_of(int nEp, int nr) { return nr * (256 / nEp); }
 
 // Reduce (sr, si) over the lanes of a wavefront that share the same energy
 // (lane offsets nEp, 2 nEp, ...).
@@ -285,12 +384,12 @@ template <int NR>
 __device__ __forceinline__ void chunk_rows(int64_t M, int nE, int nEp, int64_t (&off)[NR],
                                            bool &valid_e) {
     const int t = threadIdx.x, e = t % nEp, rs = t / nEp, rstep = 256 / nEp;
-    const int64_t r0 = (int64_t)blockIdx.x * kRB;
+    const int64_t r0 = (int64_t)blockIdx.x * (NR * rstep);
     valid_e = e < nE;
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         const int64_t row = r0 + rs + (int64_t)k * rstep;
-        off[k] = (rs + k * rstep < kRB && row < M) ? (row * nE + e) * 2 : -1;
+        off[k] = (row < M) ? (row * nE + e) * 2 : -1;
     }
 }
 
@@ -367,26 +466,55 @@ __global__ __launch_bounds__(256) void k_vupdate(const double *__restrict__ Vb, 
     }
 }
 
-// h[p] = sum_chunks partial[chunk][p] (one wavefront per pair p); also
-// written/accumulated into the Hessenberg column H[e][i][k] (layout
-// [nE][m+1][m] complex) when H is given.
-__global__ __launch_bounds__(256) void k_dots_reduce(const double *__restrict__ partial, int nchunk,
-                                                     int nvec, int nE, double *__restrict__ h,
-                                                     double *__restrict__ H, int m, int kcol,
-                                                     int accumulate) {
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+// Cross-chunk reduction of per-chunk partial sums partial[chunk][p] (p <
+// npair complex values), deterministic and in two stages.  Stage 1: grid
+// (npair/32, S); each workgroup sums a contiguous run of chunks for 32
+// consecutive p (8 chunk lanes per p, coalesced 512-byte rows), giving
+// out2[s][p].  Stage 2 sums the S values per p.
+__global__ __launch_bounds__(256) void k_reduce_stage1(const double *__restrict__ partial,
+                                                       int nchunk, int npair,
+                                                       double *__restrict__ out2) {
+    __shared__ double red[8][32][2];
+    const int t = threadIdx.x, pl = t & 31, cl = t >> 5;
+    const int p = blockIdx.x * 32 + pl;
+    const int S = gridDim.y, s = blockIdx.y;
+    const int cps = (nchunk + S - 1) / S;
+    const int c0 = s * cps, c1 = min(nchunk, c0 + cps);
+    double sr = 0.0, si = 0.0;
+    if (p < npair)
+        for (int c = c0 + cl; c < c1; c += 8) {
+            sr += partial[((int64_t)c * npair + p) * 2];
+            si += partial[((int64_t)c * npair + p) * 2 + 1];
+        }
+    red[cl][pl][0] = sr;
+    red[cl][pl][1] = si;
+    __syncthreads();
+    if (t < 32 && p < npair) {
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            ar += red[k][t][0];
+            ai += red[k][t][1];
+        }
+        out2[((int64_t)s * npair + p) * 2] = ar;
+        out2[((int64_t)s * npair + p) * 2 + 1] = ai;
+    }
+}
+
+// Stage 2 of the dot products: h[p] = sum_s out2[s][p]; also written or
+// accumulated into the Hessenberg column H[e][i][k] (layout [nE][m+1][m]
+// complex) when H is given (p = i nE + e).
+__global__ void k_dots_reduce(const double *__restrict__ out2, int S, int nvec, int nE,
+                              double *__restrict__ h, double *__restrict__ H, int m, int kcol,
+                              int accumulate) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int npair = nvec * nE;
     if (p >= npair) return;
     double sr = 0.0, si = 0.0;
-    for (int c = lane; c < nchunk; c += 64) {
-        sr += partial[((int64_t)c * npair + p) * 2];
-        si += partial[((int64_t)c * npair + p) * 2 + 1];
+    for (int s = 0; s < S; ++s) {
+        sr += out2[((int64_t)s * npair + p) * 2];
+        si += out2[((int64_t)s * npair + p) * 2 + 1];
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        sr += __shfl_xor(sr, off, 64);
-        si += __shfl_xor(si, off, 64);
-    }
-    if (lane != 0) return;
     h[2 * p] = sr;
     h[2 * p + 1] = si;
     if (H) {
@@ -461,29 +589,22 @@ __global__ void k_cycle_start(const double *__restrict__ nrm2, int nE, int m, do
     inv[e] = beta > 1e-300 ? 1.0 / beta : 0.0;
 }
 
-// After orthogonalising w = K v_k: reduce the per-chunk |w|^2 partials
-// (npart[chunk][e], one workgroup), then per energy H[k+1][k] = ||w||,
+// After orthogonalising w = K v_k: sum the stage-1 reduced |w|^2 partials
+// (npart[split][e]), then per energy H[k+1][k] = ||w||,
 // inv = 1/||w||, apply the previous Givens rotations to column k, form the
 // new one and update the residual estimate.
-__global__ __launch_bounds__(256) void k_givens(const double *__restrict__ npart, int nchunk,
-                                                double *__restrict__ H, int nE, int m, int k,
-                                                double tol, GState S, double *__restrict__ inv) {
-    __shared__ double nr2[32];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int ee = wave; ee < nE; ee += 4) {
-        double v = 0.0;
-        for (int cch = lane; cch < nchunk; cch += 64) v += npart[2 * ((int64_t)cch * nE + ee)];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) nr2[ee] = v;
-    }
-    __syncthreads();
+__global__ __launch_bounds__(64) void k_givens(const double *__restrict__ npart, int nsplit,
+                                               double *__restrict__ H, int nE, int m, int k,
+                                               double tol, GState S, double *__restrict__ inv) {
     const int e = threadIdx.x;
     if (e >= nE) return;
+    double n2 = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) n2 += npart[2 * ((int64_t)sp * nE + e)];
     double *st = S.st + e * kSt;
     double *He = H + (int64_t)e * (m + 1) * m * 2;
     auto Hr = [&](int i) -> double & { return He[(i * m + k) * 2]; };
     auto Hi = [&](int i) -> double & { return He[(i * m + k) * 2 + 1]; };
-    const double hn = sqrt(nr2[e]);
+    const double hn = sqrt(n2);
     Hr(k + 1) = hn;
     Hi(k + 1) = 0.0;
     const double beta = st[0];
@@ -643,87 +764,172 @@ struct Batch {
     GState S;
     int64_t vstride;
     int nchunk;
+    int apply_cfg;   // tile shape of the block products (kApplyCfg)
+    int nr;          // rows per thread of the vector kernels (1, 2, 4)
+    int nsplit;      // stage-1 splits of the cross-chunk reductions
+    double *out2;    // stage-1 results [nsplit][pairs][2]
+    bool lowp;       // FP32 intermediate panels in the inner iterations
+    int spmm_cfg;    // P0 SpMM variant (kSpmmCfg)
+    void set_chunks(int nr_) {
+        nr = nr_;
+        nchunk = (int)((M + (int64_t)nr * (256 / nEp) - 1) / ((int64_t)nr * (256 / nEp)));
+        nsplit = std::max(1, std::min(64, (nchunk + 127) / 128));
+    }
 };
+constexpr int kMaxSplit = 64;
 
-template <bool USE_G, bool SUB>
-void launch_block_apply(Batch &b, dim3 grid, ChPtrs mats, const double *in, const double *add,
-                        double *out) {
-    wpcd_ctx *c = b.c;
-    hipLaunchKernelGGL((k_block_apply<USE_G, SUB>), grid, dim3(256), 0, c->stream, mats, c->np,
-                       c->nq, b.W, in, b.G, add, out);
+// Candidate tile shapes (TM x TN) of the block products.
+constexpr int kApplyCfg = 4;
+constexpr int kApplyTM[kApplyCfg] = {64, 32, 32, 16};
+constexpr int kApplyTN[kApplyCfg] = {64, 64, 32, 64};
+constexpr int kNrCand[3] = {1, 2, 4};
+
+int apply_blocks(const wpcd_ctx *c, int W, int cfg) {
+    return cdiv((int64_t)c->nq * W, kApplyTN[cfg]) * cdiv(c->np, kApplyTM[cfg]) * c->nch;
 }
 
-void op_apply(Batch &b, const double *x, double *out, bool with_g, bool sub) {
+template <bool USE_G, bool SUB, int TM, int TN, class TI, class TO>
+void launch_block_apply_t(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
+    wpcd_ctx *c = b.c;
+    dim3 grid(cdiv((int64_t)c->nq * b.W, TN), cdiv(c->np, TM), c->nch);
+    hipLaunchKernelGGL((k_block_apply<USE_G, SUB, TM, TN, TI, TO>), grid, dim3(256), 0, c->stream,
+                       mats, c->np, c->nq, b.W, in, b.G, add, out);
+}
+
+template <bool USE_G, bool SUB, class TI, class TO>
+void launch_block_apply(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
+    switch (b.apply_cfg) {
+        case 0: launch_block_apply_t<USE_G, SUB, 64, 64>(b, mats, in, add, out); break;
+        case 1: launch_block_apply_t<USE_G, SUB, 32, 64>(b, mats, in, add, out); break;
+        case 2: launch_block_apply_t<USE_G, SUB, 32, 32>(b, mats, in, add, out); break;
+        default: launch_block_apply_t<USE_G, SUB, 16, 64>(b, mats, in, add, out); break;
+    }
+}
+
+// P0 SpMM candidates: 0 plain, 1 XCD-contiguous rows, 2 several nonzeros
+// in flight per lane (block form), 3 both, 4 LDS-staged tiles.
+constexpr int kSpmmCfg = 5;
+
+template <class PT, class V, int NCH>
+void launch_spmm_lds(Batch &b, const V *val, const PT *x, PT *y) {
+    wpcd_ctx *c = b.c;
+    const int nrow = c->np * c->nq;
+    hipLaunchKernelGGL((k_spmm_lds<V, NCH, PT, PT>), dim3(nrow), dim3(64), 0, c->stream,
+                       c->d_rowptr.ptr, c->d_col.ptr, val, nrow, b.W, b.Wp, x, y);
+    WPCD_HIP(hipGetLastError());
+}
+
+template <class PT, class V>
+void launch_spmm_lds_n(Batch &b, const V *val, const PT *x, PT *y) {
+    switch (b.c->nch) {
+        case 1: launch_spmm_lds<PT, V, 1>(b, val, x, y); break;
+        case 2: launch_spmm_lds<PT, V, 2>(b, val, x, y); break;
+        case 3: launch_spmm_lds<PT, V, 3>(b, val, x, y); break;
+        case 4: launch_spmm_lds<PT, V, 4>(b, val, x, y); break;
+        case 5: launch_spmm_lds<PT, V, 5>(b, val, x, y); break;
+        case 6: launch_spmm_lds<PT, V, 6>(b, val, x, y); break;
+        case 7: launch_spmm_lds<PT, V, 7>(b, val, x, y); break;
+        default: launch_spmm_lds<PT, V, 8>(b, val, x, y); break;
+    }
+}
+
+template <class PT, class V, bool XCD, int U>
+void launch_spmm_v(Batch &b, const V *val, const PT *x, PT *y) {
+    wpcd_ctx *c = b.c;
+    const int nrow = c->np * c->nq;
+    const dim3 grid(cdiv(nrow, 4)), blk(256);
+    const int64_t *rp = c->d_rowptr.ptr;
+    const int32_t *cl = c->d_col.ptr;
+    hipStream_t s = c->stream;
+    switch (c->nch) {
+        case 1: hipLaunchKernelGGL((k_spmm<V, PT, PT, XCD>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+        case 2: hipLaunchKernelGGL((k_spmm_bsr<V, 2, PT, PT, XCD, U>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+        case 3: hipLaunchKernelGGL((k_spmm_bsr<V, 3, PT, PT, XCD, U>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+        case 4: hipLaunchKernelGGL((k_spmm_bsr<V, 4, PT, PT, XCD, U>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+        case 5: hipLaunchKernelGGL((k_spmm_bsr<V, 5, PT, PT, XCD, (U > 2 ? 2 : U)>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+        case 6: hipLaunchKernelGGL((k_spmm_bsr<V, 6, PT, PT, XCD, (U > 2 ? 2 : U)>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+        case 7: hipLaunchKernelGGL((k_spmm_bsr<V, 7, PT, PT, XCD, (U > 2 ? 2 : U)>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+        default: hipLaunchKernelGGL((k_spmm_bsr<V, 8, PT, PT, XCD, (U > 2 ? 2 : U)>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
+    }
+    WPCD_HIP(hipGetLastError());
+}
+
+template <class PT>
+void launch_spmm(Batch &b, const PT *x, PT *y, int cfg) {
+    wpcd_ctx *c = b.c;
+    auto go = [&](auto val) {
+        if (cfg == 4) {
+            launch_spmm_lds_n<PT>(b, val, x, y);
+            return;
+        }
+        switch (cfg) {
+            case 0: launch_spmm_v<PT, std::remove_const_t<std::remove_pointer_t<decltype(val)>>, false, 1>(b, val, x, y); break;
+            case 1: launch_spmm_v<PT, std::remove_const_t<std::remove_pointer_t<decltype(val)>>, true, 1>(b, val, x, y); break;
+            case 2: launch_spmm_v<PT, std::remove_const_t<std::remove_pointer_t<decltype(val)>>, false, 4>(b, val, x, y); break;
+            default: launch_spmm_v<PT, std::remove_const_t<std::remove_pointer_t<decltype(val)>>, true, 4>(b, val, x, y); break;
+        }
+    };
+    if (b.fp64) go((const double *)c->d_val64.ptr);
+    else go((const float *)c->d_val32.ptr);
+}
+
+// out = (1 - K) x (sub) or K x / O P0 V~ x (with_g false: the driving
+// term).  lowp: the two intermediate panels in FP32 (inner iterations of the
+// mixed tier); otherwise FP64.
+template <class PT>
+void op_apply_t(Batch &b, const double *x, double *out, bool with_g, bool sub) {
     wpcd_ctx *c = b.c;
     ChPtrs vt{}, oo{};
     for (int a = 0; a < c->nch; ++a) {
         vt.p[a] = c->waves[c->ch_wave[a]].Vt.ptr;
         oo.p[a] = c->waves[c->ch_wave[a]].O.ptr;
     }
-    dim3 grid(cdiv(c->np, kTR), c->nch * c->nq);
+    PT *T1 = (PT *)b.T1, *T2 = (PT *)b.T2;
     {
         TimedLaunch tl(c->timer, c->stream, "apply_vt", WPCD_TIME_SOLVE);
-        if (with_g) launch_block_apply<true, false>(b, grid, vt, x, nullptr, b.T1);
-        else launch_block_apply<false, false>(b, grid, vt, x, nullptr, b.T1);
+        if (with_g) launch_block_apply<true, false>(b, vt, x, nullptr, T1);
+        else launch_block_apply<false, false>(b, vt, x, nullptr, T1);
         WPCD_HIP(hipGetLastError());
     }
-    if (c->nch > 1) {
-        const int nrow = c->np * c->nq;
+    {
         TimedLaunch tl(c->timer, c->stream, "spmm", WPCD_TIME_SOLVE);
-        auto go = [&](auto kd, auto kf) {
-            if (b.fp64)
-                hipLaunchKernelGGL(kd, dim3(cdiv(nrow, 4)), dim3(256), 0, c->stream, c->d_rowptr.ptr,
-                                   c->d_col.ptr, c->d_val64.ptr, nrow, b.W, b.Wp, b.T1, b.T2);
-            else
-                hipLaunchKernelGGL(kf, dim3(cdiv(nrow, 4)), dim3(256), 0, c->stream, c->d_rowptr.ptr,
-                                   c->d_col.ptr, c->d_val32.ptr, nrow, b.W, b.Wp, b.T1, b.T2);
-        };
-        switch (c->nch) {
-            case 2: go(k_spmm_bsr<double, 2>, k_spmm_bsr<float, 2>); break;
-            case 3: go(k_spmm_bsr<double, 3>, k_spmm_bsr<float, 3>); break;
-            case 4: go(k_spmm_bsr<double, 4>, k_spmm_bsr<float, 4>); break;
-            case 5: go(k_spmm_bsr<double, 5>, k_spmm_bsr<float, 5>); break;
-            case 6: go(k_spmm_bsr<double, 6>, k_spmm_bsr<float, 6>); break;
-            case 7: go(k_spmm_bsr<double, 7>, k_spmm_bsr<float, 7>); break;
-            default: go(k_spmm_bsr<double, 8>, k_spmm_bsr<float, 8>); break;
-        }
-        WPCD_HIP(hipGetLastError());
-    } else {
-        const int nrow = c->np * c->nq;
-        TimedLaunch tl(c->timer, c->stream, "spmm", WPCD_TIME_SOLVE);
-        if (b.fp64)
-            hipLaunchKernelGGL(k_spmm<double>, dim3(cdiv(nrow, 4)), dim3(256), 0, c->stream,
-                               c->d_rowptr.ptr, c->d_col.ptr, c->d_val64.ptr, nrow, b.W, b.Wp,
-                               b.T1, b.T2);
-        else
-            hipLaunchKernelGGL(k_spmm<float>, dim3(cdiv(nrow, 4)), dim3(256), 0, c->stream,
-                               c->d_rowptr.ptr, c->d_col.ptr, c->d_val32.ptr, nrow, b.W, b.Wp,
-                               b.T1, b.T2);
-        WPCD_HIP(hipGetLastError());
+        launch_spmm<PT>(b, T1, T2, b.spmm_cfg);
     }
     {
         TimedLaunch tl(c->timer, c->stream, "apply_o", WPCD_TIME_SOLVE);
-        if (sub) launch_block_apply<false, true>(b, grid, oo, b.T2, x, out);
-        else launch_block_apply<false, false>(b, grid, oo, b.T2, nullptr, out);
+        if (sub) launch_block_apply<false, true>(b, oo, T2, x, out);
+        else launch_block_apply<false, false>(b, oo, T2, nullptr, out);
         WPCD_HIP(hipGetLastError());
     }
 }
 
-// Dispatch on NR = rows per thread in a kRB-row chunk = max(1, kRB nEp / 256).
+void op_apply(Batch &b, const double *x, double *out, bool with_g, bool sub, bool lowp = false) {
+    if (lowp) op_apply_t<float>(b, x, out, with_g, sub);
+    else op_apply_t<double>(b, x, out, with_g, sub);
+}
+
+// Rows per thread of the vector kernels: NR in {1, 2, 4}.
 template <class F>
-void with_nr(int nEp, F &&f) {
-    switch (nEp) {
-        case 1: case 2: case 4: case 8: f(std::integral_constant<int, 1>{}); break;
-        case 16: f(std::integral_constant<int, 2>{}); break;
+void with_nr(int nr, F &&f) {
+    switch (nr) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
         default: f(std::integral_constant<int, 4>{}); break;
     }
+}
+
+// Stage 1 of the cross-chunk reduction of npair partial sums -> b.out2.
+void reduce_stage1(Batch &b, int npair) {
+    hipLaunchKernelGGL(k_reduce_stage1, dim3(cdiv(npair, 32), b.nsplit), dim3(256), 0,
+                       b.c->stream, b.partial, b.nchunk, npair, b.out2);
 }
 
 void reduce_partials(Batch &b, int nvec, double *h, double *H, int kcol, int accumulate) {
     wpcd_ctx *c = b.c;
     TimedLaunch tl(c->timer, c->stream, "gmres_reduce", WPCD_TIME_SOLVE);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(cdiv(nvec * b.nE, 4)), dim3(256), 0, c->stream,
-                       b.partial, b.nchunk, nvec, b.nE, h, H, b.m, kcol, accumulate);
+    reduce_stage1(b, nvec * b.nE);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(cdiv(nvec * b.nE, 256)), dim3(256), 0, c->stream,
+                       b.out2, b.nsplit, nvec, b.nE, h, H, b.m, kcol, accumulate);
     WPCD_HIP(hipGetLastError());
 }
 
@@ -733,7 +939,7 @@ void dots(Batch &b, const double *Vb, int nvec, const double *w, double *h, doub
     wpcd_ctx *c = b.c;
     {
         TimedLaunch tl(c->timer, c->stream, "gmres_dots", WPCD_TIME_SOLVE);
-        with_nr(b.nEp, [&](auto nr) {
+        with_nr(b.nr, [&](auto nr) {
             hipLaunchKernelGGL(k_vdots<decltype(nr)::value>, dim3(b.nchunk), dim3(256), 0,
                                c->stream, Vb, b.vstride, nvec, w, b.M, b.nE, b.nEp, b.partial);
         });
@@ -748,7 +954,7 @@ template <bool DOTS, bool NORM>
 void vupdate(Batch &b, int nvec, double *w) {
     wpcd_ctx *c = b.c;
     TimedLaunch tl(c->timer, c->stream, "gmres_update", WPCD_TIME_SOLVE);
-    with_nr(b.nEp, [&](auto nr) {
+    with_nr(b.nr, [&](auto nr) {
         hipLaunchKernelGGL((k_vupdate<decltype(nr)::value, DOTS, NORM>), dim3(b.nchunk), dim3(256),
                            0, c->stream, b.Vb, b.vstride, nvec, b.h, b.M, b.nE, b.nEp, w,
                            b.partial);
@@ -756,13 +962,169 @@ void vupdate(Batch &b, int nvec, double *w) {
     WPCD_HIP(hipGetLastError());
 }
 
+// One Arnoldi step k: w = (1 - K) v_k, classical Gram-Schmidt in two passes
+// (the second pass's dots fused into the first update, |w|^2 into the
+// second), then the Givens update of every energy and w /= |w|.  In the
+// mixed tier the operator's intermediate panels are FP32 here; the true
+// residual that starts each cycle is formed with FP64 panels, so a restart
+// is a step of iterative refinement.
+void iteration(Batch &b, int k, double tol) {
+    wpcd_ctx *c = b.c;
+    hipStream_t s = c->stream;
+    const int64_t vec = b.vstride;
+    double *vk = b.Vb + (int64_t)k * vec;
+    double *w = b.Vb + (int64_t)(k + 1) * vec;
+    op_apply(b, vk, w, true, true, b.lowp);
+    dots(b, b.Vb, k + 1, w, b.h, b.H, k, 0);
+    vupdate<true, false>(b, k + 1, w);
+    reduce_partials(b, k + 1, b.h, b.H, k, 1);
+    vupdate<false, true>(b, k + 1, w);
+    TimedLaunch tl(c->timer, s, "gmres_givens", WPCD_TIME_SOLVE);
+    reduce_stage1(b, b.nE);
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, b.out2, b.nsplit, b.H, b.nE, b.m, k,
+                       tol, b.S, b.inv);
+    hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * b.nE, 256)), dim3(256), 0, s, b.inv, b.M, b.nE, w);
+    WPCD_HIP(hipGetLastError());
+}
+
+// Capture iterations [k, k + n) of this batch as one executable graph.
+hipGraphExec_t capture_group(Batch &b, int k, int n, double tol) {
+    hipStream_t s = b.c->stream;
+    hipGraph_t g = nullptr;
+    WPCD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int i = 0; i < n; ++i) iteration(b, k + i, tol);
+    } catch (...) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(s, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+    }
+    WPCD_HIP(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    WPCD_HIP(e);
+    return ex;
+}
+
+// Graphs of a batch are valid while every pointer, size and constant the
+// captured launches use is unchanged: all of them form the key.
+IterGraphs *graphs_for(Batch &b, double tol, int check_every) {
+    wpcd_ctx *c = b.c;
+    std::vector<uint64_t> key = {
+        (uint64_t)b.Vb, (uint64_t)b.T1, (uint64_t)b.G, (uint64_t)b.H, (uint64_t)b.partial,
+        (uint64_t)b.h, (uint64_t)b.inv, (uint64_t)b.S.st, (uint64_t)b.S.cs, (uint64_t)b.S.sn,
+        (uint64_t)b.S.g, (uint64_t)c->d_rowptr.ptr, (uint64_t)c->d_col.ptr,
+        (uint64_t)(b.fp64 ? (void *)c->d_val64.ptr : (void *)c->d_val32.ptr),
+        (uint64_t)b.nE, (uint64_t)b.m, (uint64_t)b.M, (uint64_t)b.fp64, (uint64_t)b.lowp,
+        (uint64_t)b.apply_cfg, (uint64_t)b.spmm_cfg,
+        (uint64_t)b.nr, (uint64_t)b.nchunk, (uint64_t)b.nsplit, (uint64_t)b.out2,
+        (uint64_t)c->np, (uint64_t)c->nq, (uint64_t)c->nch,
+        (uint64_t)b.vstride};
+    uint64_t tb;
+    std::memcpy(&tb, &tol, sizeof tb);
+    key.push_back(tb);
+    for (int a = 0; a < c->nch; ++a) {
+        key.push_back((uint64_t)c->waves[c->ch_wave[a]].Vt.ptr);
+        key.push_back((uint64_t)c->waves[c->ch_wave[a]].O.ptr);
+    }
+    for (auto &g : c->graphs)
+        if (g.key == key) return &g;
+    if (c->graphs.size() >= 8) {
+        c->graphs.front().release();
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.emplace_back();
+    IterGraphs &g = c->graphs.back();
+    g.key = key;
+    g.exec.assign(cdiv(b.m, check_every), nullptr);
+    return &g;
+}
+
+// Microseconds per launch of f (one warm-up, then reps timed launches).
+template <class F>
+double time_launches(hipStream_t s, F &&f, int reps = 3) {
+    hipEvent_t a, z;
+    WPCD_HIP(hipEventCreate(&a));
+    WPCD_HIP(hipEventCreate(&z));
+    f();
+    WPCD_HIP(hipEventRecord(a, s));
+    for (int i = 0; i < reps; ++i) f();
+    WPCD_HIP(hipEventRecord(z, s));
+    WPCD_HIP(hipEventSynchronize(z));
+    float ms = 0.f;
+    WPCD_HIP(hipEventElapsedTime(&ms, a, z));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(z);
+    return 1e3 * ms / reps;
+}
+
+// Launch shapes of this batch (buffers must be allocated; their contents
+// are only read, or written where they are scratch).
+void choose_shapes(Batch &b, int m) {
+    wpcd_ctx *c = b.c;
+    char key[64];
+    std::snprintf(key, sizeof key, "np=%d nq=%d W=%d nch=%d", c->np, c->nq, b.W, c->nch);
+    int heur = 2;
+    for (int i = 0; i < kApplyCfg; ++i)
+        if (apply_blocks(c, b.W, i) >= 512) {
+            heur = i;
+            break;
+        }
+    ChPtrs vt{};
+    for (int a = 0; a < c->nch; ++a) vt.p[a] = c->waves[c->ch_wave[a]].Vt.ptr;
+    b.apply_cfg = tune_pick(c, "block_apply", key, kApplyCfg, heur, [&](int i) {
+        b.apply_cfg = i;
+        return time_launches(c->stream, [&] {
+            launch_block_apply<true, false>(b, vt, (const double *)b.X, nullptr, b.T1);
+            WPCD_HIP(hipGetLastError());
+        });
+    });
+    std::snprintf(key, sizeof key, "M=%lld nEp=%d", (long long)b.M, b.nEp);
+    heur = 0;
+    for (int i = 2; i >= 0; --i)
+        if (cdiv(b.M, chunk_rows_of(b.nEp, kNrCand[i])) >= 1024) {
+            heur = i;
+            break;
+        }
+    const int nvec = std::min(m + 1, 8);
+    const int ch = tune_pick(c, "vector_rows", key, 3, heur, [&](int i) {
+        b.set_chunks(kNrCand[i]);
+        // the dot products of one Gram-Schmidt pass with their reduction
+        return time_launches(c->stream, [&] {
+            with_nr(b.nr, [&](auto nr) {
+                hipLaunchKernelGGL(k_vdots<decltype(nr)::value>, dim3(b.nchunk), dim3(256), 0,
+                                   c->stream, b.Vb, b.vstride, nvec, b.Vb, b.M, b.nE, b.nEp,
+                                   b.partial);
+            });
+            reduce_partials(b, nvec, b.h, nullptr, 0, 0);
+            WPCD_HIP(hipGetLastError());
+        });
+    });
+    b.set_chunks(kNrCand[ch]);
+    // P0 SpMM: the variant for the inner iterations' panel type
+    std::snprintf(key, sizeof key, "nnz=%lld nch=%d W=%d %s%s", (long long)c->nnz, c->nch, b.W,
+                  b.fp64 ? "f64" : "f32", b.lowp ? " lowp" : "");
+    // candidates: the s-wave kernel has no unrolled form
+    std::vector<int> cand = c->nch > 1 ? std::vector<int>{0, 1, 2, 3, 4} : std::vector<int>{0, 1, 4};
+    const int pick = tune_pick(c, "spmm", key, (int)cand.size(), 0, [&](int i) {
+        return time_launches(c->stream, [&] {
+            if (b.lowp) launch_spmm<float>(b, (const float *)b.T1, (float *)b.T2, cand[i]);
+            else launch_spmm<double>(b, b.T1, b.T2, cand[i]);
+        });
+    });
+    b.spmm_cfg = cand[pick];
+}
+
 }  // namespace
 
 // Solve the batch of energies already validated by the caller.
 // idx0: entrance row per energy.
 void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
-                 bool fp64, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
+                 int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
                  GmresOut &out) {
+    const bool fp64 = prec == WPCD_FP64;
     std::vector<int> &iters = out.iters, &edge_flag = out.edge;
     std::vector<double> &resid = out.resid;
     const int nE = (int)E.size();
@@ -776,16 +1138,17 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     b.m = m;
     b.M = (int64_t)c->nch * c->nq * c->np;
     b.fp64 = fp64;
+    b.lowp = prec == WPCD_MIXED_REFINE;
     const int64_t vec = b.M * b.W;   // doubles per batched vector
     b.vstride = vec;
-    b.nchunk = cdiv(b.M, kRB);
+    const int max_chunks = cdiv(b.M, chunk_rows_of(b.nEp, 1));
     c->d_G.reserve(vec);
     c->d_X.reserve(vec);
     c->d_B.reserve(vec);
     c->d_T1.reserve(2 * vec);
     c->d_V.reserve((size_t)(m + 1) * vec);
     c->d_Hess.reserve((size_t)nE * (m + 1) * m * 2);
-    c->d_partial.reserve((size_t)b.nchunk * (m + 1) * nE * 2);
+    c->d_partial.reserve((size_t)(max_chunks + kMaxSplit) * (m + 1) * nE * 2);
     c->d_W.reserve(vec);
     c->d_misc.reserve((size_t)nE * (kSt + 2 * m + 2 * (m + 1) + m + 4) + (size_t)(m + 1) * nE * 2 +
                       (size_t)nE * m * 2 + 64);
@@ -800,6 +1163,7 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     b.Vb = c->d_V.ptr;
     b.H = c->d_Hess.ptr;
     b.partial = c->d_partial.ptr;
+    b.out2 = c->d_partial.ptr + (size_t)max_chunks * (m + 1) * nE * 2;
     double *ms = c->d_misc.ptr;
     b.S.st = ms;
     ms += nE * kSt;
@@ -819,6 +1183,7 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     b.kuse = flag + nE;              // [nE, 2 nE): GMRES columns used
 
     hipStream_t s = c->stream;
+    choose_shapes(b, m);
     // energies
     double *dE = c->d_T1.ptr;   // scratch: T1 not yet in use
     WPCD_HIP(hipMemcpyAsync(dE, E.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
@@ -885,6 +1250,10 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     int total = 0;
     std::vector<double> sth(nE * kSt);
     const int check_every = 4;
+    // graphs replay launches exactly; kernel timing needs the eager path
+    IterGraphs *graphs = (c->use_graphs && !(c->timer.enabled & WPCD_TIME_SOLVE))
+                             ? graphs_for(b, tol, check_every)
+                             : nullptr;
     bool all_done = false;
     while (total < max_iter && !all_done) {
         // cycle start from r
@@ -894,37 +1263,26 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
         hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.inv, b.M, nE, b.R);
         WPCD_HIP(hipMemcpyAsync(b.Vb, b.R, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
         WPCD_HIP(hipMemsetAsync(b.H, 0, (size_t)nE * (m + 1) * m * 2 * sizeof(double), s));
-        int k = 0;
-        for (; k < m && total < max_iter; ++k) {
-            double *vk = b.Vb + (int64_t)k * vec;
-            double *w = b.Vb + (int64_t)(k + 1) * vec;
-            op_apply(b, vk, w, true, true);
-            // classical Gram-Schmidt, two passes; the second pass's dots are
-            // fused into the first update, |w|^2 into the second
-            dots(b, b.Vb, k + 1, w, b.h, b.H, k, 0);
-            vupdate<true, false>(b, k + 1, w);
-            reduce_partials(b, k + 1, b.h, b.H, k, 1);
-            vupdate<false, true>(b, k + 1, w);
-            {
-                TimedLaunch tl(c->timer, s, "gmres_givens", WPCD_TIME_SOLVE);
-                hipLaunchKernelGGL(k_givens, dim3(1), dim3(256), 0, s, b.partial, b.nchunk, b.H, nE,
-                                   m, k, tol, b.S, b.inv);
-                hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.inv, b.M,
-                                   nE, w);
-                WPCD_HIP(hipGetLastError());
+        // iterations in groups of check_every: a full group replays its
+        // captured graph (captured on first use), the rest launch eagerly;
+        // convergence is read back after each group
+        for (int k = 0; k < m && total < max_iter;) {
+            const int kg = std::min({check_every, m - k, max_iter - total});
+            if (graphs && kg == check_every) {
+                hipGraphExec_t &ex = graphs->exec[k / check_every];
+                if (!ex) ex = capture_group(b, k, kg, tol);
+                WPCD_HIP(hipGraphLaunch(ex, s));
+            } else {
+                for (int i = 0; i < kg; ++i) iteration(b, k + i, tol);
             }
-            ++total;
-            if ((k + 1) % check_every == 0 || k + 1 == m) {
-                WPCD_HIP(hipMemcpyAsync(sth.data(), b.S.st, sth.size() * sizeof(double),
-                                        hipMemcpyDeviceToHost, s));
-                WPCD_HIP(hipStreamSynchronize(s));
-                bool done = true;
-                for (int e = 0; e < nE; ++e) done &= sth[e * kSt + 3] != 0.0;
-                if (done) {
-                    ++k;
-                    break;
-                }
-            }
+            k += kg;
+            total += kg;
+            WPCD_HIP(hipMemcpyAsync(sth.data(), b.S.st, sth.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+            WPCD_HIP(hipStreamSynchronize(s));
+            bool done = true;
+            for (int e = 0; e < nE; ++e) done &= sth[e * kSt + 3] != 0.0;
+            if (done) break;
         }
         hipLaunchKernelGGL(k_trisolve, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.H, nE, m, b.S, b.y,
                            b.kuse);
@@ -948,7 +1306,6 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
             resid[e] = bn > 0 ? std::sqrt(rn[2 * e]) / bn : 0.0;
             if (resid[e] > tol) all_done = false;
         }
-        (void)k;
     }
 }
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <thread>
 #include <vector>
 
 #include "wpcd_internal.h"
@@ -395,13 +396,14 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
                  "build_basis and build_p must come first");
     WPCD_REQUIRE(E && out && n_E >= 0, WPCD_E_INVALID, "E/out NULL or n_E < 0");
-    WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
-    WPCD_REQUIRE(prec == WPCD_MIXED || c->p_fp64, WPCD_E_STATE, "FP64 solve needs an FP64 P0 build");
+    WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED || prec == WPCD_MIXED_REFINE,
+                 WPCD_E_INVALID, "bad precision");
+    WPCD_REQUIRE(prec != WPCD_FP64 || c->p_fp64, WPCD_E_STATE, "FP64 solve needs an FP64 P0 build");
     WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE, "mixed solve needs a mixed P0 build");
     int m = 48, max_iter = 400;
     // FP32 storage of P0 perturbs the operator at the 1e-7 level: a mixed
     // solve gains nothing below 1e-9
-    double tol = prec == WPCD_MIXED ? 1e-9 : 1e-12;
+    double tol = prec == WPCD_FP64 ? 1e-12 : 1e-9;
     int want_breakup = 0, warm_kind = WPCD_WARM_NONE;
     if (opts) {
         if (opts->krylov_dim > 0) m = opts->krylov_dim;
@@ -484,7 +486,7 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
             for (int t = 0; t < nb; ++t) wc.given.push_back(opts->x0 + (size_t)active[b0 + t] * M * 2);
         }
         GmresOut go;
-        gmres_batch(c, Eb, idx0, prec == WPCD_FP64, m, max_iter, tol,
+        gmres_batch(c, Eb, idx0, prec, m, max_iter, tol,
                     warm_kind == WPCD_WARM_NONE ? nullptr : warm_fill, &wc, go);
         // amplitude list: elastic first, then open breakup pseudostates
         std::vector<int64_t> rows;
@@ -994,6 +996,31 @@ wpcd_status wpcd_solve(wpcd_ctx *c, const double *E, int32_t n_E, wpcd_precision
     return guarded(c, [&] { solve_impl(c, E, n_E, prec, opts, out, breakup_out, nullptr); });
 }
 
+wpcd_status wpcd_solve_multi(wpcd_ctx *const *ctxs, int32_t n_sys, const double *const *E,
+                             const int32_t *n_E, wpcd_precision prec, const wpcd_solve_opts *opts,
+                             wpcd_energy_result *const *out, wpcd_status *status_out) {
+    if (!ctxs || !E || !n_E || !out || n_sys < 0) return WPCD_E_INVALID;
+    for (int i = 0; i < n_sys; ++i) {
+        if (!ctxs[i]) return WPCD_E_INVALID;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return WPCD_E_INVALID;   // a context is not thread-safe
+    }
+    // one host thread per system: each context launches on its own stream,
+    // so the systems' kernels overlap on the device
+    std::vector<wpcd_status> st(n_sys, WPCD_OK);
+    std::vector<std::thread> th;
+    th.reserve(n_sys);
+    for (int i = 0; i < n_sys; ++i)
+        th.emplace_back([&, i] { st[i] = wpcd_solve(ctxs[i], E[i], n_E[i], prec, opts, out[i], nullptr); });
+    for (auto &t : th) t.join();
+    wpcd_status first = WPCD_OK;
+    for (int i = 0; i < n_sys; ++i) {
+        if (status_out) status_out[i] = st[i];
+        if (first == WPCD_OK) first = st[i];
+    }
+    return first;
+}
+
 wpcd_status wpcd_set_multipliers(wpcd_ctx *c, const double *mult, int32_t n_mult) {
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_basis && c->has_pot, WPCD_E_STATE, "no basis/potential");
@@ -1009,6 +1036,41 @@ wpcd_status wpcd_mlp_eval(wpcd_ctx *c, int32_t n_in, int32_t n_hidden, int32_t n
                           const float *params, int32_t batch, const float *X, const float *T,
                           float *Y_out, float *grad_out, double *loss_out) {
     return guarded(c, [&] { mlp_eval(c, n_in, n_hidden, n_out, params, batch, X, T, Y_out, grad_out, loss_out); });
+}
+
+wpcd_status wpcd_set_autotune(wpcd_ctx *c, int32_t mode) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(mode == WPCD_TUNE_HEURISTIC || mode == WPCD_TUNE_MEASURE ||
+                         (mode >= WPCD_TUNE_FORCE && mode < WPCD_TUNE_FORCE + 64),
+                     WPCD_E_INVALID, "unknown autotune mode");
+        c->tune.mode = mode;
+        c->tune.entries.clear();
+    });
+}
+
+wpcd_status wpcd_get_autotune(wpcd_ctx *c, wpcd_tune_entry *out, int32_t n, int32_t *n_out) {
+    return guarded(c, [&] {
+        const int cnt = (int)c->tune.entries.size();
+        for (int k = 0; k < cnt && k < n && out; ++k) {
+            const auto &e = c->tune.entries[k];
+            std::memset(&out[k], 0, sizeof(out[k]));
+            std::snprintf(out[k].name, sizeof(out[k].name), "%s", e.name.c_str());
+            std::snprintf(out[k].key, sizeof(out[k].key), "%s", e.key.c_str());
+            out[k].choice = e.choice;
+            out[k].n_candidates = e.n_cand;
+            out[k].us = e.us;
+        }
+        if (n_out) *n_out = cnt;
+    });
+}
+
+wpcd_status wpcd_set_graphs(wpcd_ctx *c, int32_t enable) {
+    return guarded(c, [&] {
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+        c->use_graphs = enable != 0;
+        for (auto &g : c->graphs) g.release();
+        c->graphs.clear();
+    });
 }
 
 wpcd_status wpcd_set_timing(wpcd_ctx *c, int32_t enable) {
@@ -1089,6 +1151,8 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->d_jac.release();
     c->d_flag.release();
     c->learned.release();
+    for (auto &g : c->graphs) g.release();
+    c->graphs.clear();
     c->d_pot.release();
     c->d_mcoef.release();
     if (c->own_stream) (void)hipStreamDestroy(c->stream);

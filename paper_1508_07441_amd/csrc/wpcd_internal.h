@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -156,6 +157,29 @@ struct Learned {
     }
 };
 
+// Launch-shape decisions of the context, keyed by kernel family and
+// problem shape (see wpcd_set_autotune).
+struct Tuning {
+    int mode = 0;
+    struct Entry {
+        std::string name, key;
+        int choice, n_cand;
+        double us;   // measured time of the choice (0: heuristic or forced)
+    };
+    std::vector<Entry> entries;
+};
+
+// Executable graphs of the GMRES iteration groups of one batch shape.
+struct IterGraphs {
+    std::vector<uint64_t> key;
+    std::vector<hipGraphExec_t> exec;
+    void release() {
+        for (auto &e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+        exec.clear();
+    }
+};
+
 }  // namespace wpcd
 
 struct wpcd_ctx {
@@ -209,6 +233,11 @@ struct wpcd_ctx {
 
     // ---- learned warm start
     wpcd::Learned learned;
+
+    // ---- launch-shape autotuning, captured iteration graphs
+    wpcd::Tuning tune;
+    bool use_graphs = true;
+    std::vector<wpcd::IterGraphs> graphs;
 };
 
 namespace wpcd {
@@ -229,6 +258,31 @@ void launch_vt(wpcd_ctx *c, int wave);
 void build_structure(wpcd_ctx *c);   // a3: counts, scan, fill (sets c->nnz)
 void build_values(wpcd_ctx *c, bool fp64);
 
+// Pick candidate 0..n_cand-1 for (name, key): forced, cached, heuristic
+// (heur) or measured (measure(i) returns microseconds), by c->tune.mode.
+template <class Measure>
+int tune_pick(wpcd_ctx *c, const char *name, const std::string &key, int n_cand, int heur,
+              Measure &&measure) {
+    Tuning &T = c->tune;
+    if (T.mode >= WPCD_TUNE_FORCE) return std::min(T.mode - WPCD_TUNE_FORCE, n_cand - 1);
+    for (const auto &e : T.entries)
+        if (e.name == name && e.key == key) return e.choice;
+    int best = heur;
+    double best_us = 0.0;
+    if (T.mode == WPCD_TUNE_MEASURE) {
+        best_us = 1e300;
+        for (int i = 0; i < n_cand; ++i) {
+            const double us = measure(i);
+            if (us < best_us) {
+                best_us = us;
+                best = i;
+            }
+        }
+    }
+    T.entries.push_back({name, key, best, n_cand, best_us});
+    return best;
+}
+
 // Batched GMRES over energies (k_solve.hip).  warm: fills the initial
 // vector in the batch layout x[row][e][2] (called after b is formed), or
 // empty for the zero start.  Per energy: iterations, final relative
@@ -239,7 +293,7 @@ struct GmresOut {
 };
 using WarmFill = void (*)(wpcd_ctx *c, void *user, double *x, int nE);
 void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
-                 bool fp64, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
+                 int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
                  GmresOut &out);
 void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
                       const std::vector<int32_t> &ens, const std::vector<double> &rho,

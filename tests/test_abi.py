@@ -39,14 +39,18 @@ def test_null_arguments_rejected_without_device():
     assert L.wpcd_build_p(None, 0, None) == P.WPCD_E_INVALID
     assert L.wpcd_solve(None, None, 0, 0, None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_set_multipliers(None, None, 0) == P.WPCD_E_INVALID
+    assert L.wpcd_solve_multi(None, 0, None, None, 0, None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_learn_train(None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_mlp_eval(None, 1, 1, 1, None, 1, None, None, None, None, None) == P.WPCD_E_INVALID
+    assert L.wpcd_set_autotune(None, 0) == P.WPCD_E_INVALID
+    assert L.wpcd_set_graphs(None, 0) == P.WPCD_E_INVALID
+    assert L.wpcd_get_autotune(None, None, 0, None) == P.WPCD_E_INVALID
     assert L.wpcd_last_error(None) == b"null context"
     L.wpcd_destroy(None)
 
 
 STRUCTS = ("wpcd_basis_desc", "wpcd_potential_desc", "wpcd_solve_opts", "wpcd_energy_result",
-           "wpcd_learn_desc", "wpcd_learn_report", "wpcd_kernel_time")
+           "wpcd_learn_desc", "wpcd_learn_report", "wpcd_tune_entry", "wpcd_kernel_time")
 
 
 def test_struct_layouts_match_header(tmp_path):

@@ -242,6 +242,15 @@ def test_c2_full_fp64_and_mixed(ctx, P):
         worst = max(worst, abs(U - ref[E]) / abs(ref[E]))
     say(f"[C2] mixed max rel amplitude error vs FP64 oracle: {worst:.3e}")
     assert worst <= 1e-6     # the mixed tier's amplitude gate
+    say("[C2] solve MIXED_REFINE")
+    res3 = ctx.solve(C2["energies"], P.WPCD_MIXED_REFINE)
+    worst = 0.0
+    for r, E in zip(res3, C2["energies"]):
+        assert r.status == P.WPCD_OK and r.residual <= 1e-8
+        U = complex(r.U_re, r.U_im)
+        worst = max(worst, abs(U - ref[E]) / abs(ref[E]))
+    say(f"[C2] mixed+refine max rel amplitude error vs FP64 oracle: {worst:.3e}")
+    assert worst <= 1e-6
 
 
 # ------------------------------------------------------------ multichannel
@@ -321,3 +330,82 @@ def test_c3_structure_and_sampled_values(ctx, P):
     vo = O.p0_pairs(p, p.copy(), 8, 20, 2, L2_CHANS, rows.astype(np.int64), col[idx])
     scale = np.abs(val).max()
     assert np.all(np.abs(val[idx] - vo) <= 1e-10 * np.abs(vo) + 1e-13 * scale)
+
+
+# ------------------------------------------------------------- autotuning
+def test_autotune_candidates_agree(ctx, P):
+    """Every candidate launch shape (forced) and the measured choice give the
+    amplitudes of the heuristic choice to rounding."""
+    n = 24
+    pot = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, channels=L2_CHANS, L=2, potential=pot)
+    ctx.build_p(P.WPCD_FP64)
+    E = [-0.05, 0.3, 1.1]
+    ctx.set_autotune(P.WPCD_TUNE_HEURISTIC)
+    ref = ctx.solve(E, P.WPCD_FP64)
+    for mode in [P.WPCD_TUNE_FORCE + i for i in range(4)] + [P.WPCD_TUNE_MEASURE]:
+        say(f"[tune] mode {mode}")
+        ctx.set_autotune(mode)
+        res = ctx.solve(E, P.WPCD_FP64)
+        for a, b in zip(ref, res):
+            assert b.status == P.WPCD_OK
+            Ua, Ub = complex(a.U_re, a.U_im), complex(b.U_re, b.U_im)
+            assert abs(Ua - Ub) <= 1e-12 * abs(Ua)
+    ent = ctx.autotune()
+    assert {e["name"] for e in ent} == {"block_apply", "vector_rows", "spmm"}
+    for e in ent:
+        assert 0 <= e["choice"] < e["n_candidates"] and e["us"] > 0.0
+    ctx.set_autotune(P.WPCD_TUNE_HEURISTIC)
+
+
+def test_graph_replays_match_eager(ctx, P):
+    """Captured iteration graphs replayed over several solves, with other
+    (eager and captured) work and synchronisations in between, give the
+    eager launches' results bit for bit."""
+    n = 24
+    pot = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, channels=L2_CHANS, L=2, potential=pot)
+    ctx.build_p(P.WPCD_FP64)
+    EA = [-0.05, 0.2, 0.6, 1.1, 1.7]
+    EB = [0.35, 0.9]
+    ctx.set_graphs(False)
+    refA = ctx.solve(EA, P.WPCD_FP64)
+    refB = ctx.solve(EB, P.WPCD_FP64)
+    ctx.set_graphs(True)
+    for rep in range(3):
+        say(f"[graphs] replay {rep}")
+        for E, ref in ((EA, refA), (EB, refB)):
+            res = ctx.solve(E, P.WPCD_FP64)
+            ctx.synchronize()
+            for a, b in zip(ref, res):
+                assert b.status == P.WPCD_OK
+                assert (a.U_re, a.U_im, a.iters) == (b.U_re, b.U_im, b.iters)
+        ctx.pair_spectrum(0, want_O=False)   # eager work between replays
+
+
+def test_solve_multi_uneven_systems(P):
+    """Three systems of different size and channel count solved at once
+    give the results of solving them one by one."""
+    yuk = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+    specs = [(16, [(0, 0)], 0, YAM, [0.1, 0.7]),
+             (22, [(0, 2), (2, 0)], 2, yuk, [-0.05, 0.3, 0.9, 1.4]),
+             (18, L2_CHANS, 2, yuk, [0.2, 1.1, 1.9])]
+    ctxs = []
+    for n, ch, L, pot, _ in specs:
+        c = P.Context(0)
+        c.build_basis(n, n, 10.0, 10.0, 8, 16, channels=ch, L=L, potential=pot)
+        c.build_p(P.WPCD_FP64)
+        ctxs.append(c)
+    say("[multi] one by one")
+    seq = [c.solve(sp[4], P.WPCD_FP64) for c, sp in zip(ctxs, specs)]
+    for rep in range(2):
+        say(f"[multi] together {rep}")
+        res = P.wpcd_solve_multi([c.h for c in ctxs], [sp[4] for sp in specs], P.WPCD_FP64)
+        for a_list, b_list in zip(seq, res):
+            for a, b in zip(a_list, b_list):
+                assert b.status == a.status == P.WPCD_OK
+                assert (a.U_re, a.U_im, a.iters) == (b.U_re, b.U_im, b.iters)
+    with pytest.raises(P.WpcdError):
+        P.wpcd_solve_multi([ctxs[0].h, ctxs[0].h], [[0.1], [0.2]], P.WPCD_FP64)
+    for c in ctxs:
+        c.close()
