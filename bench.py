@@ -76,6 +76,23 @@ def cpu_baseline(sample_stride, threads):
                       f"cell pairs): brute-force pre-selection + FP64 elements, {dt:.1f} s"}
 
 
+def copy_calibration(nbytes):
+    """One device-to-device copy of nbytes by the HIP runtime's copy kernel:
+    a kernel of known traffic (nbytes read, nbytes written) for scaling the
+    HBM byte counters."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMemset(a, 1, ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMemcpy(b, a, ctypes.c_size_t(nbytes), 3) == 0   # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    return {"read": nbytes, "write": nbytes}
+
+
 def c3_measure(P):
     """The 270k-basis case beside the main line: L = 2+ channels (0,2), (2,0),
     (2,2), 300 x 300 bins, the same Yukawa sum fitted to -0.1, 8 energies.
@@ -175,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-stride", type=int, default=1)
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-learn", action="store_true",
+                    help="skip the learned-warm-start leg (short runs under a profiler)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the run, one plain device copy y = x * 1 of this many MiB "
                          "(float32, torch elementwise kernel) to calibrate HBM byte counters")
@@ -238,13 +257,18 @@ def main():
     s_refine, r_refine = solve_time(P.WPCD_MIXED_REFINE)
     # learned warm start (mixed): trained on plain mixed solves of potential
     # variants, then the 8 energies at the base potential (a held-out point)
-    mult, e_train = learn_draws(SEED, LEARN_VARIANTS, 2, LEARN_ENERGIES, -0.05, 2.0)
-    t_learn = time.perf_counter()
-    rep = ctx.learn_train(mult, e_train, precision=P.WPCD_MIXED, n_basis=64, hidden=256,
-                          epochs=300, batch=64, seed=SEED)
-    t_learn = time.perf_counter() - t_learn
-    s_learned, r_learned = solve_time(P.WPCD_MIXED, warm_start=P.WPCD_WARM_LEARNED)
+    if not args.no_learn:
+        mult, e_train = learn_draws(SEED, LEARN_VARIANTS, 2, LEARN_ENERGIES, -0.05, 2.0)
+        t_learn = time.perf_counter()
+        rep = ctx.learn_train(mult, e_train, precision=P.WPCD_MIXED, n_basis=64, hidden=256,
+                              epochs=300, batch=64, seed=SEED)
+        t_learn = time.perf_counter() - t_learn
+        s_learned, r_learned = solve_time(P.WPCD_MIXED, warm_start=P.WPCD_WARM_LEARNED)
+    else:
+        s_learned, r_learned, rep, t_learn = s_mixed, r_mixed, None, 0.0
     # FP64 P-build throughput and FP64 solve beside it
+    ctx.build_p(P.WPCD_FP64)          # first FP64 build: launch-shape tuning
+    ctx.synchronize()
     ctx.set_timing(P.WPCD_TIME_P0)
     ctx.reset_timing()
     a = time.perf_counter()
@@ -295,10 +319,10 @@ def main():
                                "learned_initial_residual_median":
                                    sorted(x.r0 for x in r_learned)[len(r_learned) // 2],
                                "fp64_over_mixed_learned": s_fp64 / s_learned},
-        "learn": {"train_solves": rep["n_samples"], "basis": 64,
-                  "basis_mean_rel_err": rep["basis_mean_rel_err"],
-                  "loss_first": rep["loss_first"], "loss_last": rep["loss_last"],
-                  "train_s": t_learn},
+        "learn": None if rep is None else {
+            "train_solves": rep["n_samples"], "basis": 64,
+            "basis_mean_rel_err": rep["basis_mean_rel_err"],
+            "loss_first": rep["loss_first"], "loss_last": rep["loss_last"], "train_s": t_learn},
         "p_build": {"mixed_ms": 1e3 * pbuild[0] / args.steps, "fp64_ms": 1e3 * fp64_build,
                     "fp64_elements_per_s": nnz / fp64_build,
                     "elem_kernel_f32_ms": 1e3 * elem_avg_s,
@@ -321,13 +345,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride, threads)
     ctx.close()
     if args.copy_calib_mb:
-        import torch
-        n = args.copy_calib_mb * (1 << 20) // 4
-        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        y = torch.empty_like(x)
-        torch.mul(x, 1.0, out=y)
-        torch.cuda.synchronize()
-        out["copy_calib_bytes"] = {"read": 4 * n, "write": 4 * n}
+        out["copy_calib_bytes"] = copy_calibration(args.copy_calib_mb << 20)
     print(json.dumps(out), flush=True)
 
 

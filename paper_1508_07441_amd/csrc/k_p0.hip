@@ -6,6 +6,8 @@
 // the host (p, q, p^2, 3/4 q^2, q/2), so the selected set is bit-exact.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+
 #include <cmath>
 #include <type_traits>
 
@@ -180,7 +182,16 @@ struct ElemTables {
     const double *wx;      // w_c [ngx]
     const float *uxf, *wxf;
     int np, ngq, ngx;
+    uint32_t np_magic;     // ceil(2^32 / np): r / np = umulhi(r, np_magic) for r < 2^20
 };
+
+// (i, j) of a cell index r = j np + i (r < 2^20, np <= 1024): the quotient
+// by multiply-high is exact because r (np_magic - 2^32/np) / 2^32 < 2^-12 is
+// below the gap 1/np between r/np and the next integer.
+__device__ __forceinline__ void cell_ij(const ElemTables &T, uint32_t r, int &i, int &j) {
+    j = (int)__umulhi(r, T.np_magic);
+    i = (int)r - j * T.np;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -298,13 +309,12 @@ __global__ __launch_bounds__(256) void k_p0_swave_f32(ElemTables T,
 // ------------------------------------------------- compacted element kernel
 // For the 8-point q rule (64 Gauss pairs per cell pair).  About half of the
 // (q, q') pairs of a cell pair have an empty cosine interval, so a wavefront
-// first evaluates the limits of kEC cell pairs x 64 Gauss pairs, compacts
+// first evaluates the limits of EC cell pairs x 64 Gauss pairs, compacts
 // the non-empty ones into an LDS queue (ballot + popcount, order preserved),
 // then every lane integrates one queued interval at a time with the cosine
 // rule fully unrolled, and finally each cell pair is reduced over its slots
 // (FP32: (hi, lo) pairs combined with TwoSum).  Deterministic: the queue
 // order and the reduction order depend only on the inputs.
-constexpr int kEC = 4;   // cell pairs per wavefront per round
 
 struct NodeTab {
     double ux[kMaxGx], wx[kMaxGx];
@@ -317,25 +327,29 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
     e = (a - (s - bp)) + (b - bp);
 }
 
+// Interval sum over the cosine rule in FP32.  With A = t0 u0 and B = t0 + u0
+// (all terms positive, so no cancellation) the node product is
+// (t0 + s)(u0 + s) = A + s (B + s): one add and one FMA per node.
 template <int NGX>
 __device__ __forceinline__ void inner_f32(const NodeTab &N, int ngx, float lt, float lu, float h,
                                           float &s0, float &s1) {
     s0 = 0.f;
     s1 = 0.f;
+    const float A = lt * lu, B = lt + lu;
     if (NGX > 0) {
 #pragma unroll
         for (int k = 0; k < NGX; k += 2) {
             const float sa = h * N.uxf[k];
-            s0 = fmaf(N.wxf[k], __builtin_amdgcn_rsqf((lt + sa) * (lu + sa)), s0);
+            s0 = fmaf(N.wxf[k], __builtin_amdgcn_rsqf(fmaf(sa, B + sa, A)), s0);
             if (k + 1 < NGX) {
                 const float sb = h * N.uxf[k + 1];
-                s1 = fmaf(N.wxf[k + 1], __builtin_amdgcn_rsqf((lt + sb) * (lu + sb)), s1);
+                s1 = fmaf(N.wxf[k + 1], __builtin_amdgcn_rsqf(fmaf(sb, B + sb, A)), s1);
             }
         }
     } else {
         for (int k = 0; k < ngx; ++k) {
             const float sa = h * N.uxf[k];
-            const float v = N.wxf[k] * __builtin_amdgcn_rsqf((lt + sa) * (lu + sa));
+            const float v = N.wxf[k] * __builtin_amdgcn_rsqf(fmaf(sa, B + sa, A));
             if (k & 1) s1 += v;
             else s0 += v;
         }
@@ -358,28 +372,30 @@ template <int NGX>
 __device__ __forceinline__ double inner_f64(const NodeTab &N, int ngx, double lt, double lu,
                                             double h) {
     double s = 0.0;
+    const double A = lt * lu, B = lt + lu;   // (t0 + s)(u0 + s) = A + s (B + s)
     if (NGX > 0) {
 #pragma unroll
         for (int k = 0; k < NGX; ++k) {
             const double sk = h * N.ux[k];
-            s = fma(N.wx[k], rsqrt_nr((lt + sk) * (lu + sk)), s);
+            s = fma(N.wx[k], rsqrt_nr(fma(sk, B + sk, A)), s);
         }
     } else {
         for (int k = 0; k < ngx; ++k) {
             const double sk = h * N.ux[k];
-            s = fma(N.wx[k], rsqrt_nr((lt + sk) * (lu + sk)), s);
+            s = fma(N.wx[k], rsqrt_nr(fma(sk, B + sk, A)), s);
         }
     }
     return s;
 }
 
-template <bool F32, int NGX>
+template <bool F32, int NGX, int EC>
 __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                                                     const int32_t *__restrict__ rowidx,
                                                     const int32_t *__restrict__ col, int64_t nnz,
                                                     double *__restrict__ val64,
                                                     float *__restrict__ val32) {
     using R = typename std::conditional<F32, float, double>::type;
+    constexpr int kEC = EC;   // cell pairs per wavefront per round
     constexpr int QN = kEC * 64;
     __shared__ R q_lt[4][QN], q_lu[4][QN], q_h[4][QN], q_w[4][QN];
     __shared__ unsigned char q_k[4][QN], q_r[4][QN];
@@ -401,8 +417,10 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
             bool act = false;
             double lo_t = 0.0, lo_u = 0.0, h = 0.0, wab = 0.0;
             if (chunk < nch && e < nnz) {
-                const int r = rowidx[e], c = col[e];
-                const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+                // the cell pair is the same for the whole wavefront
+                int i, j, i2, j2;
+                cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
+                cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
                 const double q = T.qnode[j * 8 + a], q2 = T.qnode[j2 * 8 + b];
                 lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
                 act = h > 0.0;
@@ -452,26 +470,25 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
         for (int k = 0; k < kEC; ++k) {
             const int64_t e = chunk * kEC + k;
             if (F32) {
-                float s = (float)s_hi[w][k][lane], cc = s_lo[w][k][lane];
-                for (int off = 32; off > 0; off >>= 1) {
-                    const float so = __shfl_xor(s, off, 64), co = __shfl_xor(cc, off, 64);
-                    float t2, err;
-                    two_sum(s, so, t2, err);
-                    s = t2;
-                    cc = cc + co + err;
-                }
+                // each slot's (hi, lo) pair summed in FP64, then an FP64
+                // wavefront sum: exact enough to make the slot order immaterial
+                // at FP32 output precision, and fewer instructions than FP32
+                // TwoSum chains
+                double s = (double)s_hi[w][k][lane] + (double)s_lo[w][k][lane];
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
                 if (lane == 0 && chunk < nch && e < nnz) {
-                    const int r = rowidx[e], c = col[e];
-                    const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
-                    val32[e] = (float)(((double)s + (double)cc) * (T.rsd_p[i] * T.rsd_p[i2]) *
-                                       (T.rsd_q[j] * T.rsd_q[j2]));
+                    int i, j, i2, j2;
+                    cell_ij(T, (uint32_t)rowidx[e], i, j);
+                    cell_ij(T, (uint32_t)col[e], i2, j2);
+                    val32[e] = (float)(s * (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]));
                 }
             } else {
                 double s = (double)s_hi[w][k][lane];
                 for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
                 if (lane == 0 && chunk < nch && e < nnz) {
-                    const int r = rowidx[e], c = col[e];
-                    const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+                    int i, j, i2, j2;
+                    cell_ij(T, (uint32_t)rowidx[e], i, j);
+                    cell_ij(T, (uint32_t)col[e], i2, j2);
                     val64[e] = s * (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
                 }
             }
@@ -696,25 +713,57 @@ void build_structure(wpcd_ctx *c) {
     }
 }
 
-template <bool F32>
-static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N, int blocks) {
+// Microseconds per launch of f (one warm-up, then two timed launches).
+template <class F>
+static double time_launches_p0(hipStream_t s, F &&f) {
+    hipEvent_t a, z;
+    WPCD_HIP(hipEventCreate(&a));
+    WPCD_HIP(hipEventCreate(&z));
+    f();
+    WPCD_HIP(hipEventRecord(a, s));
+    f();
+    f();
+    WPCD_HIP(hipEventRecord(z, s));
+    WPCD_HIP(hipEventSynchronize(z));
+    float ms = 0.f;
+    WPCD_HIP(hipEventElapsedTime(&ms, a, z));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(z);
+    return 1e3 * ms / 2;
+}
+
+template <bool F32, int EC>
+static void launch_compacted_ec(wpcd_ctx *c, const ElemTables &T, const NodeTab &N) {
+    const int64_t nchunk = (c->nnz + EC - 1) / EC;
+    const int64_t want = (nchunk + 3) / 4;
+    const int blocks = (int)(want < 8192 ? want : 8192);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, c->stream, T, N, c->d_rowidx.ptr,
                            c->d_col.ptr, c->nnz, c->d_val64.ptr, c->d_val32.ptr);
     };
     switch (c->ngx) {
-        case 16: go(k_p0_swave_c<F32, 16>); break;
-        case 20: go(k_p0_swave_c<F32, 20>); break;
-        case 24: go(k_p0_swave_c<F32, 24>); break;
-        case 32: go(k_p0_swave_c<F32, 32>); break;
-        default: go(k_p0_swave_c<F32, 0>); break;
+        case 16: go(k_p0_swave_c<F32, 16, EC>); break;
+        case 20: go(k_p0_swave_c<F32, 20, EC>); break;
+        case 24: go(k_p0_swave_c<F32, 24, EC>); break;
+        case 32: go(k_p0_swave_c<F32, 32, EC>); break;
+        default: go(k_p0_swave_c<F32, 0, EC>); break;
     }
+    WPCD_HIP(hipGetLastError());
+}
+
+// Cell pairs per round (4 or 8): more pairs fill the integration passes
+// better, fewer use less LDS per wavefront.  Both give identical values.
+template <bool F32>
+static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N, int ec) {
+    if (ec == 8) launch_compacted_ec<F32, 8>(c, T, N);
+    else launch_compacted_ec<F32, 4>(c, T, N);
 }
 
 void build_values(wpcd_ctx *c, bool fp64) {
     ElemTables T{c->d_P2.ptr, c->d_rsd_p.ptr, c->d_rsd_q.ptr, c->d_qnode.ptr, c->d_qwt.ptr,
                  c->d_ux.ptr,  c->d_wx.ptr,    c->d_uxf.ptr,   c->d_wxf.ptr,   c->np,
-                 c->ngq,       c->ngx};
+                 c->ngq,       c->ngx,
+                 (uint32_t)(((1ull << 32) + (uint64_t)c->np - 1) / (uint64_t)c->np)};
     const int64_t nnz = c->nnz;
     const int NP = c->nch * c->nch;
     if (fp64) c->d_val64.reserve(nnz * NP);
@@ -754,15 +803,22 @@ void build_values(wpcd_ctx *c, bool fp64) {
             N.uxf[k] = (float)N.ux[k];
             N.wxf[k] = (float)N.wx[k];
         }
-        const int64_t nchunk = (nnz + kEC - 1) / kEC;
-        const int64_t want = (nchunk + 3) / 4;
-        const int blocks = (int)(want < 8192 ? want : 8192);
+        char key[64];
+        std::snprintf(key, sizeof key, "nnz=%lld ngx=%d %s", (long long)nnz, c->ngx,
+                      fp64 ? "f64" : "f32");
+        const int ecs[2] = {4, 8};
+        const int ec = ecs[tune_pick(c, "p0_elem", key, 2, 0, [&](int i) {
+            return time_launches_p0(c->stream, [&] {
+                if (fp64) launch_compacted<false>(c, T, N, ecs[i]);
+                else launch_compacted<true>(c, T, N, ecs[i]);
+            });
+        })];
         if (fp64) {
             TimedLaunch tl(c->timer, c->stream, "p0_elem_f64", WPCD_TIME_P0);
-            launch_compacted<false>(c, T, N, blocks);
+            launch_compacted<false>(c, T, N, ec);
         } else {
             TimedLaunch tl(c->timer, c->stream, "p0_elem_f32", WPCD_TIME_P0);
-            launch_compacted<true>(c, T, N, blocks);
+            launch_compacted<true>(c, T, N, ec);
         }
         WPCD_HIP(hipGetLastError());
         return;
