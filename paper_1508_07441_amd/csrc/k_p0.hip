@@ -6,6 +6,7 @@
 // the host (p, q, p^2, 3/4 q^2, q/2), so the selected set is bit-exact.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 
 #include <cmath>
@@ -598,6 +599,114 @@ __global__ __launch_bounds__(256) void k_p0_mc(ElemTables T, NodeTab N, McTab Mt
     }
 }
 
+// Same block by moments.  The node weight of channel pair p is
+// g_k t^-hl u^-hl2 with g_k = w_k / sqrt(t u), and its polynomial is
+// sum_c D_pc y^c with D_pc depending only on (q, q'); so
+//   sum_k g_k t^-hl u^-hl2 N_p(y_k) = sum_c D_pc M_{(hl,hl2), c},
+//   M_{(h1,h2), c} = sum_k g_k t^-h1 u^-h2 y_k^c,
+// and per node only the (HMAX+1)^2 x (DEG+1) moments are accumulated; the
+// NP polynomials are applied once per (q, q') pair.  A reordering of the
+// same sums (used for FP32 output).  NEWTON: refinement steps of the FP32
+// reciprocal square root (1 for FP32 output: 2^-45 relative).
+template <int NEWTON>
+__device__ __forceinline__ double rsqrt_n(double x) {
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    const double hx = 0.5 * x;
+#pragma unroll
+    for (int it = 0; it < NEWTON; ++it) y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
+template <int NP, int HMAX, int DEG, int NGX, bool F32OUT>
+__global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab Mt,
+                                                const double *__restrict__ coef,
+                                                const int32_t *__restrict__ rowidx,
+                                                const int32_t *__restrict__ col, int64_t nnz,
+                                                double *__restrict__ val64,
+                                                float *__restrict__ val32) {
+    constexpr int NG = (HMAX + 1) * (HMAX + 1);
+    const int lane = threadIdx.x & 63;
+    const int a = lane >> 3, b = lane & 7;
+    const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t e = wave0; e < nnz; e += nwaves) {
+        int i, j, i2, j2;
+        cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
+        cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
+        const double q = T.qnode[j * 8 + a], q2 = T.qnode[j2 * 8 + b];
+        double lo_t, lo_u, h;
+        lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
+        const bool act = h > 0.0;
+        const double a2 = q * q, b2 = q2 * q2, A = b2 + 0.25 * a2;
+        double M[NG][DEG + 1];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int c = 0; c <= DEG; ++c) M[g][c] = 0.0;
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < NGX; ++k) {
+                const double sk = h * N.ux[k];
+                const double t = lo_t + sk, u = lo_u + sk;
+                const double rt = rsqrt_n<F32OUT ? 1 : 2>(t), ru = rsqrt_n<F32OUT ? 1 : 2>(u);
+                const double it = rt * rt, iu = ru * ru, y = t - A;
+                double gt = N.wx[k] * rt * ru;
+                double gg[NG];
+#pragma unroll
+                for (int h1 = 0; h1 <= HMAX; ++h1) {
+                    double gu = gt;
+#pragma unroll
+                    for (int h2 = 0; h2 <= HMAX; ++h2) {
+                        gg[h1 * (HMAX + 1) + h2] = gu;
+                        gu *= iu;
+                    }
+                    gt *= it;
+                }
+                double yc = 1.0;
+#pragma unroll
+                for (int c = 0; c <= DEG; ++c) {
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) M[g][c] = fma(gg[g], yc, M[g][c]);
+                    yc *= y;
+                }
+            }
+        }
+        const double wab = act ? T.qwt[j * 8 + a] * T.qwt[j2 * 8 + b] * h : 0.0;
+        const double nrm = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
+        for (int p = 0; p < NP; ++p) {
+            const McPair P = Mt.p[p];
+            const int g = P.hl * (HMAX + 1) + P.hl2;
+            double v = 0.0;
+            if (act) {
+                int o = P.off;
+#pragma unroll
+                for (int c = 0; c <= DEG; ++c) {
+                    if (c > P.d) break;
+                    // D_pc = sum_a coef (q^2)^a (q'^2)^(d - c - a)
+                    double sc = 0.0, pa = 1.0;
+                    for (int aa = 0; aa <= P.d - c; ++aa) {
+                        double pb = 1.0;
+                        for (int bb = 0; bb < P.d - c - aa; ++bb) pb *= b2;
+                        sc = fma(coef[o++] * pa, pb, sc);
+                        pa *= a2;
+                    }
+                    double mg = M[0][c];
+#pragma unroll
+                    for (int gi = 1; gi < NG; ++gi)
+                        if (g == gi) mg = M[gi][c];
+                    v = fma(sc, mg, v);
+                }
+                v = wab * v / (ipow_h(a2, P.hlam) * ipow_h(b2, P.hlam2));
+            }
+            v = wave_sum(v);
+            if (lane == 0) {
+                if (F32OUT) val32[e * NP + p] = (float)(v * nrm);
+                else val64[e * NP + p] = v * nrm;
+            }
+        }
+    }
+}
+
 // General channel sets: pairs processed in chunks of 16, the coupling
 // polynomial evaluated in full at every node.
 __global__ __launch_bounds__(256) void k_p0_mc_gen(ElemTables T, NodeTab N, McTab Mt,
@@ -788,7 +897,29 @@ void build_values(wpcd_ctx *c, bool fp64) {
         };
         TimedLaunch tl(c->timer, c->stream, fp64 ? "p0_elem_mc_f64" : "p0_elem_mc_f32",
                        WPCD_TIME_P0);
-        if (c->mc_deg <= 4 && NP == 1) go(k_p0_mc<1, 4>);
+        int hmax = 0;
+        for (int p = 0; p < NP; ++p) hmax = std::max(hmax, std::max(Mt.p[p].hl, Mt.p[p].hl2));
+        // moments only for FP32 output: summing D_c M_c cancels more than the
+        // node-by-node polynomial (a few 1e-13 of the largest element on
+        // near-zero elements), which the FP64 tier does not accept
+        const bool mom = !fp64 && c->ngq == 8 && hmax <= 1 && c->mc_deg <= 4 &&
+                         (NP == 1 || NP == 4 || NP == 9) &&
+                         (c->ngx == 16 || c->ngx == 20 || c->ngx == 24 || c->ngx == 32);
+        if (mom) {
+            auto by_ngx = [&](auto np_c, auto f32_c) {
+                constexpr int NPc = decltype(np_c)::value;
+                constexpr bool F = decltype(f32_c)::value;
+                switch (c->ngx) {
+                    case 16: go(k_p0_mcm<NPc, 1, 4, 16, F>); break;
+                    case 20: go(k_p0_mcm<NPc, 1, 4, 20, F>); break;
+                    case 24: go(k_p0_mcm<NPc, 1, 4, 24, F>); break;
+                    default: go(k_p0_mcm<NPc, 1, 4, 32, F>); break;
+                }
+            };
+            if (NP == 1) by_ngx(std::integral_constant<int, 1>{}, std::true_type{});
+            else if (NP == 4) by_ngx(std::integral_constant<int, 4>{}, std::true_type{});
+            else by_ngx(std::integral_constant<int, 9>{}, std::true_type{});
+        } else if (c->mc_deg <= 4 && NP == 1) go(k_p0_mc<1, 4>);
         else if (c->mc_deg <= 4 && NP == 4) go(k_p0_mc<4, 4>);
         else if (c->mc_deg <= 4 && NP == 9) go(k_p0_mc<9, 4>);
         else go(k_p0_mc_gen);
