@@ -41,10 +41,24 @@ RANGES = (1.0, 2.0)
 ENERGIES = (-0.08, -0.05, -0.02, 0.05, 0.2, 0.5, 1.0, 2.0)
 LEARN_VARIANTS, LEARN_ENERGIES = 16, 32
 
+# HBM bytes per launch of the roofline kernel (FP32 P0 elements, this
+# workload) from two rocprofv3 counter runs, FETCH_SIZE and WRITE_SIZE, each
+# scaled by the counter's reading of a plain device copy of known size
+# (factors 2.0 and 1.0); valid only for the element-kernel source they were
+# taken on (sha256 prefix of csrc/k_p0.hip), reported as null otherwise.
+P0_ELEM_F32_TRAFFIC = {"bytes": 49.62e6, "k_p0_sha256": "55f13979e9b1eac3"}
+
 # MI355X published peaks used for the roofline fractions
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1508_07441_amd", "csrc", "k_p0.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return P0_ELEM_F32_TRAFFIC["bytes"] if h == P0_ELEM_F32_TRAFFIC["k_p0_sha256"] else None
 
 
 def algorithmic_flops_per_element(ngq, ngx):
@@ -332,7 +346,7 @@ def main():
                     / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": None, "kernel": "p0_elem_f32"},
+                     "traffic": measured_traffic(), "kernel": "p0_elem_f32"},
     }
     out["autotune"] = {f'{e["name"]} [{e["key"]}]': e["choice"] for e in ctx.autotune()}
     if not args.no_c3:
