@@ -154,6 +154,122 @@ __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq,
     }
 }
 
+// Same product on the matrix cores: a 64 x 64 output tile per workgroup, each
+// of the 4 wavefronts owning 32 x 32 as 2 x 2 tiles of the 16 x 16 x 4 MFMA
+// (v_mfma_f64_16x16x4f64 for MT = double, v_mfma_f32_16x16x4f32 for MT =
+// float with FP32 accumulation).  Operand layout of the 16 x 16 x 4 forms:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its result item
+// r < 4 is D[i][l % 16] with i = 4 (l / 16) + r for the FP32 form and
+// i = l / 16 + 4 r for the FP64 form (measured on gfx950).  Tiles staged in
+// LDS as in k_block_apply, k in steps of 16.
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class MT>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+    using V = v4d;
+    static __device__ __forceinline__ V step(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct MfmaAcc<float> {
+    using V = v4f;
+    static __device__ __forceinline__ V step(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+template <bool USE_G, bool SUB, class TI, class TO, class MT>
+__global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, int nq, int W,
+                                                          const TI *__restrict__ in,
+                                                          const double *__restrict__ G,
+                                                          const double *__restrict__ add,
+                                                          TO *__restrict__ out) {
+    constexpr int TM = 64, TN = 64, KS = 16;
+    using V = typename MfmaAcc<MT>::V;
+    __shared__ MT sA[KS][TM + 1];
+    __shared__ MT sB[KS][TN + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int a = blockIdx.z;
+    const int row0 = blockIdx.y * TM;
+    const int64_t q0 = (int64_t)blockIdx.x * TN;
+    const int64_t ncol = (int64_t)nq * W;
+    const double *Mt = mats.p[a];
+    const int64_t chbase = (int64_t)a * nq * n;
+    V acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[u][v][r] = (MT)0;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int k0 = 0; k0 < n; k0 += KS) {
+        for (int idx = t; idx < TM * KS; idx += 256) {
+            const int rr = idx / KS, kk = idx % KS;
+            const int r = row0 + rr, k = k0 + kk;
+            sA[kk][rr] = (MT)((r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0);
+        }
+        for (int idx = t; idx < KS * TN; idx += 256) {
+            const int kk = idx / TN, qq = idx % TN;
+            const int k = k0 + kk;
+            const int64_t q = q0 + qq;
+            double v = 0.0;
+            if (k < n && q < ncol) {
+                const int64_t j = q / W;
+                const int c = (int)(q - j * W);
+                const int64_t o = (chbase + j * n + k) * W;
+                if (USE_G) {
+                    const int c0 = c & ~1;
+                    const double gr = G[o + c0], gi = G[o + c0 + 1];
+                    const double xr = (double)in[o + c0], xi = (double)in[o + c0 + 1];
+                    v = (c & 1) ? (gr * xi + gi * xr) : (gr * xr - gi * xi);
+                } else {
+                    v = (double)in[o + c];
+                }
+            }
+            sB[kk][qq] = (MT)v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < KS; kb += 4) {
+            MT av[2], bv[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) av[u] = sA[kb + lk][wr * 32 + u * 16 + li];
+#pragma unroll
+            for (int v = 0; v < 2; ++v) bv[v] = sB[kb + lk][wc * 32 + v * 16 + li];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) acc[u][v] = MfmaAcc<MT>::step(av[u], bv[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int64_t q = q0 + wc * 32 + v * 16 + li;
+            if (q >= ncol) continue;
+            const int64_t j = q / W;
+            const int c = (int)(q - j * W);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + wr * 32 + u * 16 + MfmaAcc<MT>::row(lk, r);
+                if (row >= n) continue;
+                const int64_t gi = (chbase + j * n + row) * W + c;
+                const double d = (double)acc[u][v][r];
+                out[gi] = (TO)(SUB ? add[gi] - d : d);
+            }
+        }
+}
+
 // --------------------------------------------------------------- P0 SpMM
 // Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD
 // b % 8), each XCD with its own L2.  Neighbouring cell rows share most of
@@ -778,10 +894,11 @@ struct Batch {
 };
 constexpr int kMaxSplit = 64;
 
-// Candidate tile shapes (TM x TN) of the block products.
-constexpr int kApplyCfg = 4;
-constexpr int kApplyTM[kApplyCfg] = {64, 32, 32, 16};
-constexpr int kApplyTN[kApplyCfg] = {64, 64, 32, 64};
+// Candidate tile shapes (TM x TN) of the block products; the last one is
+// the FP64 matrix-core kernel (64 x 64 tiles).
+constexpr int kApplyCfg = 5;
+constexpr int kApplyTM[kApplyCfg] = {64, 32, 32, 16, 64};
+constexpr int kApplyTN[kApplyCfg] = {64, 64, 32, 64, 64};
 constexpr int kNrCand[3] = {1, 2, 4};
 
 int apply_blocks(const wpcd_ctx *c, int W, int cfg) {
@@ -796,13 +913,29 @@ void launch_block_apply_t(Batch &b, ChPtrs mats, const TI *in, const double *add
                        mats, c->np, c->nq, b.W, in, b.G, add, out);
 }
 
+template <bool USE_G, bool SUB, class TI, class TO, class MT>
+void launch_block_apply_mfma(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
+    wpcd_ctx *c = b.c;
+    dim3 grid(cdiv((int64_t)c->nq * b.W, 64), cdiv(c->np, 64), c->nch);
+    hipLaunchKernelGGL((k_block_apply_mfma<USE_G, SUB, TI, TO, MT>), grid, dim3(256), 0, c->stream,
+                       mats, c->np, c->nq, b.W, in, b.G, add, out);
+}
+
+// Tile shapes 0-3 on the vector ALUs, 4 on the FP64 matrix cores (all FP64
+// arithmetic); the inner iterations of the refine tier (FP32 panels) use the
+// FP32 matrix cores with FP32 accumulation.
 template <bool USE_G, bool SUB, class TI, class TO>
 void launch_block_apply(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
+    if (std::is_same<TI, float>::value || std::is_same<TO, float>::value) {
+        launch_block_apply_mfma<USE_G, SUB, TI, TO, float>(b, mats, in, add, out);
+        return;
+    }
     switch (b.apply_cfg) {
         case 0: launch_block_apply_t<USE_G, SUB, 64, 64>(b, mats, in, add, out); break;
         case 1: launch_block_apply_t<USE_G, SUB, 32, 64>(b, mats, in, add, out); break;
         case 2: launch_block_apply_t<USE_G, SUB, 32, 32>(b, mats, in, add, out); break;
-        default: launch_block_apply_t<USE_G, SUB, 16, 64>(b, mats, in, add, out); break;
+        case 3: launch_block_apply_t<USE_G, SUB, 16, 64>(b, mats, in, add, out); break;
+        default: launch_block_apply_mfma<USE_G, SUB, TI, TO, double>(b, mats, in, add, out); break;
     }
 }
 
@@ -1067,7 +1200,7 @@ void choose_shapes(Batch &b, int m) {
     char key[64];
     std::snprintf(key, sizeof key, "np=%d nq=%d W=%d nch=%d", c->np, c->nq, b.W, c->nch);
     int heur = 2;
-    for (int i = 0; i < kApplyCfg; ++i)
+    for (int i = 0; i < 4; ++i)   // vector-ALU tilings; the matrix-core one is measured only
         if (apply_blocks(c, b.W, i) >= 512) {
             heur = i;
             break;

@@ -343,7 +343,7 @@ def test_autotune_candidates_agree(ctx, P):
     E = [-0.05, 0.3, 1.1]
     ctx.set_autotune(P.WPCD_TUNE_HEURISTIC)
     ref = ctx.solve(E, P.WPCD_FP64)
-    for mode in [P.WPCD_TUNE_FORCE + i for i in range(4)] + [P.WPCD_TUNE_MEASURE]:
+    for mode in [P.WPCD_TUNE_FORCE + i for i in range(5)] + [P.WPCD_TUNE_MEASURE]:
         say(f"[tune] mode {mode}")
         ctx.set_autotune(mode)
         res = ctx.solve(E, P.WPCD_FP64)
