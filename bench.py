@@ -198,6 +198,60 @@ def c5_measure(P, n_var, n_e, sweep):
             "max_rel_amp_diff_learned_vs_plain": err}
 
 
+C4_SYSTEMS = ((100, 1), (150, 2), (200, 3), (250, 4), (300, 5), (400, 1))
+C4_L2_CHANNELS = ((0, 2), (2, 0), (2, 2), (2, 4), (4, 2))
+
+
+def c4_measure(P, n_var, n_e):
+    """Uneven systems: (N, n_ch) in C4_SYSTEMS (n_ch = 1: the s-wave L = 0+
+    channel; n_ch > 1: the first n_ch L = 2+ channels), the Yukawa sum fitted
+    to -0.1 on each grid, n_var potential variants (strength multipliers
+    U[0.8, 1.2], splitmix64) x n_e energies -0.05 .. 2.0.  Mixed tier.  The
+    systems are solved together (wpcd_solve_multi, one stream each) and one
+    after another; (E, variant) pairs at or below the pair threshold are
+    reported as such and not counted."""
+    fit_t = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(RANGES), fit_e2=-0.1)
+    ctxs, build_s = [], []
+    for n, nch in C4_SYSTEMS:
+        c = P.Context(0)
+        c.set_autotune(P.WPCD_TUNE_MEASURE)
+        if nch == 1:
+            c.build_basis(n, n, 10.0, 10.0, NGQ, NGX, potential=fit_t)
+        else:
+            c.build_basis(n, n, 10.0, 10.0, NGQ, NGX, channels=list(C4_L2_CHANNELS[:nch]), L=2,
+                          potential=fit_t)
+        t = time.perf_counter()
+        c.build_p(P.WPCD_MIXED)
+        c.synchronize()
+        build_s.append(time.perf_counter() - t)
+        ctxs.append(c)
+    mult, _ = learn_draws(SEED + 9, n_var, 2, 0, 0.0, 1.0)
+    E = [-0.05 + 2.05 * k / (n_e - 1) for k in range(n_e)]
+    # first pass: tuning and graph capture for every system
+    for c in ctxs:
+        c.solve(E[:min(32, n_e)], P.WPCD_MIXED)
+    t_multi = t_seq = 0.0
+    ok = 0
+    for v in range(n_var):
+        for c in ctxs:
+            c.set_multipliers(mult[v])
+        t = time.perf_counter()
+        res = P.wpcd_solve_multi([c.h for c in ctxs], [E] * len(ctxs), P.WPCD_MIXED)
+        t_multi += time.perf_counter() - t
+        ok += sum(r.status == P.WPCD_OK for rs in res for r in rs)
+        t = time.perf_counter()
+        for c in ctxs:
+            c.solve(E, P.WPCD_MIXED)
+        t_seq += time.perf_counter() - t
+    for c in ctxs:
+        c.close()
+    return {"workload": f"{len(C4_SYSTEMS)} systems (N, n_ch) {list(C4_SYSTEMS)}; {n_var} potential "
+                        f"variants x {n_e} energies each; mixed tier",
+            "p_build_s": dict(zip([f"{n}x{n}/{nch}ch" for n, nch in C4_SYSTEMS], build_s)),
+            "solved": ok, "together_s": t_multi, "one_by_one_s": t_seq,
+            "solves_per_s_together": ok / t_multi, "solves_per_s_one_by_one": ok / t_seq}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +265,9 @@ def main():
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the run, one plain device copy y = x * 1 of this many MiB "
                          "(float32, torch elementwise kernel) to calibrate HBM byte counters")
+    ap.add_argument("--c4", type=str, default="",
+                    help="uneven systems solved together: VARIANTS,ENERGIES (e.g. 6,64); off by "
+                         "default")
     ap.add_argument("--c5", type=str, default="",
                     help="learned warm start on the 270k basis: VARIANTS,ENERGIES,SWEEP "
                          "(e.g. 64,64,256); off by default (about a minute)")
@@ -351,6 +408,9 @@ def main():
     out["autotune"] = {f'{e["name"]} [{e["key"]}]': e["choice"] for e in ctx.autotune()}
     if not args.no_c3:
         out["c3"] = c3_measure(P)
+    if args.c4:
+        nv, ne = (int(x) for x in args.c4.split(","))
+        out["c4"] = c4_measure(P, nv, ne)
     if args.c5:
         nv, ne, sw = (int(x) for x in args.c5.split(","))
         out["c5"] = c5_measure(P, nv, ne, sw)

@@ -707,74 +707,101 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
     }
 }
 
-// General channel sets: pairs processed in chunks of 16, the coupling
-// polynomial evaluated in full at every node.
-__global__ __launch_bounds__(256) void k_p0_mc_gen(ElemTables T, NodeTab N, McTab Mt,
-                                                   const double *__restrict__ coef,
-                                                   const int32_t *__restrict__ rowidx,
-                                                   const int32_t *__restrict__ col, int64_t nnz,
-                                                   double *__restrict__ val64,
-                                                   float *__restrict__ val32) {
+// General channel sets (l or lam up to 4): the coupling evaluated directly
+// at every node from bipolar harmonics, as the sum of host-tabulated terms
+// coef P_l^|m1|(c1) P_lam^|M-m1|(cq) P_l'^|M|(c2) (coupling_terms), with the
+// polar cosines of pi1, q and pi2 taken from their vectors at the node's
+// cosine x = (t - A) / (q q').  No power of t, u or q is divided out, so the
+// evaluation stays accurate where pi1, pi2 or q is small.  One wavefront per
+// cell pair; each lane keeps its associated Legendre values (l <= 4, index
+// l (l + 1)/2 + m) in its own LDS column; channel pairs in chunks of 16.
+__device__ __forceinline__ void legendre_col(double c, double (*Pt)[64], int lane) {
+    const double s = sqrt(fmax(0.0, (1.0 - c) * (1.0 + c)));
+    double pmm = 1.0;   // P_m^m = (-1)^m (2m - 1)!! s^m
+#pragma unroll
+    for (int m = 0; m <= 4; ++m) {
+        if (m > 0) pmm *= -(2.0 * m - 1.0) * s;
+        Pt[m * (m + 1) / 2 + m][lane] = pmm;
+        if (m < 4) {
+            double p1 = c * (2.0 * m + 1.0) * pmm;   // P_{m+1}^m
+            Pt[(m + 1) * (m + 2) / 2 + m][lane] = p1;
+            double p0 = pmm;
+#pragma unroll
+            for (int l = m + 2; l <= 4; ++l) {
+                const double pl = (c * (2.0 * l - 1.0) * p1 - (l + m - 1.0) * p0) / (l - m);
+                Pt[l * (l + 1) / 2 + m][lane] = pl;
+                p0 = p1;
+                p1 = pl;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double dir_cos(double vx, double vz) {
+    const double r = sqrt(vx * vx + vz * vz);
+    const double c = r > 0.0 ? vz / r : 1.0;
+    return fmin(1.0, fmax(-1.0, c));
+}
+
+__global__ __launch_bounds__(64) void k_p0_mc_direct(ElemTables T, NodeTab N,
+                                                     const McTerm *__restrict__ terms,
+                                                     const int *__restrict__ first, int NP,
+                                                     const int32_t *__restrict__ rowidx,
+                                                     const int32_t *__restrict__ col, int64_t nnz,
+                                                     double *__restrict__ val64,
+                                                     float *__restrict__ val32) {
     constexpr int PC = 16;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    __shared__ double P1[15][64], Pq[15][64], P2[15][64];
+    const int lane = threadIdx.x;
     const int npair_q = T.ngq * T.ngq;
-    const int NP = Mt.npair;
-    for (int64_t e = wave0; e < nnz; e += nwaves) {
-        const int r = rowidx[e], c = col[e];
-        const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
+    for (int64_t e = blockIdx.x; e < nnz; e += gridDim.x) {
+        int i, j, i2, j2;
+        cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
+        cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
         const double nrm = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
         for (int p0 = 0; p0 < NP; p0 += PC) {
             double tot[PC];
 #pragma unroll
-            for (int s = 0; s < PC; ++s) tot[s] = 0.0;
+            for (int sx = 0; sx < PC; ++sx) tot[sx] = 0.0;
             for (int pr = lane; pr < npair_q; pr += 64) {
                 const int a = pr / T.ngq, b = pr - a * T.ngq;
                 const double q = T.qnode[j * T.ngq + a], q2 = T.qnode[j2 * T.ngq + b];
                 double lo_t, lo_u, h;
                 lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
                 if (!(h > 0.0)) continue;
-                const double a2 = q * q, b2 = q2 * q2, A = b2 + 0.25 * a2;
+                const double A = q2 * q2 + 0.25 * q * q, B = q * q2;
                 const double wab = T.qwt[j * T.ngq + a] * T.qwt[j2 * T.ngq + b] * h;
                 double acc[PC];
 #pragma unroll
-                for (int s = 0; s < PC; ++s) acc[s] = 0.0;
+                for (int sx = 0; sx < PC; ++sx) acc[sx] = 0.0;
                 for (int k = 0; k < T.ngx; ++k) {
                     const double sk = h * N.ux[k];
                     const double t = lo_t + sk, u = lo_u + sk;
-                    const double rt = rsqrt_nr(t), ru = rsqrt_nr(u);
-                    const double base = N.wx[k] * rt * ru, it = rt * rt, iu = ru * ru;
-                    const double y = t - A;
+                    const double base = N.wx[k] / sqrt(t * u);
+                    const double x = fmin(1.0, fmax(-1.0, (t - A) / B));
+                    const double sn = sqrt((1.0 - x) * (1.0 + x));
+                    legendre_col(dir_cos(0.5 * q * sn, q2 + 0.5 * q * x), P1, lane);
+                    legendre_col(dir_cos(q * sn, q * x), Pq, lane);
+                    legendre_col(dir_cos(-q * sn, -(q * x + 0.5 * q2)), P2, lane);
 #pragma unroll
-                    for (int s = 0; s < PC; ++s) {
-                        const int p = p0 + s;
+                    for (int sx = 0; sx < PC; ++sx) {
+                        const int p = p0 + sx;
                         if (p >= NP) break;
-                        const McPair P = Mt.p[p];
-                        double nv = 0.0, yc = 1.0;
-                        int o = P.off;
-                        for (int cc = 0; cc <= P.d; ++cc) {
-                            double sa = 0.0, pa = 1.0;
-                            for (int aa = 0; aa <= P.d - cc; ++aa) {
-                                double pb = 1.0;
-                                for (int bb = 0; bb < P.d - cc - aa; ++bb) pb *= b2;
-                                sa += coef[o++] * pa * pb;
-                                pa *= a2;
-                            }
-                            nv += sa * yc;
-                            yc *= y;
+                        double g = 0.0;
+                        for (int tt = first[p]; tt < first[p + 1]; ++tt) {
+                            const McTerm Tm = terms[tt];
+                            g = fma(Tm.coef * P1[Tm.i1][lane], Pq[Tm.iq][lane] * P2[Tm.i2][lane], g);
                         }
-                        const double den = ipow_h(a2, P.hlam) * ipow_h(b2, P.hlam2);
-                        acc[s] += base * ipow_h(it, P.hl) * ipow_h(iu, P.hl2) * nv / den;
+                        acc[sx] = fma(base, g, acc[sx]);
                     }
                 }
 #pragma unroll
-                for (int s = 0; s < PC; ++s) tot[s] = fma(wab, acc[s], tot[s]);
+                for (int sx = 0; sx < PC; ++sx) tot[sx] = fma(wab, acc[sx], tot[sx]);
             }
 #pragma unroll
-            for (int s = 0; s < PC; ++s) {
-                const int p = p0 + s;
-                const double v = wave_sum(tot[s]);
+            for (int sx = 0; sx < PC; ++sx) {
+                const int p = p0 + sx;
+                const double v = wave_sum(tot[sx]);
                 if (lane == 0 && p < NP) {
                     if (val64) val64[e * NP + p] = v * nrm;
                     else val32[e * NP + p] = (float)(v * nrm);
@@ -783,6 +810,7 @@ __global__ __launch_bounds__(256) void k_p0_mc_gen(ElemTables T, NodeTab N, McTa
         }
     }
 }
+
 
 // ------------------------------------------------------------------ host
 static GridView grid_view(wpcd_ctx *c) {
@@ -886,7 +914,8 @@ void build_values(wpcd_ctx *c, bool fp64) {
         }
         McTab Mt{};
         Mt.npair = NP;
-        for (int p = 0; p < NP; ++p) Mt.p[p] = c->mc_pairs[p];
+        if (!c->mc_direct)
+            for (int p = 0; p < NP; ++p) Mt.p[p] = c->mc_pairs[p];
         const int64_t want = (nnz + 3) / 4;
         const int blocks = (int)(want < 65536 ? want : 65536);
         double *v64 = fp64 ? c->d_val64.ptr : nullptr;
@@ -902,7 +931,7 @@ void build_values(wpcd_ctx *c, bool fp64) {
         // moments only for FP32 output: summing D_c M_c cancels more than the
         // node-by-node polynomial (a few 1e-13 of the largest element on
         // near-zero elements), which the FP64 tier does not accept
-        const bool mom = !fp64 && c->ngq == 8 && hmax <= 1 && c->mc_deg <= 4 &&
+        const bool mom = !fp64 && !c->mc_direct && c->ngq == 8 && hmax <= 1 && c->mc_deg <= 4 &&
                          (NP == 1 || NP == 4 || NP == 9) &&
                          (c->ngx == 16 || c->ngx == 20 || c->ngx == 24 || c->ngx == 32);
         if (mom) {
@@ -919,10 +948,15 @@ void build_values(wpcd_ctx *c, bool fp64) {
             if (NP == 1) by_ngx(std::integral_constant<int, 1>{}, std::true_type{});
             else if (NP == 4) by_ngx(std::integral_constant<int, 4>{}, std::true_type{});
             else by_ngx(std::integral_constant<int, 9>{}, std::true_type{});
-        } else if (c->mc_deg <= 4 && NP == 1) go(k_p0_mc<1, 4>);
-        else if (c->mc_deg <= 4 && NP == 4) go(k_p0_mc<4, 4>);
-        else if (c->mc_deg <= 4 && NP == 9) go(k_p0_mc<9, 4>);
-        else go(k_p0_mc_gen);
+        } else if (!c->mc_direct && c->mc_deg <= 4 && NP == 1) go(k_p0_mc<1, 4>);
+        else if (!c->mc_direct && c->mc_deg <= 4 && NP == 4) go(k_p0_mc<4, 4>);
+        else if (!c->mc_direct && c->mc_deg <= 4 && NP == 9) go(k_p0_mc<9, 4>);
+        else {
+            const int dblocks = (int)(nnz < 262144 ? nnz : 262144);
+            hipLaunchKernelGGL(k_p0_mc_direct, dim3(dblocks), dim3(64), 0, c->stream, T, N,
+                               c->d_mterms.ptr, c->d_mterm_first.ptr, NP, c->d_rowidx.ptr,
+                               c->d_col.ptr, nnz, v64, v32);
+        }
         WPCD_HIP(hipGetLastError());
         return;
     }

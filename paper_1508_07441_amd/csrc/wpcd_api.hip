@@ -909,14 +909,26 @@ wpcd_status wpcd_build_basis(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_p
         }
         upload_tables(c);
         c->swave = (c->nch == 1 && c->L == 0 && c->ch_l[0] == 0 && c->ch_lam[0] == 0);
-        {
+        // angular coupling: the fitted polynomial for l, lam <= 2 (validated
+        // and fast), the direct bipolar-harmonic terms beyond
+        c->mc_direct = false;
+        for (int a = 0; a < c->nch; ++a)
+            if (c->ch_l[a] > 2 || c->ch_lam[a] > 2) c->mc_direct = true;
+        c->mc_pairs.clear();
+        c->mc_deg = 0;
+        if (!c->mc_direct) {
             std::vector<double> coef;
             coupling_tables(c->L, c->nch, c->ch_l, c->ch_lam, c->mc_pairs, coef);
-            c->mc_deg = 0;
             for (auto &pp : c->mc_pairs) c->mc_deg = std::max(c->mc_deg, pp.d);
             upload(c->d_mcoef, coef, c->stream);
-            WPCD_HIP(hipStreamSynchronize(c->stream));
+        } else {
+            std::vector<McTerm> terms;
+            std::vector<int> first;
+            coupling_terms(c->L, c->nch, c->ch_l, c->ch_lam, terms, first);
+            upload(c->d_mterms, terms, c->stream);
+            upload(c->d_mterm_first, first, c->stream);
         }
+        WPCD_HIP(hipStreamSynchronize(c->stream));
         c->has_basis = true;
         build_pair_waves(c, pot);
     });
@@ -1155,6 +1167,8 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->graphs.clear();
     c->d_pot.release();
     c->d_mcoef.release();
+    c->d_mterms.release();
+    c->d_mterm_first.release();
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

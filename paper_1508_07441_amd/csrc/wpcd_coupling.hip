@@ -119,6 +119,92 @@ ld coupling_G(int L, int l, int lam, int l2, int lam2, ld q, ld q2, ld x) {
 
 }  // namespace
 
+namespace {
+ld ylm_norm(int l, int am) {
+    return std::sqrt((2.0L * l + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L) *
+                     lfact(l - am) / lfact(l + am));
+}
+// Y_lm = ylm_norm(l,|m|) P_l^|m|(cos theta) e^{i|m| phi} for m >= 0 and
+// (-1)^m times the conjugate for m < 0; with phi in {0, pi} all are real.
+ld ylm_sign(int m, int azimuth_sign) {
+    const int am = std::abs(m);
+    ld s = (m < 0 && (am % 2)) ? -1.0L : 1.0L;
+    if (azimuth_sign < 0 && (am % 2)) s = -s;
+    return s;
+}
+}  // namespace
+
+// Direct form of G for every channel pair at the canonical geometry
+// (q' along z, q in the xz plane at cosine x): pi1 = q' + q/2 has a
+// non-negative x component (azimuth 0), q too, pi2 = -(q + q'/2) a
+// non-positive one (azimuth pi), and Y_lam' mu(z) = delta_mu0
+// sqrt((2 lam' + 1)/(4 pi)).  Hence
+//   G = sum_{M, m1} coef P_l^|m1|(c1) P_lam^|M-m1|(x) P_l'^|M|(c2),
+// c1, c2 the polar cosines of pi1, pi2, with every constant in coef.  The
+// terms are validated against coupling_G (long double) at sample points.
+void coupling_terms(int L, int nch, const int *l, const int *lam, std::vector<McTerm> &terms,
+                    std::vector<int> &first) {
+    terms.clear();
+    first.assign(nch * nch + 1, 0);
+    const ld pi = 3.14159265358979323846264338327950288L;
+    for (int a1 = 0; a1 < nch; ++a1)
+        for (int a2 = 0; a2 < nch; ++a2) {
+            const int p = a1 * nch + a2;
+            first[p] = (int)terms.size();
+            const int la = l[a1], lb = lam[a1], lc = l[a2], ld2 = lam[a2];
+            for (int M = -L; M <= L; ++M) {
+                if (std::abs(M) > lc) continue;
+                const ld cg2 = clebsch(lc, M, ld2, 0, L, M);
+                if (cg2 == 0.0L) continue;
+                for (int m1 = -la; m1 <= la; ++m1) {
+                    const int m2 = M - m1;
+                    if (std::abs(m2) > lb) continue;
+                    const ld cg1 = clebsch(la, m1, lb, m2, L, M);
+                    if (cg1 == 0.0L) continue;
+                    const ld c = 16.0L * pi * pi / (2.0L * L + 1.0L) * cg1 * cg2 *
+                                 std::sqrt((2.0L * ld2 + 1.0L) / (4.0L * pi)) *
+                                 ylm_norm(la, std::abs(m1)) * ylm_sign(m1, +1) *
+                                 ylm_norm(lb, std::abs(m2)) * ylm_sign(m2, +1) *
+                                 ylm_norm(lc, std::abs(M)) * ylm_sign(M, -1);
+                    McTerm T;
+                    T.coef = (double)c;
+                    T.i1 = la * (la + 1) / 2 + std::abs(m1);
+                    T.iq = lb * (lb + 1) / 2 + std::abs(m2);
+                    T.i2 = lc * (lc + 1) / 2 + std::abs(M);
+                    terms.push_back(T);
+                }
+            }
+            // validation against the bipolar-harmonic evaluation
+            const ld qs[] = {0.6L, 1.4L, 2.3L}, xs[] = {-0.8L, -0.2L, 0.35L, 0.9L};
+            ld worst = 0.0L, scale = 0.0L;
+            for (ld q : qs)
+                for (ld q2 : qs)
+                    for (ld x : xs) {
+                        const ld G = coupling_G(L, la, lb, lc, ld2, q, q2, x);
+                        const ld sx = std::sqrt((1.0L - x) * (1.0L + x));
+                        const ld p1x = 0.5L * q * sx, p1z = q2 + 0.5L * q * x;
+                        const ld p2x = -q * sx, p2z = -(q * x + 0.5L * q2);
+                        const ld c1 = p1z / std::sqrt(p1x * p1x + p1z * p1z);
+                        const ld c2 = p2z / std::sqrt(p2x * p2x + p2z * p2z);
+                        ld v = 0.0L;
+                        for (int k = first[p]; k < (int)terms.size(); ++k) {
+                            const McTerm &T = terms[k];
+                            auto P = [&](int idx, ld cc) {
+                                int ll = 0;
+                                while ((ll + 1) * (ll + 2) / 2 <= idx) ++ll;
+                                return assoc_legendre(ll, idx - ll * (ll + 1) / 2, cc);
+                            };
+                            v += (ld)T.coef * P(T.i1, c1) * P(T.iq, x) * P(T.i2, c2);
+                        }
+                        worst = std::max(worst, std::fabs(v - G));
+                        scale = std::max(scale, std::fabs(G));
+                    }
+            WPCD_REQUIRE(worst <= 1e-13L * std::max(scale, (ld)1.0L), WPCD_E_INVALID,
+                         "direct coupling terms do not reproduce the coupling");
+        }
+    first[nch * nch] = (int)terms.size();
+}
+
 // Fill the coefficient table for all channel pairs (row channel a, column
 // channel a2, pair index a * nch + a2).  Layout: pairs[p] gives d = D/2,
 // the half powers l/2, l'/2, lam/2, lam'/2 and the offset into coef, where
@@ -138,14 +224,27 @@ void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<M
             P.hlam = lam[a1] / 2;
             P.hlam2 = lam[a2] / 2;
             P.off = (int)coef.size();
-            // unknowns (c, a): index order c major
-            std::vector<std::pair<int, int>> idx;
+            // unknowns (c, a): index order c major.  The monomial
+            // (q^2)^a (q'^2)^b y^c is q^(2a+c) q'^(2b+c) x^c; N carries the
+            // factor q^lam q'^lam', so terms with 2a + c < lam or 2b + c < lam'
+            // are exactly zero.  They are left out of the fit: a rounding-size
+            // coefficient there would be amplified by 1/q^lam on the nodes
+            // near q = 0.
+            std::vector<std::pair<int, int>> idx, all;
             for (int c = 0; c <= d; ++c)
-                for (int a = 0; a <= d - c; ++a) idx.push_back({c, a});
+                for (int a = 0; a <= d - c; ++a) {
+                    all.push_back({c, a});
+                    const int b = d - c - a;
+                    if (2 * a + c >= lam[a1] && 2 * b + c >= lam[a2]) idx.push_back({c, a});
+                }
             const int nu = (int)idx.size();
-            // sample points
-            const ld qs[] = {0.55L, 0.9L, 1.3L, 1.85L, 2.4L};
-            const ld xs[] = {-0.85L, -0.45L, -0.1L, 0.3L, 0.65L, 0.92L};
+            // sample points: for fixed (q, q') the polynomial has degree d <= 8
+            // in y = q q' x, so at least d + 1 distinct cosines are needed
+            // (12 here); the homogeneous (q^2, q'^2) parts of degree <= 8 need
+            // >= 9 distinct ratios q^2/q'^2 (the 6 x 6 grid gives 31)
+            const ld qs[] = {0.55L, 0.9L, 1.3L, 1.85L, 2.4L, 3.1L};
+            const ld xs[] = {-0.97L, -0.85L, -0.68L, -0.45L, -0.27L, -0.1L,
+                             0.08L,  0.3L,   0.47L,  0.65L,  0.81L,  0.92L};
             std::vector<std::vector<ld>> A;
             std::vector<ld> rhs;
             for (ld q : qs)
@@ -196,7 +295,41 @@ void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<M
             }
             WPCD_REQUIRE(worst <= 1e-13L * std::max(scale, (ld)1.0L), WPCD_E_INVALID,
                          "coupling polynomial fit failed");
-            for (int k = 0; k < nu; ++k) coef.push_back((double)sol[k]);
+            // and off the samples (an underdetermined fit interpolates the
+            // samples but not the function)
+            {
+                const ld vq[] = {0.7L, 1.15L, 2.05L, 2.7L};
+                const ld vx[] = {-0.91L, -0.33L, 0.17L, 0.59L, 0.88L};
+                ld vworst = 0.0L, vscale = 0.0L;
+                for (ld q : vq)
+                    for (ld q2 : vq)
+                        for (ld x : vx) {
+                            const ld G = coupling_G(L, l[a1], lam[a1], l[a2], lam[a2], q, q2, x);
+                            const ld t = q2 * q2 + 0.25L * q * q + q * q2 * x;
+                            const ld u = q * q + 0.25L * q2 * q2 + q * q2 * x;
+                            const ld Nv = G * std::pow(t, (ld)P.hl) * std::pow(u, (ld)P.hl2) *
+                                          std::pow(q * q, (ld)P.hlam) *
+                                          std::pow(q2 * q2, (ld)P.hlam2);
+                            const ld y = q * q2 * x;
+                            ld v = 0.0L;
+                            for (int k = 0; k < nu; ++k) {
+                                const int c = idx[k].first, a = idx[k].second, bb = d - c - a;
+                                v += sol[k] * std::pow(q * q, (ld)a) * std::pow(q2 * q2, (ld)bb) *
+                                     std::pow(y, (ld)c);
+                            }
+                            vworst = std::max(vworst, std::fabs(v - Nv));
+                            vscale = std::max(vscale, std::fabs(Nv));
+                        }
+                WPCD_REQUIRE(vworst <= 1e-12L * std::max(vscale, (ld)1.0L), WPCD_E_INVALID,
+                             "coupling polynomial does not reproduce the coupling off the fit points");
+            }
+            // stored for every (c, a) of the full layout, zeros included
+            for (const auto &ca : all) {
+                ld v = 0.0L;
+                for (int k = 0; k < nu; ++k)
+                    if (idx[k] == ca) v = sol[k];
+                coef.push_back((double)v);
+            }
         }
 }
 

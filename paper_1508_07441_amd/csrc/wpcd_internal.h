@@ -101,6 +101,14 @@ struct McPair {
     int d, hl, hl2, hlam, hlam2, off;
 };
 
+// One term of the direct angular coupling: coef times the associated
+// Legendre values with table indices i = l (l + 1)/2 + |m| at the polar
+// cosines of pi1 (i1), of q (iq) and of pi2 (i2).
+struct McTerm {
+    double coef;
+    int i1, iq, i2, pad;
+};
+
 struct PairWave {
     int l = 0;
     DBuf<double> v, O, eps, Vt;   // v, O (rows eigenvectors), eps* ascending, Vt = v O^T
@@ -204,6 +212,9 @@ struct wpcd_ctx {
     std::vector<wpcd::McPair> mc_pairs; // coupling polynomials per channel pair
     int mc_deg = 0;                     // largest d over the pairs
     wpcd::DBuf<double> d_mcoef;
+    wpcd::DBuf<wpcd::McTerm> d_mterms;  // direct coupling terms
+    wpcd::DBuf<int> d_mterm_first;      // first term of each channel pair [NP + 1]
+    bool mc_direct = false;             // general channel sets: direct evaluation
 
     // ---- potential / pair waves
     bool has_pot = false;
@@ -249,6 +260,8 @@ void gauss_legendre_gw(int n, std::vector<double> &x, std::vector<double> &w);
 // Coupling polynomial coefficients for all channel pairs (host, long double fit).
 void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<McPair> &pairs,
                      std::vector<double> &coef);
+void coupling_terms(int L, int nch, const int *l, const int *lam, std::vector<McTerm> &terms,
+                    std::vector<int> &first);
 
 // ---- kernel launchers (defined in the .hip files)
 void launch_potential(wpcd_ctx *c, int wave, double *v_out);

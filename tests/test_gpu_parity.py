@@ -282,6 +282,43 @@ def test_multichannel_p0_parity(ctx, P, shape):
     assert np.all(np.abs(v32 - vo) <= 1e-6 * np.abs(vo) + 1e-7 * scale)
 
 
+L2_CHANS5 = [(0, 2), (2, 0), (2, 2), (2, 4), (4, 2)]
+
+
+def test_five_channel_p0_and_amplitudes(ctx, P):
+    """Channels up to l = 4, lambda = 4 (coupling polynomials of degree 6,
+    the general element kernel, the 5-channel block SpMM) against the
+    oracle, FP64 and FP32 values and FP64 amplitudes."""
+    n = 10
+    ctx.build_basis(n, n, 8.0, 8.0, 8, 12, channels=L2_CHANS5, L=2, potential=_yuk_pot(2.0))
+    say("[mc5] build_p FP64")
+    ctx.build_p(P.WPCD_FP64)
+    rp, col, val = ctx.get_p()
+    p = O.cheb_edges(n, 8.0)
+    ptr_o, col_o = O.preselect(p, p.copy())
+    assert np.array_equal(rp, ptr_o) and np.array_equal(col, col_o)
+    rows = np.repeat(np.arange(n * n, dtype=np.int64), np.diff(ptr_o))
+    vo = O.p0_pairs(p, p.copy(), 8, 12, 2, L2_CHANS5, rows, col_o)
+    scale = np.abs(vo).max()
+    err = np.abs(val - vo)
+    assert np.all(err <= 1e-10 * np.abs(vo) + 1e-13 * scale), float(err.max() / scale)
+    say("[mc5] solve FP64")
+    energies = [0.1, 0.9]
+    res = ctx.solve(energies, P.WPCD_FP64)
+    pot = O.Potential("yukawa", (-2.0, -2.0), YUK_RANGES)
+    sysm = O.build_system(p, p.copy(), 2, L2_CHANS5, 8, 12, pot)
+    for r, E in zip(res, energies):
+        assert r.status == P.WPCD_OK, (E, P.STATUS_NAMES[r.status])
+        u, _, _ = O.solve_gmres(sysm, E)
+        a = O.amplitudes(sysm, E, u)
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
+    say("[mc5] build_p MIXED")
+    ctx.build_p(P.WPCD_MIXED)
+    _, _, v32 = ctx.get_p()
+    assert np.all(np.abs(v32 - vo) <= 1e-6 * np.abs(vo) + 1e-7 * scale)
+
+
 def test_multichannel_amplitudes_fp64(ctx, P):
     n = 16
     scale = 2.0
