@@ -231,6 +231,34 @@ wpcd_status wpcd_solve(wpcd_ctx *ctx, const double *E, int32_t n_E, wpcd_precisi
                        const wpcd_solve_opts *opts, wpcd_energy_result *out,
                        double *breakup_out);
 
+/* wpcd_solve with the energies E_dev[n_E] in device memory and the
+ * results written to device memory out_dev[n_E] (no breakup rows), on the
+ * context's stream.  The energy bookkeeping (threshold, on-shell bin) runs
+ * on the host, so the call copies the energies in and synchronises.
+ * Errors: as wpcd_solve.                                                  */
+wpcd_status wpcd_solve_dev(wpcd_ctx *ctx, const double *E_dev, int32_t n_E, wpcd_precision prec,
+                           const wpcd_solve_opts *opts, wpcd_energy_result *out_dev);
+
+/* Save the built P0 (structure, values in the precision it was built in)
+ * with the grid signature (sizes, Gauss orders, channels, bin edges) to a
+ * binary file; load it into a context whose basis has the same signature
+ * (P0 is potential independent, so it can be reused across potentials and
+ * runs); *nnz_cells_out (may be NULL) receives the number of cell pairs.
+ * Errors: WPCD_E_STATE (no P0 / no basis), WPCD_E_INVALID (file cannot be
+ * opened, written or read, other signature, inconsistent data).          */
+wpcd_status wpcd_save_p(wpcd_ctx *ctx, const char *path);
+wpcd_status wpcd_load_p(wpcd_ctx *ctx, const char *path, int64_t *nnz_cells_out);
+
+/* Three-body bound state of the homogeneous equation u = K(E) u (eq.(m_pvg)
+ * without the driving term): the energy in [e_lo, e_hi] (below the lowest
+ * pair level, where K is real) at which the largest real eigenvalue of K(E)
+ * equals 1.  The eigenvalue is the largest real Ritz value of 64 Arnoldi
+ * steps of K(E) on the GPU (eigenvalues of the small Hessenberg matrix on
+ * the host); E by bisection to 1e-12 relative.  Errors: WPCD_E_STATE,
+ * WPCD_E_INVALID (no sign change on the bracket), WPCD_E_BELOW_THRESHOLD
+ * (bracket not below the pair level).                                    */
+wpcd_status wpcd_bound_state(wpcd_ctx *ctx, double e_lo, double e_hi, double *e3_out);
+
 /* wpcd_solve for n_sys independent systems at once (uneven sizes and
  * channel sets allowed): system i is solved in context ctxs[i] at energies
  * E[i][0..n_E[i]) into out[i][0..n_E[i]) (no breakup rows).  Each system is

@@ -42,7 +42,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_
                 5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE"}
 
 ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_set_potential", "wpcd_pair_spectrum",
-                 "wpcd_build_p", "wpcd_get_p", "wpcd_solve", "wpcd_solve_multi",
+                 "wpcd_build_p", "wpcd_get_p", "wpcd_save_p", "wpcd_load_p", "wpcd_solve",
+                 "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_bound_state",
                  "wpcd_set_multipliers",
                  "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_autotune",
                  "wpcd_get_autotune", "wpcd_set_graphs", "wpcd_set_timing",
@@ -144,6 +145,11 @@ def lib():
                                  ctypes.POINTER(wpcd_solve_opts),
                                  ctypes.POINTER(wpcd_energy_result), dp]
         fp = ctypes.POINTER(ctypes.c_float)
+        L.wpcd_bound_state.argtypes = [vp, ctypes.c_double, ctypes.c_double, dp]
+        L.wpcd_save_p.argtypes = [vp, ctypes.c_char_p]
+        L.wpcd_load_p.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+        L.wpcd_solve_dev.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int,
+                                     ctypes.POINTER(wpcd_solve_opts), vp]
         L.wpcd_solve_multi.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(dp),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
                                        ctypes.POINTER(wpcd_solve_opts),
@@ -280,6 +286,29 @@ def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol
     return res
 
 
+def wpcd_bound_state(ctx, e_lo, e_hi):
+    e3 = ctypes.c_double()
+    _check(ctx, lib().wpcd_bound_state(ctx, float(e_lo), float(e_hi), ctypes.byref(e3)))
+    return e3.value
+
+
+def wpcd_save_p(ctx, path):
+    _check(ctx, lib().wpcd_save_p(ctx, os.fsencode(path)))
+
+
+def wpcd_load_p(ctx, path):
+    n = ctypes.c_int64()
+    _check(ctx, lib().wpcd_load_p(ctx, os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def wpcd_solve_dev(ctx, E_dev_ptr, n_E, out_dev_ptr, precision=WPCD_FP64, **kw):
+    """Energies and results in device memory (raw device pointers)."""
+    opts = _opts(**kw)
+    _check(ctx, lib().wpcd_solve_dev(ctx, ctypes.c_void_p(E_dev_ptr), n_E, precision,
+                                     ctypes.byref(opts), ctypes.c_void_p(out_dev_ptr)))
+
+
 def wpcd_solve_multi(ctxs, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0):
     """Solve several systems at once: ctxs[i] (handles) at energies[i]."""
     n = len(ctxs)
@@ -412,6 +441,16 @@ class Context:
 
     def solve(self, energies, precision=WPCD_FP64, **kw):
         return wpcd_solve(self.h, energies, precision, n_p=self.n_p, n_ch=self.n_ch, **kw)
+
+    def bound_state(self, e_lo, e_hi):
+        return wpcd_bound_state(self.h, e_lo, e_hi)
+
+    def save_p(self, path):
+        wpcd_save_p(self.h, path)
+
+    def load_p(self, path):
+        self.nnz = wpcd_load_p(self.h, path)
+        return self.nnz
 
     def set_multipliers(self, mult):
         wpcd_set_multipliers(self.h, mult)

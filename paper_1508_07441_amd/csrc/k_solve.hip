@@ -1442,6 +1442,99 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     }
 }
 
+// H[k+1][k] = |w| from the stage-1 norm partials; inv = 1/|w| (0 on breakdown).
+__global__ void k_arnoldi_norm(const double *__restrict__ npart, int nsplit, double *__restrict__ H,
+                               int m, int k, double *__restrict__ inv) {
+    if (threadIdx.x != 0) return;
+    double n2 = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) n2 += npart[2 * sp];
+    const double hn = sqrt(n2);
+    H[((int64_t)(k + 1) * m + k) * 2] = hn;
+    H[((int64_t)(k + 1) * m + k) * 2 + 1] = 0.0;
+    inv[0] = hn > 1e-300 ? 1.0 / hn : 0.0;
+}
+
+// x[row] = 1 (real start vector)
+__global__ void k_fill_re(int64_t M, double v, double *__restrict__ x) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    x[2 * r] = v;
+    x[2 * r + 1] = 0.0;
+}
+
+// m Arnoldi steps of K(E) = O P0 V~ G1(E) for one energy below the pair
+// threshold (everything real), start vector of ones; the Hessenberg matrix
+// (m+1) x m (complex layout, imaginary parts zero) is returned in H; the
+// number of steps taken (fewer on breakdown) in *steps.
+void arnoldi_kernel(wpcd_ctx *c, double E, int m, std::vector<double> &H, int &steps) {
+    const bool fp64 = c->p_fp64;
+    Batch b{};
+    b.c = c;
+    b.nE = 1;
+    b.nEp = 1;
+    b.W = 2;
+    b.Wp = 2;
+    b.m = m;
+    b.M = (int64_t)c->nch * c->nq * c->np;
+    b.fp64 = fp64;
+    b.lowp = false;
+    const int64_t vec = b.M * 2;
+    b.vstride = vec;
+    const int max_chunks = cdiv(b.M, chunk_rows_of(1, 1));
+    c->d_G.reserve(vec);
+    c->d_T1.reserve(2 * vec);
+    c->d_V.reserve((size_t)(m + 1) * vec);
+    c->d_Hess.reserve((size_t)(m + 1) * m * 2);
+    c->d_partial.reserve((size_t)(max_chunks + kMaxSplit) * (m + 1) * 2);
+    c->d_misc.reserve(2 * (size_t)(m + 1) + 8);
+    c->d_flag.reserve(4);
+    b.G = c->d_G.ptr;
+    b.T1 = c->d_T1.ptr;
+    b.T2 = c->d_T1.ptr + vec;
+    b.Vb = c->d_V.ptr;
+    b.H = c->d_Hess.ptr;
+    b.partial = c->d_partial.ptr;
+    b.out2 = c->d_partial.ptr + (size_t)max_chunks * (m + 1) * 2;
+    b.h = c->d_misc.ptr;
+    b.inv = c->d_misc.ptr + 2 * (m + 1);
+    hipStream_t s = c->stream;
+    choose_shapes(b, m);
+    ChPtrs eps{};
+    for (int a = 0; a < c->nch; ++a) eps.p[a] = c->waves[c->ch_wave[a]].eps.ptr;
+    double *dE = c->d_misc.ptr + 2 * (m + 1) + 2;
+    WPCD_HIP(hipMemcpyAsync(dE, &E, sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_resolvent, dim3(cdiv(b.M, 256)), dim3(256), 0, s, c->d_q.ptr, c->np, c->nq,
+                       c->nch, 1, dE, eps, b.G, c->d_flag.ptr);
+    WPCD_HIP(hipMemsetAsync(b.H, 0, (size_t)(m + 1) * m * 2 * sizeof(double), s));
+    hipLaunchKernelGGL(k_fill_re, dim3(cdiv(b.M, 256)), dim3(256), 0, s, b.M,
+                       1.0 / std::sqrt((double)b.M), b.Vb);
+    WPCD_HIP(hipGetLastError());
+    std::vector<double> invh(1);
+    steps = 0;
+    for (int k = 0; k < m; ++k) {
+        double *vk = b.Vb + (int64_t)k * vec;
+        double *w = b.Vb + (int64_t)(k + 1) * vec;
+        op_apply(b, vk, w, true, false);   // w = K v_k
+        dots(b, b.Vb, k + 1, w, b.h, b.H, k, 0);
+        vupdate<true, false>(b, k + 1, w);
+        reduce_partials(b, k + 1, b.h, b.H, k, 1);
+        vupdate<false, true>(b, k + 1, w);
+        reduce_stage1(b, 1);
+        hipLaunchKernelGGL(k_arnoldi_norm, dim3(1), dim3(64), 0, s, b.out2, b.nsplit, b.H, m, k, b.inv);
+        hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M, 256)), dim3(256), 0, s, b.inv, b.M, 1, w);
+        WPCD_HIP(hipGetLastError());
+        steps = k + 1;
+        if ((k + 1) % 8 == 0) {
+            WPCD_HIP(hipMemcpyAsync(invh.data(), b.inv, sizeof(double), hipMemcpyDeviceToHost, s));
+            WPCD_HIP(hipStreamSynchronize(s));
+            if (invh[0] == 0.0) break;   // invariant subspace found
+        }
+    }
+    H.resize((size_t)(m + 1) * m * 2);
+    WPCD_HIP(hipMemcpyAsync(H.data(), b.H, H.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    WPCD_HIP(hipStreamSynchronize(s));
+}
+
 void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
                       const std::vector<int32_t> &ens, const std::vector<double> &rho,
                       const std::vector<double> &rho0, std::vector<double> &out) {

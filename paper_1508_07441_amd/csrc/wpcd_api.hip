@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1006,6 +1007,263 @@ wpcd_status wpcd_get_p(wpcd_ctx *c, int64_t *row_ptr, int32_t *col, double *val)
 wpcd_status wpcd_solve(wpcd_ctx *c, const double *E, int32_t n_E, wpcd_precision prec,
                        const wpcd_solve_opts *opts, wpcd_energy_result *out, double *breakup_out) {
     return guarded(c, [&] { solve_impl(c, E, n_E, prec, opts, out, breakup_out, nullptr); });
+}
+
+namespace {
+using cd = std::complex<double>;
+
+// Eigenvalues of an n x n upper Hessenberg matrix A (row major) by the
+// shifted QR algorithm with Wilkinson shifts and deflation (complex).
+std::vector<cd> hessenberg_eigs(std::vector<cd> A, int n) {
+    auto at = [&](int i, int j) -> cd & { return A[(size_t)i * n + j]; };
+    std::vector<cd> ev;
+    int hi = n - 1, iter = 0;
+    while (hi >= 0) {
+        if (hi == 0) {
+            ev.push_back(at(0, 0));
+            break;
+        }
+        int l = hi;
+        for (; l > 0; --l) {
+            const double sc = std::abs(at(l - 1, l - 1)) + std::abs(at(l, l));
+            if (std::abs(at(l, l - 1)) <= 1e-15 * (sc > 0 ? sc : 1.0)) {
+                at(l, l - 1) = 0.0;
+                break;
+            }
+        }
+        if (l == hi) {
+            ev.push_back(at(hi, hi));
+            --hi;
+            iter = 0;
+            continue;
+        }
+        WPCD_REQUIRE(++iter <= 200, WPCD_E_NOT_CONVERGED, "Hessenberg QR did not converge");
+        const cd a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+        const cd tr2 = 0.5 * (a + d), disc = std::sqrt(tr2 * tr2 - (a * d - b * c));
+        cd mu = std::abs(tr2 + disc - d) < std::abs(tr2 - disc - d) ? tr2 + disc : tr2 - disc;
+        if (iter % 11 == 10) mu += std::abs(at(hi, hi - 1));   // exceptional shift
+        for (int k = l; k <= hi; ++k) at(k, k) -= mu;
+        std::vector<double> cs;
+        std::vector<cd> sn;
+        for (int k = l; k < hi; ++k) {
+            // G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0]
+            const cd x = at(k, k), y = at(k + 1, k);
+            const double r = std::sqrt(std::norm(x) + std::norm(y));
+            double cc = 1.0;
+            cd ss = 0.0;
+            if (r > 0) {
+                cc = std::abs(x) / r;
+                ss = (std::abs(x) > 0 ? x / std::abs(x) : cd(1.0, 0.0)) * std::conj(y) / r;
+            }
+            for (int j = k; j < n; ++j) {
+                const cd t1 = at(k, j), t2 = at(k + 1, j);
+                at(k, j) = cc * t1 + ss * t2;
+                at(k + 1, j) = -std::conj(ss) * t1 + cc * t2;
+            }
+            cs.push_back(cc);
+            sn.push_back(ss);
+        }
+        for (int k = l; k < hi; ++k) {   // times G^H from the right
+            const double cc = cs[k - l];
+            const cd ss = sn[k - l];
+            for (int i = 0; i <= std::min(k + 2, hi); ++i) {
+                const cd t1 = at(i, k), t2 = at(i, k + 1);
+                at(i, k) = cc * t1 + std::conj(ss) * t2;
+                at(i, k + 1) = -ss * t1 + cc * t2;
+            }
+        }
+        for (int k = l; k <= hi; ++k) at(k, k) += mu;
+    }
+    return ev;
+}
+
+// Largest real part of the Ritz values of K(E) from m Arnoldi steps.
+double kernel_top_ritz(wpcd_ctx *c, double E, int m) {
+    std::vector<double> H;
+    int n = 0;
+    arnoldi_kernel(c, E, m, H, n);
+    WPCD_REQUIRE(n >= 1, WPCD_E_DEVICE, "Arnoldi produced no step");
+    std::vector<cd> A((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = cd(H[((size_t)i * m + j) * 2], H[((size_t)i * m + j) * 2 + 1]);
+    double best = -1e300;
+    for (const cd &v : hessenberg_eigs(A, n)) best = std::max(best, v.real());
+    return best;
+}
+}  // namespace
+
+wpcd_status wpcd_bound_state(wpcd_ctx *c, double e_lo, double e_hi, double *e3_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
+                     "build_basis and build_p must come first");
+        WPCD_REQUIRE(e3_out && std::isfinite(e_lo) && std::isfinite(e_hi) && e_lo < e_hi,
+                     WPCD_E_INVALID, "need e_lo < e_hi and e3_out");
+        double eb = 1e300;
+        for (int a = 0; a < c->nch; ++a) eb = std::min(eb, c->waves[c->ch_wave[a]].h_eps[0]);
+        WPCD_REQUIRE(e_hi < eb, WPCD_E_BELOW_THRESHOLD,
+                     "the bracket must lie below the lowest pair level");
+        const int m = 64;
+        double f_lo = kernel_top_ritz(c, e_lo, m) - 1.0, f_hi = kernel_top_ritz(c, e_hi, m) - 1.0;
+        WPCD_REQUIRE(f_lo * f_hi <= 0.0, WPCD_E_INVALID,
+                     "no sign change of (largest eigenvalue of K) - 1 on the bracket");
+        double mid = 0.5 * (e_lo + e_hi);
+        for (int it = 0; it < 100 && e_hi - e_lo > 1e-12 * std::fabs(mid); ++it) {
+            mid = 0.5 * (e_lo + e_hi);
+            const double fm = kernel_top_ritz(c, mid, m) - 1.0;
+            if (fm * f_lo > 0) {
+                e_lo = mid;
+                f_lo = fm;
+            } else {
+                e_hi = mid;
+                f_hi = fm;
+            }
+        }
+        *e3_out = 0.5 * (e_lo + e_hi);
+    });
+}
+
+wpcd_status wpcd_solve_dev(wpcd_ctx *c, const double *E_dev, int32_t n_E, wpcd_precision prec,
+                           const wpcd_solve_opts *opts, wpcd_energy_result *out_dev) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(E_dev && out_dev && n_E >= 0, WPCD_E_INVALID, "E_dev/out_dev NULL or n_E < 0");
+        std::vector<double> E(n_E);
+        std::vector<wpcd_energy_result> out(n_E);
+        if (n_E)
+            WPCD_HIP(hipMemcpyAsync(E.data(), E_dev, n_E * sizeof(double), hipMemcpyDeviceToHost,
+                                    c->stream));
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+        solve_impl(c, E.data(), n_E, prec, opts, out.data(), nullptr, nullptr);
+        if (n_E)
+            WPCD_HIP(hipMemcpyAsync(out_dev, out.data(), n_E * sizeof(wpcd_energy_result),
+                                    hipMemcpyHostToDevice, c->stream));
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+// ---- P0 file: header (magic, version, grid signature), edges, CSR, values
+namespace {
+constexpr char kP0Magic[8] = {'W', 'P', 'C', 'D', 'P', '0', '\0', '\1'};
+
+struct P0Header {
+    char magic[8];
+    int32_t version, np, nq, ngq, ngx, L, nch, fp64;
+    int32_t l[kMaxCh], lam[kMaxCh];
+    int64_t nnz;
+};
+
+P0Header p0_header(const wpcd_ctx *c) {
+    P0Header h{};
+    std::memcpy(h.magic, kP0Magic, 8);
+    h.version = 1;
+    h.np = c->np;
+    h.nq = c->nq;
+    h.ngq = c->ngq;
+    h.ngx = c->ngx;
+    h.L = c->L;
+    h.nch = c->nch;
+    h.fp64 = c->p_fp64 ? 1 : 0;
+    for (int a = 0; a < c->nch; ++a) {
+        h.l[a] = c->ch_l[a];
+        h.lam[a] = c->ch_lam[a];
+    }
+    h.nnz = c->nnz;
+    return h;
+}
+
+struct File {
+    FILE *f;
+    explicit File(FILE *f_) : f(f_) {}
+    ~File() {
+        if (f) std::fclose(f);
+    }
+};
+}  // namespace
+
+wpcd_status wpcd_save_p(wpcd_ctx *c, const char *path) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(path, WPCD_E_INVALID, "path is NULL");
+        WPCD_REQUIRE(c->has_p, WPCD_E_STATE, "no P0 built");
+        const P0Header h = p0_header(c);
+        const int64_t nrow = (int64_t)c->np * c->nq, nv = c->nnz * c->nch * c->nch;
+        std::vector<int64_t> rp(nrow + 1);
+        std::vector<int32_t> col(c->nnz), ri(c->nnz);
+        std::vector<char> val(nv * (c->p_fp64 ? 8 : 4));
+        WPCD_HIP(hipMemcpyAsync(rp.data(), c->d_rowptr.ptr, rp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        WPCD_HIP(hipMemcpyAsync(col.data(), c->d_col.ptr, col.size() * 4, hipMemcpyDeviceToHost, c->stream));
+        WPCD_HIP(hipMemcpyAsync(ri.data(), c->d_rowidx.ptr, ri.size() * 4, hipMemcpyDeviceToHost, c->stream));
+        WPCD_HIP(hipMemcpyAsync(val.data(), c->p_fp64 ? (void *)c->d_val64.ptr : (void *)c->d_val32.ptr,
+                                val.size(), hipMemcpyDeviceToHost, c->stream));
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+        File f(std::fopen(path, "wb"));
+        WPCD_REQUIRE(f.f, WPCD_E_INVALID, std::string("cannot open for writing: ") + path);
+        bool ok = std::fwrite(&h, sizeof h, 1, f.f) == 1 &&
+                  std::fwrite(c->p.data(), 8, c->p.size(), f.f) == c->p.size() &&
+                  std::fwrite(c->q.data(), 8, c->q.size(), f.f) == c->q.size() &&
+                  std::fwrite(rp.data(), 8, rp.size(), f.f) == rp.size() &&
+                  std::fwrite(col.data(), 4, col.size(), f.f) == col.size() &&
+                  std::fwrite(ri.data(), 4, ri.size(), f.f) == ri.size() &&
+                  std::fwrite(val.data(), 1, val.size(), f.f) == val.size();
+        ok = (std::fclose(f.f) == 0) && ok;
+        f.f = nullptr;
+        WPCD_REQUIRE(ok, WPCD_E_INVALID, std::string("write failed: ") + path);
+    });
+}
+
+wpcd_status wpcd_load_p(wpcd_ctx *c, const char *path, int64_t *nnz_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(path, WPCD_E_INVALID, "path is NULL");
+        WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        File f(std::fopen(path, "rb"));
+        WPCD_REQUIRE(f.f, WPCD_E_INVALID, std::string("cannot open: ") + path);
+        P0Header h{};
+        WPCD_REQUIRE(std::fread(&h, sizeof h, 1, f.f) == 1 && std::memcmp(h.magic, kP0Magic, 8) == 0 &&
+                         h.version == 1,
+                     WPCD_E_INVALID, "not a P0 file of this library");
+        P0Header mine = p0_header(c);
+        bool same = h.np == mine.np && h.nq == mine.nq && h.ngq == mine.ngq && h.ngx == mine.ngx &&
+                    h.L == mine.L && h.nch == mine.nch;
+        for (int a = 0; same && a < h.nch; ++a) same = h.l[a] == mine.l[a] && h.lam[a] == mine.lam[a];
+        WPCD_REQUIRE(same, WPCD_E_INVALID, "P0 file was built for another basis");
+        std::vector<double> p(c->p.size()), q(c->q.size());
+        WPCD_REQUIRE(std::fread(p.data(), 8, p.size(), f.f) == p.size() &&
+                         std::fread(q.data(), 8, q.size(), f.f) == q.size() && p == c->p && q == c->q,
+                     WPCD_E_INVALID, "P0 file was built on other bin edges");
+        WPCD_REQUIRE(h.nnz >= 0 && h.nnz < ((int64_t)1 << 40), WPCD_E_INVALID, "bad nonzero count");
+        const int64_t nrow = (int64_t)c->np * c->nq, nv = h.nnz * c->nch * c->nch;
+        std::vector<int64_t> rp(nrow + 1);
+        std::vector<int32_t> col(h.nnz), ri(h.nnz);
+        std::vector<char> val(nv * (h.fp64 ? 8 : 4));
+        WPCD_REQUIRE(std::fread(rp.data(), 8, rp.size(), f.f) == rp.size() &&
+                         std::fread(col.data(), 4, col.size(), f.f) == col.size() &&
+                         std::fread(ri.data(), 4, ri.size(), f.f) == ri.size() &&
+                         std::fread(val.data(), 1, val.size(), f.f) == val.size(),
+                     WPCD_E_INVALID, "P0 file is truncated");
+        WPCD_REQUIRE(rp[0] == 0 && rp[nrow] == h.nnz, WPCD_E_INVALID, "P0 file: inconsistent row pointers");
+        for (int64_t r = 0; r < nrow; ++r)
+            WPCD_REQUIRE(rp[r] <= rp[r + 1], WPCD_E_INVALID, "P0 file: row pointers not monotone");
+        for (int64_t k = 0; k < h.nnz; ++k)
+            WPCD_REQUIRE(col[k] >= 0 && col[k] < nrow && ri[k] >= 0 && ri[k] < nrow, WPCD_E_INVALID,
+                         "P0 file: index out of range");
+        c->has_p = false;
+        c->d_rowptr.reserve(nrow + 1);
+        c->d_col.reserve(h.nnz);
+        c->d_rowidx.reserve(h.nnz);
+        WPCD_HIP(hipMemcpyAsync(c->d_rowptr.ptr, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, c->stream));
+        WPCD_HIP(hipMemcpyAsync(c->d_col.ptr, col.data(), col.size() * 4, hipMemcpyHostToDevice, c->stream));
+        WPCD_HIP(hipMemcpyAsync(c->d_rowidx.ptr, ri.data(), ri.size() * 4, hipMemcpyHostToDevice, c->stream));
+        if (h.fp64) {
+            c->d_val64.reserve(nv);
+            WPCD_HIP(hipMemcpyAsync(c->d_val64.ptr, val.data(), val.size(), hipMemcpyHostToDevice, c->stream));
+        } else {
+            c->d_val32.reserve(nv);
+            WPCD_HIP(hipMemcpyAsync(c->d_val32.ptr, val.data(), val.size(), hipMemcpyHostToDevice, c->stream));
+        }
+        WPCD_HIP(hipStreamSynchronize(c->stream));
+        c->nnz = h.nnz;
+        c->p_fp64 = h.fp64 != 0;
+        c->has_p = true;
+        if (nnz_out) *nnz_out = h.nnz;
+    });
 }
 
 wpcd_status wpcd_solve_multi(wpcd_ctx *const *ctxs, int32_t n_sys, const double *const *E,

@@ -40,6 +40,10 @@ def test_null_arguments_rejected_without_device():
     assert L.wpcd_solve(None, None, 0, 0, None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_set_multipliers(None, None, 0) == P.WPCD_E_INVALID
     assert L.wpcd_solve_multi(None, 0, None, None, 0, None, None, None) == P.WPCD_E_INVALID
+    assert L.wpcd_save_p(None, None) == P.WPCD_E_INVALID
+    assert L.wpcd_bound_state(None, 0.0, 0.0, None) == P.WPCD_E_INVALID
+    assert L.wpcd_load_p(None, None, None) == P.WPCD_E_INVALID
+    assert L.wpcd_solve_dev(None, None, 0, 0, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_learn_train(None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_mlp_eval(None, 1, 1, 1, None, 1, None, None, None, None, None) == P.WPCD_E_INVALID
     assert L.wpcd_set_autotune(None, 0) == P.WPCD_E_INVALID

@@ -446,3 +446,63 @@ def test_solve_multi_uneven_systems(P):
         P.wpcd_solve_multi([ctxs[0].h, ctxs[0].h], [[0.1], [0.2]], P.WPCD_FP64)
     for c in ctxs:
         c.close()
+
+
+def test_save_load_p_and_device_energies(ctx, P, tmp_path):
+    """A saved P0 loads into a context with the same basis (not another one)
+    and solves identically; device-resident energies give the host results."""
+    import ctypes
+    n = 24
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    nnz = ctx.build_p(P.WPCD_FP64)
+    E = [0.05, 0.6]
+    ref = ctx.solve(E, P.WPCD_FP64)
+    path = str(tmp_path / "p0.bin")
+    ctx.save_p(path)
+    c2 = P.Context(0)
+    c2.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    assert c2.load_p(path) == nnz
+    res = c2.solve(E, P.WPCD_FP64)
+    for a, b in zip(ref, res):
+        assert (a.U_re, a.U_im) == (b.U_re, b.U_im)
+    c3 = P.Context(0)
+    c3.build_basis(n + 1, n, 10.0, 10.0, 8, 16, potential=YAM)
+    with pytest.raises(P.WpcdError) as ei:
+        c3.load_p(path)
+    assert ei.value.status == P.WPCD_E_INVALID
+    # device-resident energies and results
+    hip = ctypes.CDLL("libamdhip64.so")
+    dE, dR = ctypes.c_void_p(), ctypes.c_void_p()
+    nb = ctypes.sizeof(P.wpcd_energy_result) * len(E)
+    assert hip.hipMalloc(ctypes.byref(dE), ctypes.c_size_t(8 * len(E))) == 0
+    assert hip.hipMalloc(ctypes.byref(dR), ctypes.c_size_t(nb)) == 0
+    hE = (ctypes.c_double * len(E))(*E)
+    assert hip.hipMemcpy(dE, hE, ctypes.c_size_t(8 * len(E)), 1) == 0
+    P.wpcd_solve_dev(c2.h, dE.value, len(E), dR.value, P.WPCD_FP64)
+    hR = (P.wpcd_energy_result * len(E))()
+    assert hip.hipMemcpy(hR, dR, ctypes.c_size_t(nb), 2) == 0
+    for a, b in zip(ref, hR):
+        assert (a.U_re, a.U_im, a.status) == (b.U_re, b.U_im, b.status)
+    hip.hipFree(dE)
+    hip.hipFree(dR)
+    c2.close()
+    c3.close()
+
+
+def test_bound_state_parity(ctx, P):
+    """E3 of the homogeneous equation (Arnoldi on K(E) on the GPU, largest
+    real Ritz value = 1) against the oracle's (ARPACK, bisection) on the
+    40 x 40 Yamaguchi grid; a bracket without a sign change is an error."""
+    n = 40
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    ctx.build_p(P.WPCD_FP64)
+    eps, _, _ = ctx.pair_spectrum(0, want_O=False)
+    say("[E3] GPU bound state")
+    e3 = ctx.bound_state(-3.0, eps[0] - 1e-4)
+    sysm = _oracle_system_yam(n, 16)
+    e3_o = O.bound_state(sysm, -3.0, sysm.eps[0][0] - 1e-4, tol=1e-11)
+    say(f"[E3] GPU {e3:.12f} oracle {e3_o:.12f}")
+    assert abs(e3 - e3_o) <= 1e-9 * abs(e3_o)
+    with pytest.raises(P.WpcdError) as ei:
+        ctx.bound_state(-3.0, -2.0)
+    assert ei.value.status == P.WPCD_E_INVALID
