@@ -210,8 +210,12 @@ struct Comp32 {
     }
 };
 
-__device__ __forceinline__ void lane_limits(const ElemTables &T, int i, int i2, double q, double q2,
-                                            double &lo_t, double &lo_u, double &h) {
+// Parts of the limits that depend only on the Gauss pair (q, q2).
+struct QLim {
+    double t_lo, t_hi, u_lo, u_hi, D;
+};
+
+__device__ __forceinline__ QLim q_limits(double q, double q2) {
     // Limits are rounded exactly as written (no FMA contraction): where a
     // limit is formed by cancellation (p^2 - D with D ~ p^2) the element is
     // ill-conditioned and must round the same way as the reference formula.
@@ -221,14 +225,31 @@ __device__ __forceinline__ void lane_limits(const ElemTables &T, int i, int i2, 
     // limit is formed by cancellation.
     const double m1 = q2 - 0.5 * q, p1 = q2 + 0.5 * q;
     const double m2 = q - 0.5 * q2, p2 = q + 0.5 * q2;
-    const double D = 0.75 * (q - q2) * (q + q2);
+    QLim L;
+    L.D = 0.75 * (q - q2) * (q + q2);
+    L.t_lo = m1 * m1;
+    L.t_hi = p1 * p1;
+    L.u_lo = m2 * m2;
+    L.u_hi = p2 * p2;
+    return L;
+}
+
+// Clipped interval of t = pi1^2 (and u = pi2^2 = t + D) for pair bins i, i2.
+__device__ __forceinline__ void bin_limits(const ElemTables &T, int i, int i2, const QLim &L,
+                                           double &lo_t, double &lo_u, double &h) {
+#pragma clang fp contract(off)
     const double pl1 = T.P2[i], ph1 = T.P2[i + 1];
     const double pl2 = T.P2[i2], ph2 = T.P2[i2 + 1];
-    lo_t = fmax(fmax(m1 * m1, pl1), pl2 - D);
-    double hi_t = fmin(fmin(p1 * p1, ph1), ph2 - D);
-    lo_u = fmax(fmax(m2 * m2, pl2), pl1 + D);
-    double hi_u = fmin(fmin(p2 * p2, ph2), ph1 + D);
+    lo_t = fmax(fmax(L.t_lo, pl1), pl2 - L.D);
+    double hi_t = fmin(fmin(L.t_hi, ph1), ph2 - L.D);
+    lo_u = fmax(fmax(L.u_lo, pl2), pl1 + L.D);
+    double hi_u = fmin(fmin(L.u_hi, ph2), ph1 + L.D);
     h = (hi_t > lo_t) ? 0.25 * ((hi_t - lo_t) + (hi_u - lo_u)) : 0.0;
+}
+
+__device__ __forceinline__ void lane_limits(const ElemTables &T, int i, int i2, double q, double q2,
+                                            double &lo_t, double &lo_u, double &h) {
+    bin_limits(T, i, i2, q_limits(q, q2), lo_t, lo_u, h);
 }
 
 __global__ __launch_bounds__(256) void k_p0_swave_f64(ElemTables T,
@@ -389,6 +410,28 @@ __device__ __forceinline__ double inner_f64(const NodeTab &N, int ngx, double lt
     return s;
 }
 
+// FP64 value of lane (permuted within its row of 16) by a DPP move of both
+// halves; every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G lanes (G = 16, 8 or 4), the result in every
+// lane of the group: row mirror (lane i with 15 - i), half-row mirror
+// (i with 7 - i), quad reverse, quad swap.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(G == 16 || G == 8 || G == 4, "group of 4, 8 or 16 lanes");
+    if (G == 16) v += dpp_f64<0x140>(v);
+    if (G >= 8) v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x1B>(v);   // quad_perm [3, 2, 1, 0]
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    return v;
+}
+
 template <bool F32, int NGX, int EC>
 __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                                                     const int32_t *__restrict__ rowidx,
@@ -412,20 +455,33 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
         const int64_t chunk = cbase + w;
         // phase 1: limits of kEC cell pairs, compaction into the queue
         int total = 0;
+        double scale[kEC];   // (d_i d_i2 dq_j dq_j2)^(-1/2) of each cell pair
+        // consecutive cell pairs of a row mostly share the spectator bins
+        // (j, j2): their Gauss-pair parts of the limits are kept
+        int pj = -1, pj2 = -1;
+        QLim QL{};
+        double wq = 0.0;
 #pragma unroll
         for (int k = 0; k < kEC; ++k) {
             const int64_t e = chunk * kEC + k;
             bool act = false;
             double lo_t = 0.0, lo_u = 0.0, h = 0.0, wab = 0.0;
+            scale[k] = 0.0;
             if (chunk < nch && e < nnz) {
                 // the cell pair is the same for the whole wavefront
                 int i, j, i2, j2;
                 cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
                 cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
-                const double q = T.qnode[j * 8 + a], q2 = T.qnode[j2 * 8 + b];
-                lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
+                if (j != pj || j2 != pj2) {
+                    QL = q_limits(T.qnode[j * 8 + a], T.qnode[j2 * 8 + b]);
+                    wq = T.qwt[j * 8 + a] * T.qwt[j2 * 8 + b];
+                    pj = j;
+                    pj2 = j2;
+                }
+                bin_limits(T, i, i2, QL, lo_t, lo_u, h);
                 act = h > 0.0;
-                wab = T.qwt[j * 8 + a] * T.qwt[j2 * 8 + b] * h;
+                wab = wq * h;
+                scale[k] = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
             }
             const unsigned long long m = __ballot(act);
             const int rank = __popcll(m & ((1ull << lane) - 1ull));
@@ -466,32 +522,31 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
             }
         }
         __syncthreads();
-        // phase 3: reduce each cell pair over its 64 slots
+        // phase 3: each cell pair's 64 slots summed in FP64 by 16 lanes (slots
+        // m, m + 16, m + 32, m + 48; conflict-free LDS rows), then across the
+        // 16 lanes by DPP; each slot's (hi, lo) pair is summed in FP64 first.
+        // Four cell pairs per step, so every kEC gives the same order; exact
+        // enough to make the order immaterial at FP32 output precision.
+        static_assert(kEC % 4 == 0, "cell pairs per round: a multiple of 4");
 #pragma unroll
-        for (int k = 0; k < kEC; ++k) {
+        for (int hf = 0; hf < kEC / 4; ++hf) {
+            const int k = hf * 4 + (lane >> 4), m = lane & 15;
+            auto slot = [&](int t) {
+                return F32 ? (double)s_hi[w][k][t] + (double)s_lo[w][k][t] : (double)s_hi[w][k][t];
+            };
+            double sv = slot(m);
+            sv += slot(m + 16);
+            sv += slot(m + 32);
+            sv += slot(m + 48);
+            sv = group_sum<16>(sv);
+            double sc = scale[hf * 4];
+#pragma unroll
+            for (int kk = 1; kk < 4; ++kk)
+                if ((lane >> 4) == kk) sc = scale[hf * 4 + kk];
             const int64_t e = chunk * kEC + k;
-            if (F32) {
-                // each slot's (hi, lo) pair summed in FP64, then an FP64
-                // wavefront sum: exact enough to make the slot order immaterial
-                // at FP32 output precision, and fewer instructions than FP32
-                // TwoSum chains
-                double s = (double)s_hi[w][k][lane] + (double)s_lo[w][k][lane];
-                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-                if (lane == 0 && chunk < nch && e < nnz) {
-                    int i, j, i2, j2;
-                    cell_ij(T, (uint32_t)rowidx[e], i, j);
-                    cell_ij(T, (uint32_t)col[e], i2, j2);
-                    val32[e] = (float)(s * (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]));
-                }
-            } else {
-                double s = (double)s_hi[w][k][lane];
-                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-                if (lane == 0 && chunk < nch && e < nnz) {
-                    int i, j, i2, j2;
-                    cell_ij(T, (uint32_t)rowidx[e], i, j);
-                    cell_ij(T, (uint32_t)col[e], i2, j2);
-                    val64[e] = s * (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
-                }
+            if (m == 0 && chunk < nch && e < nnz) {
+                if (F32) val32[e] = (float)(sv * sc);
+                else val64[e] = sv * sc;
             }
         }
         __syncthreads();
