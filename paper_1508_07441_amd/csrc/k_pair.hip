@@ -175,6 +175,49 @@ __device__ __forceinline__ double wsum(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Yukawa-sum potential matrix, one wavefront per element of the upper
+// triangle (i <= k; the lower triangle is its mirror): the lanes split the
+// n_gauss^2 quadrature points of the cell pair (8 x 8 lane grid, strided),
+// then a wavefront sum.  Same integrand as k_potential.
+__global__ __launch_bounds__(256) void k_potential_yukawa(const double *__restrict__ p, int n,
+                                                          int l, int nterms,
+                                                          const double *__restrict__ s,
+                                                          const double *__restrict__ mu,
+                                                          PotQuad qd, double scale,
+                                                          double *__restrict__ v) {
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= (int64_t)n * n) return;   // uniform per wavefront
+    const int i = (int)(e / n), k = (int)(e - (int64_t)i * n);
+    if (k < i) return;
+    const double ai = p[i], bi = p[i + 1], ak = p[k], bk = p[k + 1];
+    const double mi = 0.5 * (ai + bi), hi = 0.5 * (bi - ai);
+    const double mk = 0.5 * (ak + bk), hk = 0.5 * (bk - ak);
+    const int a0 = lane >> 3, b0 = lane & 7;
+    double acc = 0.0;
+    for (int t = 0; t < nterms; ++t) {
+        const double m2 = mu[t] * mu[t];
+        double st = 0.0;
+        for (int a = a0; a < qd.n; a += 8) {
+            const double x1 = mi + hi * qd.x[a];
+            for (int b = b0; b < qd.n; b += 8) {
+                const double x2 = mk + hk * qd.x[b];
+                const double den = 2.0 * x1 * x2;
+                const double sp = (x1 + x2) * (x1 + x2) + m2;
+                const double sm = (x1 - x2) * (x1 - x2) + m2;
+                const double z = (x1 * x1 + x2 * x2 + m2) / den;
+                st += (qd.w[a] * qd.w[b]) * legendre_q_dev(l, z, sp / den, sm / den);
+            }
+        }
+        acc += s[t] / M_PI * wsum(st) * hi * hk;
+    }
+    if (lane == 0) {
+        const double val = scale * acc / sqrt((bi - ai) * (bk - ak));
+        v[(int64_t)i * n + k] = val;
+        v[(int64_t)k * n + i] = val;
+    }
+}
+
 // One tournament round over blocks: workgroup s takes block pair (I, J),
 // loads the 2b columns into LDS, rotates every pair among them once (2b - 1
 // inner rounds of b disjoint pairs, one wavefront per pair, the pair's
@@ -242,6 +285,147 @@ __global__ __launch_bounds__(1024) void k_jacobi_blocks(double *__restrict__ W, 
         if (gc < n) W[(int64_t)gc * n + e] = sW[idx];
     }
     if (any) rotated[sweep] = 1;
+}
+
+// Sum over the 8 lanes of an aligned group (half-row mirror, quad reverse,
+// quad swap); the result in every lane of the group.
+__device__ __forceinline__ double gsum8(double v) {
+    v += dpp_move<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp_move<0x1B, 0xf>(v);    // quad_perm [3, 2, 1, 0]
+    v += dpp_move<0xB1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    return v;
+}
+
+// Whole one-sided Jacobi in one workgroup, for n <= 8 EPL (EPL <= 20): group g of 8
+// lanes holds two columns (A, B) in registers, element u + 8 r in lane u,
+// slot r.  Column pairs follow the odd-even transposition ordering over
+// positions 0 .. 2P - 1 (P = ceil(n / 2) groups): in even rounds group g
+// rotates the columns at positions (2g, 2g + 1), in odd rounds those at
+// (2g + 1, 2g + 2) (group P - 1 idle), and each rotated pair trades places,
+// so every pair meets once in 2P rounds.  In registers this means one column
+// per group moves per round, through an LDS mailbox: after an even round B
+// comes from group g + 1 (group P - 1 then swaps A and B), after an odd round
+// A comes from group g - 1 (indices mod P).  Sweeps repeat until a sweep
+// rotates nothing (workgroup vote) or max_sweeps; status[0] = sweeps done,
+// status[1] = 1 if converged.
+// One round of k_jacobi_wg for group g (ODD: the odd positions' pairing):
+// rotate the held pair if it is active and not yet orthogonal, then pass
+// the moving column on through the mailbox.
+template <int EPL, bool ODD>
+__device__ __forceinline__ void jacobi_round(double (&A)[EPL], double (&B)[EPL], int &idA,
+                                             int &idB, double *mail, int *mail_id, int g, int u,
+                                             int P, int Ppad, double tol2, int &any) {
+    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+        al += A[r] * A[r];
+        be += B[r] * B[r];
+        ga += A[r] * B[r];
+    }
+    al = gsum8(al);
+    be = gsum8(be);
+    ga = gsum8(ga);
+    const bool active = ODD ? g < P - 1 : g < P;
+    if (active && ga * ga > tol2 * (al * be)) {
+        // The angle only sets how much of the pair's overlap this rotation
+        // removes, so it is formed in FP32 (|ze| < 1e17 here: the norms
+        // differ by < 1e3 and |ga| > tol |A||B|); the rotation built from
+        // it, c = (1 + t^2)^(-1/2) and s = t c, is orthogonal to FP64
+        // rounding, and convergence is judged on the FP64 overlaps.
+        // (hardware reciprocal and square root: the angle needs ~1e-6)
+        const float ze = (float)(be - al) * __builtin_amdgcn_rcpf((float)(2.0 * ga));
+        const float rt = __builtin_amdgcn_rcpf(fabsf(ze) + __builtin_amdgcn_sqrtf(fmaf(ze, ze, 1.f)));
+        const double t = (double)(ze >= 0.f ? rt : -rt);
+        const double x = 1.0 + t * t;
+        double c = rsqrt(x);
+        c = c * (1.5 - 0.5 * x * c * c);   // one Newton step: c to FP64 rounding
+        const double sn = t * c;
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+            const double x = A[r], y = B[r];
+            A[r] = c * x - sn * y;
+            B[r] = sn * x + c * y;
+        }
+        any = 1;
+    }
+    double *mine = mail + (size_t)g * 8 + u;
+    const size_t stride = (size_t)Ppad * 8;
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) mine[r * stride] = ODD ? A[r] : B[r];
+    if (u == 0) mail_id[g] = ODD ? idA : idB;
+    __syncthreads();
+    if (g < P) {
+        const int src = ODD ? (g == 0 ? P - 1 : g - 1) : (g + 1 == P ? 0 : g + 1);
+        const double *from = mail + (size_t)src * 8 + u;
+        if (ODD) {
+#pragma unroll
+            for (int r = 0; r < EPL; ++r) A[r] = from[r * stride];
+            idA = mail_id[src];
+        } else {
+#pragma unroll
+            for (int r = 0; r < EPL; ++r) B[r] = from[r * stride];
+            idB = mail_id[src];
+            if (g == P - 1) {
+#pragma unroll
+                for (int r = 0; r < EPL; ++r) {
+                    const double x = A[r];
+                    A[r] = B[r];
+                    B[r] = x;
+                }
+                const int xi = idA;
+                idA = idB;
+                idB = xi;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int EPL>
+__global__ __launch_bounds__(768) void k_jacobi_wg(double *__restrict__ W, int n, double tol,
+                                                    int max_sweeps, int *__restrict__ status) {
+    extern __shared__ double mail[];   // [EPL][Ppad][8] doubles, then ids [Ppad]
+    const int tid = threadIdx.x, u = tid & 7, g = tid >> 3;
+    const int Ppad = blockDim.x >> 3;
+    const int P = (n + 1) >> 1;
+    int *mail_id = (int *)(mail + (size_t)EPL * Ppad * 8);
+    double A[EPL], B[EPL];
+    int idA = 2 * g, idB = 2 * g + 1;
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+        const int e = u + 8 * r;
+        A[r] = (idA < n && e < n) ? W[(int64_t)idA * n + e] : 0.0;
+        B[r] = (idB < n && e < n) ? W[(int64_t)idB * n + e] : 0.0;
+    }
+    const double tol2 = tol * tol;
+    int sweep = 0, converged = 0;
+    while (sweep < max_sweeps) {
+        int any = 0;
+        // 2P rounds: even and odd alternate
+        for (int rd = 0; rd < P; ++rd) {
+            jacobi_round<EPL, false>(A, B, idA, idB, mail, mail_id, g, u, P, Ppad, tol2, any);
+            jacobi_round<EPL, true>(A, B, idA, idB, mail, mail_id, g, u, P, Ppad, tol2, any);
+        }
+        ++sweep;
+        if (!__syncthreads_or(any)) {
+            converged = 1;
+            break;
+        }
+    }
+    if (g < P) {
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+            const int e = u + 8 * r;
+            if (e < n) {
+                if (idA < n) W[(int64_t)idA * n + e] = A[r];
+                if (idB < n) W[(int64_t)idB * n + e] = B[r];
+            }
+        }
+    }
+    if (tid == 0) {
+        status[0] = sweep;
+        status[1] = converged;
+    }
 }
 
 // Column norms: lam'[k] = |w_k|, eps[k] = lam'[k] - sigma.
@@ -328,21 +512,28 @@ void launch_potential(wpcd_ctx *c, int wave, double *v_out) {
     WPCD_HIP(hipMemcpyAsync(ms.ptr, host.data(), 32 * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
     PotQuad qd = pot_quad(c);
-    int threads = 256, blocks = (n * n + threads - 1) / threads;
     TimedLaunch tl(c->timer, c->stream, "potential", WPCD_TIME_PAIR);
-    hipLaunchKernelGGL(k_potential, dim3(blocks), dim3(threads), 0, c->stream, c->d_p.ptr, n, l,
-                       c->pot_kind, nt, ms.ptr, ms.ptr + 16, qd, c->pot_scale, v_out);
+    if (c->pot_kind == 0) {
+        // separable: one thread per element
+        int threads = 256, blocks = (n * n + threads - 1) / threads;
+        hipLaunchKernelGGL(k_potential, dim3(blocks), dim3(threads), 0, c->stream, c->d_p.ptr, n,
+                           l, c->pot_kind, nt, ms.ptr, ms.ptr + 16, qd, c->pot_scale, v_out);
+    } else {
+        const int64_t waves = (int64_t)n * n;
+        hipLaunchKernelGGL(k_potential_yukawa, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
+                           c->stream, c->d_p.ptr, n, l, nt, ms.ptr, ms.ptr + 16, qd, c->pot_scale,
+                           v_out);
+    }
     WPCD_HIP(hipGetLastError());
 }
+
+// Largest elements per lane of the one-workgroup Jacobi (n <= 160).
+constexpr int kWgMaxEpl = 20;
 
 void pair_diagonalise(wpcd_ctx *c, int wave, bool want_vectors) {
     const int n = c->np;
     PairWave &pw = c->waves[wave];
     constexpr int kMaxSweeps = 40;
-    const int b = (2 * 16 * n * (int)sizeof(double) <= 150 * 1024) ? 16 : 8;
-    const int nbr = (n + b - 1) / b;
-    const int NB = nbr + (nbr & 1);
-    const size_t lds = (size_t)2 * b * n * sizeof(double);
     // workspace: W [n*n] | rowlo [n] | nrm [n] | ev [n] | sigma [1]
     c->d_jac.reserve((size_t)n * n + 3 * (size_t)n + 8);
     c->d_flag.reserve(kMaxSweeps + 4);
@@ -357,31 +548,62 @@ void pair_diagonalise(wpcd_ctx *c, int wave, bool want_vectors) {
         hipLaunchKernelGGL(k_shift, dim3(1), dim3(256), 0, s, W, n, rowlo, sigma);
         WPCD_HIP(hipGetLastError());
     }
-    WPCD_HIP(hipMemsetAsync(rot, 0, kMaxSweeps * sizeof(int), s));
-    const int npl = (n + 63) / 64;
-    auto kern = npl <= 2 ? k_jacobi_blocks<2>
-              : npl <= 4 ? k_jacobi_blocks<4>
-              : npl <= 8 ? k_jacobi_blocks<8>
-                         : k_jacobi_blocks<16>;
-    WPCD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 160 * 1024));
     const double tol = 2.2e-16 * (double)n;
-    int sweep = 0;
-    bool converged = false;
-    for (; sweep < kMaxSweeps && !converged; ++sweep) {
-        {
+    if (n <= 8 * kWgMaxEpl) {
+        // whole Jacobi in one workgroup, columns in registers
+        const int need = (n + 7) / 8;
+        const int epl = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 20;
+        const int P = (n + 1) / 2, Ppad = (P + 7) / 8 * 8;
+        const size_t lds = (size_t)epl * Ppad * 8 * sizeof(double) + (size_t)Ppad * sizeof(int);
+        auto go = [&](auto kern) {
+            WPCD_HIP(hipFuncSetAttribute((const void *)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             TimedLaunch tl(c->timer, s, "jacobi_sweep", WPCD_TIME_PAIR);
-            for (int r = 0; r < NB - 1; ++r)
-                hipLaunchKernelGGL(kern, dim3(NB / 2), dim3(64 * b), lds, s, W, n, b, NB, r, tol,
-                                   rot, sweep);
+            hipLaunchKernelGGL(kern, dim3(1), dim3(Ppad * 8), lds, s, W, n, tol, kMaxSweeps, rot);
             WPCD_HIP(hipGetLastError());
+        };
+        switch (epl) {
+            case 4: go(k_jacobi_wg<4>); break;
+            case 8: go(k_jacobi_wg<8>); break;
+            case 12: go(k_jacobi_wg<12>); break;
+            case 16: go(k_jacobi_wg<16>); break;
+            default: go(k_jacobi_wg<20>); break;
         }
-        int flag = 1;
-        WPCD_HIP(hipMemcpyAsync(&flag, rot + sweep, sizeof(int), hipMemcpyDeviceToHost, s));
+        int st[2] = {0, 0};
+        WPCD_HIP(hipMemcpyAsync(st, rot, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         WPCD_HIP(hipStreamSynchronize(s));
-        converged = (flag == 0);
+        WPCD_REQUIRE(st[1] == 1, WPCD_E_NOT_CONVERGED, "pair diagonalisation did not converge");
+    } else {
+        // block-cyclic Jacobi over workgroups, one launch per tournament round
+        const int b = (2 * 16 * n * (int)sizeof(double) <= 150 * 1024) ? 16 : 8;
+        const int nbr = (n + b - 1) / b;
+        const int NB = nbr + (nbr & 1);
+        const size_t lds = (size_t)2 * b * n * sizeof(double);
+        WPCD_HIP(hipMemsetAsync(rot, 0, kMaxSweeps * sizeof(int), s));
+        const int npl = (n + 63) / 64;
+        auto kern = npl <= 2 ? k_jacobi_blocks<2>
+                  : npl <= 4 ? k_jacobi_blocks<4>
+                  : npl <= 8 ? k_jacobi_blocks<8>
+                             : k_jacobi_blocks<16>;
+        WPCD_HIP(hipFuncSetAttribute((const void *)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        int sweep = 0;
+        bool converged = false;
+        for (; sweep < kMaxSweeps && !converged; ++sweep) {
+            {
+                TimedLaunch tl(c->timer, s, "jacobi_sweep", WPCD_TIME_PAIR);
+                for (int r = 0; r < NB - 1; ++r)
+                    hipLaunchKernelGGL(kern, dim3(NB / 2), dim3(64 * b), lds, s, W, n, b, NB, r,
+                                       tol, rot, sweep);
+                WPCD_HIP(hipGetLastError());
+            }
+            int flag = 1;
+            WPCD_HIP(hipMemcpyAsync(&flag, rot + sweep, sizeof(int), hipMemcpyDeviceToHost, s));
+            WPCD_HIP(hipStreamSynchronize(s));
+            converged = (flag == 0);
+        }
+        WPCD_REQUIRE(converged, WPCD_E_NOT_CONVERGED, "pair diagonalisation did not converge");
     }
-    WPCD_REQUIRE(converged, WPCD_E_NOT_CONVERGED, "pair diagonalisation did not converge");
     {
         TimedLaunch tl(c->timer, s, "eig_finish", WPCD_TIME_PAIR);
         hipLaunchKernelGGL(k_colnorm, dim3((n + 3) / 4), dim3(256), 0, s, W, n, sigma, nrm, ev);

@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -84,7 +86,7 @@ void Timer::release() {
 // eigenproblem is solved by cyclic Jacobi rotations on the dense n x n
 // matrix; nodes are then polished by Newton steps in long double and the
 // weights recomputed from P_n'.
-void gauss_legendre_gw(int n, std::vector<double> &x, std::vector<double> &w) {
+static void gauss_legendre_compute(int n, std::vector<double> &x, std::vector<double> &w) {
     std::vector<long double> J((size_t)n * n, 0.0L), V((size_t)n * n, 0.0L);
     for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0L;
     for (int k = 1; k < n; ++k) {
@@ -157,6 +159,21 @@ void gauss_legendre_gw(int n, std::vector<double> &x, std::vector<double> &w) {
         w[k] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
     }
     if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+// The rule of each order is computed once per process and shared.
+void gauss_legendre_gw(int n, std::vector<double> &x, std::vector<double> &w) {
+    static std::mutex mu;
+    static std::map<int, std::pair<std::vector<double>, std::vector<double>>> rules;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = rules.find(n);
+    if (it == rules.end()) {
+        std::vector<double> xs, ws;
+        gauss_legendre_compute(n, xs, ws);
+        it = rules.emplace(n, std::make_pair(std::move(xs), std::move(ws))).first;
+    }
+    x = it->second.first;
+    w = it->second.second;
 }
 
 template <class T>

@@ -17,6 +17,8 @@
 
 #include <cmath>
 #include <complex>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "wpcd_internal.h"
@@ -142,8 +144,8 @@ ld ylm_sign(int m, int azimuth_sign) {
 //   G = sum_{M, m1} coef P_l^|m1|(c1) P_lam^|M-m1|(x) P_l'^|M|(c2),
 // c1, c2 the polar cosines of pi1, pi2, with every constant in coef.  The
 // terms are validated against coupling_G (long double) at sample points.
-void coupling_terms(int L, int nch, const int *l, const int *lam, std::vector<McTerm> &terms,
-                    std::vector<int> &first) {
+static void coupling_terms_compute(int L, int nch, const int *l, const int *lam,
+                                   std::vector<McTerm> &terms, std::vector<int> &first) {
     terms.clear();
     first.assign(nch * nch + 1, 0);
     const ld pi = 3.14159265358979323846264338327950288L;
@@ -209,8 +211,8 @@ void coupling_terms(int L, int nch, const int *l, const int *lam, std::vector<Mc
 // channel a2, pair index a * nch + a2).  Layout: pairs[p] gives d = D/2,
 // the half powers l/2, l'/2, lam/2, lam'/2 and the offset into coef, where
 // coefficients are stored for c = 0..d, a = 0..d-c (b = d - c - a).
-void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<McPair> &pairs,
-                     std::vector<double> &coef) {
+static void coupling_tables_compute(int L, int nch, const int *l, const int *lam,
+                                    std::vector<McPair> &pairs, std::vector<double> &coef) {
     pairs.assign(nch * nch, McPair{});
     coef.clear();
     for (int a1 = 0; a1 < nch; ++a1)
@@ -331,6 +333,51 @@ void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<M
                 coef.push_back((double)v);
             }
         }
+}
+
+// Both are pure functions of (L, channels): computed once per process for
+// each channel set and shared.
+static std::vector<int> channel_key(int L, int nch, const int *l, const int *lam) {
+    std::vector<int> k{L, nch};
+    for (int a = 0; a < nch; ++a) {
+        k.push_back(l[a]);
+        k.push_back(lam[a]);
+    }
+    return k;
+}
+
+void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<McPair> &pairs,
+                     std::vector<double> &coef) {
+    static std::mutex mu;
+    static std::map<std::vector<int>, std::pair<std::vector<McPair>, std::vector<double>>> memo;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = channel_key(L, nch, l, lam);
+    auto it = memo.find(key);
+    if (it == memo.end()) {
+        std::vector<McPair> pr;
+        std::vector<double> cf;
+        coupling_tables_compute(L, nch, l, lam, pr, cf);
+        it = memo.emplace(key, std::make_pair(std::move(pr), std::move(cf))).first;
+    }
+    pairs = it->second.first;
+    coef = it->second.second;
+}
+
+void coupling_terms(int L, int nch, const int *l, const int *lam, std::vector<McTerm> &terms,
+                    std::vector<int> &first) {
+    static std::mutex mu;
+    static std::map<std::vector<int>, std::pair<std::vector<McTerm>, std::vector<int>>> memo;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = channel_key(L, nch, l, lam);
+    auto it = memo.find(key);
+    if (it == memo.end()) {
+        std::vector<McTerm> tm;
+        std::vector<int> fi;
+        coupling_terms_compute(L, nch, l, lam, tm, fi);
+        it = memo.emplace(key, std::make_pair(std::move(tm), std::move(fi))).first;
+    }
+    terms = it->second.first;
+    first = it->second.second;
 }
 
 }  // namespace wpcd
