@@ -310,30 +310,27 @@ __device__ __forceinline__ double gsum8(double v) {
 // status[1] = 1 if converged.
 // One round of k_jacobi_wg for group g (ODD: the odd positions' pairing):
 // rotate the held pair if it is active and not yet orthogonal, then pass
-// the moving column on through the mailbox.
+// the moving column (with its squared norm) on through the mailbox.  The
+// squared norms nA, nB are carried through the rotations and recomputed at
+// the start of every sweep; only the overlap is a fresh dot product.
 template <int EPL, bool ODD>
-__device__ __forceinline__ void jacobi_round(double (&A)[EPL], double (&B)[EPL], int &idA,
-                                             int &idB, double *mail, int *mail_id, int g, int u,
-                                             int P, int Ppad, double tol2, int &any) {
-    double al = 0.0, be = 0.0, ga = 0.0;
+__device__ __forceinline__ void jacobi_round(double (&A)[EPL], double (&B)[EPL], double &nA,
+                                             double &nB, int &idA, int &idB, double *mail,
+                                             double *mail_n, int *mail_id, int g, int u, int P,
+                                             double tol2, int &any) {
+    double ga = 0.0;
 #pragma unroll
-    for (int r = 0; r < EPL; ++r) {
-        al += A[r] * A[r];
-        be += B[r] * B[r];
-        ga += A[r] * B[r];
-    }
-    al = gsum8(al);
-    be = gsum8(be);
+    for (int r = 0; r < EPL; ++r) ga += A[r] * B[r];
     ga = gsum8(ga);
     const bool active = ODD ? g < P - 1 : g < P;
-    if (active && ga * ga > tol2 * (al * be)) {
+    if (active && ga * ga > tol2 * (nA * nB)) {
         // The angle only sets how much of the pair's overlap this rotation
         // removes, so it is formed in FP32 (|ze| < 1e17 here: the norms
-        // differ by < 1e3 and |ga| > tol |A||B|); the rotation built from
-        // it, c = (1 + t^2)^(-1/2) and s = t c, is orthogonal to FP64
-        // rounding, and convergence is judged on the FP64 overlaps.
-        // (hardware reciprocal and square root: the angle needs ~1e-6)
-        const float ze = (float)(be - al) * __builtin_amdgcn_rcpf((float)(2.0 * ga));
+        // differ by < 1e3 and |ga| > tol |A||B|) with hardware reciprocal
+        // and square root; the rotation built from it, c = (1 + t^2)^(-1/2)
+        // and s = t c, is orthogonal to FP64 rounding, and convergence is
+        // judged on FP64 overlaps.
+        const float ze = (float)(nB - nA) * __builtin_amdgcn_rcpf((float)(2.0 * ga));
         const float rt = __builtin_amdgcn_rcpf(fabsf(ze) + __builtin_amdgcn_sqrtf(fmaf(ze, ze, 1.f)));
         const double t = (double)(ze >= 0.f ? rt : -rt);
         const double x = 1.0 + t * t;
@@ -342,39 +339,52 @@ __device__ __forceinline__ void jacobi_round(double (&A)[EPL], double (&B)[EPL],
         const double sn = t * c;
 #pragma unroll
         for (int r = 0; r < EPL; ++r) {
-            const double x = A[r], y = B[r];
-            A[r] = c * x - sn * y;
-            B[r] = sn * x + c * y;
+            const double xa = A[r], yb = B[r];
+            A[r] = c * xa - sn * yb;
+            B[r] = sn * xa + c * yb;
         }
+        const double cc = c * c, ss = sn * sn, cs2 = 2.0 * c * sn * ga;
+        const double a2 = cc * nA + ss * nB - cs2, b2 = ss * nA + cc * nB + cs2;
+        nA = a2;
+        nB = b2;
         any = 1;
     }
-    double *mine = mail + (size_t)g * 8 + u;
-    const size_t stride = (size_t)Ppad * 8;
+    // mailbox slot r of group g at mail[r][g][u]; at most 4 EPL groups
+    constexpr int stride = 32 * EPL;
+    double *mine = mail + g * 8 + u;
 #pragma unroll
     for (int r = 0; r < EPL; ++r) mine[r * stride] = ODD ? A[r] : B[r];
-    if (u == 0) mail_id[g] = ODD ? idA : idB;
+    if (u == 0) {
+        mail_id[g] = ODD ? idA : idB;
+        mail_n[g] = ODD ? nA : nB;
+    }
     __syncthreads();
     if (g < P) {
         const int src = ODD ? (g == 0 ? P - 1 : g - 1) : (g + 1 == P ? 0 : g + 1);
-        const double *from = mail + (size_t)src * 8 + u;
+        const double *from = mail + src * 8 + u;
         if (ODD) {
 #pragma unroll
             for (int r = 0; r < EPL; ++r) A[r] = from[r * stride];
             idA = mail_id[src];
+            nA = mail_n[src];
         } else {
 #pragma unroll
             for (int r = 0; r < EPL; ++r) B[r] = from[r * stride];
             idB = mail_id[src];
+            nB = mail_n[src];
             if (g == P - 1) {
 #pragma unroll
                 for (int r = 0; r < EPL; ++r) {
-                    const double x = A[r];
+                    const double xa = A[r];
                     A[r] = B[r];
-                    B[r] = x;
+                    B[r] = xa;
                 }
                 const int xi = idA;
                 idA = idB;
                 idB = xi;
+                const double xn = nA;
+                nA = nB;
+                nB = xn;
             }
         }
     }
@@ -384,11 +394,13 @@ __device__ __forceinline__ void jacobi_round(double (&A)[EPL], double (&B)[EPL],
 template <int EPL>
 __global__ __launch_bounds__(768) void k_jacobi_wg(double *__restrict__ W, int n, double tol,
                                                     int max_sweeps, int *__restrict__ status) {
-    extern __shared__ double mail[];   // [EPL][Ppad][8] doubles, then ids [Ppad]
+    // [EPL][4 EPL][8] column doubles, then norms [4 EPL], then ids [4 EPL]
+    // (P = ceil(n / 2) <= 4 EPL groups; blockDim = 8 ceil(P / 8) * 8)
+    extern __shared__ double mail[];
     const int tid = threadIdx.x, u = tid & 7, g = tid >> 3;
-    const int Ppad = blockDim.x >> 3;
     const int P = (n + 1) >> 1;
-    int *mail_id = (int *)(mail + (size_t)EPL * Ppad * 8);
+    double *mail_n = mail + EPL * 32 * EPL;
+    int *mail_id = (int *)(mail_n + 4 * EPL);
     double A[EPL], B[EPL];
     int idA = 2 * g, idB = 2 * g + 1;
 #pragma unroll
@@ -400,11 +412,21 @@ __global__ __launch_bounds__(768) void k_jacobi_wg(double *__restrict__ W, int n
     const double tol2 = tol * tol;
     int sweep = 0, converged = 0;
     while (sweep < max_sweeps) {
+        double nA = 0.0, nB = 0.0;
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+            nA += A[r] * A[r];
+            nB += B[r] * B[r];
+        }
+        nA = gsum8(nA);
+        nB = gsum8(nB);
         int any = 0;
         // 2P rounds: even and odd alternate
         for (int rd = 0; rd < P; ++rd) {
-            jacobi_round<EPL, false>(A, B, idA, idB, mail, mail_id, g, u, P, Ppad, tol2, any);
-            jacobi_round<EPL, true>(A, B, idA, idB, mail, mail_id, g, u, P, Ppad, tol2, any);
+            jacobi_round<EPL, false>(A, B, nA, nB, idA, idB, mail, mail_n, mail_id, g, u, P, tol2,
+                                     any);
+            jacobi_round<EPL, true>(A, B, nA, nB, idA, idB, mail, mail_n, mail_id, g, u, P, tol2,
+                                    any);
         }
         ++sweep;
         if (!__syncthreads_or(any)) {
@@ -554,7 +576,8 @@ void pair_diagonalise(wpcd_ctx *c, int wave, bool want_vectors) {
         const int need = (n + 7) / 8;
         const int epl = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 20;
         const int P = (n + 1) / 2, Ppad = (P + 7) / 8 * 8;
-        const size_t lds = (size_t)epl * Ppad * 8 * sizeof(double) + (size_t)Ppad * sizeof(int);
+        const size_t lds = (size_t)epl * 32 * epl * sizeof(double) +
+                           (size_t)4 * epl * (sizeof(double) + sizeof(int));
         auto go = [&](auto kern) {
             WPCD_HIP(hipFuncSetAttribute((const void *)kern,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
