@@ -73,21 +73,87 @@ __device__ __forceinline__ void col_range(const GridView &g, int i, int j, int j
     if (hi < lo) hi = lo;
 }
 
-// One wavefront per row cell; lanes sweep the column spectator bins.
-__global__ __launch_bounds__(256) void k_count(GridView g, int32_t *__restrict__ cnt) {
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int nrow = g.np * g.nq;
-    if (row >= nrow) return;
-    const int i = row % g.np, j = row / g.np;
-    int c = 0;
-    for (int j2 = lane; j2 < g.nq; j2 += 64) {
-        int lo, hi;
-        col_range(g, i, j, j2, lo, hi);
-        c += hi - lo;
+// Grid tables staged in LDS (p, P2: np + 1; q, Q34, H: nq + 1 doubles).
+__device__ __forceinline__ GridView stage_grid(const GridView &g, double *sm) {
+    GridView l;
+    l.np = g.np;
+    l.nq = g.nq;
+    double *p = sm, *P2 = p + g.np + 1, *q = P2 + g.np + 1, *Q34 = q + g.nq + 1,
+           *H = Q34 + g.nq + 1;
+    for (int k = threadIdx.x; k <= g.np; k += blockDim.x) {
+        p[k] = g.p[k];
+        P2[k] = g.P2[k];
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if (lane == 0) cnt[row] = c;
+    for (int k = threadIdx.x; k <= g.nq; k += blockDim.x) {
+        q[k] = g.q[k];
+        Q34[k] = g.Q34[k];
+        H[k] = g.H[k];
+    }
+    __syncthreads();
+    l.p = p;
+    l.P2 = P2;
+    l.q = q;
+    l.Q34 = Q34;
+    l.H = H;
+    return l;
+}
+
+// One wavefront per row cell (rows strided over the grid); lanes sweep the
+// column spectator bins.  cnt[row] = selected cells of the row; ranges[row]
+// [j2] = lo | hi << 16 (the column range of bin j2, n_p < 2^16).
+__global__ __launch_bounds__(256) void k_count(GridView g0, int32_t *__restrict__ cnt,
+                                               uint32_t *__restrict__ ranges) {
+    extern __shared__ double sgrid[];
+    const GridView g = stage_grid(g0, sgrid);
+    const int lane = threadIdx.x & 63;
+    const int nrow = g.np * g.nq;
+    for (int row = blockIdx.x * 4 + (threadIdx.x >> 6); row < nrow; row += gridDim.x * 4) {
+        const int i = row % g.np, j = row / g.np;
+        int c = 0;
+        for (int j2 = lane; j2 < g.nq; j2 += 64) {
+            int lo, hi;
+            col_range(g, i, j, j2, lo, hi);
+            c += hi - lo;
+            ranges[(int64_t)row * g.nq + j2] = (uint32_t)lo | ((uint32_t)hi << 16);
+        }
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+        if (lane == 0) cnt[row] = c;
+    }
+}
+
+// Exclusive prefix sum of cnt[0..n) into row_ptr[0..n] for n <= 32768, one
+// workgroup with the counts in LDS: each thread sums a contiguous segment,
+// the 1024 segment sums are scanned, then row_ptr is written coalesced from
+// segment bases and in-segment offsets.
+__global__ __launch_bounds__(1024) void k_scan_lds(const int32_t *__restrict__ cnt, int n,
+                                                   int64_t *__restrict__ row_ptr) {
+    __shared__ int32_t sc[32768];
+    __shared__ int64_t base[1024];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < n; k += 1024) sc[k] = cnt[k];
+    __syncthreads();
+    const int per = (n + 1023) / 1024;
+    const int beg = min(tid * per, n), end = min(beg + per, n);
+    int32_t run = 0;
+    for (int k = beg; k < end; ++k) {
+        const int32_t v = sc[k];
+        sc[k] = run;   // offset within the segment (< 2^31: per * 2^20 cells)
+        run += v;
+    }
+    base[tid] = run;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = tid >= off ? base[tid - off] : 0;
+        __syncthreads();
+        base[tid] += v;
+        __syncthreads();
+    }
+    // base[t] is now the inclusive sum of segments 0..t
+    for (int k = tid; k < n; k += 1024) {
+        const int sgm = k / per;
+        row_ptr[k] = (sgm ? base[sgm - 1] : 0) + sc[k];
+    }
+    if (tid == 0) row_ptr[n] = base[1023];
 }
 
 // Exclusive prefix sum of cnt[0..n) into row_ptr[0..n], one workgroup.
@@ -116,51 +182,58 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, 
     if (tid == 1023) row_ptr[n] = part[1023];
 }
 
-// One wavefront per row cell: per column bin ranges -> coalesced column
-// writes in ascending order (column index c = j2*np + i2).
-__global__ __launch_bounds__(256) void k_fill(GridView g, const int64_t *__restrict__ row_ptr,
+// One wavefront per row cell (rows strided over the grid, the same number
+// of passes for every wavefront): the column ranges from k_count ->
+// coalesced column writes in ascending order (column index c = j2*np + i2).
+__global__ __launch_bounds__(256) void k_fill(int np, int nq, const uint32_t *__restrict__ ranges,
+                                              const int64_t *__restrict__ row_ptr,
                                               int32_t *__restrict__ col,
                                               int32_t *__restrict__ rowidx) {
     __shared__ int s_off[4][65];
     __shared__ int s_lo[4][64];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int row = blockIdx.x * 4 + w;
-    const int nrow = g.np * g.nq;
-    // every wave runs the loop (uniform trip count) so all reach the barriers
-    const bool valid = row < nrow;
-    const int i = valid ? row % g.np : 0, j = valid ? row / g.np : 0;
-    int64_t base = valid ? row_ptr[row] : 0;
-    for (int j0 = 0; j0 < g.nq; j0 += 64) {
-        const int j2 = j0 + lane;
-        int lo = 0, hi = 0;
-        if (valid && j2 < g.nq) col_range(g, i, j, j2, lo, hi);
-        int c = hi - lo;
-        // inclusive scan across the wavefront
-        int incl = c;
-        for (int off = 1; off < 64; off <<= 1) {
-            int v = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += v;
-        }
-        s_off[w][lane + 1] = incl;
-        if (lane == 0) s_off[w][0] = 0;
-        s_lo[w][lane] = lo;
-        __syncthreads();
-        const int total = s_off[w][64];
-        for (int t = lane; t < total; t += 64) {
-            // owner lane: last k with s_off[k] <= t
-            int a = 0, b = 63;
-            while (a < b) {
-                int m = (a + b + 1) >> 1;
-                if (s_off[w][m] <= t) a = m;
-                else b = m - 1;
+    const int nrow = np * nq;
+    const int stride = gridDim.x * 4;
+    const int passes = (nrow + stride - 1) / stride;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int row = ps * stride + blockIdx.x * 4 + w;
+        const bool valid = row < nrow;
+        int64_t base = valid ? row_ptr[row] : 0;
+        for (int j0 = 0; j0 < nq; j0 += 64) {
+            const int j2 = j0 + lane;
+            int lo = 0, c = 0;
+            if (valid && j2 < nq) {
+                const uint32_t rg = ranges[(int64_t)row * nq + j2];
+                lo = (int)(rg & 0xffffu);
+                c = (int)(rg >> 16) - lo;
             }
-            int i2 = s_lo[w][a] + (t - s_off[w][a]);
-            col[base + t] = (j0 + a) * g.np + i2;
-            rowidx[base + t] = row;
+            // inclusive scan across the wavefront
+            int incl = c;
+            for (int off = 1; off < 64; off <<= 1) {
+                int v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            s_off[w][lane + 1] = incl;
+            if (lane == 0) s_off[w][0] = 0;
+            s_lo[w][lane] = lo;
+            __syncthreads();
+            const int total = s_off[w][64];
+            for (int t = lane; t < total; t += 64) {
+                // owner lane: last k with s_off[k] <= t
+                int a = 0, b = 63;
+                while (a < b) {
+                    int m = (a + b + 1) >> 1;
+                    if (s_off[w][m] <= t) a = m;
+                    else b = m - 1;
+                }
+                int i2 = s_lo[w][a] + (t - s_off[w][a]);
+                col[base + t] = (j0 + a) * np + i2;
+                rowidx[base + t] = row;
+            }
+            base += total;
+            __syncthreads();
         }
-        base += total;
-        __syncthreads();
     }
 }
 
@@ -877,16 +950,23 @@ void build_structure(wpcd_ctx *c) {
     GridView g = grid_view(c);
     c->d_cnt.reserve(nrow);
     c->d_rowptr.reserve((size_t)nrow + 1);
-    const int blocks = (nrow + 3) / 4;
+    c->d_ranges.reserve((size_t)nrow * c->nq);
+    const int blocks = std::min((nrow + 3) / 4, 2048);
+    const size_t lds = (size_t)(2 * (c->np + 1) + 3 * (c->nq + 1)) * sizeof(double);
     {
         TimedLaunch tl(c->timer, c->stream, "preselect_count", WPCD_TIME_P0);
-        hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), 0, c->stream, g, c->d_cnt.ptr);
+        hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), lds, c->stream, g, c->d_cnt.ptr,
+                           c->d_ranges.ptr);
         WPCD_HIP(hipGetLastError());
     }
     {
         TimedLaunch tl(c->timer, c->stream, "preselect_scan", WPCD_TIME_P0);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, c->d_cnt.ptr, nrow,
-                           c->d_rowptr.ptr);
+        if (nrow <= 32768)
+            hipLaunchKernelGGL(k_scan_lds, dim3(1), dim3(1024), 0, c->stream, c->d_cnt.ptr, nrow,
+                               c->d_rowptr.ptr);
+        else
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, c->d_cnt.ptr, nrow,
+                               c->d_rowptr.ptr);
         WPCD_HIP(hipGetLastError());
     }
     int64_t nnz = 0;
@@ -899,8 +979,8 @@ void build_structure(wpcd_ctx *c) {
     c->d_rowidx.reserve(nnz);
     {
         TimedLaunch tl(c->timer, c->stream, "preselect_fill", WPCD_TIME_P0);
-        hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, c->stream, g, c->d_rowptr.ptr,
-                           c->d_col.ptr, c->d_rowidx.ptr);
+        hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, c->stream, c->np, c->nq,
+                           c->d_ranges.ptr, c->d_rowptr.ptr, c->d_col.ptr, c->d_rowidx.ptr);
         WPCD_HIP(hipGetLastError());
     }
 }

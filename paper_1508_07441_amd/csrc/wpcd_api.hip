@@ -1422,6 +1422,7 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->d_col.release();
     c->d_rowidx.release();
     c->d_cnt.release();
+    c->d_ranges.release();
     c->d_val64.release();
     c->d_val32.release();
     c->d_G.release();

@@ -233,6 +233,7 @@ struct wpcd_ctx {
     int64_t nnz = 0;
     wpcd::DBuf<int64_t> d_rowptr;
     wpcd::DBuf<int32_t> d_col, d_rowidx, d_cnt;
+    wpcd::DBuf<uint32_t> d_ranges;   // pre-selection column ranges [row][j2]
     wpcd::DBuf<double> d_val64;
     wpcd::DBuf<float> d_val32;
 
