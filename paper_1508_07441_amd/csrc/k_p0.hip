@@ -140,14 +140,28 @@ __global__ __launch_bounds__(1024) void k_scan_lds(const int32_t *__restrict__ c
         sc[k] = run;   // offset within the segment (< 2^31: per * 2^20 cells)
         run += v;
     }
-    base[tid] = run;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t v = tid >= off ? base[tid - off] : 0;
-        __syncthreads();
-        base[tid] += v;
-        __syncthreads();
+    // inclusive scan of the 1024 segment sums: within each wavefront by
+    // shuffles, then across the 16 wavefront totals
+    __shared__ int64_t wtot[16];
+    const int lane = tid & 63, wv = tid >> 6;
+    int64_t incl = run;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
     }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    if (wv == 0) {
+        int64_t t = lane < 16 ? wtot[lane] : 0;
+        for (int off = 1; off < 16; off <<= 1) {
+            const int64_t v = __shfl_up(t, off, 64);
+            if (lane >= off) t += v;
+        }
+        if (lane < 16) wtot[lane] = t;
+    }
+    __syncthreads();
+    base[tid] = incl + (wv ? wtot[wv - 1] : 0);
+    __syncthreads();
     // base[t] is now the inclusive sum of segments 0..t
     for (int k = tid; k < n; k += 1024) {
         const int sgm = k / per;
@@ -1005,10 +1019,11 @@ static double time_launches_p0(hipStream_t s, F &&f) {
 }
 
 template <bool F32, int EC>
-static void launch_compacted_ec(wpcd_ctx *c, const ElemTables &T, const NodeTab &N) {
+static void launch_compacted_ec(wpcd_ctx *c, const ElemTables &T, const NodeTab &N,
+                                int64_t max_blocks) {
     const int64_t nchunk = (c->nnz + EC - 1) / EC;
     const int64_t want = (nchunk + 3) / 4;
-    const int blocks = (int)(want < 8192 ? want : 8192);
+    const int blocks = (int)(want < max_blocks ? want : max_blocks);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, c->stream, T, N, c->d_rowidx.ptr,
                            c->d_col.ptr, c->nnz, c->d_val64.ptr, c->d_val32.ptr);
@@ -1023,12 +1038,21 @@ static void launch_compacted_ec(wpcd_ctx *c, const ElemTables &T, const NodeTab 
     WPCD_HIP(hipGetLastError());
 }
 
-// Cell pairs per round (4 or 8): more pairs fill the integration passes
-// better, fewer use less LDS per wavefront.  Both give identical values.
+// Launch variants: cell pairs per round (4 or 8: more pairs fill the
+// integration passes better, fewer use less LDS per wavefront) and the grid
+// (at most 8192 workgroups looping over rounds, or one round per workgroup,
+// which lets the dispatcher balance the load).  All give identical values.
+struct ElemVariant {
+    int ec;
+    int64_t max_blocks;
+};
+constexpr ElemVariant kElemVariants[4] = {{4, 8192}, {8, 8192}, {4, 1 << 30}, {8, 1 << 30}};
+
 template <bool F32>
-static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N, int ec) {
-    if (ec == 8) launch_compacted_ec<F32, 8>(c, T, N);
-    else launch_compacted_ec<F32, 4>(c, T, N);
+static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N, int v) {
+    const ElemVariant ev = kElemVariants[v];
+    if (ev.ec == 8) launch_compacted_ec<F32, 8>(c, T, N, ev.max_blocks);
+    else launch_compacted_ec<F32, 4>(c, T, N, ev.max_blocks);
 }
 
 void build_values(wpcd_ctx *c, bool fp64) {
@@ -1106,19 +1130,18 @@ void build_values(wpcd_ctx *c, bool fp64) {
         char key[64];
         std::snprintf(key, sizeof key, "nnz=%lld ngx=%d %s", (long long)nnz, c->ngx,
                       fp64 ? "f64" : "f32");
-        const int ecs[2] = {4, 8};
-        const int ec = ecs[tune_pick(c, "p0_elem", key, 2, 0, [&](int i) {
+        const int v = tune_pick(c, "p0_elem", key, 4, 0, [&](int i) {
             return time_launches_p0(c->stream, [&] {
-                if (fp64) launch_compacted<false>(c, T, N, ecs[i]);
-                else launch_compacted<true>(c, T, N, ecs[i]);
+                if (fp64) launch_compacted<false>(c, T, N, i);
+                else launch_compacted<true>(c, T, N, i);
             });
-        })];
+        });
         if (fp64) {
             TimedLaunch tl(c->timer, c->stream, "p0_elem_f64", WPCD_TIME_P0);
-            launch_compacted<false>(c, T, N, ec);
+            launch_compacted<false>(c, T, N, v);
         } else {
             TimedLaunch tl(c->timer, c->stream, "p0_elem_f32", WPCD_TIME_P0);
-            launch_compacted<true>(c, T, N, ec);
+            launch_compacted<true>(c, T, N, v);
         }
         WPCD_HIP(hipGetLastError());
         return;

@@ -1221,19 +1221,25 @@ void choose_shapes(Batch &b, int m) {
             heur = i;
             break;
         }
-    const int nvec = std::min(m + 1, 8);
+    const int nvec = std::max(1, std::min(m, 8));   // w = basis vector nvec <= m
     const int ch = tune_pick(c, "vector_rows", key, 3, heur, [&](int i) {
         b.set_chunks(kNrCand[i]);
-        // the dot products of one Gram-Schmidt pass with their reduction
+        // one Gram-Schmidt step's vector work as in iteration(): the dots, the
+        // update fused with the second-pass dots, the update fused with the
+        // norm, and their reductions (w is basis vector nvec: scratch here)
+        double *w = b.Vb + (int64_t)nvec * b.vstride;
         return time_launches(c->stream, [&] {
             with_nr(b.nr, [&](auto nr) {
                 hipLaunchKernelGGL(k_vdots<decltype(nr)::value>, dim3(b.nchunk), dim3(256), 0,
-                                   c->stream, b.Vb, b.vstride, nvec, b.Vb, b.M, b.nE, b.nEp,
+                                   c->stream, b.Vb, b.vstride, nvec, w, b.M, b.nE, b.nEp,
                                    b.partial);
             });
             reduce_partials(b, nvec, b.h, nullptr, 0, 0);
+            vupdate<true, false>(b, nvec, w);
+            reduce_partials(b, nvec, b.h, nullptr, 0, 0);
+            vupdate<false, true>(b, nvec, w);
             WPCD_HIP(hipGetLastError());
-        });
+        }, 5);
     });
     b.set_chunks(kNrCand[ch]);
     // P0 SpMM: the variant for the inner iterations' panel type
