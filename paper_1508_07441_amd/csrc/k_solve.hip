@@ -705,39 +705,60 @@ __global__ void k_cycle_start(const double *__restrict__ nrm2, int nE, int m, do
     inv[e] = beta > 1e-300 ? 1.0 / beta : 0.0;
 }
 
-// After orthogonalising w = K v_k: sum the stage-1 reduced |w|^2 partials
-// (npart[split][e]), then per energy H[k+1][k] = ||w||,
-// inv = 1/||w||, apply the previous Givens rotations to column k, form the
-// new one and update the residual estimate.
-__global__ __launch_bounds__(64) void k_givens(const double *__restrict__ npart, int nsplit,
-                                               double *__restrict__ H, int nE, int m, int k,
-                                               double tol, GState S, double *__restrict__ inv) {
-    const int e = threadIdx.x;
+// After orthogonalising w = K v_k, one workgroup: the per-chunk |w|^2
+// partials npart[chunk][e] are summed in a fixed order (256 / nE threads per
+// energy, strided over chunks, then the thread sums in order), column k of
+// every energy's Hessenberg matrix is staged in LDS, and one thread per
+// energy sets H[k+1][k] = ||w|| and inv = 1/||w||, applies the previous
+// Givens rotations to column k, forms the new one and updates the residual
+// estimate.  Dynamic LDS: 256 + nE (m + 1) 2 doubles.
+__global__ __launch_bounds__(256) void k_norm_givens(const double *__restrict__ npart, int nchunk,
+                                                     double *__restrict__ H, int nE, int m, int k,
+                                                     double tol, GState S,
+                                                     double *__restrict__ inv) {
+    extern __shared__ double sm[];
+    double *red = sm, *col = sm + 256;
+    const int t = threadIdx.x;
+    const int G = 256 / nE;
+    const int ee = t % nE, ct = t / nE;
+    double acc = 0.0;
+    if (ct < G)
+        for (int ch = ct; ch < nchunk; ch += G) acc += npart[2 * ((int64_t)ch * nE + ee)];
+    red[t] = acc;
+    for (int idx = t; idx < nE * (k + 1); idx += 256) {
+        const int e = idx / (k + 1), i = idx - e * (k + 1);
+        const double *src = H + (((int64_t)e * (m + 1) + i) * m + k) * 2;
+        col[(e * (m + 1) + i) * 2] = src[0];
+        col[(e * (m + 1) + i) * 2 + 1] = src[1];
+    }
+    __syncthreads();
+    const int e = t;
     if (e >= nE) return;
     double n2 = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) n2 += npart[2 * ((int64_t)sp * nE + e)];
+    for (int g = 0; g < G; ++g) n2 += red[g * nE + e];
     double *st = S.st + e * kSt;
+    double *ce = col + (size_t)e * (m + 1) * 2;
     double *He = H + (int64_t)e * (m + 1) * m * 2;
-    auto Hr = [&](int i) -> double & { return He[(i * m + k) * 2]; };
-    auto Hi = [&](int i) -> double & { return He[(i * m + k) * 2 + 1]; };
     const double hn = sqrt(n2);
-    Hr(k + 1) = hn;
-    Hi(k + 1) = 0.0;
     const double beta = st[0];
     inv[e] = (hn > 1e-14 * beta && hn > 1e-300) ? 1.0 / hn : 0.0;
+    He[((k + 1) * m + k) * 2] = hn;
+    He[((k + 1) * m + k) * 2 + 1] = 0.0;
     if (st[3] != 0.0) return;   // already converged: leave its state alone
+    ce[(k + 1) * 2] = hn;
+    ce[(k + 1) * 2 + 1] = 0.0;
     // apply previous rotations to column k
     for (int i = 0; i < k; ++i) {
         const double c = S.cs[e * m + i];
         const double sr = S.sn[2 * (e * m + i)], si = S.sn[2 * (e * m + i) + 1];
-        const double ar = Hr(i), ai = Hi(i), br = Hr(i + 1), bi = Hi(i + 1);
+        const double ar = ce[2 * i], ai = ce[2 * i + 1], br = ce[2 * i + 2], bi = ce[2 * i + 3];
         // a' = c a + s b ;  b' = -conj(s) a + c b
-        Hr(i) = c * ar + (sr * br - si * bi);
-        Hi(i) = c * ai + (sr * bi + si * br);
-        Hr(i + 1) = -(sr * ar + si * ai) + c * br;
-        Hi(i + 1) = -(sr * ai - si * ar) + c * bi;
+        ce[2 * i] = c * ar + (sr * br - si * bi);
+        ce[2 * i + 1] = c * ai + (sr * bi + si * br);
+        ce[2 * i + 2] = -(sr * ar + si * ai) + c * br;
+        ce[2 * i + 3] = -(sr * ai - si * ar) + c * bi;
     }
-    const double ar = Hr(k), ai = Hi(k), br = Hr(k + 1), bi = Hi(k + 1);
+    const double ar = ce[2 * k], ai = ce[2 * k + 1], br = ce[2 * k + 2], bi = ce[2 * k + 3];
     const double na = sqrt(ar * ar + ai * ai), nb = sqrt(br * br + bi * bi);
     double c, sr, si;
     if (na == 0.0) {
@@ -755,10 +776,14 @@ __global__ __launch_bounds__(64) void k_givens(const double *__restrict__ npart,
     S.cs[e * m + k] = c;
     S.sn[2 * (e * m + k)] = sr;
     S.sn[2 * (e * m + k) + 1] = si;
-    Hr(k) = c * ar + (sr * br - si * bi);
-    Hi(k) = c * ai + (sr * bi + si * br);
-    Hr(k + 1) = 0.0;
-    Hi(k + 1) = 0.0;
+    ce[2 * k] = c * ar + (sr * br - si * bi);
+    ce[2 * k + 1] = c * ai + (sr * bi + si * br);
+    ce[2 * k + 2] = 0.0;
+    ce[2 * k + 3] = 0.0;
+    for (int i = 0; i <= k + 1; ++i) {
+        He[(i * m + k) * 2] = ce[2 * i];
+        He[(i * m + k) * 2 + 1] = ce[2 * i + 1];
+    }
     double *g = S.g + 2 * e * (m + 1);
     const double gr = g[2 * k], gi = g[2 * k + 1];
     g[2 * k] = c * gr;
@@ -1113,9 +1138,9 @@ void iteration(Batch &b, int k, double tol) {
     reduce_partials(b, k + 1, b.h, b.H, k, 1);
     vupdate<false, true>(b, k + 1, w);
     TimedLaunch tl(c->timer, s, "gmres_givens", WPCD_TIME_SOLVE);
-    reduce_stage1(b, b.nE);
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, b.out2, b.nsplit, b.H, b.nE, b.m, k,
-                       tol, b.S, b.inv);
+    hipLaunchKernelGGL(k_norm_givens, dim3(1), dim3(256),
+                       (256 + (size_t)b.nE * (b.m + 1) * 2) * sizeof(double), s, b.partial,
+                       b.nchunk, b.H, b.nE, b.m, k, tol, b.S, b.inv);
     hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * b.nE, 256)), dim3(256), 0, s, b.inv, b.M, b.nE, w);
     WPCD_HIP(hipGetLastError());
 }
@@ -1267,6 +1292,9 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     std::vector<int> &iters = out.iters, &edge_flag = out.edge;
     std::vector<double> &resid = out.resid;
     const int nE = (int)E.size();
+    // the Givens kernel's LDS column stage can exceed the 64 KB default
+    WPCD_HIP(hipFuncSetAttribute((const void *)k_norm_givens,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
     Batch b{};
     b.c = c;
     b.nE = nE;
