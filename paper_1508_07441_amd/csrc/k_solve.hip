@@ -95,6 +95,23 @@ __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq,
     for (int u = 0; u < UM; ++u)
 #pragma unroll
         for (int v = 0; v < UN; ++v) acc[u][v] = 0.0;
+    // the panel columns this thread stages are the same for every k step:
+    // their (j, c) split (a division by W) is done once
+    constexpr int NBL = (KS * TN + 255) / 256;
+    int64_t bbase[NBL];   // (chbase + j n) W, or -1 past the panel
+    int bc[NBL];
+#pragma unroll
+    for (int sl = 0; sl < NBL; ++sl) {
+        const int idx = t + 256 * sl;
+        const int64_t q = q0 + idx % TN;
+        bbase[sl] = -1;
+        bc[sl] = 0;
+        if (idx < KS * TN && q < ncol) {
+            const int j = (int)(q / W);
+            bc[sl] = (int)(q - (int64_t)j * W);
+            bbase[sl] = (chbase + (int64_t)j * n) * W;
+        }
+    }
     for (int k0 = 0; k0 < n; k0 += KS) {
         // A tile, transposed: sA[kk][rr] = Mat[row0 + rr][k0 + kk]
         for (int idx = t; idx < TM * KS; idx += 256) {
@@ -103,15 +120,16 @@ __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq,
             sA[kk][rr] = (r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0;
         }
         // B tile: sB[kk][qq] = Y[k0 + kk][q0 + qq]
-        for (int idx = t; idx < KS * TN; idx += 256) {
+#pragma unroll
+        for (int sl = 0; sl < NBL; ++sl) {
+            const int idx = t + 256 * sl;
+            if (idx >= KS * TN) break;
             const int kk = idx / TN, qq = idx % TN;
             const int k = k0 + kk;
-            const int64_t q = q0 + qq;
             double v = 0.0;
-            if (k < n && q < ncol) {
-                const int64_t j = q / W;
-                const int c = (int)(q - j * W);
-                const int64_t o = (chbase + j * n + k) * W;
+            if (k < n && bbase[sl] >= 0) {
+                const int64_t o = bbase[sl] + (int64_t)k * W;
+                const int c = bc[sl];
                 if (USE_G) {
                     const int c0 = c & ~1;
                     const double gr = G[o + c0], gi = G[o + c0 + 1];
@@ -138,17 +156,24 @@ __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq,
         }
         __syncthreads();
     }
+    int64_t obase[UN];   // (chbase + j n) W + c of output column v, or -1
+#pragma unroll
+    for (int v = 0; v < UN; ++v) {
+        const int64_t q = q0 + tx + 16 * v;
+        obase[v] = -1;
+        if (q < ncol) {
+            const int j = (int)(q / W);
+            obase[v] = (chbase + (int64_t)j * n) * W + (q - (int64_t)j * W);
+        }
+    }
 #pragma unroll
     for (int u = 0; u < UM; ++u) {
         const int r = row0 + ty + 16 * u;
         if (r >= n) continue;
 #pragma unroll
         for (int v = 0; v < UN; ++v) {
-            const int64_t q = q0 + tx + 16 * v;
-            if (q >= ncol) continue;
-            const int64_t j = q / W;
-            const int c = (int)(q - j * W);
-            const int64_t gi = (chbase + j * n + r) * W + c;
+            if (obase[v] < 0) continue;
+            const int64_t gi = obase[v] + (int64_t)r * W;
             out[gi] = (TO)(SUB ? add[gi] - acc[u][v] : acc[u][v]);
         }
     }
@@ -210,21 +235,36 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[u][v][r] = (MT)0;
     const int li = lane & 15, lk = lane >> 4;
+    // (j, c) of the panel columns this thread stages, once (as in k_block_apply)
+    constexpr int NBL = KS * TN / 256;
+    int64_t bbase[NBL];
+    int bc[NBL];
+#pragma unroll
+    for (int sl = 0; sl < NBL; ++sl) {
+        const int64_t q = q0 + (t + 256 * sl) % TN;
+        bbase[sl] = -1;
+        bc[sl] = 0;
+        if (q < ncol) {
+            const int j = (int)(q / W);
+            bc[sl] = (int)(q - (int64_t)j * W);
+            bbase[sl] = (chbase + (int64_t)j * n) * W;
+        }
+    }
     for (int k0 = 0; k0 < n; k0 += KS) {
         for (int idx = t; idx < TM * KS; idx += 256) {
             const int rr = idx / KS, kk = idx % KS;
             const int r = row0 + rr, k = k0 + kk;
             sA[kk][rr] = (MT)((r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0);
         }
-        for (int idx = t; idx < KS * TN; idx += 256) {
+#pragma unroll
+        for (int sl = 0; sl < NBL; ++sl) {
+            const int idx = t + 256 * sl;
             const int kk = idx / TN, qq = idx % TN;
             const int k = k0 + kk;
-            const int64_t q = q0 + qq;
             double v = 0.0;
-            if (k < n && q < ncol) {
-                const int64_t j = q / W;
-                const int c = (int)(q - j * W);
-                const int64_t o = (chbase + j * n + k) * W;
+            if (k < n && bbase[sl] >= 0) {
+                const int c = bc[sl];
+                const int64_t o = bbase[sl] + (int64_t)k * W;
                 if (USE_G) {
                     const int c0 = c & ~1;
                     const double gr = G[o + c0], gi = G[o + c0 + 1];
@@ -257,13 +297,13 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
         for (int v = 0; v < 2; ++v) {
             const int64_t q = q0 + wc * 32 + v * 16 + li;
             if (q >= ncol) continue;
-            const int64_t j = q / W;
-            const int c = (int)(q - j * W);
+            const int j = (int)(q / W);
+            const int64_t ob = (chbase + (int64_t)j * n) * W + (q - (int64_t)j * W);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = row0 + wr * 32 + u * 16 + MfmaAcc<MT>::row(lk, r);
                 if (row >= n) continue;
-                const int64_t gi = (chbase + j * n + row) * W + c;
+                const int64_t gi = ob + (int64_t)row * W;
                 const double d = (double)acc[u][v][r];
                 out[gi] = (TO)(SUB ? add[gi] - d : d);
             }
