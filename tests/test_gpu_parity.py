@@ -118,6 +118,26 @@ def test_c2_structure_full_size(ctx, P):
         assert np.all(np.abs(v - vo) <= 1e-10 * np.abs(vo) + 1e-14 * sc)
 
 
+@pytest.mark.parametrize("shape", [(128, 256), (200, 170)])
+def test_structure_scan_paths(ctx, P, shape):
+    """Row pointers on both scan paths (one LDS-resident workgroup up to
+    32768 rows, the strided one above): every row pointer nondecreasing from
+    0, and sampled rows' column lists equal the oracle's brute-force ones."""
+    n_p, n_q = shape
+    say(f"[scan] {n_p}x{n_q} rows={n_p * n_q}")
+    ctx.build_basis(n_p, n_q, 10.0, 10.0, 8, 16, potential=YAM)
+    nnz = ctx.build_p(P.WPCD_MIXED)
+    rp, col, _ = ctx.get_p(values=False)
+    assert rp[0] == 0 and rp[-1] == nnz and np.all(np.diff(rp) >= 0)
+    p, q = O.cheb_edges(n_p, 10.0), O.cheb_edges(n_q, 10.0)
+    rng = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([[0, 1, n_p * n_q - 1],
+                                     rng.choice(n_p * n_q, 40, replace=False)]))
+    ptr_o, col_o = O.preselect(p, q, rows)
+    for k, r in enumerate(rows):
+        assert np.array_equal(col[rp[r]:rp[r + 1]], col_o[ptr_o[k]:ptr_o[k + 1]]), r
+
+
 def test_determinism(ctx, P):
     ctx.build_basis(40, 40, 10.0, 10.0, 8, 16, potential=YAM)
     for prec in (P.WPCD_FP64, P.WPCD_MIXED):
