@@ -339,6 +339,36 @@ __device__ __forceinline__ void lane_limits(const ElemTables &T, int i, int i2, 
     bin_limits(T, i, i2, q_limits(q, q2), lo_t, lo_u, h);
 }
 
+// bin_limits split by what each part depends on: the row bin i (with the
+// Gauss pair) and the column bin i2.  max and min are exact, so the
+// regrouped limits equal bin_limits' bit for bit.
+struct RowLim {
+    double A1, B1, A2, B2, D;   // t: [A1, B1] before the column bin; u: [A2, B2]
+};
+
+__device__ __forceinline__ RowLim row_limits(const ElemTables &T, int i, const QLim &L) {
+#pragma clang fp contract(off)
+    const double pl1 = T.P2[i], ph1 = T.P2[i + 1];
+    RowLim R;
+    R.A1 = fmax(L.t_lo, pl1);
+    R.B1 = fmin(L.t_hi, ph1);
+    R.A2 = fmax(L.u_lo, pl1 + L.D);
+    R.B2 = fmin(L.u_hi, ph1 + L.D);
+    R.D = L.D;
+    return R;
+}
+
+__device__ __forceinline__ void cell_limits(const ElemTables &T, int i2, const RowLim &R,
+                                            double &lo_t, double &lo_u, double &h) {
+#pragma clang fp contract(off)
+    const double pl2 = T.P2[i2], ph2 = T.P2[i2 + 1];
+    lo_t = fmax(R.A1, pl2 - R.D);
+    const double hi_t = fmin(R.B1, ph2 - R.D);
+    lo_u = fmax(R.A2, pl2);
+    const double hi_u = fmin(R.B2, ph2);
+    h = (hi_t > lo_t) ? 0.25 * ((hi_t - lo_t) + (hi_u - lo_u)) : 0.0;
+}
+
 __global__ __launch_bounds__(256) void k_p0_swave_f64(ElemTables T,
                                                       const int32_t *__restrict__ rowidx,
                                                       const int32_t *__restrict__ col, int64_t nnz,
@@ -544,9 +574,11 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
         int total = 0;
         double scale[kEC];   // (d_i d_i2 dq_j dq_j2)^(-1/2) of each cell pair
         // consecutive cell pairs of a row mostly share the spectator bins
-        // (j, j2): their Gauss-pair parts of the limits are kept
-        int pj = -1, pj2 = -1;
+        // (j, j2): their Gauss-pair parts of the limits are kept, and the
+        // row-bin parts while the row is the same too
+        int pj = -1, pj2 = -1, pi = -1;
         QLim QL{};
+        RowLim RL{};
         double wq = 0.0;
 #pragma unroll
         for (int k = 0; k < kEC; ++k) {
@@ -564,8 +596,13 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                     wq = T.qwt[j * 8 + a] * T.qwt[j2 * 8 + b];
                     pj = j;
                     pj2 = j2;
+                    pi = -1;
                 }
-                bin_limits(T, i, i2, QL, lo_t, lo_u, h);
+                if (i != pi) {
+                    RL = row_limits(T, i, QL);
+                    pi = i;
+                }
+                cell_limits(T, i2, RL, lo_t, lo_u, h);
                 act = h > 0.0;
                 wab = wq * h;
                 scale[k] = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
