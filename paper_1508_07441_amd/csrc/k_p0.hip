@@ -1083,7 +1083,9 @@ struct ElemVariant {
     int ec;
     int64_t max_blocks;
 };
-constexpr ElemVariant kElemVariants[4] = {{4, 8192}, {8, 8192}, {4, 1 << 30}, {8, 1 << 30}};
+// (one round per workgroup up to 2^23 workgroups: the grid's thread count
+// must stay below 2^32)
+constexpr ElemVariant kElemVariants[4] = {{4, 8192}, {8, 8192}, {4, 1 << 23}, {8, 1 << 23}};
 
 template <bool F32>
 static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N, int v) {

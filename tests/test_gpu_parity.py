@@ -416,6 +416,38 @@ def test_c3_structure_and_sampled_values(ctx, P):
     assert np.all(np.abs(val[idx] - vo) <= 1e-10 * np.abs(vo) + 1e-13 * scale)
 
 
+def test_max_grid_1024(ctx, P):
+    """The largest grid the library takes, 1024 x 1024 bins (cell indices up
+    to 2^20 - 1, ~7e8 cell pairs, int64 offsets): sampled rows' columns and
+    sampled FP32 elements against the oracle, and |S| = 1 below breakup (a
+    property of the discrete equations at any size)."""
+    n = 1024
+    say("[max] build_basis 1024 x 1024")
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    say("[max] build_p MIXED")
+    nnz = ctx.build_p(P.WPCD_MIXED)
+    say(f"[max] nnz={nnz}")
+    rp, col, val = ctx.get_p()
+    assert rp[0] == 0 and rp[-1] == nnz and np.all(np.diff(rp) >= 0)
+    p = O.cheb_edges(n, 10.0)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([[0, n * n - 1], rng.choice(n * n, 24, replace=False)]))
+    ptr_o, col_o = O.preselect(p, p, rows)
+    for k, r in enumerate(rows):
+        assert np.array_equal(col[rp[r]:rp[r + 1]], col_o[ptr_o[k]:ptr_o[k + 1]]), r
+    idx = np.sort(rng.choice(nnz, 300, replace=False))
+    idx[-1] = nnz - 1
+    r_idx = np.searchsorted(rp, idx, side="right") - 1
+    vo = O.p0_pairs(p, p.copy(), 8, 16, 0, [(0, 0)], r_idx.astype(np.int64), col[idx])[:, 0, 0]
+    scale = np.abs(val).max()
+    assert np.all(np.abs(val[idx, 0, 0] - vo) <= FP32_REL * np.abs(vo) + 1e-7 * scale * 1e-3)
+    del col, val
+    say("[max] solve MIXED at E = -0.05")
+    r = ctx.solve([-0.05], P.WPCD_MIXED)[0]
+    assert r.status == P.WPCD_OK
+    assert abs(abs(complex(r.S_re, r.S_im)) - 1.0) <= 1e-7
+
+
 # ------------------------------------------------------------- autotuning
 def test_autotune_candidates_agree(ctx, P):
     """Every candidate launch shape (forced) and the measured choice give the
