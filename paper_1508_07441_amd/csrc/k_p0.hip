@@ -551,6 +551,16 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
+// Per-wavefront LDS of the compacted kernel: the queued intervals (t0, u0,
+// half-length, Gauss weight, destination sum slot) and the per-slot sums.
+template <class R, int EC>
+struct ElemQueue {
+    R lt[EC * 64], lu[EC * 64], h[EC * 64], w[EC * 64];
+    R s_hi[EC * 64];
+    float s_lo[EC * 64];
+    uint16_t dst[EC * 64];   // k * 64 + rank: cell pair k of the round, lane rank
+};
+
 template <bool F32, int NGX, int EC>
 __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                                                     const int32_t *__restrict__ rowidx,
@@ -559,13 +569,12 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                                                     float *__restrict__ val32) {
     using R = typename std::conditional<F32, float, double>::type;
     constexpr int kEC = EC;   // cell pairs per wavefront per round
-    constexpr int QN = kEC * 64;
-    __shared__ R q_lt[4][QN], q_lu[4][QN], q_h[4][QN], q_w[4][QN];
-    __shared__ unsigned char q_k[4][QN], q_r[4][QN];
-    __shared__ R s_hi[4][kEC][64];
-    __shared__ float s_lo[4][kEC][64];
+    // one block per wavefront: members at fixed offsets from one base, so a
+    // queue slot is one address plus immediate offsets
+    __shared__ ElemQueue<R, kEC> Qs[4];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    ElemQueue<R, kEC> &Q = Qs[w];
     const int a = lane >> 3, b = lane & 7;
     const int64_t nch = (nnz + kEC - 1) / kEC;
     for (int64_t it = 0;; ++it) {
@@ -594,8 +603,11 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                 cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
                 cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
                 if (j != pj || j2 != pj2) {
-                    QL = q_limits(T.qnode[j * 8 + a], T.qnode[j2 * 8 + b]);
-                    wq = T.qwt[j * 8 + a] * T.qwt[j2 * 8 + b];
+                    // uniform bases (scalar registers) plus the lane's node offset
+                    const double *qn = T.qnode + j * 8, *qn2 = T.qnode + j2 * 8;
+                    const double *qw = T.qwt + j * 8, *qw2 = T.qwt + j2 * 8;
+                    QL = q_limits(qn[a], qn2[b]);
+                    wq = qw[a] * qw2[b];
                     pj = j;
                     pj2 = j2;
                     pi = -1;
@@ -609,41 +621,39 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                 wab = wq * h;
                 scale[k] = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
             }
-            const unsigned long long m = __ballot(act);
-            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(act);
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
             if (act) {
                 const int slot = total + rank;
-                q_lt[w][slot] = (R)lo_t;
-                q_lu[w][slot] = (R)lo_u;
-                q_h[w][slot] = (R)h;
-                q_w[w][slot] = (R)wab;
-                q_k[w][slot] = (unsigned char)k;
-                q_r[w][slot] = (unsigned char)rank;
+                Q.lt[slot] = (R)lo_t;
+                Q.lu[slot] = (R)lo_u;
+                Q.h[slot] = (R)h;
+                Q.w[slot] = (R)wab;
+                Q.dst[slot] = (uint16_t)(k * 64 + rank);   // sum slot of this interval
             }
             total += __popcll(m);
-            s_hi[w][k][lane] = (R)0;
-            s_lo[w][k][lane] = 0.f;
+            Q.s_hi[k * 64 + lane] = (R)0;
+            Q.s_lo[k * 64 + lane] = 0.f;
         }
         __syncthreads();
         // phase 2: one queued interval per lane
         for (int base = 0; base < total; base += 64) {
             const int t = base + lane;
             if (t < total) {
-                const int k = q_k[w][t], rk = q_r[w][t];
+                const int d = Q.dst[t];
                 if (F32) {
                     float s0, s1, hi, lo;
-                    inner_f32<NGX>(N, T.ngx, (float)q_lt[w][t], (float)q_lu[w][t], (float)q_h[w][t],
-                                   s0, s1);
+                    inner_f32<NGX>(N, T.ngx, (float)Q.lt[t], (float)Q.lu[t], (float)Q.h[t], s0, s1);
                     two_sum(s0, s1, hi, lo);
-                    const float wf = (float)q_w[w][t];
+                    const float wf = (float)Q.w[t];
                     const float p = hi * wf;
                     const float ep = fmaf(hi, wf, -p);
-                    s_hi[w][k][rk] = (R)p;
-                    s_lo[w][k][rk] = fmaf(lo, wf, ep);
+                    Q.s_hi[d] = (R)p;
+                    Q.s_lo[d] = fmaf(lo, wf, ep);
                 } else {
-                    s_hi[w][k][rk] = (R)(q_w[w][t] *
-                                         inner_f64<NGX>(N, T.ngx, (double)q_lt[w][t],
-                                                        (double)q_lu[w][t], (double)q_h[w][t]));
+                    Q.s_hi[d] = (R)(Q.w[t] * inner_f64<NGX>(N, T.ngx, (double)Q.lt[t],
+                                                              (double)Q.lu[t], (double)Q.h[t]));
                 }
             }
         }
@@ -658,7 +668,8 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
         for (int hf = 0; hf < kEC / 4; ++hf) {
             const int k = hf * 4 + (lane >> 4), m = lane & 15;
             auto slot = [&](int t) {
-                return F32 ? (double)s_hi[w][k][t] + (double)s_lo[w][k][t] : (double)s_hi[w][k][t];
+                return F32 ? (double)Q.s_hi[k * 64 + t] + (double)Q.s_lo[k * 64 + t]
+                           : (double)Q.s_hi[k * 64 + t];
             };
             double sv = slot(m);
             sv += slot(m + 16);
