@@ -343,7 +343,7 @@ __device__ __forceinline__ void lane_limits(const ElemTables &T, int i, int i2, 
 // Gauss pair) and the column bin i2.  max and min are exact, so the
 // regrouped limits equal bin_limits' bit for bit.
 struct RowLim {
-    double A1, B1, A2, B2, D;   // t: [A1, B1] before the column bin; u: [A2, B2]
+    double A1, B1, A2, B2;   // t: [A1, B1] before the column bin; u: [A2, B2]
 };
 
 __device__ __forceinline__ RowLim row_limits(const ElemTables &T, int i, const QLim &L) {
@@ -354,19 +354,24 @@ __device__ __forceinline__ RowLim row_limits(const ElemTables &T, int i, const Q
     R.B1 = fmin(L.t_hi, ph1);
     R.A2 = fmax(L.u_lo, pl1 + L.D);
     R.B2 = fmin(L.u_hi, ph1 + L.D);
-    R.D = L.D;
     return R;
 }
 
-__device__ __forceinline__ void cell_limits(const ElemTables &T, int i2, const RowLim &R,
-                                            double &lo_t, double &lo_u, double &h) {
+// Returns whether the lane's interval is open (h > 0 as in bin_limits); h
+// is meaningful only then.
+__device__ __forceinline__ bool cell_limits(const ElemTables &T, int i2, const QLim &L,
+                                            const RowLim &R, double &lo_t, double &lo_u,
+                                            double &h) {
 #pragma clang fp contract(off)
     const double pl2 = T.P2[i2], ph2 = T.P2[i2 + 1];
-    lo_t = fmax(R.A1, pl2 - R.D);
-    const double hi_t = fmin(R.B1, ph2 - R.D);
+    lo_t = fmax(R.A1, pl2 - L.D);
+    const double hi_t = fmin(R.B1, ph2 - L.D);
     lo_u = fmax(R.A2, pl2);
     const double hi_u = fmin(R.B2, ph2);
-    h = (hi_t > lo_t) ? 0.25 * ((hi_t - lo_t) + (hi_u - lo_u)) : 0.0;
+    const double dt = hi_t - lo_t;
+    h = 0.25 * (dt + (hi_u - lo_u));
+    // hi_t > lo_t and h > 0 as one comparison (dt > 0 exactly when hi_t > lo_t)
+    return fmin(dt, h) > 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_p0_swave_f64(ElemTables T,
@@ -583,22 +588,23 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
         const int64_t chunk = cbase + w;
         // phase 1: limits of kEC cell pairs, compaction into the queue
         int total = 0;
-        double scale[kEC];   // (d_i d_i2 dq_j dq_j2)^(-1/2) of each cell pair
+        // cell pairs in this wavefront's round (wave-uniform; 0 past the end)
+        const int nrem = chunk < nch ? (int)std::min<int64_t>(nnz - chunk * kEC, kEC) : 0;
         // consecutive cell pairs of a row mostly share the spectator bins
         // (j, j2): their Gauss-pair parts of the limits are kept, and the
-        // row-bin parts while the row is the same too
+        // row-bin parts while the row is the same too.  The normalisation
+        // (d_i d_i2 dq_j dq_j2)^(-1/2) is folded into the Gauss weight the
+        // same way (wq: Gauss pair and spectator bins, wr: times the row bin).
         int pj = -1, pj2 = -1, pi = -1;
         QLim QL{};
         RowLim RL{};
-        double wq = 0.0;
+        double wq = 0.0, wr = 0.0;
 #pragma unroll
         for (int k = 0; k < kEC; ++k) {
-            const int64_t e = chunk * kEC + k;
-            bool act = false;
-            double lo_t = 0.0, lo_u = 0.0, h = 0.0, wab = 0.0;
-            scale[k] = 0.0;
-            if (chunk < nch && e < nnz) {
+            unsigned long long m = 0;
+            if (k < nrem) {
                 // the cell pair is the same for the whole wavefront
+                const int64_t e = chunk * kEC + k;
                 int i, j, i2, j2;
                 cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
                 cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
@@ -607,30 +613,29 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                     const double *qn = T.qnode + j * 8, *qn2 = T.qnode + j2 * 8;
                     const double *qw = T.qwt + j * 8, *qw2 = T.qwt + j2 * 8;
                     QL = q_limits(qn[a], qn2[b]);
-                    wq = qw[a] * qw2[b];
+                    wq = (qw[a] * qw2[b]) * (T.rsd_q[j] * T.rsd_q[j2]);
                     pj = j;
                     pj2 = j2;
                     pi = -1;
                 }
                 if (i != pi) {
                     RL = row_limits(T, i, QL);
+                    wr = wq * T.rsd_p[i];
                     pi = i;
                 }
-                cell_limits(T, i2, RL, lo_t, lo_u, h);
-                act = h > 0.0;
-                wab = wq * h;
-                scale[k] = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
-            }
-            const unsigned long long m = __builtin_amdgcn_ballot_w64(act);
-            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-                (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            if (act) {
-                const int slot = total + rank;
-                Q.lt[slot] = (R)lo_t;
-                Q.lu[slot] = (R)lo_u;
-                Q.h[slot] = (R)h;
-                Q.w[slot] = (R)wab;
-                Q.dst[slot] = (uint16_t)(k * 64 + rank);   // sum slot of this interval
+                double lo_t, lo_u, h;
+                const bool act = cell_limits(T, i2, QL, RL, lo_t, lo_u, h);
+                m = __builtin_amdgcn_ballot_w64(act);
+                if (act) {
+                    const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                        (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    const int slot = total + rank;
+                    Q.lt[slot] = (R)lo_t;
+                    Q.lu[slot] = (R)lo_u;
+                    Q.h[slot] = (R)h;
+                    Q.w[slot] = (R)(h * (wr * T.rsd_p[i2]));
+                    Q.dst[slot] = (uint16_t)(k * 64 + rank);   // sum slot of this interval
+                }
             }
             total += __popcll(m);
             Q.s_hi[k * 64 + lane] = (R)0;
@@ -676,14 +681,10 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
             sv += slot(m + 32);
             sv += slot(m + 48);
             sv = group_sum<16>(sv);
-            double sc = scale[hf * 4];
-#pragma unroll
-            for (int kk = 1; kk < 4; ++kk)
-                if ((lane >> 4) == kk) sc = scale[hf * 4 + kk];
-            const int64_t e = chunk * kEC + k;
-            if (m == 0 && chunk < nch && e < nnz) {
-                if (F32) val32[e] = (float)(sv * sc);
-                else val64[e] = sv * sc;
+            if (m == 0 && k < nrem) {
+                const int64_t e = chunk * kEC + k;
+                if (F32) val32[e] = (float)sv;
+                else val64[e] = sv;
             }
         }
         __syncthreads();
