@@ -136,6 +136,7 @@ def c3_measure(P):
 
     s_mixed, r_mixed = solve(P.WPCD_MIXED)
     s_refine, r_refine = solve(P.WPCD_MIXED_REFINE)
+    s_bf16, r_bf16 = solve(P.WPCD_MIXED_BF16)
     ctx.build_p(P.WPCD_FP64)
     s_fp64, r_fp64 = solve(P.WPCD_FP64)
     ok = [k for k, r in enumerate(r_fp64) if r.status == P.WPCD_OK]
@@ -148,11 +149,14 @@ def c3_measure(P):
                         "-0.1; 8 energies", "basis": 3 * 300 * 300, "nnz_cells": nnz,
             "p_build_mixed_ms": 1e3 * t_build, "p_elements_per_s": nnz / t_build,
             "channel_values_per_s": 9 * nnz / t_build,
-            "solve_s_per_energy": {"mixed": s_mixed, "mixed_refine": s_refine, "fp64": s_fp64},
+            "solve_s_per_energy": {"mixed": s_mixed, "mixed_refine": s_refine,
+                                   "mixed_bf16": s_bf16, "fp64": s_fp64},
             "iters_per_energy": {"mixed": sum(r.iters for r in r_mixed) / len(r_mixed),
                                  "mixed_refine": sum(r.iters for r in r_refine) / len(r_refine),
+                                 "mixed_bf16": sum(r.iters for r in r_bf16) / len(r_bf16),
                                  "fp64": sum(r.iters for r in r_fp64) / len(r_fp64)},
-            "max_rel_amp_err_vs_fp64": {"mixed": err(r_mixed), "mixed_refine": err(r_refine)}}
+            "max_rel_amp_err_vs_fp64": {"mixed": err(r_mixed), "mixed_refine": err(r_refine),
+                                        "mixed_bf16": err(r_bf16)}}
 
 
 def c5_measure(P, n_var, n_e, sweep):
@@ -326,6 +330,8 @@ def main():
     s_mixed, r_mixed = solve_time(P.WPCD_MIXED)
     solve_time(P.WPCD_MIXED_REFINE, reps=1)     # tune + capture
     s_refine, r_refine = solve_time(P.WPCD_MIXED_REFINE)
+    solve_time(P.WPCD_MIXED_BF16, reps=1)
+    s_bf16, r_bf16 = solve_time(P.WPCD_MIXED_BF16)
     # learned warm start (mixed): trained on plain mixed solves of potential
     # variants, then the 8 energies at the base potential (a held-out point)
     if not args.no_learn:
@@ -379,13 +385,15 @@ def main():
                                "8x8 q Gauss, 20-pt cosine rule, 8 energies", "nnz_cells": nnz,
                    "basis": N * N, "energies": list(ENERGIES)},
         "solve_s_per_energy": {"mixed": s_mixed, "mixed_learned": s_learned,
-                               "mixed_refine": s_refine, "fp64": s_fp64,
+                               "mixed_refine": s_refine, "mixed_bf16": s_bf16, "fp64": s_fp64,
                                "mixed_max_rel_amp_err_vs_fp64": amp_err(r_mixed),
                                "mixed_refine_max_rel_amp_err_vs_fp64": amp_err(r_refine),
+                               "mixed_bf16_max_rel_amp_err_vs_fp64": amp_err(r_bf16),
                                "mixed_learned_max_rel_amp_err_vs_fp64": amp_err(r_learned),
                                "iters_per_energy": {"mixed": mean_iters(r_mixed),
                                                     "mixed_learned": mean_iters(r_learned),
                                                     "mixed_refine": mean_iters(r_refine),
+                                                    "mixed_bf16": mean_iters(r_bf16),
                                                     "fp64": mean_iters(r_fp64)},
                                "learned_initial_residual_median":
                                    sorted(x.r0 for x in r_learned)[len(r_learned) // 2],

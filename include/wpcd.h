@@ -46,11 +46,16 @@ typedef enum {
 typedef enum {
     WPCD_FP64 = 0,          /* FP64 everywhere */
     WPCD_MIXED = 1,         /* P0 accumulated in FP32 with compensated sums */
-    WPCD_MIXED_REFINE = 2   /* wpcd_solve only, on a WPCD_MIXED P0: the two
+    WPCD_MIXED_REFINE = 2,  /* wpcd_solve only, on a WPCD_MIXED P0: the two
                                intermediate panels of the kernel product are
                                FP32 inside the Krylov iterations; each restart
                                forms the true residual with FP64 panels
                                (iterative refinement) */
+    WPCD_MIXED_BF16 = 3     /* wpcd_solve only, on a WPCD_MIXED P0: as
+                               WPCD_MIXED_REFINE, with the two block products
+                               of the inner iterations (V~ and O, Sec. III.B
+                               eq.(perm_z)) on the BF16 matrix cores with FP32
+                               accumulation */
 } wpcd_precision;
 
 /* Lattice basis (Sec. II.D, eq.(xij); channels eq.(si)).
@@ -225,7 +230,7 @@ wpcd_status wpcd_get_p(wpcd_ctx *ctx, int64_t *row_ptr, int32_t *col, double *va
  * (channel, k, j_k, Re S_k0, Im S_k0) as doubles, row count in n_open.
  * Per-energy failures are reported in out[e].status and do not abort the
  * batch.  prec selects the P0 values used (FP64 requires an FP64 build,
- * WPCD_MIXED and WPCD_MIXED_REFINE a mixed one).
+ * WPCD_MIXED, WPCD_MIXED_REFINE and WPCD_MIXED_BF16 a mixed one).
  * Errors: WPCD_E_STATE, WPCD_E_INVALID, WPCD_E_NOMEM, WPCD_E_DEVICE.      */
 wpcd_status wpcd_solve(wpcd_ctx *ctx, const double *E, int32_t n_E, wpcd_precision prec,
                        const wpcd_solve_opts *opts, wpcd_energy_result *out,

@@ -27,6 +27,7 @@ WPCD_E_STATE = 7
 WPCD_FP64 = 0
 WPCD_MIXED = 1
 WPCD_MIXED_REFINE = 2
+WPCD_MIXED_BF16 = 3
 WPCD_TIME_PAIR = 1
 WPCD_TIME_P0 = 2
 WPCD_TIME_SOLVE = 4

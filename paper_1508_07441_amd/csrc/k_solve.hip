@@ -189,12 +189,21 @@ __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq,
 // LDS as in k_block_apply, k in steps of 16.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// Operand tag of the BF16 form: v_mfma_f32_16x16x16bf16_1k, FP32
+// accumulation; lane l supplies A[l % 16][4 (l / 16) + q] and
+// B[4 (l / 16) + q][l % 16] for q < 4, and its result items follow the FP32
+// 16 x 16 x 4 form.  Tiles are staged in FP32 and rounded to BF16 (nearest,
+// ties to even) as the operands are formed.
+struct Bf16 {};
 
 template <class MT>
 struct MfmaAcc;
 template <>
 struct MfmaAcc<double> {
     using V = v4d;
+    using L = double;   // LDS tile element
     static __device__ __forceinline__ V step(double a, double b, V c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -203,11 +212,25 @@ struct MfmaAcc<double> {
 template <>
 struct MfmaAcc<float> {
     using V = v4f;
+    using L = float;
     static __device__ __forceinline__ V step(float a, float b, V c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
+template <>
+struct MfmaAcc<Bf16> {
+    using V = v4f;
+    using L = float;
+    static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// BF16 bits of a finite float, rounded to nearest with ties to even.
+__device__ __forceinline__ short bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
 
 template <bool USE_G, bool SUB, class TI, class TO, class MT>
 __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, int nq, int W,
@@ -217,8 +240,9 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
                                                           TO *__restrict__ out) {
     constexpr int TM = 64, TN = 64, KS = 16;
     using V = typename MfmaAcc<MT>::V;
-    __shared__ MT sA[KS][TM + 1];
-    __shared__ MT sB[KS][TN + 1];
+    using L = typename MfmaAcc<MT>::L;
+    __shared__ L sA[KS][TM + 1];
+    __shared__ L sB[KS][TN + 1];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
     const int a = blockIdx.z;
@@ -233,7 +257,7 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
 #pragma unroll
         for (int v = 0; v < 2; ++v)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[u][v][r] = (MT)0;
+            for (int r = 0; r < 4; ++r) acc[u][v][r] = 0;
     const int li = lane & 15, lk = lane >> 4;
     // (j, c) of the panel columns this thread stages, once (as in k_block_apply)
     constexpr int NBL = KS * TN / 256;
@@ -254,7 +278,7 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
         for (int idx = t; idx < TM * KS; idx += 256) {
             const int rr = idx / KS, kk = idx % KS;
             const int r = row0 + rr, k = k0 + kk;
-            sA[kk][rr] = (MT)((r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0);
+            sA[kk][rr] = (L)((r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0);
         }
 #pragma unroll
         for (int sl = 0; sl < NBL; ++sl) {
@@ -274,20 +298,37 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
                     v = (double)in[o + c];
                 }
             }
-            sB[kk][qq] = (MT)v;
+            sB[kk][qq] = (L)v;
         }
         __syncthreads();
+        if constexpr (std::is_same<MT, Bf16>::value) {
+            // one 16 x 16 x 16 step covers the whole k slab
+            v4s av[2], bv[2];
 #pragma unroll
-        for (int kb = 0; kb < KS; kb += 4) {
-            MT av[2], bv[2];
+            for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) av[u] = sA[kb + lk][wr * 32 + u * 16 + li];
+                for (int u = 0; u < 2; ++u) av[u][q] = bf16_bits(sA[4 * lk + q][wr * 32 + u * 16 + li]);
 #pragma unroll
-            for (int v = 0; v < 2; ++v) bv[v] = sB[kb + lk][wc * 32 + v * 16 + li];
+                for (int v = 0; v < 2; ++v) bv[v][q] = bf16_bits(sB[4 * lk + q][wc * 32 + v * 16 + li]);
+            }
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int v = 0; v < 2; ++v) acc[u][v] = MfmaAcc<MT>::step(av[u], bv[v], acc[u][v]);
+                for (int v = 0; v < 2; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[u], bv[v], acc[u][v], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int kb = 0; kb < KS; kb += 4) {
+                MT av[2], bv[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) av[u] = sA[kb + lk][wr * 32 + u * 16 + li];
+#pragma unroll
+                for (int v = 0; v < 2; ++v) bv[v] = sB[kb + lk][wc * 32 + v * 16 + li];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) acc[u][v] = MfmaAcc<MT>::step(av[u], bv[v], acc[u][v]);
+            }
         }
         __syncthreads();
     }
@@ -950,6 +991,7 @@ struct Batch {
     int nsplit;      // stage-1 splits of the cross-chunk reductions
     double *out2;    // stage-1 results [nsplit][pairs][2]
     bool lowp;       // FP32 intermediate panels in the inner iterations
+    bool bf16;       // ... with the block products on the BF16 matrix cores
     int spmm_cfg;    // P0 SpMM variant (kSpmmCfg)
     void set_chunks(int nr_) {
         nr = nr_;
@@ -987,12 +1029,13 @@ void launch_block_apply_mfma(Batch &b, ChPtrs mats, const TI *in, const double *
 }
 
 // Tile shapes 0-3 on the vector ALUs, 4 on the FP64 matrix cores (all FP64
-// arithmetic); the inner iterations of the refine tier (FP32 panels) use the
-// FP32 matrix cores with FP32 accumulation.
+// arithmetic); the inner iterations of the refine tiers (FP32 panels) use the
+// FP32 matrix cores, or the BF16 ones, with FP32 accumulation.
 template <bool USE_G, bool SUB, class TI, class TO>
 void launch_block_apply(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
     if (std::is_same<TI, float>::value || std::is_same<TO, float>::value) {
-        launch_block_apply_mfma<USE_G, SUB, TI, TO, float>(b, mats, in, add, out);
+        if (b.bf16) launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16>(b, mats, in, add, out);
+        else launch_block_apply_mfma<USE_G, SUB, TI, TO, float>(b, mats, in, add, out);
         return;
     }
     switch (b.apply_cfg) {
@@ -1216,6 +1259,7 @@ IterGraphs *graphs_for(Batch &b, double tol, int check_every) {
         (uint64_t)b.S.g, (uint64_t)c->d_rowptr.ptr, (uint64_t)c->d_col.ptr,
         (uint64_t)(b.fp64 ? (void *)c->d_val64.ptr : (void *)c->d_val32.ptr),
         (uint64_t)b.nE, (uint64_t)b.m, (uint64_t)b.M, (uint64_t)b.fp64, (uint64_t)b.lowp,
+        (uint64_t)b.bf16,
         (uint64_t)b.apply_cfg, (uint64_t)b.spmm_cfg,
         (uint64_t)b.nr, (uint64_t)b.nchunk, (uint64_t)b.nsplit, (uint64_t)b.out2,
         (uint64_t)c->np, (uint64_t)c->nq, (uint64_t)c->nch,
@@ -1345,7 +1389,8 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     b.m = m;
     b.M = (int64_t)c->nch * c->nq * c->np;
     b.fp64 = fp64;
-    b.lowp = prec == WPCD_MIXED_REFINE;
+    b.lowp = prec == WPCD_MIXED_REFINE || prec == WPCD_MIXED_BF16;
+    b.bf16 = prec == WPCD_MIXED_BF16;
     const int64_t vec = b.M * b.W;   // doubles per batched vector
     b.vstride = vec;
     const int max_chunks = cdiv(b.M, chunk_rows_of(b.nEp, 1));
@@ -1552,6 +1597,7 @@ void arnoldi_kernel(wpcd_ctx *c, double E, int m, std::vector<double> &H, int &s
     b.M = (int64_t)c->nch * c->nq * c->np;
     b.fp64 = fp64;
     b.lowp = false;
+    b.bf16 = false;
     const int64_t vec = b.M * 2;
     b.vstride = vec;
     const int max_chunks = cdiv(b.M, chunk_rows_of(1, 1));

@@ -414,7 +414,8 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
                  "build_basis and build_p must come first");
     WPCD_REQUIRE(E && out && n_E >= 0, WPCD_E_INVALID, "E/out NULL or n_E < 0");
-    WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED || prec == WPCD_MIXED_REFINE,
+    WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED || prec == WPCD_MIXED_REFINE ||
+                     prec == WPCD_MIXED_BF16,
                  WPCD_E_INVALID, "bad precision");
     WPCD_REQUIRE(prec != WPCD_FP64 || c->p_fp64, WPCD_E_STATE, "FP64 solve needs an FP64 P0 build");
     WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE, "mixed solve needs a mixed P0 build");

@@ -246,6 +246,8 @@ def test_status_codes(ctx, P):
     assert st[3] == P.WPCD_E_INVALID
     assert st[4] == P.WPCD_E_ON_EDGE
     assert st[5] == P.WPCD_OK
+    # an empty energy list is a valid call with no results
+    assert ctx.solve([], P.WPCD_FP64) == []
     # state errors
     c2 = P.Context(0)
     with pytest.raises(P.WpcdError) as ei:
@@ -297,6 +299,16 @@ def test_c2_full_fp64_and_mixed(ctx, P):
         U = complex(r.U_re, r.U_im)
         worst = max(worst, abs(U - ref[E]) / abs(ref[E]))
     say(f"[C2] mixed+refine max rel amplitude error vs FP64 oracle: {worst:.3e}")
+    assert worst <= 1e-6
+    say("[C2] solve MIXED_BF16")
+    res4 = ctx.solve(C2["energies"], P.WPCD_MIXED_BF16)
+    worst = 0.0
+    for r, E in zip(res4, C2["energies"]):
+        assert r.status == P.WPCD_OK and r.residual <= 1e-8
+        U = complex(r.U_re, r.U_im)
+        worst = max(worst, abs(U - ref[E]) / abs(ref[E]))
+    say(f"[C2] mixed+BF16 max rel amplitude error vs FP64 oracle: {worst:.3e}, "
+        f"iterations {[r.iters for r in res4]}")
     assert worst <= 1e-6
 
 
