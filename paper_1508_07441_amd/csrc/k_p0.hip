@@ -713,11 +713,14 @@ __device__ __forceinline__ void mc_lane_fast(const McTab &Mt, const double *__re
                                              const NodeTab &N, int ngx, double q, double q2,
                                              double lo_t, double lo_u, double h, double (&acc)[NP]) {
     const double a2 = q * q, b2 = q2 * q2, A = b2 + 0.25 * a2;
+    // q, q' are interior Gauss nodes (> 0): two reciprocals serve every
+    // channel pair's divisor (q^2)^(lam/2) (q'^2)^(lam'/2)
+    const double ra = 1.0 / a2, rb = 1.0 / b2;
     double Dc[NP][DEG + 1];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const McPair P = Mt.p[p];
-        const double den = ipow_h(a2, P.hlam) * ipow_h(b2, P.hlam2);
+        const double rden = ipow_h(ra, P.hlam) * ipow_h(rb, P.hlam2);
         int o = P.off;
 #pragma unroll
         for (int c = 0; c <= DEG; ++c) {
@@ -731,7 +734,7 @@ __device__ __forceinline__ void mc_lane_fast(const McTab &Mt, const double *__re
                     pa *= a2;
                 }
             }
-            Dc[p][c] = s / den;
+            Dc[p][c] = s * rden;
         }
         acc[p] = 0.0;
     }
@@ -831,6 +834,7 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
         lane_limits(T, i, i2, q, q2, lo_t, lo_u, h);
         const bool act = h > 0.0;
         const double a2 = q * q, b2 = q2 * q2, A = b2 + 0.25 * a2;
+        const double ra = 1.0 / a2, rb = 1.0 / b2;   // interior nodes: q, q' > 0
         double M[NG][DEG + 1];
 #pragma unroll
         for (int g = 0; g < NG; ++g)
@@ -889,7 +893,7 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
                         if (g == gi) mg = M[gi][c];
                     v = fma(sc, mg, v);
                 }
-                v = wab * v / (ipow_h(a2, P.hlam) * ipow_h(b2, P.hlam2));
+                v = wab * v * (ipow_h(ra, P.hlam) * ipow_h(rb, P.hlam2));
             }
             v = wave_sum(v);
             if (lane == 0) {
