@@ -566,6 +566,28 @@ struct ElemQueue {
     uint16_t dst[EC * 64];   // k * 64 + rank: cell pair k of the round, lane rank
 };
 
+// Sums over the 64 lanes of one wavefront of the NP values each lane has
+// stored in red[p][lane], the wavefront's own LDS block (no other wavefront
+// touches it, and a wavefront's LDS accesses are performed in order): lane
+// 4 p + x (x < 4) sums the quarter x of value p, then the quad is combined
+// by DPP.  Returns the sum of value p in lanes 4 p .. 4 p + 3 (p < NP); a
+// fixed order.  The caller brackets its stores with wave barriers.
+template <int NP>
+__device__ __forceinline__ double wave_sums(double (*red)[64], int lane) {
+    static_assert(NP <= 16, "at most 16 values");
+    __builtin_amdgcn_wave_barrier();
+    const int p = lane >> 2, x = lane & 3;
+    double s = 0.0;
+    if (p < NP) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s += red[p][x * 16 + r];
+    }
+    s += dpp_f64<0xB1>(s);   // quad_perm [1, 0, 3, 2]
+    s += dpp_f64<0x4E>(s);   // quad_perm [2, 3, 0, 1]
+    __builtin_amdgcn_wave_barrier();
+    return s;
+}
+
 template <bool F32, int NGX, int EC>
 __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
                                                     const int32_t *__restrict__ rowidx,
@@ -760,6 +782,7 @@ __global__ __launch_bounds__(256) void k_p0_mc(ElemTables T, NodeTab N, McTab Mt
                                                const int32_t *__restrict__ rowidx,
                                                const int32_t *__restrict__ col, int64_t nnz,
                                                double *__restrict__ val64, float *__restrict__ val32) {
+    __shared__ double red[4][NP][64];
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -784,13 +807,14 @@ __global__ __launch_bounds__(256) void k_p0_mc(ElemTables T, NodeTab N, McTab Mt
             }
         }
         const double nrm = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
+        double(*rw)[64] = red[threadIdx.x >> 6];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const double v = wave_sum(tot[p]);
-            if (lane == 0) {
-                if (val64) val64[e * NP + p] = v * nrm;
-                else val32[e * NP + p] = (float)(v * nrm);
-            }
+        for (int p = 0; p < NP; ++p) rw[p][lane] = tot[p];
+        const double v = wave_sums<NP>(rw, lane);
+        if ((lane & 3) == 0 && (lane >> 2) < NP) {
+            const int p = lane >> 2;
+            if (val64) val64[e * NP + p] = v * nrm;
+            else val32[e * NP + p] = (float)(v * nrm);
         }
     }
 }
@@ -821,6 +845,7 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
                                                 double *__restrict__ val64,
                                                 float *__restrict__ val32) {
     constexpr int NG = (HMAX + 1) * (HMAX + 1);
+    __shared__ double red[4][NP][64];
     const int lane = threadIdx.x & 63;
     const int a = lane >> 3, b = lane & 7;
     const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
@@ -870,6 +895,7 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
         }
         const double wab = act ? T.qwt[j * 8 + a] * T.qwt[j2 * 8 + b] * h : 0.0;
         const double nrm = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
+        double(*rw)[64] = red[threadIdx.x >> 6];
         for (int p = 0; p < NP; ++p) {
             const McPair P = Mt.p[p];
             const int g = P.hl * (HMAX + 1) + P.hl2;
@@ -895,11 +921,13 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
                 }
                 v = wab * v * (ipow_h(ra, P.hlam) * ipow_h(rb, P.hlam2));
             }
-            v = wave_sum(v);
-            if (lane == 0) {
-                if (F32OUT) val32[e * NP + p] = (float)(v * nrm);
-                else val64[e * NP + p] = v * nrm;
-            }
+            rw[p][lane] = v;
+        }
+        const double v = wave_sums<NP>(rw, lane);
+        if ((lane & 3) == 0 && (lane >> 2) < NP) {
+            const int p = lane >> 2;
+            if (F32OUT) val32[e * NP + p] = (float)(v * nrm);
+            else val64[e * NP + p] = v * nrm;
         }
     }
 }
