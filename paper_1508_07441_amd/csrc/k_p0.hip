@@ -730,6 +730,34 @@ __device__ __forceinline__ double ipow_h(double v, int h) {
     return h == 0 ? 1.0 : (h == 1 ? v : (h == 2 ? v * v : v * v * v * v));
 }
 
+// Coefficients D_c (c = 0..min(d, DEG)) of one channel pair's coupling
+// polynomial in y for fixed (q, q'):
+//   D_c = sum_{a <= d - c} coef[a] (q^2)^a (q'^2)^(d - c - a)
+// (coef: block c of the pair's table, blocks of d - c + 1 entries), as
+// (q'^2)^(d - c) H_c(r) with H_c the same polynomial in r = q^2 / q'^2 by
+// Horner; rb = 1 / q'^2.  Entries with c > d are zero.
+template <int DEG>
+__device__ __forceinline__ void coupling_coeffs(const double *__restrict__ coef, int off, int d,
+                                                double a2, double b2, double rb,
+                                                double (&D)[DEG + 1]) {
+    const double r = a2 * rb;
+    double w = 1.0;   // (q'^2)^(d - c)
+    for (int k = 0; k < d; ++k) w *= b2;
+    int o = off;
+#pragma unroll
+    for (int c = 0; c <= DEG; ++c) {
+        D[c] = 0.0;
+        if (c <= d) {
+            const int n = d - c;
+            double hh = coef[o + n];
+            for (int aa = n - 1; aa >= 0; --aa) hh = fma(hh, r, coef[o + aa]);
+            D[c] = w * hh;
+            w *= rb;
+            o += n + 1;
+        }
+    }
+}
+
 template <int NP, int DEG>
 __device__ __forceinline__ void mc_lane_fast(const McTab &Mt, const double *__restrict__ coef,
                                              const NodeTab &N, int ngx, double q, double q2,
@@ -743,21 +771,10 @@ __device__ __forceinline__ void mc_lane_fast(const McTab &Mt, const double *__re
     for (int p = 0; p < NP; ++p) {
         const McPair P = Mt.p[p];
         const double rden = ipow_h(ra, P.hlam) * ipow_h(rb, P.hlam2);
-        int o = P.off;
+        double D[DEG + 1];
+        coupling_coeffs<DEG>(coef, P.off, P.d, a2, b2, rb, D);
 #pragma unroll
-        for (int c = 0; c <= DEG; ++c) {
-            double s = 0.0;
-            if (c <= P.d) {
-                double pa = 1.0;
-                for (int a = 0; a <= P.d - c; ++a) {
-                    double pb = 1.0;
-                    for (int bb = 0; bb < P.d - c - a; ++bb) pb *= b2;
-                    s += coef[o++] * pa * pb;
-                    pa *= a2;
-                }
-            }
-            Dc[p][c] = s * rden;
-        }
+        for (int c = 0; c <= DEG; ++c) Dc[p][c] = D[c] * rden;
         acc[p] = 0.0;
     }
     for (int k = 0; k < ngx; ++k) {
@@ -901,23 +918,16 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
             const int g = P.hl * (HMAX + 1) + P.hl2;
             double v = 0.0;
             if (act) {
-                int o = P.off;
+                double D[DEG + 1];
+                coupling_coeffs<DEG>(coef, P.off, P.d, a2, b2, rb, D);
 #pragma unroll
                 for (int c = 0; c <= DEG; ++c) {
                     if (c > P.d) break;
-                    // D_pc = sum_a coef (q^2)^a (q'^2)^(d - c - a)
-                    double sc = 0.0, pa = 1.0;
-                    for (int aa = 0; aa <= P.d - c; ++aa) {
-                        double pb = 1.0;
-                        for (int bb = 0; bb < P.d - c - aa; ++bb) pb *= b2;
-                        sc = fma(coef[o++] * pa, pb, sc);
-                        pa *= a2;
-                    }
                     double mg = M[0][c];
 #pragma unroll
                     for (int gi = 1; gi < NG; ++gi)
                         if (g == gi) mg = M[gi][c];
-                    v = fma(sc, mg, v);
+                    v = fma(D[c], mg, v);
                 }
                 v = wab * v * (ipow_h(ra, P.hlam) * ipow_h(rb, P.hlam2));
             }
