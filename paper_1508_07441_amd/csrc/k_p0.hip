@@ -920,14 +920,13 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
             if (act) {
                 double D[DEG + 1];
                 coupling_coeffs<DEG>(coef, P.off, P.d, a2, b2, rb, D);
+                // g is the same for the whole wavefront: a scalar branch picks
+                // the moment row (D_c = 0 for c > d adds exact zeros)
 #pragma unroll
-                for (int c = 0; c <= DEG; ++c) {
-                    if (c > P.d) break;
-                    double mg = M[0][c];
+                for (int gi = 0; gi < NG; ++gi) {
+                    if (g != gi) continue;
 #pragma unroll
-                    for (int gi = 1; gi < NG; ++gi)
-                        if (g == gi) mg = M[gi][c];
-                    v = fma(D[c], mg, v);
+                    for (int c = 0; c <= DEG; ++c) v = fma(D[c], M[gi][c], v);
                 }
                 v = wab * v * (ipow_h(ra, P.hlam) * ipow_h(rb, P.hlam2));
             }
