@@ -16,8 +16,10 @@ and resident on the GPU when the timed region starts.
 Beside the timed steps: the solve per energy in the mixed tier, in the
 mixed tier with the learned warm start (trained at setup on 16 potential
 variants x 32 energies drawn with splitmix64: strength multipliers
-U[0.8, 1.2], energies U[-0.05, 2.0]) and in FP64, with iterations and the
-amplitude errors against the FP64 solve.
+U[0.8, 1.2], energies U[-0.05, 2.0]), in the refine and BF16 tiers and in
+FP64, with iterations and the amplitude errors against the FP64 solve; the
+oracle's P build on all host threads (cpu_baseline) and on one
+(cpu_baseline_1thread, a sample of every 8th cell row).
 
 Prints one JSON line.  value = P-matrix elements (selected cell pairs) per
 second of P-build wall time (pre-selection + elements); the whole-step time
@@ -88,6 +90,20 @@ def cpu_baseline(sample_stride, threads):
     return {"value": n / dt, "unit": "P-matrix elements/s", "cores": threads, "kind": "oracle",
             "sample": f"every {sample_stride}th of the {N*N} cell rows ({rows.size} rows, {n} "
                       f"cell pairs): brute-force pre-selection + FP64 elements, {dt:.1f} s"}
+
+
+def cpu_baseline_one_thread(sample_stride):
+    """cpu_baseline with OMP_NUM_THREADS=1, in a child process of this script
+    (called before any GPU use, so the child is started from a process that
+    has not initialised the GPU)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only",
+                        str(sample_stride)], env=env, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def copy_calibration(nbytes):
@@ -267,8 +283,12 @@ def main():
     ap.add_argument("--no-learn", action="store_true",
                     help="skip the learned-warm-start leg (short runs under a profiler)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
-                    help="after the run, one plain device copy y = x * 1 of this many MiB "
-                         "(float32, torch elementwise kernel) to calibrate HBM byte counters")
+                    help="after the run, one device-to-device copy of this many MiB by the "
+                         "HIP runtime's copy kernel, to calibrate HBM byte counters")
+    ap.add_argument("--cpu-only", type=int, default=0,
+                    help="no GPU: only the oracle baseline on every N-th cell row with this "
+                         "process's OMP_NUM_THREADS; prints its JSON (used for the 1-thread "
+                         "figure, run as a child before the GPU is touched)")
     ap.add_argument("--c4", type=str, default="",
                     help="uneven systems solved together: VARIANTS,ENERGIES (e.g. 6,64); off by "
                          "default")
@@ -276,11 +296,20 @@ def main():
                     help="learned warm start on the 270k basis: VARIANTS,ENERGIES,SWEEP "
                          "(e.g. 64,64,256); off by default (about a minute)")
     args = ap.parse_args()
+    if args.cpu_only:
+        print(json.dumps(cpu_baseline(args.cpu_only, int(os.environ.get("OMP_NUM_THREADS", "1")))),
+              flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    # the oracle on one host thread (the paper's speed-up convention), in a
+    # child process started before this process touches the GPU
+    cpu1 = None
+    if rank == 0 and not args.no_cpu_baseline:
+        cpu1 = cpu_baseline_one_thread(8 * args.cpu_sample_stride)
 
     import paper_1508_07441_amd as P
 
@@ -425,6 +454,7 @@ def main():
     if rank == 0 and not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride, threads)
+        out["cpu_baseline_1thread"] = cpu1
     ctx.close()
     if args.copy_calib_mb:
         out["copy_calib_bytes"] = copy_calibration(args.copy_calib_mb << 20)
