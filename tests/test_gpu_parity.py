@@ -400,6 +400,16 @@ def test_multichannel_amplitudes_fp64(ctx, P):
         assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
         if E < 0:
             assert abs(math.hypot(r.S_re, r.S_im) - 1.0) < 1e-12
+    # the mixed tiers on the same system (block products of three channels on
+    # the FP32 and BF16 matrix cores): the 1e-6 amplitude gate
+    refs = {E: O.amplitudes(sysm, E, O.solve_gmres(sysm, E)[0]).U00 for E in energies}
+    ctx.build_p(P.WPCD_MIXED)
+    for prec in (P.WPCD_MIXED, P.WPCD_MIXED_REFINE, P.WPCD_MIXED_BF16):
+        say(f"[mc16] solve precision {prec}")
+        for r, E in zip(ctx.solve(energies, prec), energies):
+            assert r.status == P.WPCD_OK and r.residual <= 1e-8, (prec, E)
+            U = complex(r.U_re, r.U_im)
+            assert abs(U - refs[E]) <= 1e-6 * abs(refs[E]), (prec, E, U, refs[E])
 
 
 def test_c3_structure_and_sampled_values(ctx, P):
