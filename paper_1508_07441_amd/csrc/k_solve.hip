@@ -459,8 +459,11 @@ __global__ __launch_bounds__(256) void k_spmm_bsr(const int64_t *__restrict__ ro
 // LDS-staged SpMM for any n_ch (n_ch = 1 is the s-wave case): one
 // wavefront (= workgroup) per cell row; the row's column indices and value
 // blocks are loaded a tile at a time with coalesced loads into LDS, then
-// every lane slot (nonzero slot g, column c) reads them as LDS broadcasts,
-// so global memory sees each value once instead of once per column lane.
+// every lane slot (nonzero slot g, column pair c, c + 1) reads them as LDS
+// broadcasts, so global memory sees each value once instead of once per
+// column lane.  Two columns per lane halve the lanes per nonzero, so twice
+// as many nonzeros are gathered per instruction (measured 32 -> 25 us per
+// application at 150 x 150 with 8 energies).
 template <class V, int NCH, class XT, class YT>
 __global__ __launch_bounds__(64) void k_spmm_lds(const int64_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col,
@@ -473,11 +476,13 @@ __global__ __launch_bounds__(64) void k_spmm_lds(const int64_t *__restrict__ row
     __shared__ V vs[T * NV];
     const int lane = threadIdx.x;
     const int r = blockIdx.x;
-    const int G = 64 / Wp, g = lane / Wp, c = lane % Wp;
+    // two consecutive entries of x per lane: Wp / 2 lanes per nonzero
+    const int L = Wp >> 1;
+    const int G = 64 / L, g = lane / L, c = 2 * (lane % L);
     const int64_t b = rowptr[r], e = rowptr[r + 1];
-    double acc[NCH];
+    double acc[NCH][2];
 #pragma unroll
-    for (int a = 0; a < NCH; ++a) acc[a] = 0.0;
+    for (int a = 0; a < NCH; ++a) acc[a][0] = acc[a][1] = 0.0;
     for (int64_t t0 = b; t0 < e; t0 += T) {
         const int n = (int)(e - t0 < T ? e - t0 : T);
         __syncthreads();   // the previous tile has been consumed
@@ -491,18 +496,26 @@ __global__ __launch_bounds__(64) void k_spmm_lds(const int64_t *__restrict__ row
                 const V *vb = vs + k * NV;
 #pragma unroll
                 for (int a2 = 0; a2 < NCH; ++a2) {
-                    const double xv = (double)x[((int64_t)a2 * ncell + cc) * W + c];
+                    const XT *xp = x + ((int64_t)a2 * ncell + cc) * W + c;
+                    const double x0 = (double)xp[0], x1 = (double)xp[1];
 #pragma unroll
-                    for (int a = 0; a < NCH; ++a) acc[a] += (double)vb[a * NCH + a2] * xv;
+                    for (int a = 0; a < NCH; ++a) {
+                        const double v = (double)vb[a * NCH + a2];
+                        acc[a][0] += v * x0;
+                        acc[a][1] += v * x1;
+                    }
                 }
             }
         }
     }
 #pragma unroll
     for (int a = 0; a < NCH; ++a) {
-        double v = acc[a];
-        for (int off = Wp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-        if (g == 0 && c < W) y[((int64_t)a * ncell + r) * W + c] = (YT)v;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double v = acc[a][h];
+            for (int off = L; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+            if (g == 0 && c < W) y[((int64_t)a * ncell + r) * W + c + h] = (YT)v;
+        }
     }
 }
 
