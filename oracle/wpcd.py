@@ -66,6 +66,7 @@ def lib():
                                          ctypes.c_int64, i64p, i32p]
         L.orc_geom_G.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] * 3
         L.orc_geom_G.restype = ctypes.c_double
+        L.orc_geom_G_table.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip] + [ctypes.c_double] * 3 + [dp]
         L.orc_p0_pairs.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip,
                                    i64p, i32p, ctypes.c_int64, dp]
@@ -274,6 +275,19 @@ def p0_pairs(p, q, n_gq, n_gx, L, chans, rows, cols):
 def geom_G(L, a, b, q, q2, x):
     """Angular coupling G^L_{a,b}(q, q', x) for channels a = (l, lam), b."""
     return lib().orc_geom_G(L, a[0], a[1], b[0], b[1], float(q), float(q2), float(x))
+
+
+def geom_G_table(L, chans, q, q2, x):
+    """All channel pairs of G at one node by the node-shared routine of the
+    element quadrature: array (nch, nch), rows = first channel."""
+    nch = len(chans)
+    la = np.array([c[0] for c in chans], dtype=np.intc)
+    lb = np.array([c[1] for c in chans], dtype=np.intc)
+    out = np.zeros(nch * nch)
+    if lib().orc_geom_G_table(L, nch, _p(la, ctypes.c_int), _p(lb, ctypes.c_int), float(q),
+                              float(q2), float(x), _p(out, ctypes.c_double)):
+        raise ValueError("channel set outside the supported sizes")
+    return out.reshape(nch, nch)
 
 
 # --------------------------------------------------------------- system

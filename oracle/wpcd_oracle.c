@@ -314,6 +314,33 @@ static void orc_geom_G_all(int L, int nch, const int *l, const int *lam, const d
         }
 }
 
+/* Clebsch-Gordan table of a channel list for orc_geom_G_all:
+ * cg[a][M + L][m + LMAX] = <l_a m lam_a M-m | L M> (zero where |m| > l_a). */
+static void orc_cg_table(int L, int nch, const int *l, const int *lam, double *cg)
+{
+    for (int a = 0; a < nch; ++a)
+        for (int M = -L; M <= L; ++M)
+            for (int m = -ORC_LMAX; m <= ORC_LMAX; ++m)
+                cg[(a * 17 + (M + L)) * (2 * ORC_LMAX + 1) + (m + ORC_LMAX)] =
+                    (abs(m) <= l[a]) ? orc_cg(l[a], m, lam[a], M - m, L, M) : 0.0;
+}
+
+/* Every channel pair of G at one node through the node-shared routine the
+ * element quadrature uses (exported so the tests can compare it with
+ * orc_geom_G pair by pair).  G[a*nch + a2]; returns 0, or 1 for sizes
+ * outside nch <= 8, L <= 8, l, lam <= 4.                                 */
+int orc_geom_G_table(int L, int nch, const int *l, const int *lam, double q, double q2,
+                     double x, double *G)
+{
+    if (nch < 1 || nch > 8 || L < 0 || L > 8) return 1;
+    for (int a = 0; a < nch; ++a)
+        if (l[a] < 0 || l[a] > ORC_LMAX || lam[a] < 0 || lam[a] > ORC_LMAX) return 1;
+    double cg[8 * 17 * (2 * ORC_LMAX + 1)];
+    orc_cg_table(L, nch, l, lam, cg);
+    orc_geom_G_all(L, nch, l, lam, cg, q, q2, x, G);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* One cell-pair block of P0: out[a*nch + a2] for channel rows a, columns a2.
  * i, j: row cell; i2, j2: column cell (0-based bins).
@@ -333,13 +360,7 @@ void orc_p0_block(const double *p, const double *q, int i, int j, int i2, int j2
     /* Clebsch-Gordan table per channel: cg[a][M + L][m + LMAX] */
     double cg[8 * 17 * (2 * ORC_LMAX + 1)];
     double Gn[64];
-    if (!swave) {
-        for (int a = 0; a < nch; ++a)
-            for (int M = -L; M <= L; ++M)
-                for (int m = -ORC_LMAX; m <= ORC_LMAX; ++m)
-                    cg[(a * 17 + (M + L)) * (2 * ORC_LMAX + 1) + (m + ORC_LMAX)] =
-                        (abs(m) <= l[a]) ? orc_cg(l[a], m, lam[a], M - m, L, M) : 0.0;
-    }
+    if (!swave) orc_cg_table(L, nch, l, lam, cg);
 
     for (int a = 0; a < nq_pts; ++a) {
         double qa = qm1 + qh1 * gq[a];

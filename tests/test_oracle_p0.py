@@ -9,7 +9,12 @@
 * the pre-selection is a necessary condition: every pair it drops evaluates
   to exactly zero under the rule;
 * the angular coupling G: 1 in the s-wave, the Legendre addition theorem for
-  L = 0, and the exchange symmetry G_ab(q,q',x) = G_ba(q',q,x).
+  L = 0, the exchange symmetry G_ab(q,q',x) = G_ba(q',q,x), its bipolar-
+  harmonic definition evaluated with scipy's spherical harmonics (l, lam up
+  to 4), and the node-shared evaluation of the quadrature against the
+  single-pair routine;
+* multichannel elements (L = 2+, five channels with l, lam up to 4) against a
+  Monte Carlo of the six-dimensional overlap with bipolar harmonics.
 """
 import math
 
@@ -109,18 +114,55 @@ def test_swave_cosine_integral_closed_form():
     assert checked >= 6
 
 
+def test_swave_cosine_integral_closed_form_lowest_bins():
+    """The same closed form for every selected cell pair with a p bin at
+    p = 0 or next to it (i or i' in {0, 1}), where pi1 or pi2 reaches zero
+    inside the cosine interval and the integrand has an inverse-square-root
+    end point: the mapped Gauss rule converges more slowly there, so the
+    bound is looser at 16 points and 1e-10 only at 64."""
+    n = 12
+    p = W.cheb_edges(n, 10.0)
+    q = W.cheb_edges(n, 10.0)
+    ptr, col = W.preselect(p, q)
+    checked = 0
+    worst16 = 0.0
+    for r in range(n * n):
+        i, j = r % n, r // n
+        for c in col[ptr[r]:ptr[r + 1]]:
+            i2, j2 = int(c) % n, int(c) // n
+            if min(i, i2) >= 2:
+                continue
+            qa = 0.5 * (q[j] + q[j + 1]); qb = 0.5 * (q[j2] + q[j2 + 1])
+            A = qb * qb + 0.25 * qa * qa; C = qa * qa + 0.25 * qb * qb; B = qa * qb
+            xlo = max(-1.0, (p[i] ** 2 - A) / B, (p[i2] ** 2 - C) / B)
+            xhi = min(1.0, (p[i + 1] ** 2 - A) / B, (p[i2 + 1] ** 2 - C) / B)
+            if xhi <= xlo:
+                continue
+            f = lambda x: math.log(math.sqrt(max(A + B * x, 0.0)) + math.sqrt(max(C + B * x, 0.0)))
+            exact = 2.0 / B * (f(xhi) - f(xlo))
+            pref = math.sqrt((q[j + 1] - q[j]) * (q[j2 + 1] - q[j2])
+                             / ((p[i + 1] - p[i]) * (p[i2 + 1] - p[i2]))) * qa * qb
+            e16 = abs(_elem(p, q, i, j, i2, j2, 1, 16) / pref - exact) / exact
+            e64 = abs(_elem(p, q, i, j, i2, j2, 1, 64) / pref - exact) / exact
+            worst16 = max(worst16, e16)
+            assert e16 <= 1e-3, (i, j, i2, j2, e16)
+            assert e64 <= 1e-10, (i, j, i2, j2, e64)
+            checked += 1
+    assert checked >= 30
+    # the p = 0 end point is really met: the 16-point rule is visibly worse
+    assert worst16 > 1e-6
+
+
 def test_p0_symmetric_nonnegative_c1():
     p = W.cheb_edges(C1["n_p"], C1["p_max"])
     q = W.cheb_edges(C1["n_q"], C1["q_max"])
     ptr, col = W.preselect(p, q)
-    rows = np.repeat(np.arange(p.size - 1 + 0, dtype=np.int64).repeat(0), 0)
     ncell = (p.size - 1) * (q.size - 1)
     rows = np.repeat(np.arange(ncell, dtype=np.int64), np.diff(ptr))
     val = W.p0_pairs(p, q, C1["n_gq"], C1["n_gx"], 0, [(0, 0)], rows, col)[:, 0, 0]
     import scipy.sparse as sp
     P = sp.csr_matrix((val, col, ptr), shape=(ncell, ncell))
     # structure symmetric exactly, values up to rounding order
-    S = (P != 0).astype(np.int8)
     Sfull = sp.csr_matrix((np.ones_like(val), col, ptr), shape=(ncell, ncell))
     assert (Sfull - Sfull.T).nnz == 0
     assert abs(P - P.T).max() <= 1e-14 * abs(P).max()
@@ -128,7 +170,6 @@ def test_p0_symmetric_nonnegative_c1():
     assert int(ptr[-1]) == 53105
     # the selected pairs are mostly nonzero under the rule
     assert np.count_nonzero(val) > 0.9 * val.size
-    del S
 
 
 @pytest.mark.parametrize("n", [6, 11])
@@ -263,15 +304,19 @@ def _mc_channel(p, q, cells, L, M, ch1, ch2, n, rng):
     return est.mean(), est.std() / math.sqrt(n)
 
 
-@pytest.mark.parametrize("pair", [((0, 2), (0, 2)), ((0, 2), (2, 0)), ((2, 2), (2, 0)), ((2, 2), (2, 2))])
+@pytest.mark.parametrize("pair", [((0, 2), (0, 2)), ((0, 2), (2, 0)), ((2, 2), (2, 0)), ((2, 2), (2, 2)),
+                                  ((2, 4), (4, 2)), ((4, 2), (0, 2)), ((2, 4), (2, 2))])
 def test_multichannel_element_monte_carlo(pair):
     """L = 2+ channel pair of one cell pair against a Monte Carlo of the
-    six-dimensional overlap with bipolar harmonics (two values of M)."""
+    six-dimensional overlap with bipolar harmonics (two values of M); the
+    element is computed in the five-channel set, so the node-shared
+    coupling of the quadrature is checked for l or lam = 4 as well."""
     p, q = np.array(TOY_P), np.array(TOY_Q)
     cells = (1, 1, 1, 2)
-    chans = [(0, 2), (2, 0), (2, 2)]
+    chans = FIVE_CH
     a, b = chans.index(pair[0]), chans.index(pair[1])
     fine = W.p0_pairs(p, q, 48, 48, 2, chans, np.array([1 * 4 + 1]), np.array([2 * 4 + 1]))[0, a, b]
+    assert abs(fine) > 1e-3
     rng = np.random.default_rng(99 + 3 * a + b)
     for M in (0, 1):
         vals = [_mc_channel(p, q, cells, 2, M, pair[0], pair[1], 400_000, rng) for _ in range(5)]
@@ -297,9 +342,51 @@ def test_multichannel_block_symmetry():
             V.append(vals[:, a, b])
     P = sp.csr_matrix((np.concatenate(V), (np.concatenate(R), np.concatenate(C))), shape=(3 * ncell,) * 2)
     assert abs(P - P.T).max() <= 1e-13 * abs(P).max()
-    # the node-shared evaluation of G equals the single-pair routine
-    x = 0.37
-    for a in range(3):
-        for b in range(3):
-            g1 = W.geom_G(2, ch[a], ch[b], 0.8, 1.3, x)
-            assert np.isfinite(g1)
+
+
+FIVE_CH = [(0, 2), (2, 0), (2, 2), (2, 4), (4, 2)]
+
+
+def _nodes(seed, n):
+    rng = np.random.default_rng(seed)
+    return [(rng.uniform(0.05, 4.0), rng.uniform(0.05, 4.0), rng.uniform(-1.0, 1.0)) for _ in range(n)] \
+        + [(0.8, 1.3, 1.0), (1.1, 0.4, -1.0), (0.6, 1.2, 0.0)]
+
+
+@pytest.mark.parametrize("L,chans", [(2, FIVE_CH), (0, [(0, 0), (2, 2), (4, 4)]),
+                                     (4, [(0, 4), (4, 0), (2, 2), (2, 4), (4, 2), (4, 4)])])
+def test_geom_G_node_shared_equals_pair_routine(L, chans):
+    """The node-shared evaluation of G used inside the element quadrature
+    (all channel pairs at once from one set of spherical harmonics) equals
+    the single-pair routine for every channel pair, including l or lam = 4."""
+    for (qq, q2, x) in _nodes(31 + L, 12):
+        tab = W.geom_G_table(L, chans, qq, q2, x)
+        for a, ca in enumerate(chans):
+            for b, cb in enumerate(chans):
+                g = W.geom_G(L, ca, cb, qq, q2, x)
+                assert abs(tab[a, b] - g) <= 1e-13 * max(1.0, abs(g)), (ca, cb, qq, q2, x)
+
+
+def _G_scipy(L, ca, cb, qq, q2, x):
+    """16 pi^2/(2L+1) sum_M conj(Y^{LM}_{l lam}(pi1^, q^)) Y^{LM}_{l' lam'}(pi2^, q'^) at the
+    canonical geometry, from scipy's spherical harmonics and the test-side
+    Clebsch-Gordan coefficients."""
+    s = math.sqrt((1.0 - x) * (1.0 + x))
+    qv = np.array([[qq * s, 0.0, qq * x]]); q2v = np.array([[0.0, 0.0, q2]])
+    pi1 = q2v + 0.5 * qv; pi2 = -(qv + 0.5 * q2v)
+    acc = 0.0
+    for M in range(-L, L + 1):
+        acc += (np.conj(_bip(L, M, ca[0], ca[1], pi1, qv)) * _bip(L, M, cb[0], cb[1], pi2, q2v))[0]
+    return 16.0 * math.pi ** 2 / (2 * L + 1) * acc.real
+
+
+def test_geom_G_five_channels_vs_scipy_harmonics():
+    """G for every pair of the five L = 2+ channels (l, lam up to 4) against
+    an evaluation of its bipolar-harmonic definition with scipy's spherical
+    harmonics, which shares nothing with the oracle's Legendre recursion."""
+    for (qq, q2, x) in _nodes(7, 6):
+        for ca in FIVE_CH:
+            for cb in FIVE_CH:
+                g = W.geom_G(2, ca, cb, qq, q2, x)
+                ref = _G_scipy(2, ca, cb, qq, q2, x)
+                assert abs(g - ref) <= 1e-11 * max(1.0, abs(ref)), (ca, cb, qq, q2, x, g, ref)

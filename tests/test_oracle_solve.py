@@ -7,6 +7,15 @@
   on the single open channel), which ties the resolvent's imaginary part to
   the amplitude normalisation of Sec. III.B;
 * above breakup the elastic inelasticity eta = |S| stays <= 1;
+* the breakup pseudostate elements S_k0 (same column of U, Sec. III.B): for a
+  real symmetric operator in place of P V1 the open-channel S-matrix of the
+  discrete equation is exactly unitary (K-matrix argument below), so
+  |S_00|^2 + sum_k |S_k0|^2 = 1 holds to rounding -- which fails for a wrong
+  flux factor rho_k, a wrong on-shell bin j_k or a wrong (channel, k, j)
+  index of the breakup element;
+* the converged elastic S-matrix below breakup approaches the textbook
+  separable-potential solution as the grid is refined (on-shell momentum
+  kept at the same relative place in its bin);
 * the three-body bound state of the homogeneous equation converges, as the
   grid is refined, to the textbook Nystrom solution of the separable
   three-boson equation with the same cutoffs (separable_ref.py), which shares
@@ -116,3 +125,74 @@ def test_pair_threshold_matches_separable_reference():
     errs = [e - ref.eb for e in e0]
     assert errs[0] > errs[1] > errs[2] > 0
     assert errs[2] < 1e-2 * abs(ref.eb) and errs[2] < 0.4 * errs[1]
+
+
+def _open_channel_unitarity(sysm, E, seed):
+    """Solve (1 - A G1) u = A e0 with a random real symmetric A of the
+    system's size and the oracle's resolvent, then form the amplitudes with
+    the oracle's formulas.  With G1 = G_R + i sum_o g_o e_o e_o^T over the
+    open channels o (g_o = -pi rho_o) and K_R = (1 - A G_R)^-1 A (real and
+    symmetric when A is), the open block of u is K (1 - i g K)^-1 e0, so the
+    matrix S = 1 - 2 pi i rho^(1/2) U rho^(1/2) of the open channels is
+    (1 - i k)(1 + i k)^-1 with k = (-g)^(1/2) K (-g)^(1/2) real symmetric:
+    unitary.  Returns (|S_00|^2 + sum_k |S_k0|^2, amplitude)."""
+    rng = np.random.default_rng(seed)
+    M = sysm.M
+    R = rng.normal(size=(M, M))
+    A = 0.2 * (R + R.T) / math.sqrt(M)
+    G = W.resolvent(sysm, E).ravel()
+    idx = W.entrance(sysm, E)[3]
+    e0 = np.zeros(M)
+    e0[idx] = 1.0
+    u = np.linalg.solve(np.eye(M) - A * G[None, :], A @ e0)
+    a = W.amplitudes(sysm, E, u)
+    return abs(a.S) ** 2 + sum(abs(s) ** 2 for (_, _, _, s) in a.breakup), a
+
+
+@pytest.mark.parametrize("E", [0.3, 1.2, 2.5])
+def test_breakup_elements_exact_unitarity_symmetric_operator(E):
+    sysm = _yamaguchi_system(14)
+    total, a = _open_channel_unitarity(sysm, E, 11)
+    assert len(a.breakup) >= 2
+    assert abs(total - 1.0) < 1e-12, total
+    # flux really goes into the breakup elements
+    assert sum(abs(s) ** 2 for (_, _, _, s) in a.breakup) > 1e-3
+
+
+def test_breakup_elements_exact_unitarity_three_channels():
+    """The same with the three L = 2+ channels (entrance (l, lam) = (0, 2)):
+    the open pseudostates of all three channels enter the sum, so the
+    channel part of the breakup element's index is checked too."""
+    p = W.cheb_edges(8, 6.0)
+    q = W.cheb_edges(9, 6.0)
+    pot = W.Potential("yukawa", (-1.2, -1.2), YUK_RANGES)
+    sysm = W.build_system(p, q, 2, [(0, 2), (2, 0), (2, 2)], 4, 8, pot, with_p0=False)
+    for E in (0.4, 1.5):
+        total, a = _open_channel_unitarity(sysm, E, 5)
+        assert {c for (c, _, _, _) in a.breakup} == {0, 1, 2}
+        assert abs(total - 1.0) < 1e-12, (E, total)
+        assert sum(abs(s) ** 2 for (_, _, _, s) in a.breakup) > 1e-3
+
+
+@pytest.mark.parametrize("q_target", [0.15, 0.26, 0.32])
+def test_elastic_S_converges_to_separable_reference(q_target):
+    """Below breakup, with the on-shell momentum q0 at 30% of its bin for
+    each grid (so the on-shell bin's principal-value part is alike), the
+    wave-packet S-matrix approaches the Nystrom solution of the separable
+    three-boson equation at the same q0 (same cutoffs) as N = 40 -> 80 ->
+    120; phases are compared through S itself (no branch of arg)."""
+    ref = Separable(YAM_LAMBDA, YAM_BETA, 10.0, 10.0)
+    errs = []
+    for n in (40, 80, 120):
+        sysm = _yamaguchi_system(n)
+        p = sysm.q
+        j = int(np.searchsorted(p, q_target) - 1)
+        q0 = p[j] + 0.3 * (p[j + 1] - p[j])
+        E = sysm.eps[0][0] + 0.75 * q0 * q0
+        assert E < 0.0
+        u, _, res = W.solve_gmres(sysm, E)
+        assert res < 1e-12
+        a = W.amplitudes(sysm, E, u)
+        errs.append(abs(a.S - ref.elastic(ref.eb + 0.75 * q0 * q0)))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] < 0.07, errs
