@@ -35,42 +35,107 @@ __device__ __forceinline__ int first_true(int lo, int hi, F f) {
     return lo;
 }
 
-// Column range [lo, hi) of row cell (i, j) within column spectator bin j2.
-// Selection (a necessary condition for a nonzero element): the two cells'
-// energy ranges p^2 + 3/4 q^2 overlap, |q' + q/2| can fall in D_i, and
-// |q + q'/2| can fall in D_i'.
-__device__ __forceinline__ void col_range(const GridView &g, int i, int j, int j2, int &lo,
-                                          int &hi) {
-    lo = 0;
-    hi = 0;
-    // pi1 = |q' + q/2| over q in bin j, q' in bin j2
-    double d1 = 0.0, a;
-    a = g.q[j2] - g.H[j + 1];
-    if (a > d1) d1 = a;
-    a = g.H[j] - g.q[j2 + 1];
-    if (a > d1) d1 = a;
-    if (!(g.p[i + 1] > d1 && g.p[i] < g.q[j2 + 1] + g.H[j + 1])) return;
-    const double elo = g.P2[i] + g.Q34[j];
-    const double ehi = g.P2[i + 1] + g.Q34[j + 1];
-    const double q34lo = g.Q34[j2], q34hi = g.Q34[j2 + 1];
-    double d2 = 0.0;
-    a = g.q[j] - g.H[j2 + 1];
-    if (a > d2) d2 = a;
-    a = g.H[j2] - g.q[j + 1];
-    if (a > d2) d2 = a;
-    const double pmax2 = g.q[j + 1] + g.H[j2 + 1];
-    const int n = g.np;
-    // i2 >= first with  P2[i2+1] + Q34[j2+1] > elo
-    int la = first_true(0, n, [&](int k) { return g.P2[k + 1] + q34hi > elo; });
-    // i2 >= first with  p[i2+1] > d2
-    int lc = first_true(0, n, [&](int k) { return g.p[k + 1] > d2; });
-    // i2 <  first with  !(ehi > P2[i2] + Q34[j2])
-    int hb = first_true(0, n, [&](int k) { return !(ehi > g.P2[k] + q34lo); });
-    // i2 <  first with  !(p[i2] < pmax2)
-    int hd = first_true(0, n, [&](int k) { return !(g.p[k] < pmax2); });
-    lo = la > lc ? la : lc;
-    hi = hb < hd ? hb : hd;
-    if (hi < lo) hi = lo;
+// The same first index in [0, n) by binary lifting with a step count that
+// depends on n only (top = the largest power of two <= n, the same in every
+// lane), so the loop control stays scalar however the lanes' answers differ:
+// k grows by s whenever f(k + s - 1) is false, keeping f false below k.
+template <class F>
+__device__ __forceinline__ int first_true_lift(int n, int top, F f) {
+    int k = 0;
+    for (int s = top; s > 0; s >>= 1) {
+        const int t = k + s;
+        if (t <= n && !f(t - 1)) k = t;
+    }
+    return k;
+}
+
+__device__ __forceinline__ int pow2_floor(int n) { return n > 0 ? 1 << (31 - __clz(n)) : 0; }
+
+// First index k in [0, n) with f(k) true for a monotone predicate that is
+// the same in every lane (n if none): each step tests 64 points spread over
+// the current interval, one per lane, and a ballot keeps the sub-interval
+// holding the first true one (two steps for n <= 4096).
+template <class F>
+__device__ __forceinline__ int first_true_wave(int n, F f) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n;   // answer in [lo, hi]; points >= hi count as true
+    while (hi > lo) {
+        const int step = (hi - lo + 63) >> 6;
+        const int k = lo + lane * step;          // tested point of this lane
+        const bool t = k >= hi || f(k);
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(t);
+        // lane c = the first true point; the answer is in (point c - 1,
+        // point c] (none true: beyond lane 63's point)
+        const int c = m ? (int)__builtin_ctzll(m) : 64;
+        const int nlo = c == 0 ? lo : lo + (c - 1) * step + 1;
+        const int nhi = c == 64 ? hi : min(lo + c * step, hi);
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+// Row cell (i, j): |q' + q/2| over q in bin j and q' in bin j2 reaches D_i
+// when p[i+1] > max(0, q[j2] - H[j+1], H[j] - q[j2+1]) and
+// p[i] < q[j2+1] + H[j+1].  Each of the three comparisons is monotone in j2,
+// so the column spectator bins that pass form one interval [J0, J1).  (On
+// the Chebyshev grids about a fifth of all j2 pass, and every passing j2 but
+// a few holds a selected cell.)
+__device__ __forceinline__ void row_bins(const GridView &g, int i, int j, int &J0, int &J1) {
+    const double pi1 = g.p[i + 1], pi0 = g.p[i], hj = g.H[j], hj1 = g.H[j + 1];
+    const int n = g.nq;
+    J1 = first_true_wave(n, [&](int k) { return !(pi1 > g.q[k] - hj1); });
+    const int b2 = first_true_wave(n, [&](int k) { return pi1 > hj - g.q[k + 1]; });
+    const int b3 = first_true_wave(n, [&](int k) { return pi0 < g.q[k + 1] + hj1; });
+    J0 = b2 > b3 ? b2 : b3;
+    if (J1 < J0) J1 = J0;
+}
+
+// Column range [lo, hi) of row cell (i, j) in a passing column spectator bin
+// j2: the intersection of four monotone conditions on i2,
+//   la: first i2 with  P2[i2+1] + Q34[j2+1] >  P2[i] + Q34[j]  (energy ranges)
+//   hb: first i2 with !(P2[i+1] + Q34[j+1] >  P2[i2] + Q34[j2])
+//   lc: first i2 with  p[i2+1] > max(0, q[j] - H[j2+1], H[j2] - q[j+1])
+//                                              (|q + q'/2| can reach D_i2)
+//   hd: first i2 with !(p[i2] < q[j+1] + H[j2+1])
+// Two lanes share a j2: the even one finds la and lc (the lower end), the
+// odd one hb and hd (the upper end), both with the same instructions: the
+// energy search is "first k with P2[k + o] + a > b" (even: o = 1, strict;
+// odd: o = 0, b = the row's upper energy, "!(b > x)" read as x >= b) and the
+// pi2 search "first k with p[k + o] > b" (or >= b) likewise.  col_pair
+// returns [lo, hi) in the even lane (hi == lo in the odd one).  Every
+// comparison is the same IEEE expression as in the predicate above, so the
+// selected set is the same bit for bit.
+__device__ __forceinline__ void col_pair(const GridView &g, int i, int j, int j2, bool on,
+                                         int &lo, int &hi) {
+    const bool upper = threadIdx.x & 1;
+    int e1 = 0, e2 = 0;
+    if (on) {
+        double a, d2 = 0.0;
+        a = g.q[j] - g.H[j2 + 1];
+        if (a > d2) d2 = a;
+        a = g.H[j2] - g.q[j + 1];
+        if (a > d2) d2 = a;
+        const double pmax2 = g.q[j + 1] + g.H[j2 + 1];
+        const int o = upper ? 0 : 1;
+        const double ea = upper ? g.Q34[j2] : g.Q34[j2 + 1];
+        const double eb = upper ? g.P2[i + 1] + g.Q34[j + 1] : g.P2[i] + g.Q34[j];
+        const double pb = upper ? pmax2 : d2;
+        const int n = g.np, top = pow2_floor(n);
+        const double *P2o = g.P2 + o, *po = g.p + o;
+        e1 = first_true_lift(n, top, [&](int k) {
+            const double x = P2o[k] + ea;
+            return upper ? x >= eb : x > eb;
+        });
+        e2 = first_true_lift(n, top, [&](int k) {
+            const double x = po[k];
+            return upper ? x >= pb : x > pb;
+        });
+    }
+    const int v = upper ? (e1 < e2 ? e1 : e2) : (e1 > e2 ? e1 : e2);   // hi or lo
+    const int w = __shfl_xor(v, 1, 64);
+    lo = upper ? 0 : v;
+    hi = upper ? 0 : (w > v ? w : v);
 }
 
 // Grid tables staged in LDS (p, P2: np + 1; q, Q34, H: nq + 1 doubles).
@@ -98,52 +163,66 @@ __device__ __forceinline__ GridView stage_grid(const GridView &g, double *sm) {
     return l;
 }
 
-// One wavefront per row cell (rows strided over the grid); lanes sweep the
-// column spectator bins.  cnt[row] = selected cells of the row; ranges[row]
-// [j2] = lo | hi << 16 (the column range of bin j2, n_p < 2^16).
-__global__ __launch_bounds__(256) void k_count(GridView g0, int32_t *__restrict__ cnt,
-                                               uint32_t *__restrict__ ranges) {
+__device__ __forceinline__ int wave_isum(int v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// cnt[row] = selected cells of the row.  One wavefront per row cell (cell
+// index j np + i), lanes over the row's passing column spectator bins.  No
+// barrier after the table staging, so wavefronts past the last row may
+// leave early.
+__global__ __launch_bounds__(256) void k_count(GridView g0, int32_t *__restrict__ cnt) {
     extern __shared__ double sgrid[];
     const GridView g = stage_grid(g0, sgrid);
     const int lane = threadIdx.x & 63;
     const int nrow = g.np * g.nq;
-    for (int row = blockIdx.x * 4 + (threadIdx.x >> 6); row < nrow; row += gridDim.x * 4) {
-        const int i = row % g.np, j = row / g.np;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int row = blockIdx.x * 4 + wv; row < nrow; row += gridDim.x * 4) {
+        const int j = row / g.np, i = row - j * g.np;
+        int J0, J1;
+        row_bins(g, i, j, J0, J1);
         int c = 0;
-        for (int j2 = lane; j2 < g.nq; j2 += 64) {
+        for (int jc = J0; jc < J1; jc += 32) {
+            const int j2 = jc + (lane >> 1);
             int lo, hi;
-            col_range(g, i, j, j2, lo, hi);
+            col_pair(g, i, j, j2, j2 < J1, lo, hi);
             c += hi - lo;
-            ranges[(int64_t)row * g.nq + j2] = (uint32_t)lo | ((uint32_t)hi << 16);
         }
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+        c = wave_isum(c);
         if (lane == 0) cnt[row] = c;
     }
 }
 
-// Exclusive prefix sum of cnt[0..n) into row_ptr[0..n] for n <= 32768, one
-// workgroup with the counts in LDS: each thread sums a contiguous segment,
-// the 1024 segment sums are scanned, then row_ptr is written coalesced from
-// segment bases and in-segment offsets.
-__global__ __launch_bounds__(1024) void k_scan_lds(const int32_t *__restrict__ cnt, int n,
-                                                   int64_t *__restrict__ row_ptr) {
-    __shared__ int32_t sc[32768];
-    __shared__ int64_t base[1024];
-    const int tid = threadIdx.x;
-    for (int k = tid; k < n; k += 1024) sc[k] = cnt[k];
+// Prefix sums of cnt[0..n) per tile of 16384 rows, one workgroup of 1024
+// threads per tile: row_ptr[k] = exclusive sum within k's tile, tsum[t] =
+// the tile's total (the fill kernel adds the sums of the earlier tiles).
+// Each thread sums 16 consecutive counts (stored with one pad word per 16 so
+// the 64 lanes of a wavefront hit distinct banks); the 1024 segment sums are
+// scanned by shuffles and across the 16 wavefronts; row_ptr is written
+// coalesced.
+constexpr int kScanTile = 16384, kScanSeg = 16;
+
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int n,
+                                               int64_t *__restrict__ row_ptr,
+                                               int64_t *__restrict__ tsum) {
+    __shared__ int32_t sc[kScanTile + kScanTile / kScanSeg];
+    __shared__ int64_t wtot[16];
+    __shared__ int64_t segbase[1024];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    auto pos = [](int k) { return k + k / kScanSeg; };
+    const int t0 = blockIdx.x * kScanTile;
+    const int m = min(kScanTile, n - t0);
+    for (int k = tid; k < kScanTile; k += 1024) sc[pos(k)] = k < m ? cnt[t0 + k] : 0;
     __syncthreads();
-    const int per = (n + 1023) / 1024;
-    const int beg = min(tid * per, n), end = min(beg + per, n);
     int32_t run = 0;
-    for (int k = beg; k < end; ++k) {
-        const int32_t v = sc[k];
-        sc[k] = run;   // offset within the segment (< 2^31: per * 2^20 cells)
+    const int b = tid * kScanSeg;
+#pragma unroll
+    for (int k = 0; k < kScanSeg; ++k) {
+        const int32_t v = sc[pos(b + k)];
+        sc[pos(b + k)] = run;   // offset within the segment
         run += v;
     }
-    // inclusive scan of the 1024 segment sums: within each wavefront by
-    // shuffles, then across the 16 wavefront totals
-    __shared__ int64_t wtot[16];
-    const int lane = tid & 63, wv = tid >> 6;
     int64_t incl = run;
     for (int off = 1; off < 64; off <<= 1) {
         const int64_t v = __shfl_up(incl, off, 64);
@@ -151,105 +230,124 @@ __global__ __launch_bounds__(1024) void k_scan_lds(const int32_t *__restrict__ c
     }
     if (lane == 63) wtot[wv] = incl;
     __syncthreads();
-    if (wv == 0) {
-        int64_t t = lane < 16 ? wtot[lane] : 0;
-        for (int off = 1; off < 16; off <<= 1) {
-            const int64_t v = __shfl_up(t, off, 64);
-            if (lane >= off) t += v;
-        }
-        if (lane < 16) wtot[lane] = t;
+    int64_t wbase = 0, ttot = 0;
+    for (int w = 0; w < 16; ++w) {
+        const int64_t x = wtot[w];
+        if (w < wv) wbase += x;
+        ttot += x;
     }
+    segbase[tid] = wbase + incl - run;
     __syncthreads();
-    base[tid] = incl + (wv ? wtot[wv - 1] : 0);
-    __syncthreads();
-    // base[t] is now the inclusive sum of segments 0..t
-    for (int k = tid; k < n; k += 1024) {
-        const int sgm = k / per;
-        row_ptr[k] = (sgm ? base[sgm - 1] : 0) + sc[k];
-    }
-    if (tid == 0) row_ptr[n] = base[1023];
+    for (int k = tid; k < m; k += 1024) row_ptr[t0 + k] = segbase[k / kScanSeg] + sc[pos(k)];
+    if (tid == 0) tsum[blockIdx.x] = ttot;
 }
 
-// Exclusive prefix sum of cnt[0..n) into row_ptr[0..n], one workgroup.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int n,
-                                               int64_t *__restrict__ row_ptr) {
-    __shared__ int64_t part[1024];
-    const int tid = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int beg = tid * per;
-    const int end = min(beg + per, n);
-    int64_t s = 0;
-    for (int k = beg; k < end; ++k) s += cnt[k];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int64_t v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int64_t run = tid ? part[tid - 1] : 0;
-    for (int k = beg; k < end; ++k) {
-        row_ptr[k] = run;
-        run += cnt[k];
-    }
-    if (tid == 1023) row_ptr[n] = part[1023];
-}
-
-// One wavefront per row cell (rows strided over the grid, the same number
-// of passes for every wavefront): the column ranges from k_count ->
-// coalesced column writes in ascending order (column index c = j2*np + i2).
-__global__ __launch_bounds__(256) void k_fill(int np, int nq, const uint32_t *__restrict__ ranges,
-                                              const int64_t *__restrict__ row_ptr,
+// Column indices c = j2 np + i2 of every row, ascending, from the same
+// ranges as k_count (recomputed).  One wavefront per row: the row's start is
+// its in-tile offset from k_scan plus the totals of the earlier tiles,
+// written back as the final row_ptr[row] (and row_ptr[nrow] by the last
+// row).  Each lane writes its own range's columns one after another (the
+// lanes' runs are adjacent, so a store instruction covers a few consecutive
+// cache lines).  Row lookup tables for the element kernels: hint[e / 64] =
+// the row of nonzero e for every e divisible by 64, and rstart[e] = 1 where
+// nonzero e is the first of its row (2 if the row before it is empty), else
+// 0; the row of any e is then hint[e / 64] plus the row starts after e's
+// block start up to e.
+__global__ __launch_bounds__(256) void k_fill(GridView g0, const int32_t *__restrict__ cnt,
+                                              const int64_t *__restrict__ tsum,
+                                              int64_t *__restrict__ row_ptr,
                                               int32_t *__restrict__ col,
-                                              int32_t *__restrict__ rowidx) {
-    __shared__ int s_off[4][65];
-    __shared__ int s_lo[4][64];
+                                              int32_t *__restrict__ hint,
+                                              uint8_t *__restrict__ rstart) {
+    extern __shared__ double sgrid[];
+    const GridView g = stage_grid(g0, sgrid);
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int nrow = np * nq;
-    const int stride = gridDim.x * 4;
-    const int passes = (nrow + stride - 1) / stride;
-    for (int ps = 0; ps < passes; ++ps) {
-        const int row = ps * stride + blockIdx.x * 4 + w;
-        const bool valid = row < nrow;
-        int64_t base = valid ? row_ptr[row] : 0;
-        for (int j0 = 0; j0 < nq; j0 += 64) {
-            const int j2 = j0 + lane;
-            int lo = 0, c = 0;
-            if (valid && j2 < nq) {
-                const uint32_t rg = ranges[(int64_t)row * nq + j2];
-                lo = (int)(rg & 0xffffu);
-                c = (int)(rg >> 16) - lo;
-            }
-            // inclusive scan across the wavefront
-            int incl = c;
+    const int nrow = g.np * g.nq;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int row = blockIdx.x * 4 + wv; row < nrow; row += gridDim.x * 4) {
+        const int j = row / g.np, i = row - j * g.np;
+        // sum of the earlier tiles' totals (at most 64 tiles)
+        const int tile = row / kScanTile;
+        int64_t tb = lane < tile ? tsum[lane] : 0;
+        for (int off = 32; off > 0; off >>= 1) tb += __shfl_xor(tb, off, 64);
+        const int64_t first = row_ptr[row] + tb;
+        if (lane == 0) row_ptr[row] = first;
+        // row-start mark of the row's first nonzero: 2 after an empty row
+        const uint8_t mark = (row > 0 && cnt[row - 1] == 0) ? 2 : 1;
+        int64_t base = first;
+        int J0, J1;
+        row_bins(g, i, j, J0, J1);
+        for (int jc = J0; jc < J1; jc += 32) {
+            const int j2 = jc + (lane >> 1);
+            int lo, hi;
+            col_pair(g, i, j, j2, j2 < J1, lo, hi);
+            const int cn = hi - lo;
+            int incl = cn;
             for (int off = 1; off < 64; off <<= 1) {
-                int v = __shfl_up(incl, off, 64);
+                const int v = __shfl_up(incl, off, 64);
                 if (lane >= off) incl += v;
             }
-            s_off[w][lane + 1] = incl;
-            if (lane == 0) s_off[w][0] = 0;
-            s_lo[w][lane] = lo;
-            __syncthreads();
-            const int total = s_off[w][64];
-            for (int t = lane; t < total; t += 64) {
-                // owner lane: last k with s_off[k] <= t
-                int a = 0, b = 63;
-                while (a < b) {
-                    int m = (a + b + 1) >> 1;
-                    if (s_off[w][m] <= t) a = m;
-                    else b = m - 1;
-                }
-                int i2 = s_lo[w][a] + (t - s_off[w][a]);
-                col[base + t] = (j0 + a) * np + i2;
-                rowidx[base + t] = row;
+            int64_t pos = base + (incl - cn);
+            for (int i2 = lo; i2 < hi; ++i2, ++pos) {
+                col[pos] = j2 * g.np + i2;
+                rstart[pos] = pos == first ? mark : 0;
+                if ((pos & 63) == 0) hint[pos >> 6] = row;
             }
-            base += total;
-            __syncthreads();
+            base += __shfl(incl, 63, 64);
         }
+        if (row == nrow - 1 && lane == 0) row_ptr[nrow] = base;
     }
 }
+
+// Row r of nonzero e (row_ptr[r] <= e < row_ptr[r + 1]; e is the same in
+// every lane and e < row_ptr[nrow]), by a 64-way search over row_ptr: each
+// step compares 64 boundaries spread evenly over the current row interval
+// with e (a ballot; row_ptr is nondecreasing, so the true lanes are a
+// prefix) and keeps the sub-interval that brackets e.  Three steps up to
+// 262144 rows, four up to 2^24.
+__device__ __forceinline__ int row_of(const int64_t *__restrict__ row_ptr, int nrow, int64_t e) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = nrow;   // row_ptr[lo] <= e < row_ptr[hi]
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) >> 6;
+        const int b = lo + (lane + 1) * step;
+        const bool le = b < hi && row_ptr[b] <= e;
+        const int cnt = (int)__popcll(__builtin_amdgcn_ballot_w64(le));
+        lo += cnt * step;
+        hi = min(hi, lo + step);
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Rows of nonzeros in the 64-nonzero block of e (wave-uniform e <
+// row_ptr[nrow]): the block's first row from hint, and a ballot of the
+// rstart marks of the block's 64 nonzeros (one byte per lane, the same load
+// for every lane).  A row is the first row plus the row starts after the
+// block start up to e.  A mark of 2 (an empty row skipped) makes exact()
+// false up to that point; the caller then searches row_ptr.
+struct BlockRows {
+    int r0;
+    int64_t b0;
+    unsigned long long starts, gaps;
+    __device__ __forceinline__ void start(const int32_t *hint, const uint8_t *rstart, int64_t nnz,
+                                          int64_t e) {
+        const int64_t m = e >> 6;
+        b0 = m << 6;
+        r0 = __builtin_amdgcn_readfirstlane(hint[m]);
+        const int64_t pos = b0 + (threadIdx.x & 63);
+        const int v = pos < nnz ? rstart[pos] : 0;
+        starts = __builtin_amdgcn_ballot_w64(v != 0) & ~1ull;
+        gaps = __builtin_amdgcn_ballot_w64(v > 1) & ~1ull;
+    }
+    // nonzeros b0 .. e of the block
+    __device__ __forceinline__ unsigned long long upto(int64_t e) const {
+        return ~0ull >> (63 - (int)(e - b0));
+    }
+    __device__ __forceinline__ bool exact(int64_t e) const { return (gaps & upto(e)) == 0; }
+    __device__ __forceinline__ int row(int64_t e) const {
+        return r0 + (int)__popcll(starts & upto(e));
+    }
+};
 
 // The element quadrature below may contract into FMAs.
 #pragma clang fp contract(fast)
@@ -271,6 +369,9 @@ struct ElemTables {
     const float *uxf, *wxf;
     int np, ngq, ngx;
     uint32_t np_magic;     // ceil(2^32 / np): r / np = umulhi(r, np_magic) for r < 2^20
+    int nrow;              // cells n_p n_q (rows of row_ptr)
+    const int32_t *hint;   // hint[e / 64]: row of nonzero e, e divisible by 64
+    const uint8_t *rstart; // rstart[e]: nonzero e starts its row (1; 2 after an empty row)
 };
 
 // (i, j) of a cell index r = j np + i (r < 2^20, np <= 1024): the quotient
@@ -375,7 +476,7 @@ __device__ __forceinline__ bool cell_limits(const ElemTables &T, int i2, const Q
 }
 
 __global__ __launch_bounds__(256) void k_p0_swave_f64(ElemTables T,
-                                                      const int32_t *__restrict__ rowidx,
+                                                      const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col, int64_t nnz,
                                                       double *__restrict__ val) {
     const int lane = threadIdx.x & 63;
@@ -383,7 +484,9 @@ __global__ __launch_bounds__(256) void k_p0_swave_f64(ElemTables T,
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const int npair = T.ngq * T.ngq;
     for (int64_t e = wave0; e < nnz; e += nwaves) {
-        const int r = rowidx[e], c = col[e];
+        BlockRows br{};
+        br.start(T.hint, T.rstart, nnz, e);
+        const int r = br.exact(e) ? br.row(e) : row_of(row_ptr, T.nrow, e), c = col[e];
         const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
         double acc = 0.0;
         for (int pr = lane; pr < npair; pr += 64) {
@@ -406,7 +509,7 @@ __global__ __launch_bounds__(256) void k_p0_swave_f64(ElemTables T,
 }
 
 __global__ __launch_bounds__(256) void k_p0_swave_f32(ElemTables T,
-                                                      const int32_t *__restrict__ rowidx,
+                                                      const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col, int64_t nnz,
                                                       float *__restrict__ val) {
     const int lane = threadIdx.x & 63;
@@ -414,7 +517,9 @@ __global__ __launch_bounds__(256) void k_p0_swave_f32(ElemTables T,
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const int npair = T.ngq * T.ngq;
     for (int64_t e = wave0; e < nnz; e += nwaves) {
-        const int r = rowidx[e], c = col[e];
+        BlockRows br{};
+        br.start(T.hint, T.rstart, nnz, e);
+        const int r = br.exact(e) ? br.row(e) : row_of(row_ptr, T.nrow, e), c = col[e];
         const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
         Comp32 acc;
         for (int pr = lane; pr < npair; pr += 64) {
@@ -590,7 +695,7 @@ __device__ __forceinline__ double wave_sums(double (*red)[64], int lane) {
 
 template <bool F32, int NGX, int EC>
 __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
-                                                    const int32_t *__restrict__ rowidx,
+                                                    const int64_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col, int64_t nnz,
                                                     double *__restrict__ val64,
                                                     float *__restrict__ val32) {
@@ -618,6 +723,23 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
         // (d_i d_i2 dq_j dq_j2)^(-1/2) is folded into the Gauss weight the
         // same way (wq: Gauss pair and spectator bins, wr: times the row bin).
         int pj = -1, pj2 = -1, pi = -1;
+        // rows of the round: the first by a search over row_ptr, the others
+        // by a ballot over the next 64 row boundaries (a new search only if
+        // the round crosses all of them)
+        const int64_t e0 = chunk * kEC;
+        int rows[kEC];
+        if (nrem > 0) {
+            // a round never crosses a 64-nonzero block (kEC divides 64)
+            BlockRows br{};
+            br.start(T.hint, T.rstart, nnz, e0);
+            if (br.exact(e0 + nrem - 1)) {
+#pragma unroll
+                for (int k = 0; k < kEC; ++k) rows[k] = br.row(e0 + k);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kEC; ++k) rows[k] = row_of(row_ptr, T.nrow, e0 + k);
+            }
+        }
         QLim QL{};
         RowLim RL{};
         double wq = 0.0, wr = 0.0;
@@ -626,9 +748,9 @@ __global__ __launch_bounds__(256) void k_p0_swave_c(ElemTables T, NodeTab N,
             unsigned long long m = 0;
             if (k < nrem) {
                 // the cell pair is the same for the whole wavefront
-                const int64_t e = chunk * kEC + k;
+                const int64_t e = e0 + k;
                 int i, j, i2, j2;
-                cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
+                cell_ij(T, (uint32_t)rows[k], i, j);
                 cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
                 if (j != pj || j2 != pj2) {
                     // uniform bases (scalar registers) plus the lane's node offset
@@ -796,7 +918,7 @@ __device__ __forceinline__ void mc_lane_fast(const McTab &Mt, const double *__re
 template <int NP, int DEG>
 __global__ __launch_bounds__(256) void k_p0_mc(ElemTables T, NodeTab N, McTab Mt,
                                                const double *__restrict__ coef,
-                                               const int32_t *__restrict__ rowidx,
+                                               const int64_t *__restrict__ row_ptr,
                                                const int32_t *__restrict__ col, int64_t nnz,
                                                double *__restrict__ val64, float *__restrict__ val32) {
     __shared__ double red[4][NP][64];
@@ -805,7 +927,9 @@ __global__ __launch_bounds__(256) void k_p0_mc(ElemTables T, NodeTab N, McTab Mt
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const int npair_q = T.ngq * T.ngq;
     for (int64_t e = wave0; e < nnz; e += nwaves) {
-        const int r = rowidx[e], c = col[e];
+        BlockRows br{};
+        br.start(T.hint, T.rstart, nnz, e);
+        const int r = br.exact(e) ? br.row(e) : row_of(row_ptr, T.nrow, e), c = col[e];
         const int i = r % T.np, j = r / T.np, i2 = c % T.np, j2 = c / T.np;
         double tot[NP];
 #pragma unroll
@@ -857,7 +981,7 @@ __device__ __forceinline__ double rsqrt_n(double x) {
 template <int NP, int HMAX, int DEG, int NGX, bool F32OUT>
 __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab Mt,
                                                 const double *__restrict__ coef,
-                                                const int32_t *__restrict__ rowidx,
+                                                const int64_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, int64_t nnz,
                                                 double *__restrict__ val64,
                                                 float *__restrict__ val32) {
@@ -869,7 +993,9 @@ __global__ __launch_bounds__(256) void k_p0_mcm(ElemTables T, NodeTab N, McTab M
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t e = wave0; e < nnz; e += nwaves) {
         int i, j, i2, j2;
-        cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
+        BlockRows br{};
+        br.start(T.hint, T.rstart, nnz, e);
+        cell_ij(T, (uint32_t)(br.exact(e) ? br.row(e) : row_of(row_ptr, T.nrow, e)), i, j);
         cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
         const double q = T.qnode[j * 8 + a], q2 = T.qnode[j2 * 8 + b];
         double lo_t, lo_u, h;
@@ -980,7 +1106,7 @@ __device__ __forceinline__ double dir_cos(double vx, double vz) {
 __global__ __launch_bounds__(64) void k_p0_mc_direct(ElemTables T, NodeTab N,
                                                      const McTerm *__restrict__ terms,
                                                      const int *__restrict__ first, int NP,
-                                                     const int32_t *__restrict__ rowidx,
+                                                     const int64_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, int64_t nnz,
                                                      double *__restrict__ val64,
                                                      float *__restrict__ val32) {
@@ -990,7 +1116,9 @@ __global__ __launch_bounds__(64) void k_p0_mc_direct(ElemTables T, NodeTab N,
     const int npair_q = T.ngq * T.ngq;
     for (int64_t e = blockIdx.x; e < nnz; e += gridDim.x) {
         int i, j, i2, j2;
-        cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(rowidx[e]), i, j);
+        BlockRows br{};
+        br.start(T.hint, T.rstart, nnz, e);
+        cell_ij(T, (uint32_t)(br.exact(e) ? br.row(e) : row_of(row_ptr, T.nrow, e)), i, j);
         cell_ij(T, (uint32_t)__builtin_amdgcn_readfirstlane(col[e]), i2, j2);
         const double nrm = (T.rsd_p[i] * T.rsd_p[i2]) * (T.rsd_q[j] * T.rsd_q[j2]);
         for (int p0 = 0; p0 < NP; p0 += PC) {
@@ -1051,44 +1179,59 @@ static GridView grid_view(wpcd_ctx *c) {
     return GridView{c->d_p.ptr, c->d_q.ptr, c->d_P2.ptr, c->d_Q34.ptr, c->d_H.ptr, c->np, c->nq};
 }
 
-void build_structure(wpcd_ctx *c) {
+static size_t grid_lds(const wpcd_ctx *c) {
+    return (size_t)(2 * (c->np + 1) + 3 * (c->nq + 1)) * sizeof(double);
+}
+
+// Grid of the row kernels: each workgroup stages the grid tables once and
+// takes rows with a stride.
+static int structure_blocks(const wpcd_ctx *c) { return std::min((c->np * c->nq + 3) / 4, 2048); }
+
+int scan_tiles(int nrow) { return (nrow + kScanTile - 1) / kScanTile; }
+
+int64_t structure_rows(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsum) {
     const int nrow = c->np * c->nq;
-    GridView g = grid_view(c);
-    c->d_cnt.reserve(nrow);
-    c->d_rowptr.reserve((size_t)nrow + 1);
-    c->d_ranges.reserve((size_t)nrow * c->nq);
-    const int blocks = std::min((nrow + 3) / 4, 2048);
-    const size_t lds = (size_t)(2 * (c->np + 1) + 3 * (c->nq + 1)) * sizeof(double);
+    const int nt = scan_tiles(nrow);
     {
         TimedLaunch tl(c->timer, c->stream, "preselect_count", WPCD_TIME_P0);
-        hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), lds, c->stream, g, c->d_cnt.ptr,
-                           c->d_ranges.ptr);
+        hipLaunchKernelGGL(k_count, dim3(structure_blocks(c)), dim3(256), grid_lds(c), c->stream,
+                           grid_view(c), cnt);
         WPCD_HIP(hipGetLastError());
     }
     {
         TimedLaunch tl(c->timer, c->stream, "preselect_scan", WPCD_TIME_P0);
-        if (nrow <= 32768)
-            hipLaunchKernelGGL(k_scan_lds, dim3(1), dim3(1024), 0, c->stream, c->d_cnt.ptr, nrow,
-                               c->d_rowptr.ptr);
-        else
-            hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, c->stream, c->d_cnt.ptr, nrow,
-                               c->d_rowptr.ptr);
+        hipLaunchKernelGGL(k_scan, dim3(nt), dim3(1024), 0, c->stream, cnt, nrow, row_ptr, tsum);
         WPCD_HIP(hipGetLastError());
     }
-    int64_t nnz = 0;
-    WPCD_HIP(hipMemcpyAsync(&nnz, c->d_rowptr.ptr + nrow, sizeof(int64_t), hipMemcpyDeviceToHost,
-                            c->stream));
+    int64_t ts[kMaxScanTiles];
+    WPCD_HIP(hipMemcpyAsync(ts, tsum, nt * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
     WPCD_HIP(hipStreamSynchronize(c->stream));
+    int64_t nnz = 0;
+    for (int t = 0; t < nt; ++t) nnz += ts[t];
     WPCD_REQUIRE(nnz >= 0 && nnz < ((int64_t)1 << 40), WPCD_E_DEVICE, "bad nonzero count");
+    return nnz;
+}
+
+void structure_fill(wpcd_ctx *c, const int32_t *cnt, const int64_t *tsum, int64_t *row_ptr,
+                    int32_t *col, int32_t *hint, uint8_t *rstart) {
+    TimedLaunch tl(c->timer, c->stream, "preselect_fill", WPCD_TIME_P0);
+    hipLaunchKernelGGL(k_fill, dim3(structure_blocks(c)), dim3(256), grid_lds(c), c->stream,
+                       grid_view(c), cnt, tsum, row_ptr, col, hint, rstart);
+    WPCD_HIP(hipGetLastError());
+}
+
+void build_structure(wpcd_ctx *c) {
+    const int nrow = c->np * c->nq;
+    c->d_cnt.reserve(nrow);
+    c->d_tsum.reserve(kMaxScanTiles);
+    c->d_rowptr.reserve((size_t)nrow + 1);
+    const int64_t nnz = structure_rows(c, c->d_cnt.ptr, c->d_rowptr.ptr, c->d_tsum.ptr);
     c->nnz = nnz;
     c->d_col.reserve(nnz);
-    c->d_rowidx.reserve(nnz);
-    {
-        TimedLaunch tl(c->timer, c->stream, "preselect_fill", WPCD_TIME_P0);
-        hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, c->stream, c->np, c->nq,
-                           c->d_ranges.ptr, c->d_rowptr.ptr, c->d_col.ptr, c->d_rowidx.ptr);
-        WPCD_HIP(hipGetLastError());
-    }
+    c->d_hint.reserve(hint_len(nnz));
+    c->d_rstart.reserve(nnz);
+    structure_fill(c, c->d_cnt.ptr, c->d_tsum.ptr, c->d_rowptr.ptr, c->d_col.ptr, c->d_hint.ptr,
+                   c->d_rstart.ptr);
 }
 
 // Microseconds per launch of f (one warm-up, then two timed launches).
@@ -1110,15 +1253,25 @@ static double time_launches_p0(hipStream_t s, F &&f) {
     return 1e3 * ms / 2;
 }
 
+// Where the elements are written: the structure and the value array (FP64
+// or FP32, one of them non-null).
+struct P0Dst {
+    const int64_t *row_ptr;
+    const int32_t *col;
+    int64_t nnz;
+    double *val64;
+    float *val32;
+};
+
 template <bool F32, int EC>
 static void launch_compacted_ec(wpcd_ctx *c, const ElemTables &T, const NodeTab &N,
-                                int64_t max_blocks) {
-    const int64_t nchunk = (c->nnz + EC - 1) / EC;
+                                const P0Dst &D, int64_t max_blocks) {
+    const int64_t nchunk = (D.nnz + EC - 1) / EC;
     const int64_t want = (nchunk + 3) / 4;
     const int blocks = (int)(want < max_blocks ? want : max_blocks);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, c->stream, T, N, c->d_rowidx.ptr,
-                           c->d_col.ptr, c->nnz, c->d_val64.ptr, c->d_val32.ptr);
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, c->stream, T, N, D.row_ptr, D.col,
+                           D.nnz, D.val64, D.val32);
     };
     switch (c->ngx) {
         case 16: go(k_p0_swave_c<F32, 16, EC>); break;
@@ -1143,21 +1296,26 @@ struct ElemVariant {
 constexpr ElemVariant kElemVariants[4] = {{4, 8192}, {8, 8192}, {4, 1 << 23}, {8, 1 << 23}};
 
 template <bool F32>
-static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N, int v) {
+static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N,
+                             const P0Dst &D, int v) {
     const ElemVariant ev = kElemVariants[v];
-    if (ev.ec == 8) launch_compacted_ec<F32, 8>(c, T, N, ev.max_blocks);
-    else launch_compacted_ec<F32, 4>(c, T, N, ev.max_blocks);
+    if (ev.ec == 8) launch_compacted_ec<F32, 8>(c, T, N, D, ev.max_blocks);
+    else launch_compacted_ec<F32, 4>(c, T, N, D, ev.max_blocks);
 }
 
-void build_values(wpcd_ctx *c, bool fp64) {
+// Element values of the structure (row_ptr, col) into val64 or val32.
+// measure: the launch shape of the s-wave kernel may be timed on first use
+// (otherwise a cached choice or the heuristic one is taken).
+void values_into(wpcd_ctx *c, bool fp64, const int64_t *row_ptr, const int32_t *col,
+                 const int32_t *hint, const uint8_t *rstart, int64_t nnz, double *val64,
+                 float *val32, bool measure) {
     ElemTables T{c->d_P2.ptr, c->d_rsd_p.ptr, c->d_rsd_q.ptr, c->d_qnode.ptr, c->d_qwt.ptr,
                  c->d_ux.ptr,  c->d_wx.ptr,    c->d_uxf.ptr,   c->d_wxf.ptr,   c->np,
                  c->ngq,       c->ngx,
-                 (uint32_t)(((1ull << 32) + (uint64_t)c->np - 1) / (uint64_t)c->np)};
-    const int64_t nnz = c->nnz;
+                 (uint32_t)(((1ull << 32) + (uint64_t)c->np - 1) / (uint64_t)c->np),
+                 c->np * c->nq, hint, rstart};
     const int NP = c->nch * c->nch;
-    if (fp64) c->d_val64.reserve(nnz * NP);
-    else c->d_val32.reserve(nnz * NP);
+    const P0Dst D{row_ptr, col, nnz, fp64 ? val64 : nullptr, fp64 ? nullptr : val32};
     if (nnz == 0) return;
     if (!c->swave) {
         NodeTab N{};
@@ -1171,11 +1329,11 @@ void build_values(wpcd_ctx *c, bool fp64) {
             for (int p = 0; p < NP; ++p) Mt.p[p] = c->mc_pairs[p];
         const int64_t want = (nnz + 3) / 4;
         const int blocks = (int)(want < 65536 ? want : 65536);
-        double *v64 = fp64 ? c->d_val64.ptr : nullptr;
-        float *v32 = fp64 ? nullptr : c->d_val32.ptr;
+        double *v64 = D.val64;
+        float *v32 = D.val32;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, c->stream, T, N, Mt,
-                               c->d_mcoef.ptr, c->d_rowidx.ptr, c->d_col.ptr, nnz, v64, v32);
+                               c->d_mcoef.ptr, row_ptr, col, nnz, v64, v32);
         };
         TimedLaunch tl(c->timer, c->stream, fp64 ? "p0_elem_mc_f64" : "p0_elem_mc_f32",
                        WPCD_TIME_P0);
@@ -1207,8 +1365,8 @@ void build_values(wpcd_ctx *c, bool fp64) {
         else {
             const int dblocks = (int)(nnz < 262144 ? nnz : 262144);
             hipLaunchKernelGGL(k_p0_mc_direct, dim3(dblocks), dim3(64), 0, c->stream, T, N,
-                               c->d_mterms.ptr, c->d_mterm_first.ptr, NP, c->d_rowidx.ptr,
-                               c->d_col.ptr, nnz, v64, v32);
+                               c->d_mterms.ptr, c->d_mterm_first.ptr, NP, row_ptr, col, nnz,
+                               v64, v32);
         }
         WPCD_HIP(hipGetLastError());
         return;
@@ -1226,16 +1384,16 @@ void build_values(wpcd_ctx *c, bool fp64) {
                       fp64 ? "f64" : "f32");
         const int v = tune_pick(c, "p0_elem", key, 4, 0, [&](int i) {
             return time_launches_p0(c->stream, [&] {
-                if (fp64) launch_compacted<false>(c, T, N, i);
-                else launch_compacted<true>(c, T, N, i);
+                if (fp64) launch_compacted<false>(c, T, N, D, i);
+                else launch_compacted<true>(c, T, N, D, i);
             });
-        });
+        }, measure);
         if (fp64) {
             TimedLaunch tl(c->timer, c->stream, "p0_elem_f64", WPCD_TIME_P0);
-            launch_compacted<false>(c, T, N, v);
+            launch_compacted<false>(c, T, N, D, v);
         } else {
             TimedLaunch tl(c->timer, c->stream, "p0_elem_f32", WPCD_TIME_P0);
-            launch_compacted<true>(c, T, N, v);
+            launch_compacted<true>(c, T, N, D, v);
         }
         WPCD_HIP(hipGetLastError());
         return;
@@ -1245,15 +1403,23 @@ void build_values(wpcd_ctx *c, bool fp64) {
     int blocks = (int)(want < 65536 ? want : 65536);
     if (fp64) {
         TimedLaunch tl(c->timer, c->stream, "p0_elem_f64", WPCD_TIME_P0);
-        hipLaunchKernelGGL(k_p0_swave_f64, dim3(blocks), dim3(256), 0, c->stream, T,
-                           c->d_rowidx.ptr, c->d_col.ptr, nnz, c->d_val64.ptr);
+        hipLaunchKernelGGL(k_p0_swave_f64, dim3(blocks), dim3(256), 0, c->stream, T, row_ptr, col,
+                           nnz, D.val64);
         WPCD_HIP(hipGetLastError());
     } else {
         TimedLaunch tl(c->timer, c->stream, "p0_elem_f32", WPCD_TIME_P0);
-        hipLaunchKernelGGL(k_p0_swave_f32, dim3(blocks), dim3(256), 0, c->stream, T,
-                           c->d_rowidx.ptr, c->d_col.ptr, nnz, c->d_val32.ptr);
+        hipLaunchKernelGGL(k_p0_swave_f32, dim3(blocks), dim3(256), 0, c->stream, T, row_ptr, col,
+                           nnz, D.val32);
         WPCD_HIP(hipGetLastError());
     }
+}
+
+void build_values(wpcd_ctx *c, bool fp64) {
+    const int64_t nv = c->nnz * c->nch * c->nch;
+    if (fp64) c->d_val64.reserve(nv);
+    else c->d_val32.reserve(nv);
+    values_into(c, fp64, c->d_rowptr.ptr, c->d_col.ptr, c->d_hint.ptr, c->d_rstart.ptr, c->nnz,
+                c->d_val64.ptr, c->d_val32.ptr, true);
 }
 
 }  // namespace wpcd

@@ -1172,7 +1172,7 @@ struct P0Header {
 P0Header p0_header(const wpcd_ctx *c) {
     P0Header h{};
     std::memcpy(h.magic, kP0Magic, 8);
-    h.version = 1;
+    h.version = 2;   // 2: no per-nonzero row array
     h.np = c->np;
     h.nq = c->nq;
     h.ngq = c->ngq;
@@ -1204,11 +1204,10 @@ wpcd_status wpcd_save_p(wpcd_ctx *c, const char *path) {
         const P0Header h = p0_header(c);
         const int64_t nrow = (int64_t)c->np * c->nq, nv = c->nnz * c->nch * c->nch;
         std::vector<int64_t> rp(nrow + 1);
-        std::vector<int32_t> col(c->nnz), ri(c->nnz);
+        std::vector<int32_t> col(c->nnz);
         std::vector<char> val(nv * (c->p_fp64 ? 8 : 4));
         WPCD_HIP(hipMemcpyAsync(rp.data(), c->d_rowptr.ptr, rp.size() * 8, hipMemcpyDeviceToHost, c->stream));
         WPCD_HIP(hipMemcpyAsync(col.data(), c->d_col.ptr, col.size() * 4, hipMemcpyDeviceToHost, c->stream));
-        WPCD_HIP(hipMemcpyAsync(ri.data(), c->d_rowidx.ptr, ri.size() * 4, hipMemcpyDeviceToHost, c->stream));
         WPCD_HIP(hipMemcpyAsync(val.data(), c->p_fp64 ? (void *)c->d_val64.ptr : (void *)c->d_val32.ptr,
                                 val.size(), hipMemcpyDeviceToHost, c->stream));
         WPCD_HIP(hipStreamSynchronize(c->stream));
@@ -1219,7 +1218,6 @@ wpcd_status wpcd_save_p(wpcd_ctx *c, const char *path) {
                   std::fwrite(c->q.data(), 8, c->q.size(), f.f) == c->q.size() &&
                   std::fwrite(rp.data(), 8, rp.size(), f.f) == rp.size() &&
                   std::fwrite(col.data(), 4, col.size(), f.f) == col.size() &&
-                  std::fwrite(ri.data(), 4, ri.size(), f.f) == ri.size() &&
                   std::fwrite(val.data(), 1, val.size(), f.f) == val.size();
         ok = (std::fclose(f.f) == 0) && ok;
         f.f = nullptr;
@@ -1235,7 +1233,7 @@ wpcd_status wpcd_load_p(wpcd_ctx *c, const char *path, int64_t *nnz_out) {
         WPCD_REQUIRE(f.f, WPCD_E_INVALID, std::string("cannot open: ") + path);
         P0Header h{};
         WPCD_REQUIRE(std::fread(&h, sizeof h, 1, f.f) == 1 && std::memcmp(h.magic, kP0Magic, 8) == 0 &&
-                         h.version == 1,
+                         h.version == 2,
                      WPCD_E_INVALID, "not a P0 file of this library");
         P0Header mine = p0_header(c);
         bool same = h.np == mine.np && h.nq == mine.nq && h.ngq == mine.ngq && h.ngx == mine.ngx &&
@@ -1249,26 +1247,34 @@ wpcd_status wpcd_load_p(wpcd_ctx *c, const char *path, int64_t *nnz_out) {
         WPCD_REQUIRE(h.nnz >= 0 && h.nnz < ((int64_t)1 << 40), WPCD_E_INVALID, "bad nonzero count");
         const int64_t nrow = (int64_t)c->np * c->nq, nv = h.nnz * c->nch * c->nch;
         std::vector<int64_t> rp(nrow + 1);
-        std::vector<int32_t> col(h.nnz), ri(h.nnz);
+        std::vector<int32_t> col(h.nnz);
         std::vector<char> val(nv * (h.fp64 ? 8 : 4));
         WPCD_REQUIRE(std::fread(rp.data(), 8, rp.size(), f.f) == rp.size() &&
                          std::fread(col.data(), 4, col.size(), f.f) == col.size() &&
-                         std::fread(ri.data(), 4, ri.size(), f.f) == ri.size() &&
                          std::fread(val.data(), 1, val.size(), f.f) == val.size(),
                      WPCD_E_INVALID, "P0 file is truncated");
         WPCD_REQUIRE(rp[0] == 0 && rp[nrow] == h.nnz, WPCD_E_INVALID, "P0 file: inconsistent row pointers");
         for (int64_t r = 0; r < nrow; ++r)
             WPCD_REQUIRE(rp[r] <= rp[r + 1], WPCD_E_INVALID, "P0 file: row pointers not monotone");
         for (int64_t k = 0; k < h.nnz; ++k)
-            WPCD_REQUIRE(col[k] >= 0 && col[k] < nrow && ri[k] >= 0 && ri[k] < nrow, WPCD_E_INVALID,
+            WPCD_REQUIRE(col[k] >= 0 && col[k] < nrow, WPCD_E_INVALID,
                          "P0 file: index out of range");
         c->has_p = false;
+        // row hints of the element kernels: the row of every 64th nonzero
+        std::vector<int32_t> hint(wpcd::hint_len(h.nnz), 0);
+        std::vector<uint8_t> rstart(h.nnz, 0);
+        for (int64_t r = 0; r < nrow; ++r) {
+            if (rp[r] < rp[r + 1]) rstart[rp[r]] = (r > 0 && rp[r - 1] == rp[r]) ? 2 : 1;
+            for (int64_t e = (rp[r] + 63) / 64 * 64; e < rp[r + 1]; e += 64) hint[e / 64] = (int32_t)r;
+        }
         c->d_rowptr.reserve(nrow + 1);
         c->d_col.reserve(h.nnz);
-        c->d_rowidx.reserve(h.nnz);
+        c->d_hint.reserve(hint.size());
+        c->d_rstart.reserve(h.nnz);
+        WPCD_HIP(hipMemcpyAsync(c->d_hint.ptr, hint.data(), hint.size() * 4, hipMemcpyHostToDevice, c->stream));
+        WPCD_HIP(hipMemcpyAsync(c->d_rstart.ptr, rstart.data(), rstart.size(), hipMemcpyHostToDevice, c->stream));
         WPCD_HIP(hipMemcpyAsync(c->d_rowptr.ptr, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, c->stream));
         WPCD_HIP(hipMemcpyAsync(c->d_col.ptr, col.data(), col.size() * 4, hipMemcpyHostToDevice, c->stream));
-        WPCD_HIP(hipMemcpyAsync(c->d_rowidx.ptr, ri.data(), ri.size() * 4, hipMemcpyHostToDevice, c->stream));
         if (h.fp64) {
             c->d_val64.reserve(nv);
             WPCD_HIP(hipMemcpyAsync(c->d_val64.ptr, val.data(), val.size(), hipMemcpyHostToDevice, c->stream));
@@ -1421,9 +1427,10 @@ void wpcd_destroy(wpcd_ctx *c) {
     }
     c->d_rowptr.release();
     c->d_col.release();
-    c->d_rowidx.release();
     c->d_cnt.release();
-    c->d_ranges.release();
+    c->d_hint.release();
+    c->d_rstart.release();
+    c->d_tsum.release();
     c->d_val64.release();
     c->d_val32.release();
     c->d_G.release();

@@ -232,8 +232,9 @@ struct wpcd_ctx {
     bool p_fp64 = false;
     int64_t nnz = 0;
     wpcd::DBuf<int64_t> d_rowptr;
-    wpcd::DBuf<int32_t> d_col, d_rowidx, d_cnt;
-    wpcd::DBuf<uint32_t> d_ranges;   // pre-selection column ranges [row][j2]
+    wpcd::DBuf<int32_t> d_col, d_cnt, d_hint;   // columns, row counts, row hints (one per 64 nonzeros)
+    wpcd::DBuf<int64_t> d_tsum;                  // pre-selection scan: per-tile totals
+    wpcd::DBuf<uint8_t> d_rstart;                // 1 where a nonzero starts its row
     wpcd::DBuf<double> d_val64;
     wpcd::DBuf<float> d_val32;
 
@@ -271,16 +272,33 @@ void launch_vt(wpcd_ctx *c, int wave);
 
 void build_structure(wpcd_ctx *c);   // a3: counts, scan, fill (sets c->nnz)
 void build_values(wpcd_ctx *c, bool fp64);
+// The same into given device buffers: row counts cnt[n_p n_q] and row_ptr
+// [n_p n_q + 1] (returns nnz), columns col[nnz], values val64 or val32
+// [nnz][n_ch][n_ch].
+// Row counts cnt[n_p n_q], row_ptr[n_p n_q + 1], per-tile totals
+// tsum[kMaxScanTiles]; returns nnz.  The fill then writes col[nnz], the
+// final row_ptr and the row lookup tables of the element kernels,
+// hint[hint_len(nnz)] and rstart[nnz].
+constexpr int kMaxScanTiles = 64;   // tiles of 16384 rows: n_p n_q <= 2^20
+inline int64_t hint_len(int64_t nnz) { return (nnz + 63) / 64 + 1; }
+int scan_tiles(int nrow);
+int64_t structure_rows(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsum);
+void structure_fill(wpcd_ctx *c, const int32_t *cnt, const int64_t *tsum, int64_t *row_ptr,
+                    int32_t *col, int32_t *hint, uint8_t *rstart);
+void values_into(wpcd_ctx *c, bool fp64, const int64_t *row_ptr, const int32_t *col,
+                 const int32_t *hint, const uint8_t *rstart, int64_t nnz, double *val64,
+                 float *val32, bool measure);
 
 // Pick candidate 0..n_cand-1 for (name, key): forced, cached, heuristic
 // (heur) or measured (measure(i) returns microseconds), by c->tune.mode.
 template <class Measure>
 int tune_pick(wpcd_ctx *c, const char *name, const std::string &key, int n_cand, int heur,
-              Measure &&measure) {
+              Measure &&measure, bool allow_measure = true) {
     Tuning &T = c->tune;
     if (T.mode >= WPCD_TUNE_FORCE) return std::min(T.mode - WPCD_TUNE_FORCE, n_cand - 1);
     for (const auto &e : T.entries)
         if (e.name == name && e.key == key) return e.choice;
+    if (!allow_measure) return heur;   // not recorded: a later call may still measure
     int best = heur;
     double best_us = 0.0;
     if (T.mode == WPCD_TUNE_MEASURE) {
