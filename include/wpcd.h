@@ -216,6 +216,36 @@ wpcd_status wpcd_pair_spectrum(wpcd_ctx *ctx, int32_t l, double *eps_out, double
  * Errors: WPCD_E_STATE, WPCD_E_NOMEM, WPCD_E_DEVICE.                      */
 wpcd_status wpcd_build_p(wpcd_ctx *ctx, wpcd_precision prec, int64_t *nnz_cells_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * P0 as wpcd_build_p (same kernels, same bits), written into the caller's
+ * device buffers, with no hipMalloc, hipFree or other allocation.
+ *   row_ptr  device int64[n_p*n_q + 1]          (written)
+ *   col      device int32[cap_nnz]               (first nnz written)
+ *   val      device float[cap_nnz*n_ch*n_ch] for WPCD_MIXED or
+ *            double[cap_nnz*n_ch*n_ch] for WPCD_FP64 (first nnz blocks written)
+ * *nnz_cells_out (may be NULL) receives the number of cell pairs once the
+ * pre-selection has counted them, also when cap_nnz is too small.  The
+ * context's own P0 (wpcd_build_p's) is neither used nor changed, so this
+ * does not enable wpcd_solve.  The intermediates (row counts, per-tile
+ * totals, row lookup tables of the element kernels) live in one fixed
+ * device array of WPCD_NOALLOC_SCRATCH_BYTES per GPU, taken at wpcd_create
+ * and held until the process ends; it needs 512 B + 4 n_p n_q B +
+ * 1.07 nnz B (about 21 MB for 300 x 300 bins with 19.2 million cell
+ * pairs).  Every call on one GPU, from any context or thread, shares that
+ * array: calls that overlap in time on one GPU race and must be
+ * serialised by the caller.  Nothing in the array needs to start at zero.
+ * Launch shapes are the cached or heuristic choices (no timing launches),
+ * and per-kernel timing is off during the call.  Returns when the values
+ * are written (the context's stream is synchronised).
+ * Errors: WPCD_E_STATE (no basis), WPCD_E_INVALID (NULL pointer, bad
+ * precision, nnz > cap_nnz, or the grid or nnz beyond the fixed scratch),
+ * WPCD_E_DEVICE.                                                        */
+#define WPCD_NOALLOC_SCRATCH_BYTES (32ll << 20)
+wpcd_status wpcd_build_p_noalloc(wpcd_ctx *ctx, wpcd_precision prec, int64_t *row_ptr,
+                                 int32_t *col, void *val, int64_t cap_nnz,
+                                 int64_t *nnz_cells_out);
+
 /* Copy P0 to caller buffers: row_ptr[n_p*n_q+1], col[nnz], val[nnz*n_ch*n_ch]
  * (FP64; FP32 values are widened).  Any pointer may be NULL to skip it.
  * Errors: WPCD_E_STATE (no P0).                                          */

@@ -43,7 +43,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_
                 5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE"}
 
 ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_set_potential", "wpcd_pair_spectrum",
-                 "wpcd_build_p", "wpcd_get_p", "wpcd_save_p", "wpcd_load_p", "wpcd_solve",
+                 "wpcd_build_p", "wpcd_build_p_noalloc", "wpcd_get_p", "wpcd_save_p",
+                 "wpcd_load_p", "wpcd_solve",
                  "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_bound_state",
                  "wpcd_set_multipliers",
                  "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_autotune",
@@ -140,6 +141,8 @@ def lib():
         L.wpcd_set_potential.argtypes = [vp, ctypes.POINTER(wpcd_potential_desc)]
         L.wpcd_pair_spectrum.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
         L.wpcd_build_p.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.wpcd_build_p_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64)]
         L.wpcd_get_p.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int32), dp]
         L.wpcd_solve.argtypes = [vp, dp, ctypes.c_int32, ctypes.c_int,
@@ -243,6 +246,17 @@ def wpcd_build_p(ctx, precision=WPCD_FP64):
     n = ctypes.c_int64()
     _check(ctx, lib().wpcd_build_p(ctx, precision, ctypes.byref(n)))
     return n.value
+
+
+def wpcd_build_p_noalloc(ctx, precision, row_ptr_dev, col_dev, val_dev, cap_nnz):
+    """P0 into caller device buffers (integer device addresses), no
+    allocation; returns (status, nnz) without raising, so a caller can
+    re-size on WPCD_E_INVALID with nnz set."""
+    n = ctypes.c_int64(-1)
+    st = lib().wpcd_build_p_noalloc(ctx, precision, ctypes.c_void_p(row_ptr_dev),
+                                    ctypes.c_void_p(col_dev), ctypes.c_void_p(val_dev),
+                                    cap_nnz, ctypes.byref(n))
+    return st, n.value
 
 
 def wpcd_get_p(ctx, n_cells, nnz, n_ch=1, values=True):

@@ -809,6 +809,40 @@ static void mlp_eval(wpcd_ctx *c, int nin, int nh, int nout, const float *params
 
 using namespace wpcd;
 
+// ---- fixed device scratch of wpcd_build_p_noalloc
+// The intermediates of that call (row counts, per-tile totals, row hints and
+// row-start marks of the element kernels) live in one file-scope device
+// array of WPCD_NOALLOC_SCRATCH_BYTES per device, so the call allocates
+// nothing.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is taken once per device with
+// hipGetSymbolAddress (in wpcd_create, with that device current) and only
+// that address is used.
+static __device__ __align__(256) unsigned char scratch[WPCD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device `dev` (looked
+// up once per device).  Returns a HIP error code.
+hipError_t scratch_setup(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    return hipSuccess;
+}
+
+unsigned char *scratch_of(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr;
+}
+}  // namespace
+
 template <class F>
 static wpcd_status guarded(wpcd_ctx *c, F &&f) {
     if (!c) return WPCD_E_INVALID;
@@ -840,7 +874,7 @@ wpcd_status wpcd_create(int device, void *hip_stream, wpcd_ctx **out) {
     wpcd_ctx *c = new (std::nothrow) wpcd_ctx();
     if (!c) return WPCD_E_NOMEM;
     c->device = device;
-    if (hipSetDevice(device) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || scratch_setup(device) != hipSuccess) {
         delete c;
         return WPCD_E_DEVICE;
     }
@@ -978,6 +1012,50 @@ wpcd_status wpcd_pair_spectrum(wpcd_ctx *c, int32_t l, double *eps_out, double *
                                     hipMemcpyDeviceToHost, c->stream));
         WPCD_HIP(hipStreamSynchronize(c->stream));
         if (scale_out) *scale_out = c->pot_scale;
+    });
+}
+
+wpcd_status wpcd_build_p_noalloc(wpcd_ctx *c, wpcd_precision prec, int64_t *row_ptr,
+                                 int32_t *col, void *val, int64_t cap_nnz, int64_t *nnz_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
+        WPCD_REQUIRE(row_ptr && col && val && cap_nnz >= 0, WPCD_E_INVALID,
+                     "row_ptr, col and val must be device pointers and cap_nnz >= 0");
+        unsigned char *base = scratch_of(c->device);
+        WPCD_REQUIRE(base, WPCD_E_STATE, "no scratch address for this device");
+        // scratch layout: per-tile totals | row counts | row hints | row starts
+        const int64_t nrow = (int64_t)c->np * c->nq;
+        const int64_t off_cnt = 256 * ((kMaxScanTiles * 8 + 255) / 256);
+        const int64_t off_hint = off_cnt + 256 * ((4 * nrow + 255) / 256);
+        WPCD_REQUIRE(off_hint <= WPCD_NOALLOC_SCRATCH_BYTES, WPCD_E_INVALID,
+                     "grid too large for the fixed scratch");
+        // timing events are not created here
+        const int timing = c->timer.enabled;
+        c->timer.enabled = 0;
+        struct Restore {
+            wpcd_ctx *c;
+            int t;
+            ~Restore() { c->timer.enabled = t; }
+        } restore{c, timing};
+        int32_t *cnt = reinterpret_cast<int32_t *>(base + off_cnt);
+        int64_t *tsum = reinterpret_cast<int64_t *>(base);
+        const int64_t nnz = structure_rows(c, cnt, row_ptr, tsum);
+        if (nnz_out) *nnz_out = nnz;
+        const int64_t off_rs = off_hint + 256 * ((4 * hint_len(nnz) + 255) / 256);
+        WPCD_REQUIRE(nnz <= cap_nnz, WPCD_E_INVALID,
+                     "P0 has " + std::to_string(nnz) + " nonzero cells, cap_nnz is " +
+                         std::to_string(cap_nnz));
+        WPCD_REQUIRE(off_rs + nnz <= WPCD_NOALLOC_SCRATCH_BYTES, WPCD_E_INVALID,
+                     "P0 too large for the fixed scratch (" + std::to_string(nnz) +
+                         " nonzero cells)");
+        int32_t *hint = reinterpret_cast<int32_t *>(base + off_hint);
+        uint8_t *rstart = reinterpret_cast<uint8_t *>(base + off_rs);
+        structure_fill(c, cnt, tsum, row_ptr, col, hint, rstart);
+        const bool fp64 = prec == WPCD_FP64;
+        values_into(c, fp64, row_ptr, col, hint, rstart, nnz, fp64 ? (double *)val : nullptr,
+                    fp64 ? nullptr : (float *)val, false);
+        WPCD_HIP(hipStreamSynchronize(c->stream));
     });
 }
 
