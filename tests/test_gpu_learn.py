@@ -103,11 +103,12 @@ def test_given_warm_start_residual_judge(ctx, P):
         say(f"[warm] E={b.E}: plain {b.iters} it, exact start r0={g.r0:.1e} {g.iters} it")
 
 
-def test_learned_warm_start_gain(ctx, P):
+def test_learned_warm_start_same_amplitudes_lower_initial_residual(ctx, P):
     """Training on plain solves of potential variants, then a held-out
     variant: the same amplitudes as the plain solve at the same residual,
-    an initial residual well below that of the zero start; the iteration
-    counts of both are printed (the gain measured, not assumed)."""
+    and an initial residual well below that of the zero start.  No gain in
+    iterations is asserted (the counts of both are printed): the warm start
+    is judged by its initial residual only."""
     n = 40
     pot = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
     ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=pot)

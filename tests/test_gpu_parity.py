@@ -106,23 +106,35 @@ def test_c2_structure_full_size(ctx, P):
     h.update(col.astype("<i4").tobytes())
     assert nnz == g["nnz_cells"]
     assert h.hexdigest() == g["sha256_rowptr_i64_col_i32"]
-    # sampled rows of values, oracle element by element
+    # sampled rows of values, oracle element by element: the FP64 elements,
+    # then the FP32-compensated ones of the bench's element kernel (8-point
+    # q rule, 20-point cosine rule) on the same rows
+    say("[C2] build_p MIXED")
+    ctx.build_p(P.WPCD_MIXED)
+    _, _, val32 = ctx.get_p()
     rng = np.random.default_rng(7)
     rows = np.sort(rng.choice(150 * 150, 120, replace=False))
     p = O.cheb_edges(150, 10.0)
+    worst = 0.0
     for r in rows[:120]:
         cols = col[rp[r]:rp[r + 1]]
         vo = O.p0_pairs(p, p, 8, 20, 0, [(0, 0)], np.full(cols.size, r, dtype=np.int64), cols)[:, 0, 0]
         v = val[rp[r]:rp[r + 1], 0, 0]
         sc = max(np.abs(vo).max(), 1e-300) if vo.size else 1.0
         assert np.all(np.abs(v - vo) <= 1e-10 * np.abs(vo) + 1e-14 * sc)
+        v32 = val32[rp[r]:rp[r + 1], 0, 0]
+        assert np.all(np.abs(v32 - vo) <= FP32_REL * np.abs(vo) + 1e-10 * sc), r
+        if vo.size:
+            worst = max(worst, float(np.max(np.abs(v32 - vo) / np.maximum(np.abs(vo), 1e-10 * sc))))
+    say(f"[C2] FP32 elements on 120 sampled rows: max rel err {worst:.2e}")
 
 
-@pytest.mark.parametrize("shape", [(128, 256), (200, 170)])
+@pytest.mark.parametrize("shape", [(100, 150), (128, 256), (200, 170)])
 def test_structure_scan_paths(ctx, P, shape):
-    """Row pointers on both scan paths (one LDS-resident workgroup up to
-    32768 rows, the strided one above): every row pointer nondecreasing from
-    0, and sampled rows' column lists equal the oracle's brute-force ones."""
+    """Row pointers when the scan runs in one tile of 16384 rows (ragged),
+    in exactly two, and in three with a ragged last one: every row pointer
+    nondecreasing from 0, and sampled rows' column lists equal the oracle's
+    brute-force ones (rows at the tile seams included)."""
     n_p, n_q = shape
     say(f"[scan] {n_p}x{n_q} rows={n_p * n_q}")
     ctx.build_basis(n_p, n_q, 10.0, 10.0, 8, 16, potential=YAM)
@@ -131,7 +143,8 @@ def test_structure_scan_paths(ctx, P, shape):
     assert rp[0] == 0 and rp[-1] == nnz and np.all(np.diff(rp) >= 0)
     p, q = O.cheb_edges(n_p, 10.0), O.cheb_edges(n_q, 10.0)
     rng = np.random.default_rng(11)
-    rows = np.unique(np.concatenate([[0, 1, n_p * n_q - 1],
+    seams = [t * 16384 + d for t in (1, 2) for d in (-1, 0, 1) if 0 <= t * 16384 + d < n_p * n_q]
+    rows = np.unique(np.concatenate([np.array([0, 1, n_p * n_q - 1] + seams, dtype=np.int64),
                                      rng.choice(n_p * n_q, 40, replace=False)]))
     ptr_o, col_o = O.preselect(p, q, rows)
     for k, r in enumerate(rows):
@@ -436,6 +449,86 @@ def test_c3_structure_and_sampled_values(ctx, P):
     vo = O.p0_pairs(p, p.copy(), 8, 20, 2, L2_CHANS, rows.astype(np.int64), col[idx])
     scale = np.abs(val).max()
     assert np.all(np.abs(val[idx] - vo) <= 1e-10 * np.abs(vo) + 1e-13 * scale)
+    # the FP32 elements of the 270k basis's own kernel (moments of the
+    # coupling polynomials, 20-point cosine rule) on the same blocks
+    say("[C3] build_p MIXED")
+    assert ctx.build_p(P.WPCD_MIXED) == nnz
+    _, _, v32 = ctx.get_p()
+    err = np.abs(v32[idx] - vo)
+    say(f"[C3] FP32 blocks: max err / scale {err.max() / scale:.2e}")
+    assert np.all(err <= 1e-6 * np.abs(vo) + 1e-7 * scale)
+
+
+def _oracle_l2_system(n, ngx, e2=-0.1):
+    """The oracle's 3-channel L = 2+ system on an n x n grid (Yukawa sum
+    fitted to a pair level at e2), P0 computed once."""
+    p = O.cheb_edges(n, 10.0)
+    s_o = O.fit_strength(p, YUK_RANGES, e2)
+    sysm = O.build_system(p, p.copy(), 2, L2_CHANS, 8, ngx,
+                          O.Potential("yukawa", (-s_o, -s_o), YUK_RANGES), with_p0=False)
+    sysm.row_ptr, sysm.col = O.preselect(p, p.copy())
+    rows = np.repeat(np.arange(n * n, dtype=np.int64), np.diff(sysm.row_ptr))
+    sysm.val = O.p0_pairs(p, p.copy(), 8, ngx, 2, L2_CHANS, rows, sysm.col)
+    return sysm
+
+
+def test_three_channel_rule_of_the_270k_basis(ctx, P):
+    """The 270k basis's quadrature rule (8 q points, 20 cosine points) and
+    channels on a 40 x 40 grid (4,800 basis states): every FP32 element of
+    its kernel against the oracle, and the amplitudes of all four precision
+    tiers against the oracle's (FP64 1e-10, mixed tiers 1e-6)."""
+    n = 40
+    fit = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+    say("[mc40] oracle system")
+    sysm = _oracle_l2_system(n, 20)
+    vo = sysm.val
+    scale = np.abs(vo).max()
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 20, channels=L2_CHANS, L=2, potential=fit)
+    say("[mc40] build_p MIXED")
+    nnz = ctx.build_p(P.WPCD_MIXED)
+    rp, col, v32 = ctx.get_p()
+    assert nnz == int(sysm.row_ptr[-1])
+    assert np.array_equal(rp, sysm.row_ptr) and np.array_equal(col, sysm.col)
+    err = np.abs(v32 - vo)
+    say(f"[mc40] FP32 elements: max err / scale {err.max() / scale:.2e}")
+    assert np.all(err <= 1e-6 * np.abs(vo) + 1e-7 * scale)
+    energies = [-0.05, 0.5, 1.5]
+    refs = {}
+    for E in energies:
+        u, _, _ = O.solve_gmres(sysm, E)
+        refs[E] = O.amplitudes(sysm, E, u).U00
+    for prec in (P.WPCD_MIXED, P.WPCD_MIXED_REFINE, P.WPCD_MIXED_BF16):
+        say(f"[mc40] solve precision {prec}")
+        for r, E in zip(ctx.solve(energies, prec), energies):
+            assert r.status == P.WPCD_OK, (prec, E, P.STATUS_NAMES[r.status])
+            U = complex(r.U_re, r.U_im)
+            say(f"[mc40]   E={E}: rel err {abs(U - refs[E]) / abs(refs[E]):.2e}, {r.iters} it")
+            assert abs(U - refs[E]) <= 1e-6 * abs(refs[E]), (prec, E, U, refs[E])
+    say("[mc40] build_p FP64 + solve")
+    ctx.build_p(P.WPCD_FP64)
+    for r, E in zip(ctx.solve(energies, P.WPCD_FP64), energies):
+        assert r.status == P.WPCD_OK
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - refs[E]) <= 1e-10 * abs(refs[E]), (E, U, refs[E])
+
+
+def test_three_channel_fp32_elements_full_grid(ctx, P):
+    """Every FP32 element of a ragged-size 3-channel grid with the 270k
+    basis's rule (n_q = 8, n_x = 20) against the oracle."""
+    n_p, n_q = 23, 27
+    ctx.build_basis(n_p, n_q, 9.0, 11.0, 8, 20, channels=L2_CHANS, L=2, potential=_yuk_pot(1.3))
+    say("[mc23x27] build_p MIXED")
+    nnz = ctx.build_p(P.WPCD_MIXED)
+    rp, col, v32 = ctx.get_p()
+    p, q = O.cheb_edges(n_p, 9.0), O.cheb_edges(n_q, 11.0)
+    ptr_o, col_o = O.preselect(p, q)
+    assert nnz == int(ptr_o[-1]) and np.array_equal(rp, ptr_o) and np.array_equal(col, col_o)
+    rows = np.repeat(np.arange(n_p * n_q, dtype=np.int64), np.diff(ptr_o))
+    vo = O.p0_pairs(p, q, 8, 20, 2, L2_CHANS, rows, col_o)
+    scale = np.abs(vo).max()
+    err = np.abs(v32 - vo)
+    say(f"[mc23x27] FP32 elements: max err / scale {err.max() / scale:.2e}")
+    assert np.all(err <= 1e-6 * np.abs(vo) + 1e-7 * scale)
 
 
 def test_max_grid_1024(ctx, P):
@@ -544,7 +637,8 @@ def test_graph_replays_match_eager(ctx, P):
 
 def test_solve_multi_uneven_systems(P):
     """Three systems of different size and channel count solved at once
-    give the results of solving them one by one."""
+    give the results of solving them one by one, and those equal the
+    oracle's amplitudes."""
     yuk = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
     specs = [(16, [(0, 0)], 0, YAM, [0.1, 0.7]),
              (22, [(0, 2), (2, 0)], 2, yuk, [-0.05, 0.3, 0.9, 1.4]),
@@ -564,6 +658,19 @@ def test_solve_multi_uneven_systems(P):
             for a, b in zip(a_list, b_list):
                 assert b.status == a.status == P.WPCD_OK
                 assert (a.U_re, a.U_im, a.iters) == (b.U_re, b.U_im, b.iters)
+    # and every system's amplitudes equal the oracle's
+    for (n, ch, L, pot, Es), rs in zip(specs, seq):
+        p = O.cheb_edges(n, 10.0)
+        if pot is YAM:
+            opot = O.Potential("yamaguchi", (YAM_LAMBDA,), (YAM_BETA,))
+        else:
+            s_o = O.fit_strength(p, YUK_RANGES, -0.1)
+            opot = O.Potential("yukawa", (-s_o, -s_o), YUK_RANGES)
+        sysm = O.build_system(p, p.copy(), L, ch, 8, 16, opot)
+        for r, E in zip(rs, Es):
+            a = O.amplitudes(sysm, E, O.solve_gmres(sysm, E)[0])
+            U = complex(r.U_re, r.U_im)
+            assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (n, E, U, a.U00)
     with pytest.raises(P.WpcdError):
         P.wpcd_solve_multi([ctxs[0].h, ctxs[0].h], [[0.1], [0.2]], P.WPCD_FP64)
     for c in ctxs:
