@@ -110,7 +110,10 @@ typedef struct {
  * operator at the 1e-7 level).  want_breakup:
  * fill breakup_out in wpcd_solve.  warm_start: a WPCD_WARM_* value; x0
  * (WPCD_WARM_GIVEN only): host array [n_E][M][2] of (re, im) doubles in
- * channel-basis order, M = n_ch*n_q*n_p.                                 */
+ * channel-basis order, M = n_ch*n_q*n_p.  err_est: nonzero to fill
+ * err_vs_fp64 of every result (see wpcd_energy_result); this needs the P0
+ * values in FP64 as well, which the first such call computes on the
+ * existing structure and keeps (8 B per channel value).                  */
 typedef struct {
     int32_t max_iter;
     int32_t krylov_dim;
@@ -118,6 +121,8 @@ typedef struct {
     int32_t want_breakup;
     int32_t warm_start;
     const double *x0;
+    int32_t err_est;
+    int32_t pad_;
 } wpcd_solve_opts;
 
 /* Per-energy result.  status is a wpcd_status value for this energy.
@@ -125,7 +130,14 @@ typedef struct {
  * S = 1 - 2 pi i A (Sec. III.B, m = 1), delta = arg(S)/2, eta = |S|.
  * n_open: open breakup pseudostate channels (breakup_out rows).
  * warm: 1 if a warm start was kept (alpha != 0); r0: relative residual of
- * the initial vector (1 for the zero start).                             */
+ * the initial vector (1 for the zero start).
+ * err_vs_fp64 (opts.err_est set, else NaN): |U - U64| / |U|, the relative
+ * difference of this amplitude from the FP64 path's (FP64 P0 values, FP64
+ * solve), estimated as the on-shell component of the correction d of one
+ * step of iterative refinement: r64 = b64 - (1 - K64) u with the FP64 P0,
+ * (1 - K) d = r64 solved in this tier to 1e-4.  Exact to first order in the
+ * FP32 rounding of P0 (and in the solver's residual); the returned U is not
+ * corrected.  For WPCD_FP64 it measures the solver's remaining error.      */
 typedef struct {
     double E, q0;
     int32_t j0, status, iters, n_open;
@@ -133,6 +145,7 @@ typedef struct {
     double delta, eta, residual;
     int32_t warm, pad_;
     double r0;
+    double err_vs_fp64;
 } wpcd_energy_result;
 
 /* Training of the learned warm start (not part of the paper's method).
@@ -301,7 +314,9 @@ wpcd_status wpcd_bound_state(wpcd_ctx *ctx, double e_lo, double e_hi, double *e3
  * kernels share the device.  The contexts must be distinct (a context is
  * not thread-safe) and on the same device or not.  status_out[i] (may be
  * NULL) receives each system's call status; the return value is the first
- * non-OK one.  Errors: WPCD_E_INVALID (NULL arrays, repeated context).   */
+ * non-OK one.  opts is shared by all systems, so opts->warm_start may not
+ * be WPCD_WARM_GIVEN (one x0 cannot match systems of different sizes).
+ * Errors: WPCD_E_INVALID (NULL arrays, repeated context, WPCD_WARM_GIVEN). */
 wpcd_status wpcd_solve_multi(wpcd_ctx *const *ctxs, int32_t n_sys, const double *const *E,
                              const int32_t *n_E, wpcd_precision prec, const wpcd_solve_opts *opts,
                              wpcd_energy_result *const *out, wpcd_status *status_out);

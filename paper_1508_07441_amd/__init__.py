@@ -74,7 +74,8 @@ class wpcd_potential_desc(ctypes.Structure):
 class wpcd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("krylov_dim", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("want_breakup", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("x0", ctypes.POINTER(ctypes.c_double))]
+                ("warm_start", ctypes.c_int32), ("x0", ctypes.POINTER(ctypes.c_double)),
+                ("err_est", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class wpcd_energy_result(ctypes.Structure):
@@ -86,7 +87,8 @@ class wpcd_energy_result(ctypes.Structure):
                 ("S_re", ctypes.c_double), ("S_im", ctypes.c_double),
                 ("delta", ctypes.c_double), ("eta", ctypes.c_double),
                 ("residual", ctypes.c_double), ("warm", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("r0", ctypes.c_double)]
+                ("pad_", ctypes.c_int32), ("r0", ctypes.c_double),
+                ("err_vs_fp64", ctypes.c_double)]
 
 
 class wpcd_learn_desc(ctypes.Structure):
@@ -271,13 +273,14 @@ def wpcd_get_p(ctx, n_cells, nnz, n_ch=1, values=True):
 
 
 def _opts(max_iter=0, krylov_dim=0, tol=0.0, want_breakup=False, warm_start=WPCD_WARM_NONE,
-          x0=None):
+          x0=None, err_est=False):
     return wpcd_solve_opts(max_iter, krylov_dim, tol, 1 if want_breakup else 0, warm_start,
-                           _dp(x0))
+                           _dp(x0), 1 if err_est else 0, 0)
 
 
 def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0,
-               want_breakup=False, n_p=0, n_ch=1, warm_start=WPCD_WARM_NONE, x0=None):
+               want_breakup=False, n_p=0, n_ch=1, warm_start=WPCD_WARM_NONE, x0=None,
+               err_est=False):
     """x0 (warm_start=WPCD_WARM_GIVEN): complex array [n_E][M]."""
     E = np.ascontiguousarray(energies, dtype=np.float64)
     out = (wpcd_energy_result * max(1, E.size))()
@@ -287,7 +290,7 @@ def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol
         if x0c.ndim != 2 or x0c.shape[0] != E.size:
             raise ValueError("x0 must be [n_E][M] complex")
         x0r = x0c.view(np.float64).reshape(-1)
-    opts = _opts(max_iter, krylov_dim, tol, want_breakup, warm_start, x0r)
+    opts = _opts(max_iter, krylov_dim, tol, want_breakup, warm_start, x0r, err_est)
     br = np.zeros(E.size * max(1, n_p) * n_ch * 5) if want_breakup else None
     _check(ctx, lib().wpcd_solve(ctx, _dp(E), E.size, precision, ctypes.byref(opts), out,
                                  _dp(br)))

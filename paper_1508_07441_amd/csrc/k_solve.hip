@@ -1382,134 +1382,29 @@ void choose_shapes(Batch &b, int m) {
 
 // Solve the batch of energies already validated by the caller.
 // idx0: entrance row per energy.
-void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
-                 int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
-                 GmresOut &out) {
-    const bool fp64 = prec == WPCD_FP64;
-    std::vector<int> &iters = out.iters, &edge_flag = out.edge;
-    std::vector<double> &resid = out.resid;
-    const int nE = (int)E.size();
-    // the Givens kernel's LDS column stage can exceed the 64 KB default
-    WPCD_HIP(hipFuncSetAttribute((const void *)k_norm_givens,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
-    Batch b{};
-    b.c = c;
-    b.nE = nE;
-    b.W = 2 * nE;
-    b.nEp = 1;
-    while (b.nEp < nE) b.nEp <<= 1;
-    b.Wp = 2 * b.nEp;
-    b.m = m;
-    b.M = (int64_t)c->nch * c->nq * c->np;
-    b.fp64 = fp64;
-    b.lowp = prec == WPCD_MIXED_REFINE || prec == WPCD_MIXED_BF16;
-    b.bf16 = prec == WPCD_MIXED_BF16;
-    const int64_t vec = b.M * b.W;   // doubles per batched vector
-    b.vstride = vec;
-    const int max_chunks = cdiv(b.M, chunk_rows_of(b.nEp, 1));
-    c->d_G.reserve(vec);
-    c->d_X.reserve(vec);
-    c->d_B.reserve(vec);
-    c->d_T1.reserve(2 * vec);
-    c->d_V.reserve((size_t)(m + 1) * vec);
-    c->d_Hess.reserve((size_t)nE * (m + 1) * m * 2);
-    c->d_partial.reserve((size_t)(max_chunks + kMaxSplit) * (m + 1) * nE * 2);
-    c->d_W.reserve(vec);
-    c->d_misc.reserve((size_t)nE * (kSt + 2 * m + 2 * (m + 1) + m + 4) + (size_t)(m + 1) * nE * 2 +
-                      (size_t)nE * m * 2 + 64);
-    c->d_flag.reserve(2 * nE + 4);
-    c->d_idx.reserve(nE);
-    b.G = c->d_G.ptr;
-    b.X = c->d_X.ptr;
-    b.B = c->d_B.ptr;
-    b.T1 = c->d_T1.ptr;
-    b.T2 = c->d_T1.ptr + vec;
-    b.R = c->d_W.ptr;
-    b.Vb = c->d_V.ptr;
-    b.H = c->d_Hess.ptr;
-    b.partial = c->d_partial.ptr;
-    b.out2 = c->d_partial.ptr + (size_t)max_chunks * (m + 1) * nE * 2;
-    double *ms = c->d_misc.ptr;
-    b.S.st = ms;
-    ms += nE * kSt;
-    b.S.cs = ms;
-    ms += nE * m;
-    b.S.sn = ms;
-    ms += 2 * nE * m;
-    b.S.g = ms;
-    ms += 2 * nE * (m + 1);
-    b.h = ms;
-    ms += 2 * (m + 1) * nE;
-    b.inv = ms;
-    ms += nE;
-    b.y = ms;
-    ms += 2 * nE * m;
-    int32_t *flag = c->d_flag.ptr;   // [0, nE): resolvent edge flags
-    b.kuse = flag + nE;              // [nE, 2 nE): GMRES columns used
-
-    hipStream_t s = c->stream;
-    choose_shapes(b, m);
-    // energies
-    double *dE = c->d_T1.ptr;   // scratch: T1 not yet in use
-    WPCD_HIP(hipMemcpyAsync(dE, E.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
-    WPCD_HIP(hipMemsetAsync(flag, 0, nE * sizeof(int32_t), s));
-    ChPtrs eps{};
-    for (int a = 0; a < c->nch; ++a) eps.p[a] = c->waves[c->ch_wave[a]].eps.ptr;
-    {
-        TimedLaunch tl(c->timer, s, "resolvent", WPCD_TIME_SOLVE);
-        hipLaunchKernelGGL(k_resolvent, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, c->d_q.ptr,
-                           c->np, c->nq, c->nch, nE, dE, eps, b.G, flag);
-        WPCD_HIP(hipGetLastError());
-    }
-    edge_flag.assign(nE, 0);
-    WPCD_HIP(hipMemcpyAsync(edge_flag.data(), flag, nE * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    // right-hand side b = O P0 V~ e0
-    WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
-    WPCD_HIP(hipMemcpyAsync(c->d_idx.ptr, idx0.data(), nE * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, s, c->d_idx.ptr, nE, b.X);
-    WPCD_HIP(hipGetLastError());
-    op_apply(b, b.X, b.B, false, false);
-    // ||b||
+// |B| of every energy: the residual normalisation of the cycles (host st
+// and the device state's st[1]).
+void rhs_norms(Batch &b, std::vector<double> &st) {
+    const int nE = b.nE;
+    hipStream_t s = b.c->stream;
     dots(b, b.B, 1, b.B, b.h, nullptr, 0, 0);
-    // st[1] = ||b||: copy via host (small)
     std::vector<double> h0(2 * nE);
     WPCD_HIP(hipMemcpyAsync(h0.data(), b.h, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
     WPCD_HIP(hipStreamSynchronize(s));
-    std::vector<double> st(nE * kSt, 0.0);
+    st.assign(nE * kSt, 0.0);
     for (int e = 0; e < nE; ++e) st[e * kSt + 1] = std::sqrt(h0[2 * e]);
     WPCD_HIP(hipMemcpyAsync(b.S.st, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    out.warm.assign(nE, 0);
-    out.r0.assign(nE, 1.0);
-    if (warm) {
-        // proposed x0, judged by the minimal initial residual over its scalings
-        warm(c, warm_user, b.X, nE);
-        op_apply(b, b.X, b.R, true, true);
-        dots(b, b.R, 1, b.B, b.h, nullptr, 0, 0);
-        dots(b, b.R, 1, b.R, b.h + 2 * nE, nullptr, 0, 0);
-        {
-            TimedLaunch tl(c->timer, s, "warm_judge", WPCD_TIME_SOLVE);
-            hipLaunchKernelGGL(k_warm_alpha, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.h, b.h + 2 * nE,
-                               nE, b.y);
-            hipLaunchKernelGGL(k_warm_apply, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.y, b.M,
-                               nE, b.B, b.X, b.R);
-            WPCD_HIP(hipGetLastError());
-        }
-        dots(b, b.R, 1, b.R, b.h, nullptr, 0, 0);
-        std::vector<double> al(2 * nE), rr(2 * nE);
-        WPCD_HIP(hipMemcpyAsync(al.data(), b.y, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
-        WPCD_HIP(hipMemcpyAsync(rr.data(), b.h, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
-        WPCD_HIP(hipStreamSynchronize(s));
-        for (int e = 0; e < nE; ++e) {
-            out.warm[e] = (al[2 * e] != 0.0 || al[2 * e + 1] != 0.0) ? 1 : 0;
-            const double bn = st[e * kSt + 1];
-            out.r0[e] = bn > 0 ? std::sqrt(std::max(rr[2 * e], 0.0)) / bn : 0.0;
-        }
-    } else {
-        // x = 0, r = b
-        WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
-        WPCD_HIP(hipMemcpyAsync(b.R, b.B, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
+}
 
+// Restarted GMRES cycles from x = b.X with r = b.R = b.B - (1 - K) x until
+// every energy's true relative residual |r| / |B| (st[1] = |B|) is <= tol
+// or max_iter iterations are spent.
+void restart_cycles(Batch &b, double tol, int max_iter, const std::vector<double> &st,
+                    std::vector<int> &iters, std::vector<double> &resid) {
+    const int nE = b.nE, m = b.m;
+    wpcd_ctx *c = b.c;
+    hipStream_t s = c->stream;
+    const int64_t vec = b.M * b.W;
     iters.assign(nE, 0);
     resid.assign(nE, 1.0);
     int total = 0;
@@ -1572,6 +1467,167 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
             if (resid[e] > tol) all_done = false;
         }
     }
+}
+
+void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
+                 int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
+                 GmresOut &out, bool err_est) {
+    const bool fp64 = prec == WPCD_FP64;
+    std::vector<int> &iters = out.iters, &edge_flag = out.edge;
+    std::vector<double> &resid = out.resid;
+    const int nE = (int)E.size();
+    // the Givens kernel's LDS column stage can exceed the 64 KB default
+    WPCD_HIP(hipFuncSetAttribute((const void *)k_norm_givens,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+    Batch b{};
+    b.c = c;
+    b.nE = nE;
+    b.W = 2 * nE;
+    b.nEp = 1;
+    while (b.nEp < nE) b.nEp <<= 1;
+    b.Wp = 2 * b.nEp;
+    b.m = m;
+    b.M = (int64_t)c->nch * c->nq * c->np;
+    b.fp64 = fp64;
+    b.lowp = prec == WPCD_MIXED_REFINE || prec == WPCD_MIXED_BF16;
+    b.bf16 = prec == WPCD_MIXED_BF16;
+    const int64_t vec = b.M * b.W;   // doubles per batched vector
+    b.vstride = vec;
+    const int max_chunks = cdiv(b.M, chunk_rows_of(b.nEp, 1));
+    c->d_G.reserve(vec);
+    c->d_X.reserve(vec);
+    c->d_B.reserve(vec);
+    c->d_T1.reserve(2 * vec);
+    c->d_V.reserve((size_t)(m + 1) * vec);
+    c->d_Hess.reserve((size_t)nE * (m + 1) * m * 2);
+    c->d_partial.reserve((size_t)(max_chunks + kMaxSplit) * (m + 1) * nE * 2);
+    c->d_W.reserve(vec);
+    if (err_est) c->d_X2.reserve(vec);
+    c->d_misc.reserve((size_t)nE * (kSt + 2 * m + 2 * (m + 1) + m + 4) + (size_t)(m + 1) * nE * 2 +
+                      (size_t)nE * m * 2 + 64);
+    c->d_flag.reserve(2 * nE + 4);
+    c->d_idx.reserve(nE);
+    b.G = c->d_G.ptr;
+    b.X = c->d_X.ptr;
+    b.B = c->d_B.ptr;
+    b.T1 = c->d_T1.ptr;
+    b.T2 = c->d_T1.ptr + vec;
+    b.R = c->d_W.ptr;
+    b.Vb = c->d_V.ptr;
+    b.H = c->d_Hess.ptr;
+    b.partial = c->d_partial.ptr;
+    b.out2 = c->d_partial.ptr + (size_t)max_chunks * (m + 1) * nE * 2;
+    double *ms = c->d_misc.ptr;
+    b.S.st = ms;
+    ms += nE * kSt;
+    b.S.cs = ms;
+    ms += nE * m;
+    b.S.sn = ms;
+    ms += 2 * nE * m;
+    b.S.g = ms;
+    ms += 2 * nE * (m + 1);
+    b.h = ms;
+    ms += 2 * (m + 1) * nE;
+    b.inv = ms;
+    ms += nE;
+    b.y = ms;
+    ms += 2 * nE * m;
+    int32_t *flag = c->d_flag.ptr;   // [0, nE): resolvent edge flags
+    b.kuse = flag + nE;              // [nE, 2 nE): GMRES columns used
+
+    hipStream_t s = c->stream;
+    choose_shapes(b, m);
+    // energies
+    double *dE = c->d_T1.ptr;   // scratch: T1 not yet in use
+    WPCD_HIP(hipMemcpyAsync(dE, E.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
+    WPCD_HIP(hipMemsetAsync(flag, 0, nE * sizeof(int32_t), s));
+    ChPtrs eps{};
+    for (int a = 0; a < c->nch; ++a) eps.p[a] = c->waves[c->ch_wave[a]].eps.ptr;
+    {
+        TimedLaunch tl(c->timer, s, "resolvent", WPCD_TIME_SOLVE);
+        hipLaunchKernelGGL(k_resolvent, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, c->d_q.ptr,
+                           c->np, c->nq, c->nch, nE, dE, eps, b.G, flag);
+        WPCD_HIP(hipGetLastError());
+    }
+    edge_flag.assign(nE, 0);
+    WPCD_HIP(hipMemcpyAsync(edge_flag.data(), flag, nE * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // right-hand side b = O P0 V~ e0
+    WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
+    WPCD_HIP(hipMemcpyAsync(c->d_idx.ptr, idx0.data(), nE * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, s, c->d_idx.ptr, nE, b.X);
+    WPCD_HIP(hipGetLastError());
+    op_apply(b, b.X, b.B, false, false);
+    std::vector<double> st;
+    rhs_norms(b, st);
+    out.warm.assign(nE, 0);
+    out.r0.assign(nE, 1.0);
+    if (warm) {
+        // proposed x0, judged by the minimal initial residual over its scalings
+        warm(c, warm_user, b.X, nE);
+        op_apply(b, b.X, b.R, true, true);
+        dots(b, b.R, 1, b.B, b.h, nullptr, 0, 0);
+        dots(b, b.R, 1, b.R, b.h + 2 * nE, nullptr, 0, 0);
+        {
+            TimedLaunch tl(c->timer, s, "warm_judge", WPCD_TIME_SOLVE);
+            hipLaunchKernelGGL(k_warm_alpha, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.h, b.h + 2 * nE,
+                               nE, b.y);
+            hipLaunchKernelGGL(k_warm_apply, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.y, b.M,
+                               nE, b.B, b.X, b.R);
+            WPCD_HIP(hipGetLastError());
+        }
+        dots(b, b.R, 1, b.R, b.h, nullptr, 0, 0);
+        std::vector<double> al(2 * nE), rr(2 * nE);
+        WPCD_HIP(hipMemcpyAsync(al.data(), b.y, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
+        WPCD_HIP(hipMemcpyAsync(rr.data(), b.h, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
+        WPCD_HIP(hipStreamSynchronize(s));
+        for (int e = 0; e < nE; ++e) {
+            out.warm[e] = (al[2 * e] != 0.0 || al[2 * e + 1] != 0.0) ? 1 : 0;
+            const double bn = st[e * kSt + 1];
+            out.r0[e] = bn > 0 ? std::sqrt(std::max(rr[2 * e], 0.0)) / bn : 0.0;
+        }
+    } else {
+        // x = 0, r = b
+        WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
+        WPCD_HIP(hipMemcpyAsync(b.R, b.B, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+
+    restart_cycles(b, tol, max_iter, st, iters, resid);
+    if (!err_est) return;
+    // Error against the FP64 path: the residual of x with the FP64 P0 values,
+    // r64 = b64 - (1 - K64) x, and the correction d from (1 - K) d = r64
+    // solved in this tier to a relative residual of 1e-4; d ~ x64 - x, so its
+    // on-shell component is the amplitude's difference from the FP64 solution
+    // (to first order in the FP32 rounding of P0).  x itself is kept.
+    const bool fp64_saved = b.fp64;
+    double *X2 = c->d_X2.ptr;
+    WPCD_HIP(hipMemcpyAsync(X2, b.X, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+    WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
+    hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, s, c->d_idx.ptr, nE, b.X);
+    WPCD_HIP(hipGetLastError());
+    b.fp64 = true;
+    op_apply(b, b.X, b.B, false, false);          // b64
+    op_apply(b, X2, b.R, true, true);             // (1 - K64) x
+    hipLaunchKernelGGL(k_sub_from, dim3(cdiv(vec, 256)), dim3(256), 0, s, b.B, vec, b.R);
+    WPCD_HIP(hipGetLastError());
+    b.fp64 = fp64_saved;
+    WPCD_HIP(hipMemcpyAsync(b.B, b.R, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+    WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
+    std::vector<double> st2;
+    rhs_norms(b, st2);
+    std::vector<int> it2(nE, 0);
+    std::vector<double> res2(nE, 1.0);
+    restart_cycles(b, 1e-4, std::max(max_iter, 64), st2, it2, res2);
+    out.dU.assign(2 * nE, 0.0);
+    out.U.assign(2 * nE, 0.0);
+    for (int e = 0; e < nE; ++e) {
+        const int64_t off = (idx0[e] * nE + e) * 2;
+        WPCD_HIP(hipMemcpyAsync(&out.dU[2 * e], b.X + off, 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        WPCD_HIP(hipMemcpyAsync(&out.U[2 * e], X2 + off, 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+    }
+    WPCD_HIP(hipMemcpyAsync(b.X, X2, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
+    WPCD_HIP(hipStreamSynchronize(s));
 }
 
 // H[k+1][k] = |w| from the stage-1 norm partials; inv = 1/|w| (0 on breakdown).

@@ -424,12 +424,14 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     // solve gains nothing below 1e-9
     double tol = prec == WPCD_FP64 ? 1e-12 : 1e-9;
     int want_breakup = 0, warm_kind = WPCD_WARM_NONE;
+    bool err_est = false;
     if (opts) {
         if (opts->krylov_dim > 0) m = opts->krylov_dim;
         if (opts->max_iter > 0) max_iter = opts->max_iter;
         if (opts->tol > 0) tol = opts->tol;
         want_breakup = opts->want_breakup;
         warm_kind = opts->warm_start;
+        err_est = opts->err_est != 0;
     }
     WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
     WPCD_REQUIRE(warm_kind >= WPCD_WARM_NONE && warm_kind <= WPCD_WARM_GIVEN, WPCD_E_INVALID,
@@ -460,6 +462,7 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
         r.E = E[e];
         r.status = WPCD_OK;
         r.r0 = 1.0;
+        r.err_vs_fp64 = std::numeric_limits<double>::quiet_NaN();
         if (!std::isfinite(E[e])) {
             r.status = WPCD_E_INVALID;
             continue;
@@ -479,6 +482,11 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
         active.push_back(e);
         idx0v.push_back(((int64_t)a0 * c->nq + j0) * c->np);
         rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
+    }
+    // the error estimate needs the FP64 P0 values on the same structure
+    if (err_est && !c->has_val64 && !active.empty()) {
+        build_values(c, true);
+        c->has_val64 = true;
     }
     const int kBatch = 32;
     for (size_t b0 = 0; b0 < active.size(); b0 += kBatch) {
@@ -506,7 +514,7 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
         }
         GmresOut go;
         gmres_batch(c, Eb, idx0, prec, m, max_iter, tol,
-                    warm_kind == WPCD_WARM_NONE ? nullptr : warm_fill, &wc, go);
+                    warm_kind == WPCD_WARM_NONE ? nullptr : warm_fill, &wc, go, err_est);
         // amplitude list: elastic first, then open breakup pseudostates
         std::vector<int64_t> rows;
         std::vector<int32_t> ens;
@@ -559,6 +567,11 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
             r.delta = 0.5 * std::atan2(r.S_im, r.S_re);
             r.eta = std::hypot(r.S_re, r.S_im);
             r.n_open = n_br[t];
+            if (err_est) {
+                const double du = std::hypot(go.dU[2 * t], go.dU[2 * t + 1]);
+                const double u = std::hypot(go.U[2 * t], go.U[2 * t + 1]);
+                r.err_vs_fp64 = u > 0.0 ? du / u : std::numeric_limits<double>::quiet_NaN();
+            }
             if (r.status == WPCD_OK) ok.push_back(t);
             if (breakup_out && want_breakup) {
                 double *dst = breakup_out + (size_t)e * c->np * c->nch * 5;
@@ -942,7 +955,10 @@ wpcd_status wpcd_build_basis(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_p
         c->has_basis = false;
         c->learned.release();
         c->has_pot = false;
-        if (!same_grid) c->has_p = false;
+        if (!same_grid) {
+            c->has_p = false;
+            c->has_val64 = false;
+        }
         c->np = b->n_p;
         c->nq = b->n_q;
         c->ngq = b->n_gauss_q;
@@ -1064,11 +1080,13 @@ wpcd_status wpcd_build_p(wpcd_ctx *c, wpcd_precision prec, int64_t *nnz_out) {
         WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
         WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
         c->has_p = false;
+        c->has_val64 = false;
         build_structure(c);
         build_values(c, prec == WPCD_FP64);
         WPCD_HIP(hipStreamSynchronize(c->stream));
         c->has_p = true;
         c->p_fp64 = prec == WPCD_FP64;
+        c->has_val64 = c->p_fp64;
         if (nnz_out) *nnz_out = c->nnz;
     });
 }
@@ -1363,6 +1381,7 @@ wpcd_status wpcd_load_p(wpcd_ctx *c, const char *path, int64_t *nnz_out) {
         WPCD_HIP(hipStreamSynchronize(c->stream));
         c->nnz = h.nnz;
         c->p_fp64 = h.fp64 != 0;
+        c->has_val64 = c->p_fp64;
         c->has_p = true;
         if (nnz_out) *nnz_out = h.nnz;
     });
@@ -1372,6 +1391,8 @@ wpcd_status wpcd_solve_multi(wpcd_ctx *const *ctxs, int32_t n_sys, const double 
                              const int32_t *n_E, wpcd_precision prec, const wpcd_solve_opts *opts,
                              wpcd_energy_result *const *out, wpcd_status *status_out) {
     if (!ctxs || !E || !n_E || !out || n_sys < 0) return WPCD_E_INVALID;
+    // one opts for systems of different sizes: a caller-given x0 cannot fit them all
+    if (opts && opts->warm_start == WPCD_WARM_GIVEN) return WPCD_E_INVALID;
     for (int i = 0; i < n_sys; ++i) {
         if (!ctxs[i]) return WPCD_E_INVALID;
         for (int j = 0; j < i; ++j)

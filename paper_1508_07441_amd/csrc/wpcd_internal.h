@@ -229,7 +229,8 @@ struct wpcd_ctx {
 
     // ---- P0
     bool has_p = false;
-    bool p_fp64 = false;
+    bool p_fp64 = false;     // P0 built in FP64 (else FP32 values in d_val32)
+    bool has_val64 = false;  // d_val64 holds the FP64 values of the current structure
     int64_t nnz = 0;
     wpcd::DBuf<int64_t> d_rowptr;
     wpcd::DBuf<int32_t> d_col, d_cnt, d_hint;   // columns, row counts, row hints (one per 64 nonzeros)
@@ -239,7 +240,7 @@ struct wpcd_ctx {
     wpcd::DBuf<float> d_val32;
 
     // ---- solve workspace
-    wpcd::DBuf<double> d_G, d_X, d_B, d_W, d_T1, d_T2, d_V, d_Hess, d_partial, d_misc;
+    wpcd::DBuf<double> d_G, d_X, d_X2, d_B, d_W, d_T1, d_T2, d_V, d_Hess, d_partial, d_misc;
     wpcd::DBuf<int64_t> d_idx;
     wpcd::DBuf<double> d_jac;   // Jacobi workspace (A and V per wave)
     wpcd::DBuf<int32_t> d_flag;
@@ -322,11 +323,12 @@ int tune_pick(wpcd_ctx *c, const char *name, const std::string &key, int n_cand,
 struct GmresOut {
     std::vector<int> iters, edge, warm;
     std::vector<double> resid, r0;
+    std::vector<double> U, dU;   // err_est: on-shell x and its FP64 correction, [nE][2]
 };
 using WarmFill = void (*)(wpcd_ctx *c, void *user, double *x, int nE);
 void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
                  int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
-                 GmresOut &out);
+                 GmresOut &out, bool err_est = false);
 void arnoldi_kernel(wpcd_ctx *c, double E, int m, std::vector<double> &H, int &steps);
 void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
                       const std::vector<int32_t> &ens, const std::vector<double> &rho,

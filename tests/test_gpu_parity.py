@@ -531,6 +531,34 @@ def test_three_channel_fp32_elements_full_grid(ctx, P):
     assert np.all(err <= 1e-6 * np.abs(vo) + 1e-7 * scale)
 
 
+def test_err_vs_fp64_matches_true_error(ctx, P):
+    """The per-amplitude error estimate of the mixed tiers (one FP64
+    refinement step's correction) against the true difference from the
+    oracle's amplitude, at 8 energies below and above breakup on a 60 x 60
+    s-wave grid with the bench's rule; NaN when not asked for; tiny in
+    FP64."""
+    n = 60
+    fit = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 20, potential=fit)
+    p = O.cheb_edges(n, 10.0)
+    s_o = O.fit_strength(p, YUK_RANGES, -0.1)
+    sysm = O.build_system(p, p.copy(), 0, [(0, 0)], 8, 20,
+                          O.Potential("yukawa", (-s_o, -s_o), YUK_RANGES))
+    ref = {E: O.amplitudes(sysm, E, O.solve_gmres(sysm, E)[0]).U00 for E in ENERGIES}
+    ctx.build_p(P.WPCD_MIXED)
+    assert all(math.isnan(r.err_vs_fp64) for r in ctx.solve(ENERGIES, P.WPCD_MIXED))
+    for prec in (P.WPCD_MIXED, P.WPCD_MIXED_REFINE, P.WPCD_MIXED_BF16):
+        say(f"[err] precision {prec}")
+        for r in ctx.solve(ENERGIES, prec, err_est=True):
+            assert r.status == P.WPCD_OK
+            true = abs(complex(r.U_re, r.U_im) - ref[r.E]) / abs(ref[r.E])
+            say(f"[err]   E={r.E:+.2f}: reported {r.err_vs_fp64:.3e} true {true:.3e}")
+            assert abs(r.err_vs_fp64 - true) <= 0.05 * true + 2e-10, (prec, r.E)
+    ctx.build_p(P.WPCD_FP64)
+    for r in ctx.solve(ENERGIES, P.WPCD_FP64, err_est=True):
+        assert r.status == P.WPCD_OK and r.err_vs_fp64 < 1e-10, (r.E, r.err_vs_fp64)
+
+
 def test_max_grid_1024(ctx, P):
     """The largest grid the library takes, 1024 x 1024 bins (cell indices up
     to 2^20 - 1, ~7e8 cell pairs, int64 offsets): sampled rows' columns and
