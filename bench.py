@@ -48,7 +48,7 @@ LEARN_VARIANTS, LEARN_ENERGIES = 16, 32
 # scaled by the counter's reading of a plain device copy of known size
 # (factors 2.0 and 1.0); valid only for the element-kernel source they were
 # taken on (sha256 prefix of csrc/k_p0.hip), reported as null otherwise.
-P0_ELEM_F32_TRAFFIC = {"bytes": 4.9596e+07, "k_p0_sha256": "dde348622f75ab91"}
+P0_ELEM_F32_TRAFFIC = {"bytes": 5.2085e+07, "k_p0_sha256": "28f1c7dae4d99356"}
 
 # MI355X published peaks used for the roofline fractions
 PEAK_FP32_VECTOR_TFLOPS = 157.3
@@ -92,6 +92,25 @@ def cpu_baseline(sample_stride, threads):
                       f"cell pairs): brute-force pre-selection + FP64 elements, {dt:.1f} s"}
 
 
+def cpu_solve_baseline(threads):
+    """The oracle's FP64 GMRES (same algorithm class as the GPU solve:
+    restarted GMRES on the factored kernel with the sparse P0) on the same
+    150 x 150 system at the 8 energies, one after another."""
+    import oracle.wpcd as O
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    p = O.cheb_edges(N, 10.0)
+    s = O.fit_strength(p, RANGES, -0.1)
+    sysm = O.build_system(p, p.copy(), 0, [(0, 0)], NGQ, NGX,
+                          O.Potential("yukawa", (-s, -s), RANGES))
+    t0 = time.perf_counter()
+    for E in ENERGIES:
+        O.solve_gmres(sysm, E)
+    dt = time.perf_counter() - t0
+    return {"value": dt / len(ENERGIES), "unit": "s/energy", "cores": threads, "kind": "oracle",
+            "sample": f"the {len(ENERGIES)} energies of the workload, FP64 GMRES to 1e-13, "
+                      f"{dt:.1f} s"}
+
+
 def cpu_baseline_one_thread(sample_stride):
     """cpu_baseline with OMP_NUM_THREADS=1, in a child process of this script
     (called before any GPU use, so the child is started from a process that
@@ -123,6 +142,85 @@ def copy_calibration(nbytes):
     return {"read": nbytes, "write": nbytes}
 
 
+def torch_copy_calibration(nbytes):
+    """One device-to-device copy of nbytes by torch's elementwise copy kernel
+    (ordinary vector loads and stores): a second plain copy kernel of known
+    traffic for the byte counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return {"read": nbytes, "write": nbytes}
+
+
+def active_pair_fraction(p, q, ngq, rows, cols, stride=64):
+    """Fraction of the (q, q') Gauss pairs of the selected cell pairs whose
+    clipped cosine interval is not empty (the integrand is evaluated only
+    there), on every stride-th nonzero: the same limit expressions as the
+    element quadrature, in numpy."""
+    import numpy as np
+    x, w = np.polynomial.legendre.leggauss(ngq)
+    r, c = rows[::stride], cols[::stride]
+    npb = p.size - 1
+    i, j, i2, j2 = r % npb, r // npb, c % npb, c // npb
+    qa = 0.5 * (q[j][:, None] + q[j + 1][:, None]) + 0.5 * (q[j + 1] - q[j])[:, None] * x[None, :]
+    qb = 0.5 * (q[j2][:, None] + q[j2 + 1][:, None]) + 0.5 * (q[j2 + 1] - q[j2])[:, None] * x[None, :]
+    qa, qb = qa[:, :, None], qb[:, None, :]
+    D = 0.75 * (qa - qb) * (qa + qb)
+    tlo, thi = (qb - 0.5 * qa) ** 2, (qb + 0.5 * qa) ** 2
+    P2 = p * p
+    pl1, ph1 = P2[i][:, None, None], P2[i + 1][:, None, None]
+    pl2, ph2 = P2[i2][:, None, None], P2[i2 + 1][:, None, None]
+    lo = np.maximum(np.maximum(tlo, pl1), pl2 - D)
+    hi = np.minimum(np.minimum(thi, ph1), ph2 - D)
+    return float(np.mean(hi > lo)), int(r.size)
+
+
+def solve_kernel_rates(P, ctx, prec, energies, nnz, n, nch):
+    """HIP-event times of the solve's kernels in one batched solve (eager
+    launches, the library's stream) and what they move or compute per
+    launch: the P0 SpMM (P0 stream: values + columns + row pointers read
+    once for all batched energies; x gather: one panel row of 2 n_E doubles
+    per nonzero and column channel, from L2 / MALL) and the block products
+    (2 N^2 N_q n_ch 2 n_E flops each)."""
+    ctx.set_timing(P.WPCD_TIME_SOLVE)
+    ctx.reset_timing()
+    ctx.solve(energies, prec)
+    ctx.synchronize()
+    tim = ctx.timing()
+    ctx.set_timing(0)
+    W = 2 * len(energies)
+    vsize = 8 if prec == P.WPCD_FP64 else 4
+    sp_ms, sp_n = tim["spmm"]
+    t_sp = sp_ms / sp_n / 1e3
+    p0_bytes = nnz * (nch * nch * vsize + 4) + 8 * (n * n + 1)
+    gather = nnz * nch * W * 8
+    bl_ms = tim["apply_vt"][0] + tim["apply_o"][0]
+    bl_n = tim["apply_vt"][1] + tim["apply_o"][1]
+    t_bl = bl_ms / bl_n / 1e3
+    flops = 2.0 * n * n * n * nch * W
+    return {"spmm": {"us_per_launch": 1e6 * t_sp, "launches": sp_n,
+                     "p0_stream_bytes": p0_bytes, "p0_stream_GBps": p0_bytes / t_sp / 1e9,
+                     "p0_stream_frac_hbm": p0_bytes / t_sp / 1e9 / PEAK_HBM_GBS,
+                     "x_gather_bytes": gather, "x_gather_GBps": gather / t_sp / 1e9},
+            "block_product": {"us_per_launch": 1e6 * t_bl, "launches": bl_n, "flops": flops,
+                              "TFLOPs": flops / t_bl / 1e12,
+                              "frac_fp64_peak": flops / t_bl / 1e12 / PEAK_FP64_VECTOR_TFLOPS}}
+
+
+def preselect_rate(tim, nnz, n_cells, builds):
+    """Pre-selection (count + scan + fill) HIP-event time per build against
+    its algorithmic bytes: 4 B column per nonzero + 8 B row pointer per
+    row."""
+    ms = sum(tim.get(k, (0.0, 1))[0] for k in ("preselect_count", "preselect_scan",
+                                                "preselect_fill")) / builds
+    nbytes = 4 * nnz + 8 * (n_cells + 1)
+    return {"us": 1e3 * ms, "bytes": nbytes, "GBps": nbytes / (ms / 1e3) / 1e9,
+            "frac_hbm": nbytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS}
+
+
 def c3_measure(P):
     """The 270k-basis case beside the main line: L = 2+ channels (0,2), (2,0),
     (2,2), 300 x 300 bins, the same Yukawa sum fitted to -0.1, 8 energies.
@@ -140,6 +238,12 @@ def c3_measure(P):
     nnz = ctx.build_p(P.WPCD_MIXED)
     ctx.synchronize()
     t_build = time.perf_counter() - t
+    ctx.set_timing(P.WPCD_TIME_P0)
+    ctx.reset_timing()
+    ctx.build_p(P.WPCD_MIXED)
+    ctx.synchronize()
+    presel = preselect_rate(ctx.timing(), nnz, 300 * 300, 1)
+    ctx.set_timing(0)
 
     def solve(prec):
         ctx.solve(ENERGIES, prec)            # tune + capture
@@ -151,10 +255,12 @@ def c3_measure(P):
         return best / len(ENERGIES), res
 
     s_mixed, r_mixed = solve(P.WPCD_MIXED)
+    rates_mixed = solve_kernel_rates(P, ctx, P.WPCD_MIXED, ENERGIES, nnz, 300, 3)
     s_refine, r_refine = solve(P.WPCD_MIXED_REFINE)
     s_bf16, r_bf16 = solve(P.WPCD_MIXED_BF16)
     ctx.build_p(P.WPCD_FP64)
     s_fp64, r_fp64 = solve(P.WPCD_FP64)
+    rates_fp64 = solve_kernel_rates(P, ctx, P.WPCD_FP64, ENERGIES, nnz, 300, 3)
     ok = [k for k, r in enumerate(r_fp64) if r.status == P.WPCD_OK]
 
     def err(ra):
@@ -172,7 +278,9 @@ def c3_measure(P):
                                  "mixed_bf16": sum(r.iters for r in r_bf16) / len(r_bf16),
                                  "fp64": sum(r.iters for r in r_fp64) / len(r_fp64)},
             "max_rel_amp_err_vs_fp64": {"mixed": err(r_mixed), "mixed_refine": err(r_refine),
-                                        "mixed_bf16": err(r_bf16)}}
+                                        "mixed_bf16": err(r_bf16)},
+            "preselect": presel,
+            "solve_kernels": {"mixed": rates_mixed, "fp64": rates_fp64}}
 
 
 def c5_measure(P, n_var, n_e, sweep):
@@ -289,12 +397,11 @@ def main():
                     help="no GPU: only the oracle baseline on every N-th cell row with this "
                          "process's OMP_NUM_THREADS; prints its JSON (used for the 1-thread "
                          "figure, run as a child before the GPU is touched)")
-    ap.add_argument("--c4", type=str, default="",
-                    help="uneven systems solved together: VARIANTS,ENERGIES (e.g. 6,64); off by "
-                         "default")
-    ap.add_argument("--c5", type=str, default="",
+    ap.add_argument("--c4", type=str, default="6,64",
+                    help="uneven systems solved together: VARIANTS,ENERGIES ('' to skip)")
+    ap.add_argument("--c5", type=str, default="64,64,256",
                     help="learned warm start on the 270k basis: VARIANTS,ENERGIES,SWEEP "
-                         "(e.g. 64,64,256); off by default (about a minute)")
+                         "('' to skip)")
     args = ap.parse_args()
     if args.cpu_only:
         print(json.dumps(cpu_baseline(args.cpu_only, int(os.environ.get("OMP_NUM_THREADS", "1")))),
@@ -357,6 +464,14 @@ def main():
         return min(ts) / len(ENERGIES), r
 
     s_mixed, r_mixed = solve_time(P.WPCD_MIXED)
+    rates_mixed = solve_kernel_rates(P, ctx, P.WPCD_MIXED, ENERGIES, nnz, N, 1)
+    # fraction of Gauss pairs with a non-empty cosine interval (sampled)
+    import numpy as np
+    rp_h, col_h, _ = ctx.get_p(values=False)
+    grid = np.array([10.0 * (1.0 - math.cos(math.pi * k / (2 * N))) for k in range(N + 1)])
+    grid[0], grid[N] = 0.0, 10.0
+    act_frac, act_n = active_pair_fraction(grid, grid, NGQ,
+                                           np.repeat(np.arange(N * N), np.diff(rp_h)), col_h)
     solve_time(P.WPCD_MIXED_REFINE, reps=1)     # tune + capture
     s_refine, r_refine = solve_time(P.WPCD_MIXED_REFINE)
     solve_time(P.WPCD_MIXED_BF16, reps=1)
@@ -384,6 +499,7 @@ def main():
     tim64 = ctx.timing()
     ctx.set_timing(0)
     s_fp64, r_fp64 = solve_time(P.WPCD_FP64)
+    rates_fp64 = solve_kernel_rates(P, ctx, P.WPCD_FP64, ENERGIES, nnz, N, 1)
 
     def amp_err(ra):
         return max(abs(complex(x.U_re, x.U_im) - complex(y.U_re, y.U_im)) / abs(complex(y.U_re, y.U_im))
@@ -392,6 +508,7 @@ def main():
     def mean_iters(ra):
         return sum(x.iters for x in ra) / len(ra)
 
+    presel = preselect_rate(tim, nnz, N * N, args.steps)
     elem_ms, elem_n = tim.get("p0_elem_f32", (0.0, 1))
     elem_avg_s = elem_ms / max(elem_n, 1) / 1e3
     flops = algorithmic_flops_per_element(NGQ, NGX) * nnz
@@ -435,12 +552,17 @@ def main():
                     "fp64_elements_per_s": nnz / fp64_build,
                     "elem_kernel_f32_ms": 1e3 * elem_avg_s,
                     "elem_kernel_f64_ms": e64_ms / max(e64_n, 1),
-                    "preselect_ms": sum(tim.get(k, (0.0, 1))[0] for k in
-                                        ("preselect_count", "preselect_scan", "preselect_fill"))
-                    / args.steps},
+                    "preselect_ms": presel["us"] / 1e3, "preselect": presel},
+        "solve_kernels": {"mixed": rates_mixed, "fp64": rates_fp64},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": measured_traffic(), "kernel": "p0_elem_f32"},
+                     "traffic": measured_traffic(), "kernel": "p0_elem_f32",
+                     "flops_per_cell_pair": algorithmic_flops_per_element(NGQ, NGX),
+                     "active_pair_frac": act_frac, "active_pair_sample": act_n,
+                     "achieved_active": achieved * (23 + 7 * NGX * act_frac) / (23 + 7 * NGX),
+                     "note": "achieved counts the cosine rule for all n_q^2 Gauss pairs of every "
+                             "cell pair (an upper bound of the useful work); achieved_active "
+                             "counts it only for the pairs with a non-empty interval"},
     }
     out["autotune"] = {f'{e["name"]} [{e["key"]}]': e["choice"] for e in ctx.autotune()}
     if not args.no_c3:
@@ -454,10 +576,12 @@ def main():
     if rank == 0 and not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_stride, threads)
+        out["cpu_baseline"]["solve"] = cpu_solve_baseline(threads)
         out["cpu_baseline_1thread"] = cpu1
     ctx.close()
     if args.copy_calib_mb:
         out["copy_calib_bytes"] = copy_calibration(args.copy_calib_mb << 20)
+        out["torch_copy_calib_bytes"] = torch_copy_calibration(args.copy_calib_mb << 20)
     print(json.dumps(out), flush=True)
 
 
