@@ -13,7 +13,8 @@ The steps follow the paper (Pomerantsev, Kukulin, Rubtsova, Sakhiev,
    h1 = h0 + v diagonalised to give the rotation O (eq.(exp_z));
 3. pre-selection of the nonzero lattice elements (Sec. IV.B);
 4. the lattice permutation matrix P0 (eqs.(perm),(gal));
-5. the channel resolvent G1 (Sec. II.D, diagonal in the channel WP basis);
+5. the channel resolvent G1 (Sec. II.D, diagonal in the channel WP basis),
+   at E or averaged over E's on-shell energy bin (Sec. II.C);
 6. the factored kernel K = O P0 V~ G1 with V~ = O^T V1 (eq.(kernel));
 7. the matrix Faddeev equation U = P V1 + P V1 G1 U (eq.(m_pvg)) for the
    on-shell column, by dense LU, by GMRES, and by the paper's iterations
@@ -373,14 +374,75 @@ def resolvent_bin(E: float, eps_k: float, qlo: float, qhi: float, qmax: float):
     raise OnEdge("zero spectator energy")
 
 
-def resolvent(sysm: System, E: float):
-    """Diagonal of G1(E) in the channel WP basis, shape (nch, Nq, Np)."""
+def log_integral(s: float, qa: float, qb: float) -> float:
+    """F(s) = int_qa^qb ln|s - 3/4 q^2| dq in closed form (b = sqrt(3)/2):
+    s > 0, a = sqrt(s): [((b q - a)(ln|b q - a| - 1) + (a + b q)(ln(a + b q) - 1)) / b];
+    s < 0, k = sqrt(-s): [q ln(k^2 + b^2 q^2) - 2 q + (2 k / b) atan(b q / k)];
+    s = 0: [2 q (ln(b q) - 1)]."""
+    b = math.sqrt(3.0) / 2.0
+
+    def tlogt(t):
+        return t * (math.log(abs(t)) - 1.0) if t != 0.0 else 0.0
+
+    def prim(q):
+        if s > 0.0:
+            a = math.sqrt(s)
+            return (tlogt(b * q - a) + tlogt(a + b * q)) / b
+        if s < 0.0:
+            kap = math.sqrt(-s)
+            return q * math.log(-s + 0.75 * q * q) - 2.0 * q + 2.0 * kap / b * math.atan(b * q / kap)
+        return 2.0 * tlogt(b * q) / b if q > 0.0 else 0.0
+
+    return prim(qb) - prim(qa)
+
+
+def shell_overlap(s1: float, s2: float, qa: float, qb: float) -> float:
+    """Length of {q in [qa, qb] : s1 < 3/4 q^2 < s2}."""
+    if s2 <= 0.0:
+        return 0.0
+    q1 = math.sqrt(4.0 * s1 / 3.0) if s1 > 0.0 else 0.0
+    q2 = math.sqrt(4.0 * s2 / 3.0)
+    return max(0.0, min(qb, q2) - max(qa, q1))
+
+
+def resolvent_bin_avg(E1: float, E2: float, eps_k: float, qlo: float, qhi: float):
+    """The channel resolvent eigenvalue averaged over the on-shell energy
+    interval [E1, E2] (Sec. II.C, the bin average of g_0i(E) carried over
+    to the three-body channel resolvent):
+      (1/(D dq)) int_{E1}^{E2} dE int_{qlo}^{qhi} dq / (E - eps_k - 3/4 q^2 + i0),
+    D = E2 - E1, dq = qhi - qlo.  The E integral is ln|E2 - c| - ln|E1 - c|
+    - i pi [E1 < c < E2] with c = eps_k + 3/4 q^2; the q integral of the logs
+    is log_integral, that of the step the overlap length."""
+    D, dq = E2 - E1, qhi - qlo
+    s1, s2 = E1 - eps_k, E2 - eps_k
+    re = (log_integral(s2, qlo, qhi) - log_integral(s1, qlo, qhi)) / (D * dq)
+    im = -math.pi * shell_overlap(s1, s2, qlo, qhi) / (D * dq)
+    return complex(re, im)
+
+
+def energy_bin(sysm: System, E: float):
+    """On-shell energy interval of E for the averaged resolvent: the
+    energies eps*_0 + 3/4 q^2 over the entrance spectator bin j0 that holds
+    q0 (every E in it gives the same averaged kernel and amplitudes)."""
+    a0, j0, q0, idx = entrance(sysm, E)
+    eb = sysm.eps[0][0]
+    return eb + 0.75 * sysm.q[j0] ** 2, eb + 0.75 * sysm.q[j0 + 1] ** 2
+
+
+def resolvent(sysm: System, E: float, averaged: bool = False):
+    """Diagonal of G1(E) in the channel WP basis, shape (nch, Nq, Np); with
+    averaged, each eigenvalue averaged over E's on-shell energy bin."""
     G = np.zeros((len(sysm.chans), sysm.Nq, sysm.Np), dtype=complex)
     qmax = sysm.q[-1]
+    if averaged:
+        E1, E2 = energy_bin(sysm, E)
     for a, (l, lam) in enumerate(sysm.chans):
         for j in range(sysm.Nq):
             for k in range(sysm.Np):
-                G[a, j, k] = resolvent_bin(E, sysm.eps[l][k], sysm.q[j], sysm.q[j + 1], qmax)
+                if averaged:
+                    G[a, j, k] = resolvent_bin_avg(E1, E2, sysm.eps[l][k], sysm.q[j], sysm.q[j + 1])
+                else:
+                    G[a, j, k] = resolvent_bin(E, sysm.eps[l][k], sysm.q[j], sysm.q[j + 1], qmax)
     return G
 
 
@@ -494,9 +556,9 @@ def gmres(matvec, b, tol=1e-13, m=50, max_restarts=200, x0=None):
     return x, its, np.linalg.norm(r) / bn
 
 
-def solve_gmres(sysm: System, E: float, tol=1e-13, m=50):
+def solve_gmres(sysm: System, E: float, tol=1e-13, m=50, averaged=False):
     a0, j0, q0, idx = entrance(sysm, E)
-    G = resolvent(sysm, E)
+    G = resolvent(sysm, E, averaged)
     b = rhs(sysm, idx)
     u, its, res = gmres(lambda y: y - apply_K(sysm, G, y), b, tol=tol, m=m)
     return u, its, res
@@ -560,33 +622,57 @@ class Amplitude:
     S: complex
     delta: float
     eta: float
-    breakup: list   # (channel, k, j_k, S_k0)
+    breakup: list   # (channel, k, j, S_(k j)0)
+    breakup_dist: list = None   # (channel, k, eps*_k, sum_j |S_(k j)0|^2, bins)
 
 
-def amplitudes(sysm: System, E: float, u):
-    """Elastic amplitude A = (2/(3 q0)) U00 / dq_j0 (Sec. III.B with m = 1),
-    S = 1 - 2 pi i A; breakup pseudostate elements
-    S_k0 = -2 pi i sqrt(rho_k rho_0) u_k, rho = 2/(3 q dq)."""
+def amplitudes(sysm: System, E: float, u, averaged: bool = False):
+    """Elastic amplitude A = rho0 U00 with rho0 = 2/(3 q0 dq_j0) (Sec.
+    III.B with m = 1), S = 1 - 2 pi i A; breakup elements
+    S_(kj)0 = -2 pi i sqrt(rho_kj rho_0) u_(kj) of every open channel state,
+    rho = -Im G1 / pi: the pseudostate's on-shell bin with rho = 2/(3 q dq)
+    for the resolvent at E; for the averaged resolvent every bin j whose
+    shell overlaps the on-shell energy bin [E1, E2], rho = overlap / (D dq),
+    and rho0 = 1 / D (the elastic state's whole bin).  breakup_dist sums
+    |S|^2 over the bins of each pseudostate: the breakup distribution over
+    the pair energy eps*_k."""
     a0, j0, q0, idx = entrance(sysm, E)
     dq = sysm.q[1:] - sysm.q[:-1]
-    rho0 = 2.0 / (3.0 * q0 * dq[j0])
+    if averaged:
+        E1, E2 = energy_bin(sysm, E)
+        D = E2 - E1
+        rho0 = 1.0 / D
+    else:
+        rho0 = 2.0 / (3.0 * q0 * dq[j0])
     U00 = u[idx]
     A = rho0 * U00
     S = 1.0 - 2j * math.pi * A
-    br = []
+    br, dist = [], []
     for a, (l, lam) in enumerate(sysm.chans):
         for k, ek in enumerate(sysm.eps[l]):
-            if (a == a0 and k == 0) or ek >= E:
+            if a == a0 and k == 0:
                 continue
-            qk = math.sqrt(4.0 * (E - ek) / 3.0)
-            jk = int(np.searchsorted(sysm.q, qk) - 1)
-            if jk < 0 or jk >= sysm.Nq:
+            states = []
+            if averaged:
+                for j in range(sysm.Nq):
+                    ov = shell_overlap(E1 - ek, E2 - ek, sysm.q[j], sysm.q[j + 1])
+                    if ov > 0.0:
+                        states.append((j, ov / (D * dq[j])))
+            elif ek < E:
+                qk = math.sqrt(4.0 * (E - ek) / 3.0)
+                jk = int(np.searchsorted(sysm.q, qk) - 1)
+                if 0 <= jk < sysm.Nq:
+                    states.append((jk, 2.0 / (3.0 * qk * dq[jk])))
+            if not states:
                 continue
-            rk = 2.0 / (3.0 * qk * dq[jk])
-            Sk = -2j * math.pi * math.sqrt(rk * rho0) * u[(a * sysm.Nq + jk) * sysm.Np + k]
-            br.append((a, k, jk, Sk))
+            tot = 0.0
+            for j, rk in states:
+                Sk = -2j * math.pi * math.sqrt(rk * rho0) * u[(a * sysm.Nq + j) * sysm.Np + k]
+                br.append((a, k, j, Sk))
+                tot += abs(Sk) ** 2
+            dist.append((a, k, float(ek), tot, len(states)))
     d = 0.5 * math.atan2(S.imag, S.real)
-    return Amplitude(E, q0, j0, U00, A, S, d, abs(S), br)
+    return Amplitude(E, q0, j0, U00, A, S, d, abs(S), br, dist)
 
 
 # ----------------------------------------------------------- bound state
