@@ -465,6 +465,18 @@ def main():
 
     s_mixed, r_mixed = solve_time(P.WPCD_MIXED)
     rates_mixed = solve_kernel_rates(P, ctx, P.WPCD_MIXED, ENERGIES, nnz, N, 1)
+    # the energy-averaged channel resolvent beside the one at E: elastic
+    # phases and inelasticities at the same energies
+    solve_time(P.WPCD_MIXED, reps=1, resolvent=P.WPCD_RESOLVENT_AVERAGED)
+    s_avg, r_avg = solve_time(P.WPCD_MIXED, resolvent=P.WPCD_RESOLVENT_AVERAGED)
+    resolvent_cmp = {
+        "energies": list(ENERGIES),
+        "delta_deg_at_E": [math.degrees(r.delta) for r in r_mixed],
+        "delta_deg_averaged": [math.degrees(r.delta) for r in r_avg],
+        "eta_at_E": [r.eta for r in r_mixed], "eta_averaged": [r.eta for r in r_avg],
+        "solve_s_per_energy_averaged": s_avg,
+        "note": "averaged: channel resolvent eigenvalues averaged over the on-shell energy bin "
+                "(histogram amplitudes, flux factor 1/D); mixed tier"}
     # fraction of Gauss pairs with a non-empty cosine interval (sampled)
     import numpy as np
     rp_h, col_h, _ = ctx.get_p(values=False)
@@ -554,6 +566,7 @@ def main():
                     "elem_kernel_f64_ms": e64_ms / max(e64_n, 1),
                     "preselect_ms": presel["us"] / 1e3, "preselect": presel},
         "solve_kernels": {"mixed": rates_mixed, "fp64": rates_fp64},
+        "resolvent_variants": resolvent_cmp,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": measured_traffic(), "kernel": "p0_elem_f32",

@@ -113,7 +113,22 @@ typedef struct {
  * channel-basis order, M = n_ch*n_q*n_p.  err_est: nonzero to fill
  * err_vs_fp64 of every result (see wpcd_energy_result); this needs the P0
  * values in FP64 as well, which the first such call computes on the
- * existing structure and keeps (8 B per channel value).                  */
+ * existing structure and keeps (8 B per channel value).
+ * resolvent: WPCD_RESOLVENT_AT_E (default, 0) projects the channel
+ * resolvent on every channel state at the energy E; WPCD_RESOLVENT_AVERAGED
+ * averages each eigenvalue over E's on-shell energy interval (Sec. II.C),
+ * [eps*_1 + 3/4 q_j0^2, eps*_1 + 3/4 q_(j0+1)^2] of width D, the energies of
+ * the entrance spectator bin j0 holding q0:
+ *   (1/(D dq_j)) int dE int dq / (E - eps*_k - 3/4 q^2 + i0)   (closed form).
+ * All energies of one bin then give the same amplitudes (histogram form);
+ * the elastic flux factor is 1/D (A = U / D) and every pseudostate bin whose
+ * shell eps*_k + 3/4 q^2 meets the interval is an open breakup state with
+ * flux factor (its length inside the shell) / (D dq_j).                   */
+#define WPCD_RESOLVENT_AT_E 0
+#define WPCD_RESOLVENT_AVERAGED 1
+/* want_breakup values */
+#define WPCD_BREAKUP_ELEMENTS 1   /* rows (channel, k, j, Re S, Im S) per open state (resolvent at E only) */
+#define WPCD_BREAKUP_DIST 2       /* rows (channel, k, eps*_k, sum_j |S|^2, bins) per pseudostate */
 typedef struct {
     int32_t max_iter;
     int32_t krylov_dim;
@@ -122,13 +137,16 @@ typedef struct {
     int32_t warm_start;
     const double *x0;
     int32_t err_est;
-    int32_t pad_;
+    int32_t resolvent;
 } wpcd_solve_opts;
 
 /* Per-energy result.  status is a wpcd_status value for this energy.
- * U = on-shell element of the transition matrix, A = (2/(3 q0)) U / dq_j0,
- * S = 1 - 2 pi i A (Sec. III.B, m = 1), delta = arg(S)/2, eta = |S|.
- * n_open: open breakup pseudostate channels (breakup_out rows).
+ * U = on-shell element of the transition matrix, A = (2/(3 q0)) U / dq_j0
+ * (A = U / D with the averaged resolvent), S = 1 - 2 pi i A (Sec. III.B,
+ * m = 1), delta = arg(S)/2, eta = |S|.
+ * n_open: rows written to breakup_out for this energy (open breakup states
+ * with WPCD_BREAKUP_ELEMENTS or none asked, pseudostates with open bins with
+ * WPCD_BREAKUP_DIST).
  * warm: 1 if a warm start was kept (alpha != 0); r0: relative residual of
  * the initial vector (1 for the zero start).
  * err_vs_fp64 (opts.err_est set, else NaN): |U - U64| / |U|, the relative
@@ -269,8 +287,13 @@ wpcd_status wpcd_get_p(wpcd_ctx *ctx, int64_t *row_ptr, int32_t *col, double *va
  * K = O P0 V~ G1 (eq.(kernel)) applied on the GPU, and a batched restarted
  * GMRES solve of (1 - K) u = O P0 V~ e0 for the on-shell column of
  * eq.(m_pvg).  out[n_E] receives the amplitudes.  breakup_out, if not NULL
- * and opts->want_breakup, receives per energy up to n_p*n_ch rows of
- * (channel, k, j_k, Re S_k0, Im S_k0) as doubles, row count in n_open.
+ * and opts->want_breakup is set, receives per energy (at offset
+ * e*n_p*n_ch*5 doubles) up to n_p*n_ch rows of 5 doubles, row count in
+ * n_open: WPCD_BREAKUP_ELEMENTS, (channel, k, j_k, Re S_k0, Im S_k0) with
+ * S_k0 = -2 pi i sqrt(rho_k rho_0) u_k (Sec. III.B, breakup as transitions to
+ * the pair's discretised continuum); WPCD_BREAKUP_DIST, the breakup
+ * distribution over the pair energy, (channel, k, eps*_k, sum over the
+ * pseudostate's open bins of |S|^2, number of those bins).
  * Per-energy failures are reported in out[e].status and do not abort the
  * batch.  prec selects the P0 values used (FP64 requires an FP64 build,
  * WPCD_MIXED, WPCD_MIXED_REFINE and WPCD_MIXED_BF16 a mixed one).

@@ -35,6 +35,10 @@ WPCD_TIME_ALL = 7
 WPCD_WARM_NONE = 0
 WPCD_WARM_LEARNED = 1
 WPCD_WARM_GIVEN = 2
+WPCD_RESOLVENT_AT_E = 0
+WPCD_RESOLVENT_AVERAGED = 1
+WPCD_BREAKUP_ELEMENTS = 1
+WPCD_BREAKUP_DIST = 2
 WPCD_TUNE_HEURISTIC = 0
 WPCD_TUNE_MEASURE = 1
 WPCD_TUNE_FORCE = 16
@@ -75,7 +79,7 @@ class wpcd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("krylov_dim", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("want_breakup", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("x0", ctypes.POINTER(ctypes.c_double)),
-                ("err_est", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("err_est", ctypes.c_int32), ("resolvent", ctypes.c_int32)]
 
 
 class wpcd_energy_result(ctypes.Structure):
@@ -273,15 +277,19 @@ def wpcd_get_p(ctx, n_cells, nnz, n_ch=1, values=True):
 
 
 def _opts(max_iter=0, krylov_dim=0, tol=0.0, want_breakup=False, warm_start=WPCD_WARM_NONE,
-          x0=None, err_est=False):
-    return wpcd_solve_opts(max_iter, krylov_dim, tol, 1 if want_breakup else 0, warm_start,
-                           _dp(x0), 1 if err_est else 0, 0)
+          x0=None, err_est=False, resolvent=0):
+    wb = int(want_breakup) if not isinstance(want_breakup, bool) else (1 if want_breakup else 0)
+    return wpcd_solve_opts(max_iter, krylov_dim, tol, wb, warm_start, _dp(x0),
+                           1 if err_est else 0, resolvent)
 
 
 def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0,
                want_breakup=False, n_p=0, n_ch=1, warm_start=WPCD_WARM_NONE, x0=None,
-               err_est=False):
-    """x0 (warm_start=WPCD_WARM_GIVEN): complex array [n_E][M]."""
+               err_est=False, resolvent=0):
+    """want_breakup: False, True / WPCD_BREAKUP_ELEMENTS or WPCD_BREAKUP_DIST
+    (returns the rows per energy beside the results); resolvent: a
+    WPCD_RESOLVENT_* value; x0 (warm_start=WPCD_WARM_GIVEN): complex array
+    [n_E][M]."""
     E = np.ascontiguousarray(energies, dtype=np.float64)
     out = (wpcd_energy_result * max(1, E.size))()
     x0r = None
@@ -290,7 +298,7 @@ def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol
         if x0c.ndim != 2 or x0c.shape[0] != E.size:
             raise ValueError("x0 must be [n_E][M] complex")
         x0r = x0c.view(np.float64).reshape(-1)
-    opts = _opts(max_iter, krylov_dim, tol, want_breakup, warm_start, x0r, err_est)
+    opts = _opts(max_iter, krylov_dim, tol, want_breakup, warm_start, x0r, err_est, resolvent)
     br = np.zeros(E.size * max(1, n_p) * n_ch * 5) if want_breakup else None
     _check(ctx, lib().wpcd_solve(ctx, _dp(E), E.size, precision, ctypes.byref(opts), out,
                                  _dp(br)))

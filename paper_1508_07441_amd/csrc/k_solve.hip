@@ -64,6 +64,58 @@ __global__ void k_resolvent(const double *__restrict__ q, int np, int nq, int nc
     G[2 * idx + 1] = im;
 }
 
+// Channel resolvent averaged over the on-shell energy interval [E1, E2] of
+// each energy (Sec. II.C; width D = E2 - E1):
+//   G = (1/(D dq_j)) int_{E1}^{E2} dE int_{q_j}^{q_j+1} dq / (E - eps*_k - 3/4 q^2 + i0)
+//     = (F(E2 - eps*_k) - F(E1 - eps*_k)) / (D dq) - i pi L / (D dq),
+// F(s) = int ln|s - 3/4 q^2| dq over the bin, L = the length of the bin
+// inside the shell E1 < eps*_k + 3/4 q^2 < E2.  With b = sqrt(3)/2:
+//   s > 0, a = sqrt(s): [((b q - a)(ln|b q - a| - 1) + (a + b q)(ln(a + b q) - 1)) / b]
+//   s < 0, c = sqrt(-s): [q ln(c^2 + b^2 q^2) - 2 q + (2 c / b) atan(b q / c)]
+//   s = 0: [2 q (ln(b q) - 1)]
+__device__ __forceinline__ double tlogt_m1(double t) {   // t (ln|t| - 1), 0 at t = 0
+    return t != 0.0 ? t * (log(fabs(t)) - 1.0) : 0.0;
+}
+
+__device__ double log_prim(double s, double q) {
+    const double b = 0.86602540378443864676;   // sqrt(3)/2
+    if (s > 0.0) {
+        const double a = sqrt(s);
+        return (tlogt_m1(b * q - a) + tlogt_m1(a + b * q)) / b;
+    }
+    if (s < 0.0) {
+        const double c = sqrt(-s);
+        return q * log(-s + 0.75 * q * q) - 2.0 * q + 2.0 * c / b * atan(b * q / c);
+    }
+    return q > 0.0 ? 2.0 * tlogt_m1(b * q) / b : 0.0;
+}
+
+__global__ void k_resolvent_avg(const double *__restrict__ q, int np, int nq, int nch, int nE,
+                                const double *__restrict__ ebin, ChPtrs eps,
+                                double *__restrict__ G) {
+    const int64_t M = (int64_t)nch * nq * np;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * nE) return;
+    const int e = (int)(idx % nE);
+    const int64_t row = idx / nE;
+    const int k = (int)(row % np);
+    const int j = (int)((row / np) % nq);
+    const int a = (int)(row / ((int64_t)np * nq));
+    const double E1 = ebin[2 * e], E2 = ebin[2 * e + 1];
+    const double s1 = E1 - eps.p[a][k], s2 = E2 - eps.p[a][k];
+    const double ql = q[j], qh = q[j + 1];
+    const double w = (E2 - E1) * (qh - ql);
+    const double re = ((log_prim(s2, qh) - log_prim(s2, ql)) - (log_prim(s1, qh) - log_prim(s1, ql))) / w;
+    double L = 0.0;
+    if (s2 > 0.0) {
+        const double q1 = s1 > 0.0 ? sqrt(4.0 * s1 / 3.0) : 0.0;
+        const double q2 = sqrt(4.0 * s2 / 3.0);
+        L = fmax(0.0, fmin(qh, q2) - fmax(ql, q1));
+    }
+    G[2 * idx] = re;
+    G[2 * idx + 1] = -M_PI * L / w;
+}
+
 // ------------------------------------------------------- block products
 // out[(b, r)][c] = sum_k Mat_b[r][k] y[(b, k)][c],  b = a*nq + j, Mat_b = mats[a]
 // y = G (.) in (complex product, USE_G) or in; out = that (SUB false) or
@@ -1471,7 +1523,7 @@ void restart_cycles(Batch &b, double tol, int max_iter, const std::vector<double
 
 void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
                  int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
-                 GmresOut &out, bool err_est) {
+                 GmresOut &out, bool err_est, const std::vector<double> *ebin) {
     const bool fp64 = prec == WPCD_FP64;
     std::vector<int> &iters = out.iters, &edge_flag = out.edge;
     std::vector<double> &resid = out.resid;
@@ -1543,7 +1595,16 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     WPCD_HIP(hipMemsetAsync(flag, 0, nE * sizeof(int32_t), s));
     ChPtrs eps{};
     for (int a = 0; a < c->nch; ++a) eps.p[a] = c->waves[c->ch_wave[a]].eps.ptr;
-    {
+    if (ebin) {
+        // on-shell energy intervals [E1, E2] per energy (after dE in the scratch)
+        double *dB = dE + nE;
+        WPCD_HIP(hipMemcpyAsync(dB, ebin->data(), 2 * nE * sizeof(double), hipMemcpyHostToDevice,
+                                s));
+        TimedLaunch tl(c->timer, s, "resolvent", WPCD_TIME_SOLVE);
+        hipLaunchKernelGGL(k_resolvent_avg, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s,
+                           c->d_q.ptr, c->np, c->nq, c->nch, nE, dB, eps, b.G);
+        WPCD_HIP(hipGetLastError());
+    } else {
         TimedLaunch tl(c->timer, s, "resolvent", WPCD_TIME_SOLVE);
         hipLaunchKernelGGL(k_resolvent, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, c->d_q.ptr,
                            c->np, c->nq, c->nch, nE, dE, eps, b.G, flag);

@@ -425,6 +425,7 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     double tol = prec == WPCD_FP64 ? 1e-12 : 1e-9;
     int want_breakup = 0, warm_kind = WPCD_WARM_NONE;
     bool err_est = false;
+    int rmode = WPCD_RESOLVENT_AT_E;
     if (opts) {
         if (opts->krylov_dim > 0) m = opts->krylov_dim;
         if (opts->max_iter > 0) max_iter = opts->max_iter;
@@ -432,7 +433,17 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
         want_breakup = opts->want_breakup;
         warm_kind = opts->warm_start;
         err_est = opts->err_est != 0;
+        rmode = opts->resolvent;
     }
+    WPCD_REQUIRE(rmode == WPCD_RESOLVENT_AT_E || rmode == WPCD_RESOLVENT_AVERAGED, WPCD_E_INVALID,
+                 "resolvent must be a WPCD_RESOLVENT_* value");
+    WPCD_REQUIRE(want_breakup >= 0 && want_breakup <= WPCD_BREAKUP_DIST, WPCD_E_INVALID,
+                 "want_breakup must be 0, WPCD_BREAKUP_ELEMENTS or WPCD_BREAKUP_DIST");
+    WPCD_REQUIRE(!(rmode == WPCD_RESOLVENT_AVERAGED && want_breakup == WPCD_BREAKUP_ELEMENTS),
+                 WPCD_E_INVALID,
+                 "breakup elements need the resolvent at E (a pseudostate has several open "
+                 "bins with the averaged one): ask for WPCD_BREAKUP_DIST");
+    const bool averaged = rmode == WPCD_RESOLVENT_AVERAGED;
     WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
     WPCD_REQUIRE(warm_kind >= WPCD_WARM_NONE && warm_kind <= WPCD_WARM_GIVEN, WPCD_E_INVALID,
                  "warm_start must be a WPCD_WARM_* value");
@@ -455,7 +466,7 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     std::vector<wpcd_energy_result> res(n_E);
     std::vector<int> active;
     std::vector<int64_t> idx0v;
-    std::vector<double> rho0v;
+    std::vector<double> rho0v, ebinv;
     for (int e = 0; e < n_E; ++e) {
         wpcd_energy_result &r = res[e];
         std::memset(&r, 0, sizeof(r));
@@ -481,7 +492,15 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
         r.j0 = j0;
         active.push_back(e);
         idx0v.push_back(((int64_t)a0 * c->nq + j0) * c->np);
-        rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
+        if (averaged) {
+            // on-shell energy interval: the energies of the entrance bin j0
+            const double e1 = eb + 0.75 * c->q[j0] * c->q[j0], e2 = eb + 0.75 * c->q[j0 + 1] * c->q[j0 + 1];
+            ebinv.push_back(e1);
+            ebinv.push_back(e2);
+            rho0v.push_back(1.0 / (e2 - e1));
+        } else {
+            rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
+        }
     }
     // the error estimate needs the FP64 P0 values on the same structure
     if (err_est && !c->has_val64 && !active.empty()) {
@@ -491,12 +510,16 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     const int kBatch = 32;
     for (size_t b0 = 0; b0 < active.size(); b0 += kBatch) {
         const int nb = (int)std::min(active.size() - b0, (size_t)kBatch);
-        std::vector<double> Eb(nb), rho0(nb);
+        std::vector<double> Eb(nb), rho0(nb), ebin;
         std::vector<int64_t> idx0(nb);
         for (int t = 0; t < nb; ++t) {
             Eb[t] = E[active[b0 + t]];
             idx0[t] = idx0v[b0 + t];
             rho0[t] = rho0v[b0 + t];
+            if (averaged) {
+                ebin.push_back(ebinv[2 * (b0 + t)]);
+                ebin.push_back(ebinv[2 * (b0 + t) + 1]);
+            }
         }
         WarmCtx wc;
         wc.kind = warm_kind;
@@ -514,7 +537,8 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
         }
         GmresOut go;
         gmres_batch(c, Eb, idx0, prec, m, max_iter, tol,
-                    warm_kind == WPCD_WARM_NONE ? nullptr : warm_fill, &wc, go, err_est);
+                    warm_kind == WPCD_WARM_NONE ? nullptr : warm_fill, &wc, go, err_est,
+                    averaged ? &ebin : nullptr);
         // amplitude list: elastic first, then open breakup pseudostates
         std::vector<int64_t> rows;
         std::vector<int32_t> ens;
@@ -525,13 +549,34 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
             ens.push_back(t);
             rho.push_back(rho0[t]);
         }
+        // open breakup states: the pseudostate's on-shell bin (resolvent at
+        // E, rho = 2/(3 q dq)), or every bin whose shell eps + 3/4 q^2 meets
+        // the on-shell energy interval (averaged, rho = overlap / (D dq))
         for (int t = 0; t < nb; ++t) {
             first_br[t] = (int)rows.size();
             n_br[t] = 0;
             for (int a = 0; a < c->nch; ++a) {
                 const std::vector<double> &ev = c->waves[c->ch_wave[a]].h_eps;
                 for (int k = 0; k < c->np; ++k) {
-                    if ((a == a0 && k == 0) || !(ev[k] < Eb[t])) continue;
+                    if (a == a0 && k == 0) continue;
+                    if (averaged) {
+                        const double e1 = ebin[2 * t], e2 = ebin[2 * t + 1], D = e2 - e1;
+                        const double s1 = e1 - ev[k], s2 = e2 - ev[k];
+                        if (!(s2 > 0.0)) continue;
+                        const double q1 = s1 > 0.0 ? std::sqrt(4.0 * s1 / 3.0) : 0.0;
+                        const double q2 = std::sqrt(4.0 * s2 / 3.0);
+                        int j = (int)(std::upper_bound(c->q.begin(), c->q.end(), q1) - c->q.begin()) - 1;
+                        for (j = std::max(j, 0); j < c->nq && c->q[j] < q2; ++j) {
+                            const double ov = std::min(c->q[j + 1], q2) - std::max(c->q[j], q1);
+                            if (!(ov > 0.0)) continue;
+                            rows.push_back(((int64_t)a * c->nq + j) * c->np + k);
+                            ens.push_back(t);
+                            rho.push_back(ov / (D * (c->q[j + 1] - c->q[j])));
+                            ++n_br[t];
+                        }
+                        continue;
+                    }
+                    if (!(ev[k] < Eb[t])) continue;
                     const double qk = std::sqrt(4.0 * (Eb[t] - ev[k]) / 3.0);
                     if (qk >= qmax) continue;
                     const int jk =
@@ -566,14 +611,14 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
             r.S_im = amp[4 * t + 3];
             r.delta = 0.5 * std::atan2(r.S_im, r.S_re);
             r.eta = std::hypot(r.S_re, r.S_im);
-            r.n_open = n_br[t];
+            r.n_open = n_br[t];   // open channel states (elements); distribution rows below
             if (err_est) {
                 const double du = std::hypot(go.dU[2 * t], go.dU[2 * t + 1]);
                 const double u = std::hypot(go.U[2 * t], go.U[2 * t + 1]);
                 r.err_vs_fp64 = u > 0.0 ? du / u : std::numeric_limits<double>::quiet_NaN();
             }
             if (r.status == WPCD_OK) ok.push_back(t);
-            if (breakup_out && want_breakup) {
+            if (breakup_out && want_breakup == WPCD_BREAKUP_ELEMENTS) {
                 double *dst = breakup_out + (size_t)e * c->np * c->nch * 5;
                 for (int u = 0; u < n_br[t]; ++u) {
                     const int row = first_br[t] + u;
@@ -587,6 +632,32 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
                     dst[5 * u + 3] = amp[4 * row + 2];
                     dst[5 * u + 4] = amp[4 * row + 3];
                 }
+            } else if (want_breakup == WPCD_BREAKUP_DIST) {
+                // one row per pseudostate with open bins, in row order
+                // (channel major, then k): summed |S|^2 over its bins
+                double *dst = breakup_out ? breakup_out + (size_t)e * c->np * c->nch * 5 : nullptr;
+                int nd = 0;
+                for (int u = 0; u < n_br[t];) {
+                    const int64_t r0 = rows[first_br[t] + u];
+                    const int a = (int)(r0 / ((int64_t)c->nq * c->np)), k = (int)(r0 % c->np);
+                    double ptot = 0.0;
+                    int nbin = 0;
+                    for (; u < n_br[t]; ++u, ++nbin) {
+                        const int row = first_br[t] + u;
+                        const int64_t rr = rows[row];
+                        if ((int)(rr / ((int64_t)c->nq * c->np)) != a || (int)(rr % c->np) != k) break;
+                        ptot += amp[4 * row + 2] * amp[4 * row + 2] + amp[4 * row + 3] * amp[4 * row + 3];
+                    }
+                    if (dst) {
+                        dst[5 * nd + 0] = a;
+                        dst[5 * nd + 1] = k;
+                        dst[5 * nd + 2] = c->waves[c->ch_wave[a]].h_eps[k];
+                        dst[5 * nd + 3] = ptot;
+                        dst[5 * nd + 4] = nbin;
+                    }
+                    ++nd;
+                }
+                r.n_open = nd;
             }
         }
         if (collect && !ok.empty()) {

@@ -328,7 +328,8 @@ struct GmresOut {
 using WarmFill = void (*)(wpcd_ctx *c, void *user, double *x, int nE);
 void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
                  int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
-                 GmresOut &out, bool err_est = false);
+                 GmresOut &out, bool err_est = false,
+                 const std::vector<double> *ebin = nullptr);   // [nE][2]: averaged resolvent
 void arnoldi_kernel(wpcd_ctx *c, double E, int m, std::vector<double> &H, int &steps);
 void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
                       const std::vector<int32_t> &ens, const std::vector<double> &rho,

@@ -559,6 +559,72 @@ def test_err_vs_fp64_matches_true_error(ctx, P):
         assert r.status == P.WPCD_OK and r.err_vs_fp64 < 1e-10, (r.E, r.err_vs_fp64)
 
 
+def _check_averaged(ctx, P, sysm, energies, label, prec, tol):
+    """Amplitudes and the breakup distribution with the energy-averaged
+    resolvent against the oracle's."""
+    res, dist = ctx.solve(energies, prec, resolvent=P.WPCD_RESOLVENT_AVERAGED,
+                          want_breakup=P.WPCD_BREAKUP_DIST)
+    for r, rows, E in zip(res, dist, energies):
+        assert r.status == P.WPCD_OK, (label, E, P.STATUS_NAMES[r.status])
+        u, _, _ = O.solve_gmres(sysm, E, averaged=True)
+        a = O.amplitudes(sysm, E, u, averaged=True)
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - a.U00) <= tol * abs(a.U00), (label, E, U, a.U00)
+        assert abs(complex(r.S_re, r.S_im) - a.S) <= tol * 10, (label, E)
+        assert len(rows) == len(a.breakup_dist), (label, E, len(rows), len(a.breakup_dist))
+        pmax = max([d[3] for d in a.breakup_dist], default=0.0)
+        for g, o in zip(rows, a.breakup_dist):
+            assert (int(g[0]), int(g[1]), int(g[4])) == (o[0], o[1], o[4]), (label, E, g, o)
+            assert abs(g[2] - o[2]) <= 1e-12 * max(1.0, abs(o[2]))
+            assert abs(g[3] - o[3]) <= tol * max(o[3], 1e-3 * pmax), (label, E, g[3], o[3])
+        say(f"[{label}] E={E:+.3f}: |S|={abs(a.S):.12f} delta={math.degrees(a.delta):+.4f} deg, "
+            f"{len(rows)} pseudostates open, sum P={sum(d[3] for d in a.breakup_dist):.4e}")
+    return res
+
+
+def test_averaged_resolvent_parity(ctx, P):
+    """The energy-averaged channel resolvent (Sec. II.C): FP64 amplitudes and
+    breakup distributions against the oracle's (1e-10) on an s-wave grid and
+    a three-channel L = 2+ grid, the mixed tier within 1e-6; |S| = 1 below
+    breakup; all energies of one bin alike; elements are refused with it."""
+    n = 24
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, potential=YAM)
+    ctx.build_p(P.WPCD_FP64)
+    sysm = _oracle_system_yam(n, 16)
+    energies = [-0.09, -0.04, 0.05, 0.3, 0.8, 1.7]
+    say("[avg24] FP64")
+    res = _check_averaged(ctx, P, sysm, energies, "avg24", P.WPCD_FP64, 1e-10)
+    for r in res[:2]:
+        assert abs(math.hypot(r.S_re, r.S_im) - 1.0) < 1e-12
+    # histogram form: another energy of the same bin gives the same amplitude
+    E1, E2 = O.energy_bin(sysm, 0.3)
+    r2 = ctx.solve([E1 + 0.9 * (E2 - E1)], P.WPCD_FP64, resolvent=P.WPCD_RESOLVENT_AVERAGED)[0]
+    assert abs(complex(r2.U_re, r2.U_im) - complex(res[3].U_re, res[3].U_im)) <= 1e-11 * abs(
+        complex(res[3].U_re, res[3].U_im))
+    # the distribution also with the resolvent at E (one bin per pseudostate)
+    _, dist_e = ctx.solve([0.8], P.WPCD_FP64, want_breakup=P.WPCD_BREAKUP_DIST)
+    a = O.amplitudes(sysm, 0.8, O.solve_gmres(sysm, 0.8)[0])
+    assert len(dist_e[0]) == len(a.breakup_dist)
+    for g, o in zip(dist_e[0], a.breakup_dist):
+        assert int(g[4]) == 1 and abs(g[3] - o[3]) <= 1e-10 * max(o[3], 1e-12)
+    with pytest.raises(P.WpcdError) as ei:
+        ctx.solve([0.8], P.WPCD_FP64, resolvent=P.WPCD_RESOLVENT_AVERAGED,
+                  want_breakup=P.WPCD_BREAKUP_ELEMENTS)
+    assert ei.value.status == P.WPCD_E_INVALID
+    say("[avg24] mixed")
+    ctx.build_p(P.WPCD_MIXED)
+    _check_averaged(ctx, P, sysm, energies, "avg24-mixed", P.WPCD_MIXED, 1e-6)
+    # three channels
+    nc = 12
+    ctx.build_basis(nc, nc, 8.0, 8.0, 8, 16, channels=L2_CHANS, L=2, potential=_yuk_pot(2.0))
+    ctx.build_p(P.WPCD_FP64)
+    p = O.cheb_edges(nc, 8.0)
+    sys3 = O.build_system(p, p.copy(), 2, L2_CHANS, 8, 16,
+                          O.Potential("yukawa", (-2.0, -2.0), YUK_RANGES))
+    say("[avg3ch] FP64")
+    _check_averaged(ctx, P, sys3, [0.2, 0.9, 1.6], "avg3ch", P.WPCD_FP64, 1e-10)
+
+
 def test_max_grid_1024(ctx, P):
     """The largest grid the library takes, 1024 x 1024 bins (cell indices up
     to 2^20 - 1, ~7e8 cell pairs, int64 offsets): sampled rows' columns and
