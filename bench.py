@@ -326,6 +326,32 @@ def c5_measure(P, n_var, n_e, sweep):
             "max_rel_amp_diff_learned_vs_plain": err}
 
 
+def model_fill_measure(P):
+    """The paper's model matrix fills (Sec. IV.A): dense, and sparse at
+    alpha = 0.01 by filtering inside the dense launch or by selecting the
+    kept elements first; GPU time of the fill kernels (HIP events), best of
+    three."""
+    ctx = P.Context(0)
+    out = {}
+    for name, kind, M, K in (("trig", 0, 4096, 256), ("gauss", 1, 2048, 16)):
+        row = {"M": M, "K": K}
+        for label, mode, prec, alpha in (("dense_fp64", 0, P.WPCD_FP64, 1.0),
+                                         ("dense_fp32", 0, P.WPCD_MIXED, 1.0),
+                                         ("filtered_fp32_alpha0.01", 1, P.WPCD_MIXED, 0.01),
+                                         ("selected_fp32_alpha0.01", 2, P.WPCD_MIXED, 0.01)):
+            best = 1e30
+            for _ in range(3):
+                _, ms = ctx.model_fill(kind, mode, M, K, alpha=alpha, seed=SEED, precision=prec)
+                best = min(best, ms)
+            row[label + "_ms"] = best
+        row["elements_per_s_dense_fp32"] = M * M / (row["dense_fp32_ms"] / 1e3)
+        row["selected_over_filtered_speedup"] = (row["filtered_fp32_alpha0.01_ms"]
+                                                 / row["selected_fp32_alpha0.01_ms"])
+        out[name] = row
+    ctx.close()
+    return out
+
+
 C4_SYSTEMS = ((100, 1), (150, 2), (200, 3), (250, 4), (300, 5), (400, 1))
 C4_L2_CHANNELS = ((0, 2), (2, 0), (2, 2), (2, 4), (4, 2))
 
@@ -580,6 +606,7 @@ def main():
     out["autotune"] = {f'{e["name"]} [{e["key"]}]': e["choice"] for e in ctx.autotune()}
     if not args.no_c3:
         out["c3"] = c3_measure(P)
+    out["model_fill"] = model_fill_measure(P)
     if args.c4:
         nv, ne = (int(x) for x in args.c4.split(","))
         out["c4"] = c4_measure(P, nv, ne)

@@ -320,6 +320,30 @@ wpcd_status wpcd_solve_dev(wpcd_ctx *ctx, const double *E_dev, int32_t n_E, wpcd
 wpcd_status wpcd_save_p(wpcd_ctx *ctx, const char *path);
 wpcd_status wpcd_load_p(wpcd_ctx *ctx, const char *path, int64_t *nnz_cells_out);
 
+/* The paper's model matrix fills (Sec. IV.A), a micro-benchmark of filling
+ * a matrix of costly elements on the GPU, dense and sparse:
+ *   kind 0, eq.(Atrig): A(i,j) = sum_{k=1..K} (sin^k u_ij + cos^k w_ij);
+ *   kind 1, eq.(Agau):  A(i,j) = sum_{k=1..K} int_{u_ij}^{w_ij} (sin^k t + cos^k t) dt,
+ *                       by the 48-point Gauss-Legendre rule;
+ * u_ij, w_ij = outputs 2(i M + j) and 2(i M + j) + 1 of the splitmix64
+ * stream of `seed` (counter form mix(seed + (n+1) 0x9E3779B97F4A7C15),
+ * u = (x >> 11) 2^-53).  mode 0: every element, one thread each (the
+ * paper's M^2 threads), into dense_out[M*M] (row major, may be NULL);
+ * mode 1, eq.(Acond) by filtering in the same launch: elements with
+ * u_ij > alpha are zero and not evaluated; mode 2, eq.(Acond) with the kept
+ * elements selected first (ballot compaction, ascending flat index
+ * i M + j) and then evaluated with every lane busy: idx_out[cap] and
+ * val_out[cap] (may be NULL), *nnz_out = the number kept (also when it
+ * exceeds cap, which returns WPCD_E_INVALID).  prec WPCD_FP64 or WPCD_MIXED
+ * (FP32 arithmetic); values are returned as doubles.  *ms_out: GPU time of
+ * the fill's kernels (HIP events on the context's stream).  Limits:
+ * M <= 8192, K <= 4096.  Errors: WPCD_E_INVALID, WPCD_E_NOMEM,
+ * WPCD_E_DEVICE.                                                         */
+wpcd_status wpcd_model_fill(wpcd_ctx *ctx, int32_t kind, int32_t mode, int32_t M, int32_t K,
+                            double alpha, uint64_t seed, wpcd_precision prec, double *dense_out,
+                            int64_t *idx_out, double *val_out, int64_t cap, int64_t *nnz_out,
+                            double *ms_out);
+
 /* Three-body bound state of the homogeneous equation u = K(E) u (eq.(m_pvg)
  * without the driving term): the energy in [e_lo, e_hi] (below the lowest
  * pair level, where K is real) at which the largest real eigenvalue of K(E)

@@ -49,7 +49,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_
 ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_set_potential", "wpcd_pair_spectrum",
                  "wpcd_build_p", "wpcd_build_p_noalloc", "wpcd_get_p", "wpcd_save_p",
                  "wpcd_load_p", "wpcd_solve",
-                 "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_bound_state",
+                 "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_bound_state", "wpcd_model_fill",
                  "wpcd_set_multipliers",
                  "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_autotune",
                  "wpcd_get_autotune", "wpcd_set_graphs", "wpcd_set_timing",
@@ -156,6 +156,10 @@ def lib():
                                  ctypes.POINTER(wpcd_energy_result), dp]
         fp = ctypes.POINTER(ctypes.c_float)
         L.wpcd_bound_state.argtypes = [vp, ctypes.c_double, ctypes.c_double, dp]
+        L.wpcd_model_fill.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                      ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64), dp,
+                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp]
         L.wpcd_save_p.argtypes = [vp, ctypes.c_char_p]
         L.wpcd_load_p.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
         L.wpcd_solve_dev.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int,
@@ -310,6 +314,28 @@ def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol
             brs.append(rows.copy())
         return res, brs
     return res
+
+
+def wpcd_model_fill(ctx, kind, mode, M, K, alpha=1.0, seed=0, precision=WPCD_FP64, cap=None):
+    """Model matrix fill (kind 0 trig, 1 Gauss; mode 0 dense, 1 filtered, 2
+    selected).  Returns (dense M x M array or (idx, val), GPU ms)."""
+    n = ctypes.c_int64()
+    ms = np.zeros(1)
+    if mode != 2:
+        out = np.zeros(M * M)
+        _check(ctx, lib().wpcd_model_fill(ctx, kind, mode, M, K, alpha, seed, precision, _dp(out),
+                                          None, None, 0, ctypes.byref(n), _dp(ms)))
+        return out.reshape(M, M), float(ms[0])
+    if cap is None:   # first call counts
+        lib().wpcd_model_fill(ctx, kind, mode, M, K, alpha, seed, precision, None, None, None, 0,
+                              ctypes.byref(n), _dp(ms))
+        cap = n.value
+    idx = np.zeros(max(cap, 1), dtype=np.int64)
+    val = np.zeros(max(cap, 1))
+    _check(ctx, lib().wpcd_model_fill(ctx, kind, mode, M, K, alpha, seed, precision, None,
+                                      idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(val),
+                                      cap, ctypes.byref(n), _dp(ms)))
+    return (idx[:n.value], val[:n.value]), float(ms[0])
 
 
 def wpcd_bound_state(ctx, e_lo, e_hi):
@@ -470,6 +496,9 @@ class Context:
 
     def bound_state(self, e_lo, e_hi):
         return wpcd_bound_state(self.h, e_lo, e_hi)
+
+    def model_fill(self, kind, mode, M, K, alpha=1.0, seed=0, precision=WPCD_FP64, cap=None):
+        return wpcd_model_fill(self.h, kind, mode, M, K, alpha, seed, precision, cap)
 
     def save_p(self, path):
         wpcd_save_p(self.h, path)

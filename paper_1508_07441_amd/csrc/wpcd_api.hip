@@ -1146,6 +1146,30 @@ wpcd_status wpcd_build_p_noalloc(wpcd_ctx *c, wpcd_precision prec, int64_t *row_
     });
 }
 
+wpcd_status wpcd_model_fill(wpcd_ctx *c, int32_t kind, int32_t mode, int32_t M, int32_t K,
+                            double alpha, uint64_t seed, wpcd_precision prec, double *dense_out,
+                            int64_t *idx_out, double *val_out, int64_t cap, int64_t *nnz_out,
+                            double *ms_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(kind == 0 || kind == 1, WPCD_E_INVALID, "kind must be 0 (trig) or 1 (Gauss)");
+        WPCD_REQUIRE(mode >= 0 && mode <= 2, WPCD_E_INVALID, "mode must be 0, 1 or 2");
+        WPCD_REQUIRE(M >= 1 && M <= 8192 && K >= 1 && K <= 4096, WPCD_E_INVALID,
+                     "need 1 <= M <= 8192 and 1 <= K <= 4096");
+        WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID,
+                     "precision must be WPCD_FP64 or WPCD_MIXED (FP32)");
+        WPCD_REQUIRE(mode != 2 || cap >= 0, WPCD_E_INVALID, "cap < 0");
+        WPCD_REQUIRE(std::isfinite(alpha), WPCD_E_INVALID, "alpha not finite");
+        ModelRequest r{kind, mode, M, K, alpha, seed, prec == WPCD_FP64, dense_out, idx_out, val_out,
+                       cap};
+        ModelResult res{};
+        model_fill(c, r, res);
+        if (nnz_out) *nnz_out = res.nnz;
+        if (ms_out) *ms_out = res.ms;
+        WPCD_REQUIRE(mode != 2 || res.nnz <= cap, WPCD_E_INVALID,
+                     "selected elements (" + std::to_string(res.nnz) + ") exceed cap");
+    });
+}
+
 wpcd_status wpcd_build_p(wpcd_ctx *c, wpcd_precision prec, int64_t *nnz_out) {
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");

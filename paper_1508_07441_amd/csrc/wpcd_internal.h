@@ -271,6 +271,23 @@ void launch_potential(wpcd_ctx *c, int wave, double *v_out);
 void pair_diagonalise(wpcd_ctx *c, int wave, bool want_vectors);
 void launch_vt(wpcd_ctx *c, int wave);
 
+// Model matrix fills of Sec. IV.A (k_model.hip).
+struct ModelRequest {
+    int kind, mode, M, K;   // kind 0 eq.(Atrig), 1 eq.(Agau); mode 0 dense, 1 filtered, 2 selected
+    double alpha;
+    uint64_t seed;
+    bool fp64;
+    double *dense_out;      // host [M*M] (modes 0, 1) or NULL
+    int64_t *idx_out;       // host [cap] (mode 2) or NULL
+    double *val_out;        // host [cap] (mode 2) or NULL
+    int64_t cap;
+};
+struct ModelResult {
+    int64_t nnz;
+    double ms;
+};
+void model_fill(wpcd_ctx *c, const ModelRequest &r, ModelResult &res);
+
 void build_structure(wpcd_ctx *c);   // a3: counts, scan, fill (sets c->nnz)
 void build_values(wpcd_ctx *c, bool fp64);
 // The same into given device buffers: row counts cnt[n_p n_q] and row_ptr
