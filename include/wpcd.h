@@ -356,10 +356,16 @@ wpcd_status wpcd_bound_state(wpcd_ctx *ctx, double e_lo, double e_hi, double *e3
 
 /* wpcd_solve for n_sys independent systems at once (uneven sizes and
  * channel sets allowed): system i is solved in context ctxs[i] at energies
- * E[i][0..n_E[i]) into out[i][0..n_E[i]) (no breakup rows).  Each system is
- * driven by its own host thread on its context's stream, so the systems'
- * kernels share the device.  The contexts must be distinct (a context is
- * not thread-safe) and on the same device or not.  status_out[i] (may be
+ * E[i][0..n_E[i]) into out[i][0..n_E[i]) (no breakup rows).  Contexts on one
+ * device are solved in lockstep by one host thread: the systems' batches of
+ * energies start their GMRES cycles together, and every group of iterations
+ * of all of them is replayed as one captured HIP graph (each system's
+ * launches a branch on its own context's stream), with one convergence
+ * read-back per group; a system whose energies have converged leaves the
+ * cycle (a graph of the remaining ones is captured on first use).  Contexts
+ * on several devices are driven by one host thread each.  The contexts must
+ * be distinct (a context is not thread-safe) and share the Krylov
+ * dimension (one opts).  status_out[i] (may be
  * NULL) receives each system's call status; the return value is the first
  * non-OK one.  opts is shared by all systems, so opts->warm_start may not
  * be WPCD_WARM_GIVEN (one x0 cannot match systems of different sizes).

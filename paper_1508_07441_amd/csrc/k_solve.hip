@@ -1448,82 +1448,247 @@ void rhs_norms(Batch &b, std::vector<double> &st) {
     WPCD_HIP(hipMemcpyAsync(b.S.st, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s));
 }
 
-// Restarted GMRES cycles from x = b.X with r = b.R = b.B - (1 - K) x until
-// every energy's true relative residual |r| / |B| (st[1] = |B|) is <= tol
-// or max_iter iterations are spent.
-void restart_cycles(Batch &b, double tol, int max_iter, const std::vector<double> &st,
-                    std::vector<int> &iters, std::vector<double> &resid) {
-    const int nE = b.nE, m = b.m;
-    wpcd_ctx *c = b.c;
-    hipStream_t s = c->stream;
-    const int64_t vec = b.M * b.W;
-    iters.assign(nE, 0);
-    resid.assign(nE, 1.0);
-    int total = 0;
-    std::vector<double> sth(nE * kSt);
-    const int check_every = 4;
-    // graphs replay launches exactly; kernel timing needs the eager path
-    IterGraphs *graphs = (c->use_graphs && !(c->timer.enabled & WPCD_TIME_SOLVE))
-                             ? graphs_for(b, tol, check_every)
-                             : nullptr;
-    bool all_done = false;
-    while (total < max_iter && !all_done) {
-        // cycle start from r
-        dots(b, b.R, 1, b.R, b.h, nullptr, 0, 0);
-        hipLaunchKernelGGL(k_cycle_start, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.h, nE, m, tol, b.S,
-                           b.inv);
-        hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.inv, b.M, nE, b.R);
-        WPCD_HIP(hipMemcpyAsync(b.Vb, b.R, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
-        WPCD_HIP(hipMemsetAsync(b.H, 0, (size_t)nE * (m + 1) * m * 2 * sizeof(double), s));
-        // iterations in groups of check_every: a full group replays its
-        // captured graph (captured on first use), the rest launch eagerly;
-        // convergence is read back after each group
-        for (int k = 0; k < m && total < max_iter;) {
-            const int kg = std::min({check_every, m - k, max_iter - total});
-            if (graphs && kg == check_every) {
-                hipGraphExec_t &ex = graphs->exec[k / check_every];
-                if (!ex) ex = capture_group(b, k, kg, tol);
-                WPCD_HIP(hipGraphLaunch(ex, s));
-            } else {
-                for (int i = 0; i < kg; ++i) iteration(b, k + i, tol);
-            }
-            k += kg;
-            total += kg;
-            WPCD_HIP(hipMemcpyAsync(sth.data(), b.S.st, sth.size() * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
-            WPCD_HIP(hipStreamSynchronize(s));
-            bool done = true;
-            for (int e = 0; e < nE; ++e) done &= sth[e * kSt + 3] != 0.0;
-            if (done) break;
+// One batch of energies of one system through the restarted GMRES.
+struct GmresRun {
+    Batch b;
+    std::vector<double> st, rn;   // per-energy state (st[1] = |B|), residual norms^2
+    GmresOut *out = nullptr;
+    int max_iter = 0;
+    double tol = 0.0;
+    bool err_est = false;
+    std::vector<int64_t> idx0;
+};
+
+GmresRun *gmres_run_new() { return new GmresRun(); }
+void gmres_run_delete(GmresRun *r) { delete r; }
+
+// Iterations [k, k + n) of several batches (on their own streams, one
+// device) as one executable graph: the first stream forks to the others and
+// joins them at the end, so the batches' launches form parallel branches.
+hipGraphExec_t capture_multi(const std::vector<Batch *> &bs, int k, int n, double tol) {
+    hipStream_t s0 = bs[0]->c->stream;
+    hipGraph_t g = nullptr;
+    std::vector<hipEvent_t> evs;
+    auto cleanup = [&] {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    };
+    WPCD_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    try {
+        hipEvent_t fork;
+        WPCD_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        evs.push_back(fork);
+        WPCD_HIP(hipEventRecord(fork, s0));
+        for (size_t r = 1; r < bs.size(); ++r) WPCD_HIP(hipStreamWaitEvent(bs[r]->c->stream, fork, 0));
+        for (Batch *b : bs)
+            for (int i = 0; i < n; ++i) iteration(*b, k + i, tol);
+        for (size_t r = 1; r < bs.size(); ++r) {
+            hipEvent_t join;
+            WPCD_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+            evs.push_back(join);
+            WPCD_HIP(hipEventRecord(join, bs[r]->c->stream));
+            WPCD_HIP(hipStreamWaitEvent(s0, join, 0));
         }
-        hipLaunchKernelGGL(k_trisolve, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.H, nE, m, b.S, b.y,
-                           b.kuse);
-        hipLaunchKernelGGL(k_xupdate, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.Vb, b.vstride,
-                           b.y, b.kuse, m, b.M, nE, b.X);
-        WPCD_HIP(hipGetLastError());
-        // per-energy iteration count: columns used in this cycle
-        WPCD_HIP(hipMemcpyAsync(sth.data(), b.S.st, sth.size() * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
-        // true residual r = b - (1 - K) x
-        op_apply(b, b.X, b.R, true, true);
-        hipLaunchKernelGGL(k_sub_from, dim3(cdiv(vec, 256)), dim3(256), 0, s, b.B, vec, b.R);
-        dots(b, b.R, 1, b.R, b.h, nullptr, 0, 0);
-        std::vector<double> rn(2 * nE);
-        WPCD_HIP(hipMemcpyAsync(rn.data(), b.h, 2 * nE * sizeof(double), hipMemcpyDeviceToHost, s));
-        WPCD_HIP(hipStreamSynchronize(s));
-        all_done = true;
-        for (int e = 0; e < nE; ++e) {
-            if (resid[e] > tol) iters[e] += (int)sth[e * kSt + 4];
-            const double bn = st[e * kSt + 1];
-            resid[e] = bn > 0 ? std::sqrt(rn[2 * e]) / bn : 0.0;
-            if (resid[e] > tol) all_done = false;
+    } catch (...) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(s0, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        cleanup();
+        throw;
+    }
+    const hipError_t ec = hipStreamEndCapture(s0, &g);
+    cleanup();
+    WPCD_HIP(ec);
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    WPCD_HIP(e);
+    return ex;
+}
+
+// Restarted GMRES cycles of one or several batches in lockstep: from
+// x = b.X with r = b.R = b.B - (1 - K) x until every energy's true relative
+// residual |r| / |B| (st[1] = |B|) is <= tol or max_iter iterations are
+// spent.  All batches start a cycle together and run their groups of
+// check_every iterations together; a group of several batches replays one
+// graph holding all of them (captured on first use per set of batches),
+// a single batch its own graph; convergence is read back after each group,
+// and a batch whose energies have all converged leaves the cycle.
+void gmres_cycles(std::vector<GmresRun *> &runs) {
+    const int check_every = 4;
+    const int m = runs[0]->b.m;
+    for (GmresRun *r : runs)
+        WPCD_REQUIRE(r->b.m == m, WPCD_E_INVALID, "batches solved together need one krylov_dim");
+    struct State {
+        GmresRun *r;
+        std::vector<double> sth;
+        int total = 0;
+        bool all_done = false, in_cycle = false, started = false;
+        IterGraphs *graphs = nullptr;
+    };
+    std::vector<State> xs;
+    bool graphs_ok = true;
+    for (GmresRun *r : runs) {
+        State x;
+        x.r = r;
+        x.sth.assign((size_t)r->b.nE * kSt, 0.0);
+        r->out->iters.assign(r->b.nE, 0);
+        r->out->resid.assign(r->b.nE, 1.0);
+        wpcd_ctx *c = r->b.c;
+        graphs_ok &= c->use_graphs && !(c->timer.enabled & WPCD_TIME_SOLVE) &&
+                     c->device == runs[0]->b.c->device;
+        xs.push_back(std::move(x));
+    }
+    if (graphs_ok)
+        for (State &x : xs) x.graphs = graphs_for(x.r->b, x.r->tol, check_every);
+    // events joining the other streams' pending work into a multi-batch graph launch
+    struct Joins {
+        std::vector<hipEvent_t> e;
+        ~Joins() {
+            for (hipEvent_t v : e)
+                if (v) (void)hipEventDestroy(v);
+        }
+        hipEvent_t &operator[](size_t i) { return e[i]; }
+    } joins;
+    joins.e.assign(runs.size(), nullptr);
+    if (graphs_ok && runs.size() > 1)
+        for (size_t i = 1; i < runs.size(); ++i)
+            WPCD_HIP(hipEventCreateWithFlags(&joins.e[i], hipEventDisableTiming));
+    auto active = [](const State &x) { return x.total < x.r->max_iter && !x.all_done; };
+    for (;;) {
+        bool any = false;
+        for (State &x : xs) any |= active(x);
+        if (!any) break;
+        // cycle start from r
+        for (State &x : xs) {
+            x.started = x.in_cycle = active(x);
+            if (!x.started) continue;
+            Batch &b = x.r->b;
+            hipStream_t s = b.c->stream;
+            const int nE = b.nE;
+            dots(b, b.R, 1, b.R, b.h, nullptr, 0, 0);
+            hipLaunchKernelGGL(k_cycle_start, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.h, nE, m,
+                               x.r->tol, b.S, b.inv);
+            hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.inv, b.M, nE,
+                               b.R);
+            WPCD_HIP(hipMemcpyAsync(b.Vb, b.R, b.vstride * sizeof(double), hipMemcpyDeviceToDevice,
+                                    s));
+            WPCD_HIP(hipMemsetAsync(b.H, 0, (size_t)nE * (m + 1) * m * 2 * sizeof(double), s));
+        }
+        for (int k = 0; k < m;) {
+            std::vector<State *> in;
+            for (State &x : xs)
+                if (x.in_cycle) in.push_back(&x);
+            if (in.empty()) break;
+            bool full = graphs_ok;
+            hipStream_t rb_stream = nullptr;   // read-back stream when one graph ran them all
+            std::vector<int> kg(in.size());
+            for (size_t i = 0; i < in.size(); ++i) {
+                kg[i] = std::min({check_every, m - k, in[i]->r->max_iter - in[i]->total});
+                full &= kg[i] == check_every;
+            }
+            if (full && in.size() == 1) {
+                hipGraphExec_t &ex = in[0]->graphs->exec[k / check_every];
+                if (!ex) ex = capture_group(in[0]->r->b, k, check_every, in[0]->r->tol);
+                WPCD_HIP(hipGraphLaunch(ex, in[0]->r->b.c->stream));
+            } else if (full) {
+                // one graph for this set of batches at this k
+                std::vector<uint64_t> key = {(uint64_t)(k / check_every), (uint64_t)in.size()};
+                for (State *x : in) {
+                    key.push_back(0x9e37ull);
+                    key.insert(key.end(), x->graphs->key.begin(), x->graphs->key.end());
+                }
+                wpcd_ctx *c0 = in[0]->r->b.c;
+                hipGraphExec_t ex = nullptr;
+                for (auto &mg : c0->multi_graphs)
+                    if (mg.key == key) ex = mg.exec;
+                if (!ex) {
+                    std::vector<Batch *> bs;
+                    for (State *x : in) bs.push_back(&x->r->b);
+                    ex = capture_multi(bs, k, check_every, in[0]->r->tol);
+                    if (c0->multi_graphs.size() >= 64) {
+                        (void)hipGraphExecDestroy(c0->multi_graphs.front().exec);
+                        c0->multi_graphs.erase(c0->multi_graphs.begin());
+                    }
+                    c0->multi_graphs.push_back({key, ex});
+                }
+                // the graph runs on the first stream: it starts after the
+                // other streams' pending work, and the read-backs below go
+                // on the first stream after it
+                for (size_t i = 1; i < in.size(); ++i) {
+                    WPCD_HIP(hipEventRecord(joins[i], in[i]->r->b.c->stream));
+                    WPCD_HIP(hipStreamWaitEvent(c0->stream, joins[i], 0));
+                }
+                WPCD_HIP(hipGraphLaunch(ex, c0->stream));
+                rb_stream = c0->stream;
+            } else {
+                for (size_t i = 0; i < in.size(); ++i)
+                    for (int t = 0; t < kg[i]; ++t) iteration(in[i]->r->b, k + t, in[i]->r->tol);
+            }
+            for (size_t i = 0; i < in.size(); ++i) {
+                State &x = *in[i];
+                x.total += kg[i];
+                WPCD_HIP(hipMemcpyAsync(x.sth.data(), x.r->b.S.st, x.sth.size() * sizeof(double),
+                                        hipMemcpyDeviceToHost,
+                                        rb_stream ? rb_stream : x.r->b.c->stream));
+            }
+            for (State *x : in) WPCD_HIP(hipStreamSynchronize(x->r->b.c->stream));
+            if (rb_stream) WPCD_HIP(hipStreamSynchronize(rb_stream));
+            for (State *x : in) {
+                bool done = true;
+                for (int e = 0; e < x->r->b.nE; ++e) done &= x->sth[e * kSt + 3] != 0.0;
+                if (done || x->total >= x->r->max_iter) x->in_cycle = false;
+            }
+            k += check_every;
+        }
+        // end of the cycle: x from the least-squares solution, true residual
+        for (State &x : xs) {
+            if (!x.started) continue;
+            Batch &b = x.r->b;
+            hipStream_t s = b.c->stream;
+            const int nE = b.nE;
+            const int64_t vec = b.M * b.W;
+            hipLaunchKernelGGL(k_trisolve, dim3(cdiv(nE, 64)), dim3(64), 0, s, b.H, nE, m, b.S, b.y,
+                               b.kuse);
+            hipLaunchKernelGGL(k_xupdate, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, b.Vb,
+                               b.vstride, b.y, b.kuse, m, b.M, nE, b.X);
+            WPCD_HIP(hipGetLastError());
+            // per-energy iteration count: columns used in this cycle
+            WPCD_HIP(hipMemcpyAsync(x.sth.data(), b.S.st, x.sth.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+            op_apply(b, b.X, b.R, true, true);
+            hipLaunchKernelGGL(k_sub_from, dim3(cdiv(vec, 256)), dim3(256), 0, s, b.B, vec, b.R);
+            dots(b, b.R, 1, b.R, b.h, nullptr, 0, 0);
+            x.r->rn.assign(2 * nE, 0.0);
+            WPCD_HIP(hipMemcpyAsync(x.r->rn.data(), b.h, 2 * nE * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+        }
+        for (State &x : xs)
+            if (x.started) WPCD_HIP(hipStreamSynchronize(x.r->b.c->stream));
+        for (State &x : xs) {
+            if (!x.started) continue;
+            const int nE = x.r->b.nE;
+            std::vector<int> &iters = x.r->out->iters;
+            std::vector<double> &resid = x.r->out->resid;
+            x.all_done = true;
+            for (int e = 0; e < nE; ++e) {
+                if (resid[e] > x.r->tol) iters[e] += (int)x.sth[e * kSt + 4];
+                const double bn = x.r->st[e * kSt + 1];
+                resid[e] = bn > 0 ? std::sqrt(x.r->rn[2 * e]) / bn : 0.0;
+                if (resid[e] > x.r->tol) x.all_done = false;
+            }
         }
     }
 }
 
-void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
-                 int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
-                 GmresOut &out, bool err_est, const std::vector<double> *ebin) {
+void gmres_setup(GmresRun &run, wpcd_ctx *c, const std::vector<double> &E,
+                 const std::vector<int64_t> &idx0, int prec, int m, int max_iter, double tol,
+                 WarmFill warm, void *warm_user, GmresOut &out, bool err_est,
+                 const std::vector<double> *ebin) {
+    run.out = &out;
+    run.max_iter = max_iter;
+    run.tol = tol;
+    run.err_est = err_est;
+    run.idx0 = idx0;
     const bool fp64 = prec == WPCD_FP64;
     std::vector<int> &iters = out.iters, &edge_flag = out.edge;
     std::vector<double> &resid = out.resid;
@@ -1531,7 +1696,8 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     // the Givens kernel's LDS column stage can exceed the 64 KB default
     WPCD_HIP(hipFuncSetAttribute((const void *)k_norm_givens,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
-    Batch b{};
+    Batch &b = run.b;
+    b = Batch{};
     b.c = c;
     b.nE = nE;
     b.W = 2 * nE;
@@ -1618,7 +1784,7 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, s, c->d_idx.ptr, nE, b.X);
     WPCD_HIP(hipGetLastError());
     op_apply(b, b.X, b.B, false, false);
-    std::vector<double> st;
+    std::vector<double> &st = run.st;
     rhs_norms(b, st);
     out.warm.assign(nE, 0);
     out.r0.assign(nE, 1.0);
@@ -1651,9 +1817,18 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
         WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
         WPCD_HIP(hipMemcpyAsync(b.R, b.B, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+}
 
-    restart_cycles(b, tol, max_iter, st, iters, resid);
-    if (!err_est) return;
+void gmres_finish(GmresRun &run) {
+    if (!run.err_est) return;
+    Batch &b = run.b;
+    wpcd_ctx *c = b.c;
+    hipStream_t s = c->stream;
+    const int nE = b.nE;
+    const int64_t vec = b.M * b.W;
+    const std::vector<int64_t> &idx0 = run.idx0;
+    GmresOut &out = *run.out;
+    const int max_iter = run.max_iter;
     // Error against the FP64 path: the residual of x with the FP64 P0 values,
     // r64 = b64 - (1 - K64) x, and the correction d from (1 - K) d = r64
     // solved in this tier to a relative residual of 1e-4; d ~ x64 - x, so its
@@ -1673,11 +1848,15 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     b.fp64 = fp64_saved;
     WPCD_HIP(hipMemcpyAsync(b.B, b.R, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
     WPCD_HIP(hipMemsetAsync(b.X, 0, vec * sizeof(double), s));
-    std::vector<double> st2;
-    rhs_norms(b, st2);
-    std::vector<int> it2(nE, 0);
-    std::vector<double> res2(nE, 1.0);
-    restart_cycles(b, 1e-4, std::max(max_iter, 64), st2, it2, res2);
+    GmresOut o2;
+    GmresRun r2;
+    r2.b = b;
+    r2.out = &o2;
+    r2.max_iter = std::max(max_iter, 64);
+    r2.tol = 1e-4;
+    rhs_norms(r2.b, r2.st);
+    std::vector<GmresRun *> one{&r2};
+    gmres_cycles(one);
     out.dU.assign(2 * nE, 0.0);
     out.U.assign(2 * nE, 0.0);
     for (int e = 0; e < nE; ++e) {
@@ -1690,6 +1869,17 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
     WPCD_HIP(hipMemcpyAsync(b.X, X2, vec * sizeof(double), hipMemcpyDeviceToDevice, s));
     WPCD_HIP(hipStreamSynchronize(s));
 }
+
+void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<int64_t> &idx0,
+                 int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
+                 GmresOut &out, bool err_est, const std::vector<double> *ebin) {
+    GmresRun run;
+    gmres_setup(run, c, E, idx0, prec, m, max_iter, tol, warm, warm_user, out, err_est, ebin);
+    std::vector<GmresRun *> one{&run};
+    gmres_cycles(one);
+    gmres_finish(run);
+}
+
 
 // H[k+1][k] = |w| from the stage-1 norm partials; inv = 1/|w| (0 on breakdown).
 __global__ void k_arnoldi_norm(const double *__restrict__ npart, int nsplit, double *__restrict__ H,

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -408,110 +409,149 @@ static void warm_fill(wpcd_ctx *c, void *user, double *x, int nE) {
 
 // Steps 3-4 for a list of energies; collect, if given, receives the
 // converged solutions and their features.
-static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision prec,
-                       const wpcd_solve_opts *opts, wpcd_energy_result *out, double *breakup_out,
-                       Collect *collect) {
-    WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
-                 "build_basis and build_p must come first");
-    WPCD_REQUIRE(E && out && n_E >= 0, WPCD_E_INVALID, "E/out NULL or n_E < 0");
-    WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED || prec == WPCD_MIXED_REFINE ||
-                     prec == WPCD_MIXED_BF16,
-                 WPCD_E_INVALID, "bad precision");
-    WPCD_REQUIRE(prec != WPCD_FP64 || c->p_fp64, WPCD_E_STATE, "FP64 solve needs an FP64 P0 build");
-    WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE, "mixed solve needs a mixed P0 build");
+// One wpcd_solve call's work on one context, in steps, so that several
+// systems' batches can iterate in lockstep (wpcd_solve_multi): plan (checks,
+// energies, on-shell bins), then per batch of up to kBatch energies
+// begin_batch (GMRES set-up), gmres_cycles over the batches, end_batch
+// (error estimate, amplitudes), and finish (results out).
+struct SolveJob {
+    static constexpr int kBatch = 32;
+    wpcd_ctx *c = nullptr;
+    const double *E = nullptr;
+    int n_E = 0;
+    wpcd_precision prec = WPCD_FP64;
+    const wpcd_solve_opts *opts = nullptr;
+    wpcd_energy_result *out = nullptr;
+    double *breakup_out = nullptr;
+    Collect *collect = nullptr;
+    // plan
     int m = 48, max_iter = 400;
-    // FP32 storage of P0 perturbs the operator at the 1e-7 level: a mixed
-    // solve gains nothing below 1e-9
-    double tol = prec == WPCD_FP64 ? 1e-12 : 1e-9;
+    double tol = 0.0;
     int want_breakup = 0, warm_kind = WPCD_WARM_NONE;
-    bool err_est = false;
-    int rmode = WPCD_RESOLVENT_AT_E;
-    if (opts) {
-        if (opts->krylov_dim > 0) m = opts->krylov_dim;
-        if (opts->max_iter > 0) max_iter = opts->max_iter;
-        if (opts->tol > 0) tol = opts->tol;
-        want_breakup = opts->want_breakup;
-        warm_kind = opts->warm_start;
-        err_est = opts->err_est != 0;
-        rmode = opts->resolvent;
-    }
-    WPCD_REQUIRE(rmode == WPCD_RESOLVENT_AT_E || rmode == WPCD_RESOLVENT_AVERAGED, WPCD_E_INVALID,
-                 "resolvent must be a WPCD_RESOLVENT_* value");
-    WPCD_REQUIRE(want_breakup >= 0 && want_breakup <= WPCD_BREAKUP_DIST, WPCD_E_INVALID,
-                 "want_breakup must be 0, WPCD_BREAKUP_ELEMENTS or WPCD_BREAKUP_DIST");
-    WPCD_REQUIRE(!(rmode == WPCD_RESOLVENT_AVERAGED && want_breakup == WPCD_BREAKUP_ELEMENTS),
-                 WPCD_E_INVALID,
-                 "breakup elements need the resolvent at E (a pseudostate has several open "
-                 "bins with the averaged one): ask for WPCD_BREAKUP_DIST");
-    const bool averaged = rmode == WPCD_RESOLVENT_AVERAGED;
-    WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
-    WPCD_REQUIRE(warm_kind >= WPCD_WARM_NONE && warm_kind <= WPCD_WARM_GIVEN, WPCD_E_INVALID,
-                 "warm_start must be a WPCD_WARM_* value");
-    const int64_t M = (int64_t)c->nch * c->nq * c->np;
-    if (warm_kind == WPCD_WARM_GIVEN) WPCD_REQUIRE(opts->x0, WPCD_E_INVALID, "x0 is NULL");
-    if (warm_kind == WPCD_WARM_LEARNED)
-        WPCD_REQUIRE(c->learned.ready && c->learned.M == M &&
-                         c->learned.n_mult == (int)c->pot_mult.size(),
-                     WPCD_E_STATE, "no learned warm start for this basis and potential");
-    // entrance channel: l = 0, lam = L
+    bool err_est = false, averaged = false;
+    int64_t M = 0;
     int a0 = -1;
-    for (int a = 0; a < c->nch; ++a)
-        if (c->ch_l[a] == 0 && c->ch_lam[a] == c->L) {
-            a0 = a;
-            break;
-        }
-    WPCD_REQUIRE(a0 >= 0, WPCD_E_INVALID, "no entrance channel (l = 0, lam = L)");
-    const double eb = c->waves[c->ch_wave[a0]].h_eps[0];
-    const double qmax = c->q[c->nq];
-    std::vector<wpcd_energy_result> res(n_E);
+    double eb = 0.0, qmax = 0.0;
+    std::vector<wpcd_energy_result> res;
     std::vector<int> active;
     std::vector<int64_t> idx0v;
     std::vector<double> rho0v, ebinv;
-    for (int e = 0; e < n_E; ++e) {
-        wpcd_energy_result &r = res[e];
-        std::memset(&r, 0, sizeof(r));
-        r.E = E[e];
-        r.status = WPCD_OK;
-        r.r0 = 1.0;
-        r.err_vs_fp64 = std::numeric_limits<double>::quiet_NaN();
-        if (!std::isfinite(E[e])) {
-            r.status = WPCD_E_INVALID;
-            continue;
+    // current batch
+    size_t b0 = 0;
+    int nb = 0;
+    std::vector<double> Eb, rho0, ebin;
+    std::vector<int64_t> idx0;
+    WarmCtx wc;
+    GmresOut go;
+    std::unique_ptr<GmresRun, void (*)(GmresRun *)> run{nullptr, gmres_run_delete};
+
+    size_t n_batches() const { return (active.size() + kBatch - 1) / kBatch; }
+
+    void plan() {
+        WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
+                     "build_basis and build_p must come first");
+        WPCD_REQUIRE(E && out && n_E >= 0, WPCD_E_INVALID, "E/out NULL or n_E < 0");
+        WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED || prec == WPCD_MIXED_REFINE ||
+                         prec == WPCD_MIXED_BF16,
+                     WPCD_E_INVALID, "bad precision");
+        WPCD_REQUIRE(prec != WPCD_FP64 || c->p_fp64, WPCD_E_STATE, "FP64 solve needs an FP64 P0 build");
+        WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE, "mixed solve needs a mixed P0 build");
+        m = 48;
+        max_iter = 400;
+        // FP32 storage of P0 perturbs the operator at the 1e-7 level: a mixed
+        // solve gains nothing below 1e-9
+        tol = prec == WPCD_FP64 ? 1e-12 : 1e-9;
+        want_breakup = 0;
+        warm_kind = WPCD_WARM_NONE;
+        err_est = false;
+        int rmode = WPCD_RESOLVENT_AT_E;
+        if (opts) {
+            if (opts->krylov_dim > 0) m = opts->krylov_dim;
+            if (opts->max_iter > 0) max_iter = opts->max_iter;
+            if (opts->tol > 0) tol = opts->tol;
+            want_breakup = opts->want_breakup;
+            warm_kind = opts->warm_start;
+            err_est = opts->err_est != 0;
+            rmode = opts->resolvent;
         }
-        if (E[e] <= eb) {
-            r.status = WPCD_E_BELOW_THRESHOLD;
-            continue;
+        WPCD_REQUIRE(rmode == WPCD_RESOLVENT_AT_E || rmode == WPCD_RESOLVENT_AVERAGED, WPCD_E_INVALID,
+                     "resolvent must be a WPCD_RESOLVENT_* value");
+        WPCD_REQUIRE(want_breakup >= 0 && want_breakup <= WPCD_BREAKUP_DIST, WPCD_E_INVALID,
+                     "want_breakup must be 0, WPCD_BREAKUP_ELEMENTS or WPCD_BREAKUP_DIST");
+        WPCD_REQUIRE(!(rmode == WPCD_RESOLVENT_AVERAGED && want_breakup == WPCD_BREAKUP_ELEMENTS),
+                     WPCD_E_INVALID,
+                     "breakup elements need the resolvent at E (a pseudostate has several open "
+                     "bins with the averaged one): ask for WPCD_BREAKUP_DIST");
+        averaged = rmode == WPCD_RESOLVENT_AVERAGED;
+        WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
+        WPCD_REQUIRE(warm_kind >= WPCD_WARM_NONE && warm_kind <= WPCD_WARM_GIVEN, WPCD_E_INVALID,
+                     "warm_start must be a WPCD_WARM_* value");
+        M = (int64_t)c->nch * c->nq * c->np;
+        if (warm_kind == WPCD_WARM_GIVEN) WPCD_REQUIRE(opts->x0, WPCD_E_INVALID, "x0 is NULL");
+        if (warm_kind == WPCD_WARM_LEARNED)
+            WPCD_REQUIRE(c->learned.ready && c->learned.M == M &&
+                             c->learned.n_mult == (int)c->pot_mult.size(),
+                         WPCD_E_STATE, "no learned warm start for this basis and potential");
+        // entrance channel: l = 0, lam = L
+        a0 = -1;
+        for (int a = 0; a < c->nch; ++a)
+            if (c->ch_l[a] == 0 && c->ch_lam[a] == c->L) {
+                a0 = a;
+                break;
+            }
+        WPCD_REQUIRE(a0 >= 0, WPCD_E_INVALID, "no entrance channel (l = 0, lam = L)");
+        eb = c->waves[c->ch_wave[a0]].h_eps[0];
+        qmax = c->q[c->nq];
+        res.assign(n_E, wpcd_energy_result{});
+        for (int e = 0; e < n_E; ++e) {
+            wpcd_energy_result &r = res[e];
+            std::memset(&r, 0, sizeof(r));
+            r.E = E[e];
+            r.status = WPCD_OK;
+            r.r0 = 1.0;
+            r.err_vs_fp64 = std::numeric_limits<double>::quiet_NaN();
+            if (!std::isfinite(E[e])) {
+                r.status = WPCD_E_INVALID;
+                continue;
+            }
+            if (E[e] <= eb) {
+                r.status = WPCD_E_BELOW_THRESHOLD;
+                continue;
+            }
+            const double q0 = std::sqrt(4.0 * (E[e] - eb) / 3.0);
+            r.q0 = q0;
+            if (q0 >= qmax) {
+                r.status = WPCD_E_INVALID;
+                continue;
+            }
+            const int j0 = (int)(std::upper_bound(c->q.begin(), c->q.end(), q0) - c->q.begin()) - 1;
+            r.j0 = j0;
+            active.push_back(e);
+            idx0v.push_back(((int64_t)a0 * c->nq + j0) * c->np);
+            if (averaged) {
+                // on-shell energy interval: the energies of the entrance bin j0
+                const double e1 = eb + 0.75 * c->q[j0] * c->q[j0], e2 = eb + 0.75 * c->q[j0 + 1] * c->q[j0 + 1];
+                ebinv.push_back(e1);
+                ebinv.push_back(e2);
+                rho0v.push_back(1.0 / (e2 - e1));
+            } else {
+                rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
+            }
         }
-        const double q0 = std::sqrt(4.0 * (E[e] - eb) / 3.0);
-        r.q0 = q0;
-        if (q0 >= qmax) {
-            r.status = WPCD_E_INVALID;
-            continue;
-        }
-        const int j0 = (int)(std::upper_bound(c->q.begin(), c->q.end(), q0) - c->q.begin()) - 1;
-        r.j0 = j0;
-        active.push_back(e);
-        idx0v.push_back(((int64_t)a0 * c->nq + j0) * c->np);
-        if (averaged) {
-            // on-shell energy interval: the energies of the entrance bin j0
-            const double e1 = eb + 0.75 * c->q[j0] * c->q[j0], e2 = eb + 0.75 * c->q[j0 + 1] * c->q[j0 + 1];
-            ebinv.push_back(e1);
-            ebinv.push_back(e2);
-            rho0v.push_back(1.0 / (e2 - e1));
-        } else {
-            rho0v.push_back(2.0 / (3.0 * q0 * (c->q[j0 + 1] - c->q[j0])));
+        // the error estimate needs the FP64 P0 values on the same structure
+        if (err_est && !c->has_val64 && !active.empty()) {
+            build_values(c, true);
+            c->has_val64 = true;
         }
     }
-    // the error estimate needs the FP64 P0 values on the same structure
-    if (err_est && !c->has_val64 && !active.empty()) {
-        build_values(c, true);
-        c->has_val64 = true;
-    }
-    const int kBatch = 32;
-    for (size_t b0 = 0; b0 < active.size(); b0 += kBatch) {
-        const int nb = (int)std::min(active.size() - b0, (size_t)kBatch);
-        std::vector<double> Eb(nb), rho0(nb), ebin;
-        std::vector<int64_t> idx0(nb);
+
+    void begin_batch(size_t t) {
+        b0 = t * kBatch;
+        nb = (int)std::min(active.size() - b0, (size_t)kBatch);
+        Eb.assign(nb, 0.0);
+        rho0.assign(nb, 0.0);
+        ebin.clear();
+        idx0.assign(nb, 0);
         for (int t = 0; t < nb; ++t) {
             Eb[t] = E[active[b0 + t]];
             idx0[t] = idx0v[b0 + t];
@@ -521,7 +561,7 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
                 ebin.push_back(ebinv[2 * (b0 + t) + 1]);
             }
         }
-        WarmCtx wc;
+        wc = WarmCtx{};
         wc.kind = warm_kind;
         if (warm_kind == WPCD_WARM_LEARNED) {
             const Learned &L = c->learned;
@@ -535,10 +575,15 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
         } else if (warm_kind == WPCD_WARM_GIVEN) {
             for (int t = 0; t < nb; ++t) wc.given.push_back(opts->x0 + (size_t)active[b0 + t] * M * 2);
         }
-        GmresOut go;
-        gmres_batch(c, Eb, idx0, prec, m, max_iter, tol,
+        go = GmresOut{};
+        run.reset(gmres_run_new());
+        gmres_setup(*run, c, Eb, idx0, prec, m, max_iter, tol,
                     warm_kind == WPCD_WARM_NONE ? nullptr : warm_fill, &wc, go, err_est,
                     averaged ? &ebin : nullptr);
+    }
+
+    void end_batch() {
+        gmres_finish(*run);
         // amplitude list: elastic first, then open breakup pseudostates
         std::vector<int64_t> rows;
         std::vector<int32_t> ens;
@@ -674,7 +719,32 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
             collect->n += (int64_t)ok.size();
         }
     }
-    for (int e = 0; e < n_E; ++e) out[e] = res[e];
+
+    void finish() {
+        for (int e = 0; e < n_E; ++e) out[e] = res[e];
+    }
+};
+
+static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision prec,
+                       const wpcd_solve_opts *opts, wpcd_energy_result *out, double *breakup_out,
+                       Collect *collect) {
+    SolveJob j;
+    j.c = c;
+    j.E = E;
+    j.n_E = n_E;
+    j.prec = prec;
+    j.opts = opts;
+    j.out = out;
+    j.breakup_out = breakup_out;
+    j.collect = collect;
+    j.plan();
+    for (size_t t = 0; t < j.n_batches(); ++t) {
+        j.begin_batch(t);
+        std::vector<GmresRun *> one{j.run.get()};
+        gmres_cycles(one);
+        j.end_batch();
+    }
+    j.finish();
 }
 
 static uint64_t splitmix_next(uint64_t &st) {
@@ -1493,14 +1563,59 @@ wpcd_status wpcd_solve_multi(wpcd_ctx *const *ctxs, int32_t n_sys, const double 
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return WPCD_E_INVALID;   // a context is not thread-safe
     }
-    // one host thread per system: each context launches on its own stream,
-    // so the systems' kernels overlap on the device
     std::vector<wpcd_status> st(n_sys, WPCD_OK);
-    std::vector<std::thread> th;
-    th.reserve(n_sys);
-    for (int i = 0; i < n_sys; ++i)
-        th.emplace_back([&, i] { st[i] = wpcd_solve(ctxs[i], E[i], n_E[i], prec, opts, out[i], nullptr); });
-    for (auto &t : th) t.join();
+    bool one_device = true;
+    for (int i = 1; i < n_sys; ++i) one_device &= ctxs[i]->device == ctxs[0]->device;
+    if (!one_device) {
+        // systems on several devices: one host thread per system
+        std::vector<std::thread> th;
+        th.reserve(n_sys);
+        for (int i = 0; i < n_sys; ++i)
+            th.emplace_back([&, i] { st[i] = wpcd_solve(ctxs[i], E[i], n_E[i], prec, opts, out[i], nullptr); });
+        for (auto &t : th) t.join();
+    } else {
+        // one device: the systems' batches iterate in lockstep, and each group
+        // of iterations of all of them is one captured graph (gmres_cycles)
+        std::vector<SolveJob> jobs(n_sys);
+        auto step = [&](int i, auto &&f) {
+            if (st[i] != WPCD_OK) return;
+            const wpcd_status r = guarded(ctxs[i], f);
+            st[i] = r;
+        };
+        for (int i = 0; i < n_sys; ++i) {
+            SolveJob &j = jobs[i];
+            j.c = ctxs[i];
+            j.E = E[i];
+            j.n_E = n_E[i];
+            j.prec = prec;
+            j.opts = opts;
+            j.out = out[i];
+            step(i, [&] { j.plan(); });
+        }
+        size_t nbt = 0;
+        for (int i = 0; i < n_sys; ++i)
+            if (st[i] == WPCD_OK) nbt = std::max(nbt, jobs[i].n_batches());
+        for (size_t t = 0; t < nbt; ++t) {
+            std::vector<GmresRun *> runs;
+            std::vector<int> who;
+            for (int i = 0; i < n_sys; ++i) {
+                if (st[i] != WPCD_OK || t >= jobs[i].n_batches()) continue;
+                step(i, [&] { jobs[i].begin_batch(t); });
+                if (st[i] != WPCD_OK) continue;
+                runs.push_back(jobs[i].run.get());
+                who.push_back(i);
+            }
+            if (runs.empty()) continue;
+            const wpcd_status r = guarded(ctxs[who[0]], [&] { gmres_cycles(runs); });
+            if (r != WPCD_OK)
+                for (int i : who) {
+                    st[i] = r;
+                    ctxs[i]->err = ctxs[who[0]]->err;
+                }
+            for (int i : who) step(i, [&] { jobs[i].end_batch(); });
+        }
+        for (int i = 0; i < n_sys; ++i) step(i, [&] { jobs[i].finish(); });
+    }
     wpcd_status first = WPCD_OK;
     for (int i = 0; i < n_sys; ++i) {
         if (status_out) status_out[i] = st[i];
@@ -1558,6 +1673,8 @@ wpcd_status wpcd_set_graphs(wpcd_ctx *c, int32_t enable) {
         c->use_graphs = enable != 0;
         for (auto &g : c->graphs) g.release();
         c->graphs.clear();
+        for (auto &g : c->multi_graphs) (void)hipGraphExecDestroy(g.exec);
+        c->multi_graphs.clear();
     });
 }
 
@@ -1643,6 +1760,8 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->learned.release();
     for (auto &g : c->graphs) g.release();
     c->graphs.clear();
+    for (auto &g : c->multi_graphs) (void)hipGraphExecDestroy(g.exec);
+    c->multi_graphs.clear();
     c->d_pot.release();
     c->d_mcoef.release();
     c->d_mterms.release();

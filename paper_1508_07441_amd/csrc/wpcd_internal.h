@@ -178,6 +178,13 @@ struct Tuning {
 };
 
 // Executable graphs of the GMRES iteration groups of one batch shape.
+// Graph of one group of iterations of several batches (key: the batches'
+// graph keys and the group's first iteration).
+struct MultiGraph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+};
+
 struct IterGraphs {
     std::vector<uint64_t> key;
     std::vector<hipGraphExec_t> exec;
@@ -252,6 +259,7 @@ struct wpcd_ctx {
     wpcd::Tuning tune;
     bool use_graphs = true;
     std::vector<wpcd::IterGraphs> graphs;
+    std::vector<wpcd::MultiGraph> multi_graphs;   // lockstep groups led by this context
 };
 
 namespace wpcd {
@@ -347,6 +355,18 @@ void gmres_batch(wpcd_ctx *c, const std::vector<double> &E, const std::vector<in
                  int prec, int m, int max_iter, double tol, WarmFill warm, void *warm_user,
                  GmresOut &out, bool err_est = false,
                  const std::vector<double> *ebin = nullptr);   // [nE][2]: averaged resolvent
+// The same in three parts, so that batches of several systems can iterate in
+// lockstep: set up (resolvent, driving term, initial vector), restarted
+// cycles of one or several runs together, finish (error estimate).
+struct GmresRun;
+GmresRun *gmres_run_new();
+void gmres_run_delete(GmresRun *r);
+void gmres_setup(GmresRun &run, wpcd_ctx *c, const std::vector<double> &E,
+                 const std::vector<int64_t> &idx0, int prec, int m, int max_iter, double tol,
+                 WarmFill warm, void *warm_user, GmresOut &out, bool err_est,
+                 const std::vector<double> *ebin);
+void gmres_cycles(std::vector<GmresRun *> &runs);
+void gmres_finish(GmresRun &run);
 void arnoldi_kernel(wpcd_ctx *c, double E, int m, std::vector<double> &H, int &steps);
 void amplitudes_batch(wpcd_ctx *c, int nE, const std::vector<int64_t> &rows,
                       const std::vector<int32_t> &ens, const std::vector<double> &rho,
