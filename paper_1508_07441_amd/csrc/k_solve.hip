@@ -571,6 +571,119 @@ __global__ __launch_bounds__(64) void k_spmm_lds(const int64_t *__restrict__ row
     }
 }
 
+template <class T> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
+// P0 SpMM with its memory latencies overlapped.  One wavefront per cell row
+// (a 64-thread workgroup), two entries of x per lane as above.  The row's
+// nonzeros go in tiles of T: the columns and channel-coupling values of the
+// next tile are loaded (contiguously, into registers) while the current
+// tile's x rows are gathered, and are parked in LDS once it is consumed.
+// Inside a tile each lane issues the gathers of SU nonzeros, every column
+// channel, before it uses any of them (SU = 2 for three or more channels:
+// fewer registers, more wavefronts resident, measured faster than 4 or 8 on
+// the 300 x 300 three-channel operator).  The sums run in the same order as
+// k_spmm_lds, so both give the same bits.
+// With PERM the workgroups visit the rows in the order perm[0, ncell): XCD x
+// (workgroups g = x mod 8) walks the contiguous stretch perm[s_x, s_x+1),
+// workgroup g taking entry s_x + g / 8, where s_0..s_8 = perm[ncell ..
+// ncell + 8] split the order into eight parts of equal nonzero count.  perm
+// lists the cells in square tiles of the (p, q) lattice; neighbouring cells
+// touch largely the same columns, so an XCD's concurrent rows share their x
+// panel rows in its L2 instead of fetching them again.
+template <class V, int NCH, class XT, class YT, bool PERM>
+__global__ __launch_bounds__(64) void k_spmm_pipe(const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const V *__restrict__ val, int ncell, int W,
+                                                  int Wp, const XT *__restrict__ x,
+                                                  YT *__restrict__ y,
+                                                  const int32_t *__restrict__ perm) {
+    using X2 = typename Pair2<XT>::type;
+    constexpr int NV = NCH * NCH;
+    constexpr int T = NV <= 16 ? 64 : 32;   // nonzeros per tile (<= 64)
+    constexpr int NVL = (T * NV + 63) / 64;  // staged values per lane
+    constexpr int SU = NCH >= 3 ? 2 : 4;     // nonzeros gathered together per lane
+    __shared__ int32_t cs[T];
+    __shared__ V vs[T * NV];
+    const int lane = threadIdx.x;
+    int r = blockIdx.x;
+    if (PERM) {
+        const int xcd = blockIdx.x & 7;
+        const int lr = perm[ncell + xcd] + (int)(blockIdx.x >> 3);
+        if (lr >= perm[ncell + xcd + 1]) return;   // the whole workgroup leaves
+        r = perm[lr];
+    }
+    const int L = Wp >> 1;
+    const int G = 64 / L, g = lane / L, c = 2 * (lane % L);
+    const bool colok = c < W;
+    const int64_t b = rowptr[r], e = rowptr[r + 1];
+    double acc[NCH][2];
+#pragma unroll
+    for (int a = 0; a < NCH; ++a) acc[a][0] = acc[a][1] = 0.0;
+    int32_t pc = 0;
+    V pv[NVL];
+    auto fetch = [&](int64_t t0) {
+        const int n = (int)(e - t0 < T ? e - t0 : T);
+        pc = lane < n ? col[t0 + lane] : 0;
+#pragma unroll
+        for (int u = 0; u < NVL; ++u) {
+            const int k = lane + 64 * u;
+            pv[u] = k < n * NV ? val[t0 * NV + k] : V(0);
+        }
+    };
+    if (b < e) fetch(b);
+    for (int64_t t0 = b; t0 < e; t0 += T) {
+        const int n = (int)(e - t0 < T ? e - t0 : T);
+        __syncthreads();   // the previous tile has been consumed
+        if (lane < T) cs[lane] = pc;
+#pragma unroll
+        for (int u = 0; u < NVL; ++u)
+            if (lane + 64 * u < T * NV) vs[lane + 64 * u] = pv[u];
+        __syncthreads();
+        if (t0 + T < e) fetch(t0 + T);
+        for (int k0 = 0; k0 < n; k0 += G * SU) {
+            int kv[SU];
+            X2 xv[SU][NCH];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int k = k0 + u * G + g;
+                const bool ok = colok && k < n;
+                kv[u] = ok ? k : 0;   // slots past the tile read x = 0
+                const int64_t cc = ok ? cs[k] : 0;
+#pragma unroll
+                for (int a2 = 0; a2 < NCH; ++a2) {
+                    if (ok) xv[u][a2] = *(const X2 *)(x + ((int64_t)a2 * ncell + cc) * W + c);
+                    else xv[u][a2] = X2{XT(0), XT(0)};
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const V *vb = vs + kv[u] * NV;
+#pragma unroll
+                for (int a2 = 0; a2 < NCH; ++a2) {
+                    const double x0 = (double)xv[u][a2].x, x1 = (double)xv[u][a2].y;
+#pragma unroll
+                    for (int a = 0; a < NCH; ++a) {
+                        const double v = (double)vb[a * NCH + a2];
+                        acc[a][0] += v * x0;
+                        acc[a][1] += v * x1;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NCH; ++a) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double v = acc[a][h];
+            for (int off = L; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+            if (g == 0 && colok) y[((int64_t)a * ncell + r) * W + c + h] = (YT)v;
+        }
+    }
+}
+
 // ------------------------------------------------------ Krylov vector ops
 // Rows are processed in chunks of NR * (256 / nEp) per workgroup (nEp =
 // pow2 >= nE).  Thread t handles energy e = t % nEp and rows r0 + t / nEp +
@@ -1113,30 +1226,95 @@ void launch_block_apply(Batch &b, ChPtrs mats, const TI *in, const double *add, 
 }
 
 // P0 SpMM candidates: 0 plain, 1 XCD-contiguous rows, 2 several nonzeros
-// in flight per lane (block form), 3 both, 4 LDS-staged tiles.
-constexpr int kSpmmCfg = 5;
+// in flight per lane (block form), 3 both, 4 LDS-staged tiles, 5 LDS-staged
+// tiles with the loads of a tile overlapped (k_spmm_pipe), 6 as 5 with the
+// rows visited in lattice tiles, XCD-contiguous and balanced.
+constexpr int kSpmmCfg = 7;
 
-template <class PT, class V, int NCH>
+template <class PT, class V, int NCH, bool PERM, bool PIPE>
 void launch_spmm_lds(Batch &b, const V *val, const PT *x, PT *y) {
     wpcd_ctx *c = b.c;
     const int nrow = c->np * c->nq;
-    hipLaunchKernelGGL((k_spmm_lds<V, NCH, PT, PT>), dim3(nrow), dim3(64), 0, c->stream,
-                       c->d_rowptr.ptr, c->d_col.ptr, val, nrow, b.W, b.Wp, x, y);
+    const int grid = PERM ? c->perm_grid : nrow;
+    if (PIPE)
+        hipLaunchKernelGGL((k_spmm_pipe<V, NCH, PT, PT, PERM>), dim3(grid), dim3(64), 0,
+                           c->stream, c->d_rowptr.ptr, c->d_col.ptr, val, nrow, b.W, b.Wp, x,
+                           y, PERM ? c->d_perm.ptr : nullptr);
+    else
+        hipLaunchKernelGGL((k_spmm_lds<V, NCH, PT, PT>), dim3(nrow), dim3(64), 0, c->stream,
+                           c->d_rowptr.ptr, c->d_col.ptr, val, nrow, b.W, b.Wp, x, y);
     WPCD_HIP(hipGetLastError());
 }
 
-template <class PT, class V>
+template <class PT, class V, bool PERM, bool PIPE>
 void launch_spmm_lds_n(Batch &b, const V *val, const PT *x, PT *y) {
     switch (b.c->nch) {
-        case 1: launch_spmm_lds<PT, V, 1>(b, val, x, y); break;
-        case 2: launch_spmm_lds<PT, V, 2>(b, val, x, y); break;
-        case 3: launch_spmm_lds<PT, V, 3>(b, val, x, y); break;
-        case 4: launch_spmm_lds<PT, V, 4>(b, val, x, y); break;
-        case 5: launch_spmm_lds<PT, V, 5>(b, val, x, y); break;
-        case 6: launch_spmm_lds<PT, V, 6>(b, val, x, y); break;
-        case 7: launch_spmm_lds<PT, V, 7>(b, val, x, y); break;
-        default: launch_spmm_lds<PT, V, 8>(b, val, x, y); break;
+        case 1: launch_spmm_lds<PT, V, 1, PERM, PIPE>(b, val, x, y); break;
+        case 2: launch_spmm_lds<PT, V, 2, PERM, PIPE>(b, val, x, y); break;
+        case 3: launch_spmm_lds<PT, V, 3, PERM, PIPE>(b, val, x, y); break;
+        case 4: launch_spmm_lds<PT, V, 4, PERM, PIPE>(b, val, x, y); break;
+        case 5: launch_spmm_lds<PT, V, 5, PERM, PIPE>(b, val, x, y); break;
+        case 6: launch_spmm_lds<PT, V, 6, PERM, PIPE>(b, val, x, y); break;
+        case 7: launch_spmm_lds<PT, V, 7, PERM, PIPE>(b, val, x, y); break;
+        default: launch_spmm_lds<PT, V, 8, PERM, PIPE>(b, val, x, y); break;
     }
+}
+
+// Row visiting order of the tiled SpMM variants: the cells in square tiles
+// of kPermTile x kPermTile lattice cells (tiles in row-major order over
+// (j, i), cells row-major inside a tile), followed by the nine bounds that
+// cut it into eight stretches of equal nonzero count, one per XCD (the row
+// lengths vary several-fold over the lattice, so equal row counts would
+// leave XCDs idle).  Built on the host from the row pointers, uploaded
+// before any launch that uses it (never inside a graph capture); the order
+// is valid for any P of this grid, the balance is that of the P it was
+// built for.
+constexpr int kPermTile = 32;
+
+void ensure_perm(wpcd_ctx *c) {
+    const int nrow = c->np * c->nq;
+    if (c->perm_np == c->np && c->perm_nq == c->nq && c->perm_nnz == c->nnz && c->d_perm.ptr)
+        return;
+    std::vector<int64_t> rp(nrow + 1);
+    WPCD_HIP(hipMemcpyAsync(rp.data(), c->d_rowptr.ptr, rp.size() * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, c->stream));
+    WPCD_HIP(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> perm;
+    perm.reserve((size_t)nrow + 9);
+    for (int tj = 0; tj < c->nq; tj += kPermTile)
+        for (int ti = 0; ti < c->np; ti += kPermTile)
+            for (int j = tj; j < std::min(c->nq, tj + kPermTile); ++j)
+                for (int i = ti; i < std::min(c->np, ti + kPermTile); ++i)
+                    perm.push_back(j * c->np + i);
+    const int64_t total = rp[nrow];
+    int64_t acc = 0;
+    int next = 1, grid = 0, prev = 0;
+    perm.push_back(0);
+    for (int k = 0; k < nrow && next < 8; ++k) {
+        acc += rp[perm[k] + 1] - rp[perm[k]];
+        while (next < 8 && acc * 8 >= total * next) {
+            perm.push_back(k + 1);
+            grid = std::max(grid, k + 1 - prev);
+            prev = k + 1;
+            ++next;
+        }
+    }
+    while (next < 8) {   // empty P: the remaining stretches are empty
+        perm.push_back(nrow);
+        grid = std::max(grid, nrow - prev);
+        prev = nrow;
+        ++next;
+    }
+    perm.push_back(nrow);
+    grid = std::max(grid, nrow - prev);
+    c->d_perm.reserve(perm.size());
+    WPCD_HIP(hipMemcpyAsync(c->d_perm.ptr, perm.data(), perm.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, c->stream));
+    WPCD_HIP(hipStreamSynchronize(c->stream));
+    c->perm_np = c->np;
+    c->perm_nq = c->nq;
+    c->perm_nnz = c->nnz;
+    c->perm_grid = 8 * std::max(grid, 1);
 }
 
 template <class PT, class V, bool XCD, int U>
@@ -1164,9 +1342,12 @@ template <class PT>
 void launch_spmm(Batch &b, const PT *x, PT *y, int cfg) {
     wpcd_ctx *c = b.c;
     auto go = [&](auto val) {
-        if (cfg == 4) {
-            launch_spmm_lds_n<PT>(b, val, x, y);
-            return;
+        using VT = std::remove_const_t<std::remove_pointer_t<decltype(val)>>;
+        switch (cfg) {
+            case 4: launch_spmm_lds_n<PT, VT, false, false>(b, val, x, y); return;
+            case 5: launch_spmm_lds_n<PT, VT, false, true>(b, val, x, y); return;
+            case 6: launch_spmm_lds_n<PT, VT, true, true>(b, val, x, y); return;
+            default: break;
         }
         switch (cfg) {
             case 0: launch_spmm_v<PT, std::remove_const_t<std::remove_pointer_t<decltype(val)>>, false, 1>(b, val, x, y); break;
@@ -1420,7 +1601,9 @@ void choose_shapes(Batch &b, int m) {
     std::snprintf(key, sizeof key, "nnz=%lld nch=%d W=%d %s%s", (long long)c->nnz, c->nch, b.W,
                   b.fp64 ? "f64" : "f32", b.lowp ? " lowp" : "");
     // candidates: the s-wave kernel has no unrolled form
-    std::vector<int> cand = c->nch > 1 ? std::vector<int>{0, 1, 2, 3, 4} : std::vector<int>{0, 1, 4};
+    std::vector<int> cand =
+        c->nch > 1 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6} : std::vector<int>{0, 1, 4, 5, 6};
+    ensure_perm(c);   // before any capture
     const int pick = tune_pick(c, "spmm", key, (int)cand.size(), 0, [&](int i) {
         return time_launches(c->stream, [&] {
             if (b.lowp) launch_spmm<float>(b, (const float *)b.T1, (float *)b.T2, cand[i]);

@@ -1741,6 +1741,7 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->d_cnt.release();
     c->d_hint.release();
     c->d_rstart.release();
+    c->d_perm.release();
     c->d_tsum.release();
     c->d_val64.release();
     c->d_val32.release();

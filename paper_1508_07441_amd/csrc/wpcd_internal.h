@@ -243,6 +243,10 @@ struct wpcd_ctx {
     wpcd::DBuf<int32_t> d_col, d_cnt, d_hint;   // columns, row counts, row hints (one per 64 nonzeros)
     wpcd::DBuf<int64_t> d_tsum;                  // pre-selection scan: per-tile totals
     wpcd::DBuf<uint8_t> d_rstart;                // 1 where a nonzero starts its row
+    wpcd::DBuf<int32_t> d_perm;                  // SpMM row order in lattice tiles
+    int perm_np = 0, perm_nq = 0;                // grid d_perm was built for
+    int64_t perm_nnz = -1;                       // nonzero count it was balanced for
+    int perm_grid = 0;                           // workgroups of a tiled SpMM launch
     wpcd::DBuf<double> d_val64;
     wpcd::DBuf<float> d_val32;
 

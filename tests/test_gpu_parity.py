@@ -668,7 +668,7 @@ def test_autotune_candidates_agree(ctx, P):
     E = [-0.05, 0.3, 1.1]
     ctx.set_autotune(P.WPCD_TUNE_HEURISTIC)
     ref = ctx.solve(E, P.WPCD_FP64)
-    for mode in [P.WPCD_TUNE_FORCE + i for i in range(5)] + [P.WPCD_TUNE_MEASURE]:
+    for mode in [P.WPCD_TUNE_FORCE + i for i in range(8)] + [P.WPCD_TUNE_MEASURE]:
         say(f"[tune] mode {mode}")
         ctx.set_autotune(mode)
         res = ctx.solve(E, P.WPCD_FP64)
@@ -680,6 +680,35 @@ def test_autotune_candidates_agree(ctx, P):
     assert {e["name"] for e in ent} == {"block_apply", "vector_rows", "spmm"}
     for e in ent:
         assert 0 <= e["choice"] < e["n_candidates"] and e["us"] > 0.0
+    ctx.set_autotune(P.WPCD_TUNE_HEURISTIC)
+
+
+@pytest.mark.parametrize("chans", ["s", "L2"])
+def test_tiled_spmm_ragged_grid(ctx, P, chans):
+    """Every SpMM variant (forced in turn; the last ones visit the rows in
+    lattice tiles) on a grid whose sides are not multiples of the tile and
+    whose cell count is not a multiple of 8 (padding workgroups) gives the
+    amplitudes of the plain launch to rounding."""
+    np_, nq = 37, 43                     # 1591 cells
+    if chans == "s":
+        ctx.build_basis(np_, nq, 10.0, 10.0, 8, 16, potential=YAM)
+    else:
+        pot = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+        ctx.build_basis(np_, nq, 10.0, 10.0, 8, 16, channels=L2_CHANS, L=2, potential=pot)
+    E = [-0.05, 0.4, 1.3]
+    for prec in (P.WPCD_FP64, P.WPCD_MIXED):
+        ctx.build_p(prec)
+        ctx.set_autotune(P.WPCD_TUNE_FORCE)
+        say(f"[tiled spmm] {chans} prec={prec} force 0")
+        ref = ctx.solve(E, prec)
+        for f in range(1, 8):                          # clamped past the last candidate
+            ctx.set_autotune(P.WPCD_TUNE_FORCE + f)
+            say(f"[tiled spmm] {chans} prec={prec} force {f}")
+            res = ctx.solve(E, prec)
+            for a, b in zip(ref, res):
+                assert a.status == P.WPCD_OK and b.status == P.WPCD_OK
+                Ua, Ub = complex(a.U_re, a.U_im), complex(b.U_re, b.U_im)
+                assert abs(Ua - Ub) <= 1e-10 * abs(Ua)
     ctx.set_autotune(P.WPCD_TUNE_HEURISTIC)
 
 
