@@ -164,36 +164,61 @@ __global__ __launch_bounds__(256) void k_block_apply(ChPtrs mats, int n, int nq,
             bbase[sl] = (chbase + (int64_t)j * n) * W;
         }
     }
-    for (int k0 = 0; k0 < n; k0 += KS) {
-        // A tile, transposed: sA[kk][rr] = Mat[row0 + rr][k0 + kk]
-        for (int idx = t; idx < TM * KS; idx += 256) {
+    // The loads of k step k0 + KS are issued before the products of step k0
+    // (held raw in registers, parked in LDS at the top of the next step), so
+    // the global-memory latency of a step overlaps the previous step's FMAs.
+    constexpr int NAL = (TM * KS + 255) / 256;
+    double ra[NAL];
+    double rg[NBL][2], rx[NBL][2];   // raw G and panel entries (USE_G: the pair)
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int sl = 0; sl < NAL; ++sl) {
+            const int idx = t + 256 * sl;
             const int rr = idx / KS, kk = idx % KS;
             const int r = row0 + rr, k = k0 + kk;
-            sA[kk][rr] = (r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0;
+            ra[sl] = (idx < TM * KS && r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0;
+        }
+#pragma unroll
+        for (int sl = 0; sl < NBL; ++sl) {
+            const int idx = t + 256 * sl;
+            const int kk = idx / TN;
+            const int k = k0 + kk;
+            const bool ok = idx < KS * TN && k < n && bbase[sl] >= 0;
+            const int64_t o = bbase[sl] + (int64_t)k * W;
+            const int c = bc[sl];
+            if (USE_G) {
+                const int c0 = c & ~1;
+                rg[sl][0] = ok ? G[o + c0] : 0.0;
+                rg[sl][1] = ok ? G[o + c0 + 1] : 0.0;
+                rx[sl][0] = ok ? (double)in[o + c0] : 0.0;
+                rx[sl][1] = ok ? (double)in[o + c0 + 1] : 0.0;
+            } else {
+                rx[sl][0] = ok ? (double)in[o + c] : 0.0;
+            }
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < n; k0 += KS) {
+        // A tile, transposed: sA[kk][rr] = Mat[row0 + rr][k0 + kk]
+#pragma unroll
+        for (int sl = 0; sl < NAL; ++sl) {
+            const int idx = t + 256 * sl;
+            if (idx < TM * KS) sA[idx % KS][idx / KS] = ra[sl];
         }
         // B tile: sB[kk][qq] = Y[k0 + kk][q0 + qq]
 #pragma unroll
         for (int sl = 0; sl < NBL; ++sl) {
             const int idx = t + 256 * sl;
             if (idx >= KS * TN) break;
-            const int kk = idx / TN, qq = idx % TN;
-            const int k = k0 + kk;
-            double v = 0.0;
-            if (k < n && bbase[sl] >= 0) {
-                const int64_t o = bbase[sl] + (int64_t)k * W;
-                const int c = bc[sl];
-                if (USE_G) {
-                    const int c0 = c & ~1;
-                    const double gr = G[o + c0], gi = G[o + c0 + 1];
-                    const double xr = (double)in[o + c0], xi = (double)in[o + c0 + 1];
-                    v = (c & 1) ? (gr * xi + gi * xr) : (gr * xr - gi * xi);
-                } else {
-                    v = (double)in[o + c];
-                }
+            double v = rx[sl][0];
+            if (USE_G) {
+                const double gr = rg[sl][0], gi = rg[sl][1], xr = rx[sl][0], xi = rx[sl][1];
+                v = (bc[sl] & 1) ? (gr * xi + gi * xr) : (gr * xr - gi * xi);
             }
-            sB[kk][qq] = v;
+            sB[idx / TN][idx % TN] = v;
         }
         __syncthreads();
+        if (k0 + KS < n) fetch(k0 + KS);
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
             double av[UM], bv[UN];
@@ -326,33 +351,53 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
             bbase[sl] = (chbase + (int64_t)j * n) * W;
         }
     }
+    // loads of the next k step in flight during this step's products (as in
+    // k_block_apply)
+    constexpr int NAL = TM * KS / 256;
+    double ra[NAL], rg[NBL][2], rx[NBL][2];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int sl = 0; sl < NAL; ++sl) {
+            const int idx = t + 256 * sl;
+            const int r = row0 + idx / KS, k = k0 + idx % KS;
+            ra[sl] = (r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0;
+        }
+#pragma unroll
+        for (int sl = 0; sl < NBL; ++sl) {
+            const int k = k0 + (t + 256 * sl) / TN;
+            const bool ok = k < n && bbase[sl] >= 0;
+            const int64_t o = bbase[sl] + (int64_t)k * W;
+            const int c = bc[sl];
+            if (USE_G) {
+                const int c0 = c & ~1;
+                rg[sl][0] = ok ? G[o + c0] : 0.0;
+                rg[sl][1] = ok ? G[o + c0 + 1] : 0.0;
+                rx[sl][0] = ok ? (double)in[o + c0] : 0.0;
+                rx[sl][1] = ok ? (double)in[o + c0 + 1] : 0.0;
+            } else {
+                rx[sl][0] = ok ? (double)in[o + c] : 0.0;
+            }
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 < n; k0 += KS) {
-        for (int idx = t; idx < TM * KS; idx += 256) {
-            const int rr = idx / KS, kk = idx % KS;
-            const int r = row0 + rr, k = k0 + kk;
-            sA[kk][rr] = (L)((r < n && k < n) ? Mt[(int64_t)r * n + k] : 0.0);
+#pragma unroll
+        for (int sl = 0; sl < NAL; ++sl) {
+            const int idx = t + 256 * sl;
+            sA[idx % KS][idx / KS] = (L)ra[sl];
         }
 #pragma unroll
         for (int sl = 0; sl < NBL; ++sl) {
             const int idx = t + 256 * sl;
-            const int kk = idx / TN, qq = idx % TN;
-            const int k = k0 + kk;
-            double v = 0.0;
-            if (k < n && bbase[sl] >= 0) {
-                const int c = bc[sl];
-                const int64_t o = bbase[sl] + (int64_t)k * W;
-                if (USE_G) {
-                    const int c0 = c & ~1;
-                    const double gr = G[o + c0], gi = G[o + c0 + 1];
-                    const double xr = (double)in[o + c0], xi = (double)in[o + c0 + 1];
-                    v = (c & 1) ? (gr * xi + gi * xr) : (gr * xr - gi * xi);
-                } else {
-                    v = (double)in[o + c];
-                }
+            double v = rx[sl][0];
+            if (USE_G) {
+                const double gr = rg[sl][0], gi = rg[sl][1], xr = rx[sl][0], xi = rx[sl][1];
+                v = (bc[sl] & 1) ? (gr * xi + gi * xr) : (gr * xr - gi * xi);
             }
-            sB[kk][qq] = (L)v;
+            sB[idx / TN][idx % TN] = (L)v;
         }
         __syncthreads();
+        if (k0 + KS < n) fetch(k0 + KS);
         if constexpr (std::is_same<MT, Bf16>::value) {
             // one 16 x 16 x 16 step covers the whole k slab
             v4s av[2], bv[2];
@@ -717,16 +762,25 @@ __device__ __forceinline__ void chunk_dots(const double *__restrict__ Vb, int64_
             ar[g] = 0.0;
             ai[g] = 0.0;
         }
+        // all 8 x NR loads first (absent entries read as 0), then the sums
+        double vr[8][NR], vi[8][NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const bool ok = off[k] >= 0 && valid_e && i0 + g < nvec;
+                const double *v = Vb + (int64_t)(i0 + g) * vstride + off[k];
+                vr[g][k] = ok ? v[0] : 0.0;
+                vi[g][k] = ok ? v[1] : 0.0;
+            }
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             if (off[k] < 0 || !valid_e) continue;
 #pragma unroll
             for (int g = 0; g < 8; ++g) {
                 if (i0 + g < nvec) {
-                    const double *v = Vb + (int64_t)(i0 + g) * vstride + off[k];
-                    const double vr = v[0], vi = v[1];
-                    ar[g] += vr * wr[k] + vi * wi[k];
-                    ai[g] += vr * wi[k] - vi * wr[k];
+                    ar[g] += vr[g][k] * wr[k] + vi[g][k] * wi[k];
+                    ai[g] += vr[g][k] * wi[k] - vi[g][k] * wr[k];
                 }
             }
         }
@@ -806,15 +860,34 @@ __global__ __launch_bounds__(256) void k_vupdate(const double *__restrict__ Vb, 
         wi[k] = (off[k] >= 0 && valid_e) ? w[off[k] + 1] : 0.0;
     }
     if (valid_e) {
-        for (int i = 0; i < nvec; ++i) {
-            const double hr = h[2 * (i * nE + e)], hi = h[2 * (i * nE + e) + 1];
-            const double *v = Vb + (int64_t)i * vstride;
+        // four vectors at a time, their coefficients and rows loaded before
+        // any is used (the loads are independent; the sums keep their order)
+        constexpr int U = 4;
+        for (int i0 = 0; i0 < nvec; i0 += U) {
+            double hr[U], hi[U], vr[U][NR], vi[U][NR];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                if (off[k] < 0) continue;
-                const double vr = v[off[k]], vi = v[off[k] + 1];
-                wr[k] -= hr * vr - hi * vi;
-                wi[k] -= hr * vi + hi * vr;
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u;
+                const bool ok = i < nvec;
+                hr[u] = ok ? h[2 * (i * nE + e)] : 0.0;
+                hi[u] = ok ? h[2 * (i * nE + e) + 1] : 0.0;
+                const double *v = Vb + (int64_t)i * vstride;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const bool okk = ok && off[k] >= 0;
+                    vr[u][k] = okk ? v[off[k]] : 0.0;
+                    vi[u][k] = okk ? v[off[k] + 1] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i0 + u >= nvec) break;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    if (off[k] < 0) continue;
+                    wr[k] -= hr[u] * vr[u][k] - hi[u] * vi[u][k];
+                    wi[k] -= hr[u] * vi[u][k] + hi[u] * vr[u][k];
+                }
             }
         }
 #pragma unroll
@@ -857,9 +930,21 @@ __global__ __launch_bounds__(256) void k_reduce_stage1(const double *__restrict_
     const int c0 = s * cps, c1 = min(nchunk, c0 + cps);
     double sr = 0.0, si = 0.0;
     if (p < npair)
-        for (int c = c0 + cl; c < c1; c += 8) {
-            sr += partial[((int64_t)c * npair + p) * 2];
-            si += partial[((int64_t)c * npair + p) * 2 + 1];
+        for (int cb = c0 + cl; cb < c1; cb += 32) {
+            // four chunks' loads in flight, summed in chunk order
+            double xr[4], xi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = cb + 8 * u;
+                xr[u] = c < c1 ? partial[((int64_t)c * npair + p) * 2] : 0.0;
+                xi[u] = c < c1 ? partial[((int64_t)c * npair + p) * 2 + 1] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (cb + 8 * u >= c1) break;
+                sr += xr[u];
+                si += xi[u];
+            }
         }
     red[cl][pl][0] = sr;
     red[cl][pl][1] = si;
@@ -886,9 +971,20 @@ __global__ void k_dots_reduce(const double *__restrict__ out2, int S, int nvec, 
     const int npair = nvec * nE;
     if (p >= npair) return;
     double sr = 0.0, si = 0.0;
-    for (int s = 0; s < S; ++s) {
-        sr += out2[((int64_t)s * npair + p) * 2];
-        si += out2[((int64_t)s * npair + p) * 2 + 1];
+    for (int s0 = 0; s0 < S; s0 += 4) {
+        double xr[4], xi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u;
+            xr[u] = s < S ? out2[((int64_t)s * npair + p) * 2] : 0.0;
+            xi[u] = s < S ? out2[((int64_t)s * npair + p) * 2 + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (s0 + u >= S) break;
+            sr += xr[u];
+            si += xi[u];
+        }
     }
     h[2 * p] = sr;
     h[2 * p + 1] = si;
@@ -924,11 +1020,23 @@ __global__ void k_xupdate(const double *__restrict__ Vb, int64_t vstride,
     const int e = (int)(idx % nE);
     double xr = x[2 * idx], xi = x[2 * idx + 1];
     const int ku = kuse[e];
-    for (int i = 0; i < ku; ++i) {
-        const double yr = y[2 * (e * m + i)], yi = y[2 * (e * m + i) + 1];
-        const double vr = Vb[i * vstride + 2 * idx], vi = Vb[i * vstride + 2 * idx + 1];
-        xr += yr * vr - yi * vi;
-        xi += yr * vi + yi * vr;
+    for (int i0 = 0; i0 < ku; i0 += 4) {
+        double yr[4], yi[4], vr[4], vi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u;
+            const bool ok = i < ku;
+            yr[u] = ok ? y[2 * (e * m + i)] : 0.0;
+            yi[u] = ok ? y[2 * (e * m + i) + 1] : 0.0;
+            vr[u] = ok ? Vb[i * vstride + 2 * idx] : 0.0;
+            vi[u] = ok ? Vb[i * vstride + 2 * idx + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u >= ku) break;
+            xr += yr[u] * vr[u] - yi[u] * vi[u];
+            xi += yr[u] * vi[u] + yi[u] * vr[u];
+        }
     }
     x[2 * idx] = xr;
     x[2 * idx + 1] = xi;
@@ -982,7 +1090,19 @@ __global__ __launch_bounds__(256) void k_norm_givens(const double *__restrict__ 
     const int ee = t % nE, ct = t / nE;
     double acc = 0.0;
     if (ct < G)
-        for (int ch = ct; ch < nchunk; ch += G) acc += npart[2 * ((int64_t)ch * nE + ee)];
+        for (int cb = ct; cb < nchunk; cb += 4 * G) {
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ch = cb + u * G;
+                x[u] = ch < nchunk ? npart[2 * ((int64_t)ch * nE + ee)] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (cb + u * G >= nchunk) break;
+                acc += x[u];
+            }
+        }
     red[t] = acc;
     for (int idx = t; idx < nE * (k + 1); idx += 256) {
         const int e = idx / (k + 1), i = idx - e * (k + 1);
