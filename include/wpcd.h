@@ -428,13 +428,15 @@ wpcd_status wpcd_set_graphs(wpcd_ctx *ctx, int32_t enable);
 
 /* Kernel timing with HIP events recorded on the context's stream around
  * each launch.  enable is a bit mask of kernel groups: WPCD_TIME_PAIR (pair
- * potential and diagonalisation), WPCD_TIME_P0 (pre-selection and element
- * kernels), WPCD_TIME_SOLVE (resolvent, kernel products, GMRES); 0 turns
- * timing off.  wpcd_get_timing copies the accumulated table (up to n
- * entries, count in *n_out); wpcd_reset_timing clears it.                */
+ * potential and diagonalisation), WPCD_TIME_P0 (P0 element kernels),
+ * WPCD_TIME_SOLVE (resolvent, kernel products, GMRES), WPCD_TIME_PRESELECT
+ * (pre-selection count, scan and fill); 0 turns timing off.
+ * wpcd_get_timing copies the accumulated table (up to n entries, count in
+ * *n_out); wpcd_reset_timing clears it.                                  */
 #define WPCD_TIME_PAIR 1
 #define WPCD_TIME_P0 2
 #define WPCD_TIME_SOLVE 4
+#define WPCD_TIME_PRESELECT 8
 wpcd_status wpcd_set_timing(wpcd_ctx *ctx, int32_t enable);
 wpcd_status wpcd_get_timing(wpcd_ctx *ctx, wpcd_kernel_time *out, int32_t n, int32_t *n_out);
 wpcd_status wpcd_reset_timing(wpcd_ctx *ctx);

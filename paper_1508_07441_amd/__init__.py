@@ -31,7 +31,8 @@ WPCD_MIXED_BF16 = 3
 WPCD_TIME_PAIR = 1
 WPCD_TIME_P0 = 2
 WPCD_TIME_SOLVE = 4
-WPCD_TIME_ALL = 7
+WPCD_TIME_PRESELECT = 8
+WPCD_TIME_ALL = 15
 WPCD_WARM_NONE = 0
 WPCD_WARM_LEARNED = 1
 WPCD_WARM_GIVEN = 2

@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_fill(GridView g0, const int32_t *__rest
                                               int64_t *__restrict__ row_ptr,
                                               int32_t *__restrict__ col,
                                               int32_t *__restrict__ hint,
-                                              uint8_t *__restrict__ rstart) {
+                                              uint8_t *__restrict__ rstart, int64_t cap) {
     extern __shared__ double sgrid[];
     const GridView g = stage_grid(g0, sgrid);
     const int lane = threadIdx.x & 63;
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_fill(GridView g0, const int32_t *__rest
                 if (lane >= off) incl += v;
             }
             int64_t pos = base + (incl - cn);
-            for (int i2 = lo; i2 < hi; ++i2, ++pos) {
+            for (int i2 = lo; i2 < hi && pos < cap; ++i2, ++pos) {
                 col[pos] = j2 * g.np + i2;
                 rstart[pos] = pos == first ? mark : 0;
                 if ((pos & 63) == 0) hint[pos >> 6] = row;
@@ -1189,20 +1189,26 @@ static int structure_blocks(const wpcd_ctx *c) { return std::min((c->np * c->nq 
 
 int scan_tiles(int nrow) { return (nrow + kScanTile - 1) / kScanTile; }
 
-int64_t structure_rows(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsum) {
+// Count and scan kernels of the pre-selection (no host wait).
+static void structure_count_scan(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsum) {
     const int nrow = c->np * c->nq;
     const int nt = scan_tiles(nrow);
     {
-        TimedLaunch tl(c->timer, c->stream, "preselect_count", WPCD_TIME_P0);
+        TimedLaunch tl(c->timer, c->stream, "preselect_count", WPCD_TIME_PRESELECT);
         hipLaunchKernelGGL(k_count, dim3(structure_blocks(c)), dim3(256), grid_lds(c), c->stream,
                            grid_view(c), cnt);
         WPCD_HIP(hipGetLastError());
     }
     {
-        TimedLaunch tl(c->timer, c->stream, "preselect_scan", WPCD_TIME_P0);
+        TimedLaunch tl(c->timer, c->stream, "preselect_scan", WPCD_TIME_PRESELECT);
         hipLaunchKernelGGL(k_scan, dim3(nt), dim3(1024), 0, c->stream, cnt, nrow, row_ptr, tsum);
         WPCD_HIP(hipGetLastError());
     }
+}
+
+int64_t structure_rows(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsum) {
+    const int nt = scan_tiles(c->np * c->nq);
+    structure_count_scan(c, cnt, row_ptr, tsum);
     int64_t ts[kMaxScanTiles];
     WPCD_HIP(hipMemcpyAsync(ts, tsum, nt * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
     WPCD_HIP(hipStreamSynchronize(c->stream));
@@ -1213,25 +1219,48 @@ int64_t structure_rows(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsu
 }
 
 void structure_fill(wpcd_ctx *c, const int32_t *cnt, const int64_t *tsum, int64_t *row_ptr,
-                    int32_t *col, int32_t *hint, uint8_t *rstart) {
-    TimedLaunch tl(c->timer, c->stream, "preselect_fill", WPCD_TIME_P0);
+                    int32_t *col, int32_t *hint, uint8_t *rstart, int64_t cap) {
+    TimedLaunch tl(c->timer, c->stream, "preselect_fill", WPCD_TIME_PRESELECT);
     hipLaunchKernelGGL(k_fill, dim3(structure_blocks(c)), dim3(256), grid_lds(c), c->stream,
-                       grid_view(c), cnt, tsum, row_ptr, col, hint, rstart);
+                       grid_view(c), cnt, tsum, row_ptr, col, hint, rstart, cap);
     WPCD_HIP(hipGetLastError());
 }
 
+// The structure depends on the bin edges alone.  When they equal those of
+// the last completed build, that build's nonzero count sizes the buffers
+// and the element launch, and the count, scan and fill kernels run without
+// the host waiting for their total in between; the total the fill writes
+// (row_ptr[nrow]) is copied to pinned host memory on the stream and
+// compared once the build has finished (nnz_check, copied by
+// structure_count_copy after the element launch), and a mismatch rebuilds
+// on the waiting path.  The fill never writes past the buffers either way.
 void build_structure(wpcd_ctx *c) {
     const int nrow = c->np * c->nq;
     c->d_cnt.reserve(nrow);
     c->d_tsum.reserve(kMaxScanTiles);
     c->d_rowptr.reserve((size_t)nrow + 1);
-    const int64_t nnz = structure_rows(c, c->d_cnt.ptr, c->d_rowptr.ptr, c->d_tsum.ptr);
+    c->nnz_check = c->pred_nnz >= 0 && c->h_nnz && c->pred_p == c->p && c->pred_q == c->q;
+    int64_t nnz;
+    if (c->nnz_check) {
+        structure_count_scan(c, c->d_cnt.ptr, c->d_rowptr.ptr, c->d_tsum.ptr);
+        nnz = c->pred_nnz;
+    } else {
+        nnz = structure_rows(c, c->d_cnt.ptr, c->d_rowptr.ptr, c->d_tsum.ptr);
+    }
     c->nnz = nnz;
     c->d_col.reserve(nnz);
     c->d_hint.reserve(hint_len(nnz));
     c->d_rstart.reserve(nnz);
     structure_fill(c, c->d_cnt.ptr, c->d_tsum.ptr, c->d_rowptr.ptr, c->d_col.ptr, c->d_hint.ptr,
-                   c->d_rstart.ptr);
+                   c->d_rstart.ptr, nnz);
+}
+
+// The copy of the deferred count (after the element launch, so it does not
+// sit between the fill and the elements on the stream).
+void structure_count_copy(wpcd_ctx *c) {
+    if (c->nnz_check)
+        WPCD_HIP(hipMemcpyAsync(c->h_nnz, c->d_rowptr.ptr + (int64_t)c->np * c->nq,
+                                sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
 }
 
 // Microseconds per launch of f (one warm-up, then two timed launches).

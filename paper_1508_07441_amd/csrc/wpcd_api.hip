@@ -1208,7 +1208,7 @@ wpcd_status wpcd_build_p_noalloc(wpcd_ctx *c, wpcd_precision prec, int64_t *row_
                          " nonzero cells)");
         int32_t *hint = reinterpret_cast<int32_t *>(base + off_hint);
         uint8_t *rstart = reinterpret_cast<uint8_t *>(base + off_rs);
-        structure_fill(c, cnt, tsum, row_ptr, col, hint, rstart);
+        structure_fill(c, cnt, tsum, row_ptr, col, hint, rstart, nnz);
         const bool fp64 = prec == WPCD_FP64;
         values_into(c, fp64, row_ptr, col, hint, rstart, nnz, fp64 ? (double *)val : nullptr,
                     fp64 ? nullptr : (float *)val, false);
@@ -1246,9 +1246,27 @@ wpcd_status wpcd_build_p(wpcd_ctx *c, wpcd_precision prec, int64_t *nnz_out) {
         WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
         c->has_p = false;
         c->has_val64 = false;
+        if (!c->h_nnz) {
+            void *h = nullptr;
+            if (hipHostMalloc(&h, sizeof(int64_t)) == hipSuccess) c->h_nnz = (int64_t *)h;
+            else (void)hipGetLastError();   // no pinned word: every build waits for its count
+        }
         build_structure(c);
         build_values(c, prec == WPCD_FP64);
+        structure_count_copy(c);
         WPCD_HIP(hipStreamSynchronize(c->stream));
+        if (c->nnz_check && *c->h_nnz != c->nnz) {
+            // the count differs from the last build's on the same edges:
+            // build again on the waiting path
+            c->pred_nnz = -1;
+            build_structure(c);
+            build_values(c, prec == WPCD_FP64);
+            WPCD_HIP(hipStreamSynchronize(c->stream));
+        }
+        c->nnz_check = false;
+        c->pred_nnz = c->nnz;
+        c->pred_p = c->p;
+        c->pred_q = c->q;
         c->has_p = true;
         c->p_fp64 = prec == WPCD_FP64;
         c->has_val64 = c->p_fp64;
@@ -1716,6 +1734,8 @@ void wpcd_destroy(wpcd_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->h_nnz) (void)hipHostFree(c->h_nnz);
+    c->h_nnz = nullptr;
     c->timer.release();
     c->d_p.release();
     c->d_q.release();

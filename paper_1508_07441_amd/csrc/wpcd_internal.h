@@ -239,6 +239,13 @@ struct wpcd_ctx {
     bool p_fp64 = false;     // P0 built in FP64 (else FP32 values in d_val32)
     bool has_val64 = false;  // d_val64 holds the FP64 values of the current structure
     int64_t nnz = 0;
+    // the nonzero count of the last completed build and its bin edges (the
+    // structure depends on them alone); h_nnz: pinned word the deferred
+    // count is copied to; nnz_check: this build's count awaits that check
+    int64_t pred_nnz = -1;
+    std::vector<double> pred_p, pred_q;
+    int64_t *h_nnz = nullptr;
+    bool nnz_check = false;
     wpcd::DBuf<int64_t> d_rowptr;
     wpcd::DBuf<int32_t> d_col, d_cnt, d_hint;   // columns, row counts, row hints (one per 64 nonzeros)
     wpcd::DBuf<int64_t> d_tsum;                  // pre-selection scan: per-tile totals
@@ -313,8 +320,9 @@ constexpr int kMaxScanTiles = 64;   // tiles of 16384 rows: n_p n_q <= 2^20
 inline int64_t hint_len(int64_t nnz) { return (nnz + 63) / 64 + 1; }
 int scan_tiles(int nrow);
 int64_t structure_rows(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsum);
+void structure_count_copy(wpcd_ctx *c);
 void structure_fill(wpcd_ctx *c, const int32_t *cnt, const int64_t *tsum, int64_t *row_ptr,
-                    int32_t *col, int32_t *hint, uint8_t *rstart);
+                    int32_t *col, int32_t *hint, uint8_t *rstart, int64_t cap);
 void values_into(wpcd_ctx *c, bool fp64, const int64_t *row_ptr, const int32_t *col,
                  const int32_t *hint, const uint8_t *rstart, int64_t nnz, double *val64,
                  float *val32, bool measure);

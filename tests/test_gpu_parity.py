@@ -657,6 +657,31 @@ def test_max_grid_1024(ctx, P):
     assert abs(abs(complex(r.S_re, r.S_im)) - 1.0) <= 1e-7
 
 
+def test_repeat_builds_on_same_edges(ctx, P):
+    """A build on the bin edges of the previous build (whose nonzero count
+    then sizes the buffers before the new count is known) gives the same
+    structure and values; a build on other edges in between, and the build
+    after it, match the oracle's structure."""
+    pa, qa = O.cheb_edges(40, 10.0), O.cheb_edges(44, 10.0)
+    pb, qb = O.cheb_edges(37, 10.0), O.cheb_edges(29, 10.0)
+    runs = []
+    for p, q, tag in ((pa, qa, "a"), (pa, qa, "a again"), (pb, qb, "b"), (pa, qa, "a after b"),
+                      (pa, qa, "a repeated")):
+        ctx.build_basis(p.size - 1, q.size - 1, 10.0, 10.0, 8, 16, potential=YAM)
+        say(f"[repeat builds] {tag}")
+        for prec in (P.WPCD_MIXED, P.WPCD_FP64):
+            nnz = ctx.build_p(prec)
+            rp, col, val = ctx.get_p()
+            ptr_o, col_o = O.preselect(p, q)
+            assert nnz == int(ptr_o[-1]) == int(rp[-1])
+            assert np.array_equal(rp, ptr_o) and np.array_equal(col, col_o)
+            runs.append((tag[0], prec, val.copy()))
+    for tag in "ab":
+        for prec in (P.WPCD_MIXED, P.WPCD_FP64):
+            vals = [v for t, pr, v in runs if t == tag and pr == prec]
+            assert all(np.array_equal(v, vals[0]) for v in vals[1:])
+
+
 # ------------------------------------------------------------- autotuning
 def test_autotune_candidates_agree(ctx, P):
     """Every candidate launch shape (forced) and the measured choice give the
