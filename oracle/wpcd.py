@@ -309,6 +309,12 @@ class System:
     col: np.ndarray = None
     val: np.ndarray = None                      # (nnz, nch, nch)
     _P0: object = None
+    # pair wave of each channel (key into eps, O, v); None: the channel's l
+    wave: list = None
+
+    def wkey(self, a: int):
+        """Key of channel a's pair wave in eps, O and v."""
+        return self.chans[a][0] if self.wave is None else self.wave[a]
 
     @property
     def Np(self):
@@ -425,7 +431,7 @@ def energy_bin(sysm: System, E: float):
     energies eps*_0 + 3/4 q^2 over the entrance spectator bin j0 that holds
     q0 (every E in it gives the same averaged kernel and amplitudes)."""
     a0, j0, q0, idx = entrance(sysm, E)
-    eb = sysm.eps[0][0]
+    eb = sysm.eps[sysm.wkey(a0)][0]
     return eb + 0.75 * sysm.q[j0] ** 2, eb + 0.75 * sysm.q[j0 + 1] ** 2
 
 
@@ -436,13 +442,14 @@ def resolvent(sysm: System, E: float, averaged: bool = False):
     qmax = sysm.q[-1]
     if averaged:
         E1, E2 = energy_bin(sysm, E)
-    for a, (l, lam) in enumerate(sysm.chans):
+    for a in range(len(sysm.chans)):
+        eps = sysm.eps[sysm.wkey(a)]
         for j in range(sysm.Nq):
             for k in range(sysm.Np):
                 if averaged:
-                    G[a, j, k] = resolvent_bin_avg(E1, E2, sysm.eps[l][k], sysm.q[j], sysm.q[j + 1])
+                    G[a, j, k] = resolvent_bin_avg(E1, E2, eps[k], sysm.q[j], sysm.q[j + 1])
                 else:
-                    G[a, j, k] = resolvent_bin(E, sysm.eps[l][k], sysm.q[j], sysm.q[j + 1], qmax)
+                    G[a, j, k] = resolvent_bin(E, eps[k], sysm.q[j], sysm.q[j + 1], qmax)
     return G
 
 
@@ -450,15 +457,15 @@ def resolvent(sysm: System, E: float, averaged: bool = False):
 def _blockwise(sysm: System, y, mats):
     """Apply a per-channel N x N matrix to the pair index of y (nch, Nq, Np)."""
     out = np.empty_like(y)
-    for a, (l, lam) in enumerate(sysm.chans):
-        out[a] = y[a] @ mats[l].T
+    for a in range(len(sysm.chans)):
+        out[a] = y[a] @ mats[sysm.wkey(a)].T
     return out
 
 
 def apply_A(sysm: System, y):
     """A y = O P0 V~ y, with V~ = O^T (O v O^T) = v O^T per pair wave (eq.(kernel))."""
     y = y.reshape(len(sysm.chans), sysm.Nq, sysm.Np)
-    vt = {l: sysm.v[l] @ sysm.O[l].T for l in sysm.v}
+    vt = {w: sysm.v[w] @ sysm.O[w].T for w in sysm.v}
     y2 = _blockwise(sysm, y, vt)
     y3 = (sysm.P0_matrix() @ y2.ravel()).reshape(y.shape)
     return _blockwise(sysm, y3, sysm.O).ravel()
@@ -476,7 +483,7 @@ def entrance(sysm: System, E: float):
     if not a0:
         raise ValueError("no entrance channel (l=0, lam=L)")
     a0 = a0[0]
-    eb = sysm.eps[0][0]
+    eb = sysm.eps[sysm.wkey(a0)][0]
     if E <= eb:
         raise ValueError("energy below the two-body threshold")
     q0 = math.sqrt(4.0 * (E - eb) / 3.0)
@@ -648,8 +655,8 @@ def amplitudes(sysm: System, E: float, u, averaged: bool = False):
     A = rho0 * U00
     S = 1.0 - 2j * math.pi * A
     br, dist = [], []
-    for a, (l, lam) in enumerate(sysm.chans):
-        for k, ek in enumerate(sysm.eps[l]):
+    for a in range(len(sysm.chans)):
+        for k, ek in enumerate(sysm.eps[sysm.wkey(a)]):
             if a == a0 and k == 0:
                 continue
             states = []

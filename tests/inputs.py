@@ -75,3 +75,11 @@ def learn_draws(seed: int, n_var: int, n_mult: int, n_E: int, e_lo: float, e_hi:
         mult.append([0.8 + 0.4 * x for x in row[:n_mult]])
         E.append([e_lo + (e_hi - e_lo) * x for x in row[n_mult:]])
     return mult, E
+
+# Three nucleons, pair s-waves (Sec. III.B eq.(gal) with spin and isospin):
+# channels (pair spin s, pair isospin t) with the deuteron channel first;
+# the 1S0 pair potential is the fitted Yukawa sum with both strengths times
+# NUC_SINGLET_MULT (no bound pair), the 3S1 one the fitted sum itself.
+NUC_DOUBLET = [(1, 0), (0, 1)]   # three-body spin 1/2
+NUC_QUARTET = [(1, 0)]           # three-body spin 3/2
+NUC_SINGLET_MULT = (0.7, 0.7)
