@@ -326,6 +326,49 @@ def c5_measure(P, n_var, n_e, sweep):
             "max_rel_amp_diff_learned_vs_plain": err}
 
 
+def nucleon_measure(P):
+    """Three nucleons in pair s-waves (Sec. III.B eq.(gal) with spin and
+    isospin) on the 150 x 150 grid: 3S1 pair potential = the Yukawa sum
+    fitted to -0.1 (the deuteron), 1S0 = the same with both strengths x 0.7
+    (unbound); doublet (channels 3S1, 1S0) and quartet (3S1).  P build
+    (mixed) and the 8-energy solve (mixed, FP64) per energy, elastic phases."""
+    ctx = P.Context(0)
+    ctx.set_autotune(P.WPCD_TUNE_MEASURE)
+    fit = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(RANGES), fit_e2=-0.1)
+    out = {"workload": "3N pair s-waves, 150x150 bins, 3S1 Yukawa sum fitted to -0.1, "
+                       "1S0 x 0.7; doublet (3S1, 1S0) and quartet (3S1); 8 energies"}
+    for name, two_S, chans, mult in (("doublet", 1, [(1, 0), (0, 1)], [[1.0, 1.0], [0.7, 0.7]]),
+                                     ("quartet", 3, [(1, 0)], None)):
+        ctx.build_basis_nucleons(N, N, 10.0, 10.0, NGQ, NGX, two_S=two_S, channels=chans,
+                                 potential=fit, mult=mult)
+        nnz = ctx.build_p(P.WPCD_MIXED)
+        ctx.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            ctx.build_p(P.WPCD_MIXED)
+        ctx.synchronize()
+        t_build = (time.perf_counter() - t) / 3
+        row = {"n_ch": len(chans), "nnz_cells": nnz, "p_build_mixed_ms": 1e3 * t_build,
+               "channel_values_per_s": len(chans) ** 2 * nnz / t_build}
+        for prec, label in ((P.WPCD_MIXED, "mixed"), (P.WPCD_FP64, "fp64")):
+            if prec == P.WPCD_FP64:
+                ctx.build_p(P.WPCD_FP64)
+            ctx.solve(ENERGIES, prec)
+            best, res = 1e30, None
+            for _ in range(3):
+                a = time.perf_counter()
+                res = ctx.solve(ENERGIES, prec)
+                best = min(best, time.perf_counter() - a)
+            row[f"solve_s_per_energy_{label}"] = best / len(ENERGIES)
+            row[f"iters_per_energy_{label}"] = sum(r.iters for r in res) / len(res)
+            if label == "fp64":
+                row["delta_deg"] = [math.degrees(r.delta) for r in res]
+                row["eta"] = [r.eta for r in res]
+        out[name] = row
+    ctx.close()
+    return out
+
+
 def model_fill_measure(P):
     """The paper's model matrix fills (Sec. IV.A): dense, and sparse at
     alpha = 0.01 by filtering inside the dense launch or by selecting the
@@ -617,6 +660,7 @@ def main():
     if not args.no_c3:
         out["c3"] = c3_measure(P)
     out["model_fill"] = model_fill_measure(P)
+    out["nucleons"] = nucleon_measure(P)
     if args.c4:
         nv, ne = (int(x) for x in args.c4.split(","))
         out["c4"] = c4_measure(P, nv, ne)

@@ -227,6 +227,35 @@ wpcd_status wpcd_create(int device, void *hip_stream, wpcd_ctx **out);
 wpcd_status wpcd_build_basis(wpcd_ctx *ctx, const wpcd_basis_desc *basis,
                              const wpcd_potential_desc *pot);
 
+/* Three nucleons with pair interactions in s-waves only (Sec. III.B,
+ * eq.(gal) with the spin and isospin of the nucleons; the paper's
+ * realistic case of Sec. V.A couples many more channels).  Channel a has
+ * pair spin s[a] and pair isospin t[a], l = lam = 0, with s + t odd (the
+ * pair antisymmetric): (1, 0) is 3S1, (0, 1) is 1S0; channel 0 must be
+ * (1, 0), whose pair bound state (the deuteron) is the entrance state.
+ * two_S = 1 (three-body spin 1/2, channels (1, 0) and optionally (0, 1))
+ * or 3 (spin 3/2, channel (1, 0) only); three-body isospin 1/2.  The
+ * permutation kernel between channels a and b is the s-wave one times
+ *   g_ab = (1/2) (sigma_ab tau_ab + sigma_ba tau_ba),
+ *   sigma_ab = (-1)^(s_b) sqrt((2 s_a + 1)(2 s_b + 1)) {1/2 1/2 s_b; 1/2 S s_a},
+ * tau_ab the same with t and total isospin 1/2 (the cyclic permutation of
+ * the three nucleons between recoupled spin and isospin states; 6j symbols
+ * by Racah's sum): g = [[1/4, -3/4], [-3/4, 1/4]] for the doublet, -1/2 for
+ * the quartet.  Channel a's pair potential is pot with strength term k
+ * times mult[a * pot->n_terms + k] (mult NULL: 1); pot->fit_e2 fits the
+ * common scale on channel 0.  basis gives the grid and the quadratures
+ * (its n_ch, L, l and lam are not read).  wpcd_pair_spectrum's l then
+ * selects the channel.  Errors: WPCD_E_INVALID for the conditions above. */
+typedef struct {
+    int32_t two_S;
+    int32_t n_ch;
+    const int32_t *s, *t;
+    const double *mult;
+} wpcd_nucleon_desc;
+wpcd_status wpcd_build_basis_nucleons(wpcd_ctx *ctx, const wpcd_basis_desc *basis,
+                                      const wpcd_potential_desc *pot,
+                                      const wpcd_nucleon_desc *nuc);
+
 /* Replace only the pair potential (the grid and any built P0 stay valid,
  * since P0 does not depend on the potential -- Sec. III.C).              */
 wpcd_status wpcd_set_potential(wpcd_ctx *ctx, const wpcd_potential_desc *pot);

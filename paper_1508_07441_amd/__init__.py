@@ -47,7 +47,8 @@ WPCD_TUNE_FORCE = 16
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_CONVERGED",
                 5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE"}
 
-ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_set_potential", "wpcd_pair_spectrum",
+ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_build_basis_nucleons",
+                 "wpcd_set_potential", "wpcd_pair_spectrum",
                  "wpcd_build_p", "wpcd_build_p_noalloc", "wpcd_get_p", "wpcd_save_p",
                  "wpcd_load_p", "wpcd_solve",
                  "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_bound_state", "wpcd_model_fill",
@@ -67,6 +68,12 @@ class wpcd_basis_desc(ctypes.Structure):
                 ("n_gauss_q", ctypes.c_int32), ("n_gauss_x", ctypes.c_int32),
                 ("L", ctypes.c_int32), ("n_ch", ctypes.c_int32),
                 ("l", ctypes.POINTER(ctypes.c_int32)), ("lam", ctypes.POINTER(ctypes.c_int32))]
+
+
+class wpcd_nucleon_desc(ctypes.Structure):
+    _fields_ = [("two_S", ctypes.c_int32), ("n_ch", ctypes.c_int32),
+                ("s", ctypes.POINTER(ctypes.c_int32)), ("t", ctypes.POINTER(ctypes.c_int32)),
+                ("mult", ctypes.POINTER(ctypes.c_double))]
 
 
 class wpcd_potential_desc(ctypes.Structure):
@@ -145,6 +152,9 @@ def lib():
         L.wpcd_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
         L.wpcd_build_basis.argtypes = [vp, ctypes.POINTER(wpcd_basis_desc),
                                        ctypes.POINTER(wpcd_potential_desc)]
+        L.wpcd_build_basis_nucleons.argtypes = [vp, ctypes.POINTER(wpcd_basis_desc),
+                                                ctypes.POINTER(wpcd_potential_desc),
+                                                ctypes.POINTER(wpcd_nucleon_desc)]
         L.wpcd_set_potential.argtypes = [vp, ctypes.POINTER(wpcd_potential_desc)]
         L.wpcd_pair_spectrum.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
         L.wpcd_build_p.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
@@ -226,6 +236,27 @@ def wpcd_build_basis(ctx, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, channels
                         lam.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     pd, keep = _pot_desc(potential)
     _check(ctx, lib().wpcd_build_basis(ctx, ctypes.byref(d), ctypes.byref(pd)))
+    del keep
+
+
+def wpcd_build_basis_nucleons(ctx, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, two_S,
+                              channels=((1, 0), (0, 1)), potential=None, mult=None,
+                              p_edges=None, q_edges=None):
+    """channels: (pair spin s, pair isospin t) per channel, (1, 0) first;
+    mult: per channel, one strength multiplier per potential term."""
+    s_ = np.ascontiguousarray([c[0] for c in channels], dtype=np.int32)
+    t_ = np.ascontiguousarray([c[1] for c in channels], dtype=np.int32)
+    m_ = None if mult is None else np.ascontiguousarray(mult, dtype=np.float64).ravel()
+    pe = None if p_edges is None else np.ascontiguousarray(p_edges, dtype=np.float64)
+    qe = None if q_edges is None else np.ascontiguousarray(q_edges, dtype=np.float64)
+    d = wpcd_basis_desc(n_p, n_q, float(p_max), float(q_max), 0 if pe is None else 1,
+                        _dp(pe), _dp(qe), n_gauss_q, n_gauss_x, 0, 0, None, None)
+    nd = wpcd_nucleon_desc(int(two_S), len(channels),
+                           s_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           t_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(m_))
+    pd, keep = _pot_desc(potential)
+    _check(ctx, lib().wpcd_build_basis_nucleons(ctx, ctypes.byref(d), ctypes.byref(pd),
+                                                ctypes.byref(nd)))
     del keep
 
 
@@ -477,6 +508,13 @@ class Context:
                     channels=((0, 0),), L=0, potential=None, p_edges=None, q_edges=None):
         wpcd_build_basis(self.h, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, channels, L,
                          potential, p_edges, q_edges)
+        self.n_p, self.n_q, self.n_ch = n_p, n_q, len(channels)
+
+    def build_basis_nucleons(self, n_p, n_q, p_max=10.0, q_max=10.0, n_gauss_q=8, n_gauss_x=16,
+                             two_S=1, channels=((1, 0), (0, 1)), potential=None, mult=None,
+                             p_edges=None, q_edges=None):
+        wpcd_build_basis_nucleons(self.h, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, two_S,
+                                  channels, potential, mult, p_edges, q_edges)
         self.n_p, self.n_q, self.n_ch = n_p, n_q, len(channels)
 
     def set_potential(self, potential):

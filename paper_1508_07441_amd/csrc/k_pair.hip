@@ -527,8 +527,9 @@ void launch_potential(wpcd_ctx *c, int wave, double *v_out) {
     DBuf<double> &ms = c->d_pot;
     ms.reserve(2 * 16);
     std::vector<double> host(32, 0.0);
+    const std::vector<double> &wm = c->waves[wave].mult;   // per-wave multipliers (nucleons)
     for (int t = 0; t < nt; ++t) {
-        host[t] = c->pot_s[t];
+        host[t] = c->pot_s[t] * (t < (int)wm.size() ? wm[t] : 1.0);
         host[16 + t] = c->pot_mu[t];
     }
     WPCD_HIP(hipMemcpyAsync(ms.ptr, host.data(), 32 * sizeof(double), hipMemcpyHostToDevice,

@@ -335,6 +335,79 @@ static void coupling_tables_compute(int L, int nch, const int *l, const int *lam
         }
 }
 
+// ---- three nucleons, pair s-waves (Sec. III.B eq.(gal) with spin and
+// isospin; Sec. V.A).  Arguments of the 6j symbols are given doubled (2j),
+// so half-integers stay integers.
+namespace {
+
+// Triangle coefficient Delta(a b c) of doubled arguments.
+ld tri_delta(int a2, int b2, int c2) {
+    return std::sqrt(lfact((a2 + b2 - c2) / 2) * lfact((a2 - b2 + c2) / 2) *
+                     lfact((-a2 + b2 + c2) / 2) / lfact((a2 + b2 + c2) / 2 + 1));
+}
+
+bool triad(int a2, int b2, int c2) {
+    return c2 >= std::abs(a2 - b2) && c2 <= a2 + b2 && (a2 + b2 + c2) % 2 == 0;
+}
+
+// Wigner 6j symbol {j1 j2 j3; j4 j5 j6} by Racah's sum (doubled arguments).
+ld sixj2(int j1, int j2, int j3, int j4, int j5, int j6) {
+    if (!triad(j1, j2, j3) || !triad(j1, j5, j6) || !triad(j4, j2, j6) || !triad(j4, j5, j3))
+        return 0.0L;
+    const ld pre = tri_delta(j1, j2, j3) * tri_delta(j1, j5, j6) * tri_delta(j4, j2, j6) *
+                   tri_delta(j4, j5, j3);
+    const int a1 = (j1 + j2 + j3) / 2, a2 = (j1 + j5 + j6) / 2, a3 = (j4 + j2 + j6) / 2,
+              a4 = (j4 + j5 + j3) / 2;
+    const int b1 = (j1 + j2 + j4 + j5) / 2, b2 = (j2 + j3 + j5 + j6) / 2,
+              b3 = (j3 + j1 + j6 + j4) / 2;
+    const int tmin = std::max(std::max(a1, a2), std::max(a3, a4));
+    const int tmax = std::min(b1, std::min(b2, b3));
+    ld sum = 0.0L;
+    for (int t = tmin; t <= tmax; ++t) {
+        const ld term = lfact(t + 1) / (lfact(t - a1) * lfact(t - a2) * lfact(t - a3) *
+                                        lfact(t - a4) * lfact(b1 - t) * lfact(b2 - t) *
+                                        lfact(b3 - t));
+        sum += (t % 2 ? -term : term);
+    }
+    return pre * sum;
+}
+
+// <(x_a 1/2) X | C | (x_b 1/2) X> for two spins 1/2 of the pair (2, 3)
+// coupled to x and the third to X (2X = two_X): the cyclic permutation of
+// the three particles between recoupled states,
+//   (-1)^(x_b) sqrt((2 x_a + 1)(2 x_b + 1)) {1/2 1/2 x_b; 1/2 X x_a}.
+ld cyclic_recoupling(int xa, int xb, int two_X) {
+    const ld v = std::sqrt((ld)((2 * xa + 1) * (2 * xb + 1))) *
+                 sixj2(1, 1, 2 * xb, 1, two_X, 2 * xa);
+    return (xb % 2) ? -v : v;
+}
+}  // namespace
+
+// g_ab = (1/2)(sigma_ab tau_ab + sigma_ba tau_ba) for channels a = (s_a,
+// t_a): spin part with total 2S = two_S, isospin part with total 1/2; the
+// second term is the other cyclic permutation (the inverse, whose matrix is
+// the transpose).  Stored as McPair entries of degree 0 with one
+// coefficient each, so the multichannel element kernels multiply the
+// s-wave integrand by g_ab.
+void nucleon_tables(int two_S, int nch, const int *s, const int *t, std::vector<McPair> &pairs,
+                    std::vector<double> &coef, std::vector<double> &g) {
+    pairs.assign(nch * nch, McPair{});
+    coef.assign(nch * nch, 0.0);
+    g.assign(nch * nch, 0.0);
+    for (int a = 0; a < nch; ++a)
+        for (int b = 0; b < nch; ++b) {
+            const ld sab = cyclic_recoupling(s[a], s[b], two_S), sba = cyclic_recoupling(s[b], s[a], two_S);
+            const ld tab = cyclic_recoupling(t[a], t[b], 1), tba = cyclic_recoupling(t[b], t[a], 1);
+            const double v = (double)(0.5L * (sab * tab + sba * tba));
+            McPair &P = pairs[a * nch + b];
+            P.d = 0;
+            P.hl = P.hl2 = P.hlam = P.hlam2 = 0;
+            P.off = a * nch + b;
+            coef[a * nch + b] = v;
+            g[a * nch + b] = v;
+        }
+}
+
 // Both are pure functions of (L, channels): computed once per process for
 // each channel set and shared.
 static std::vector<int> channel_key(int L, int nch, const int *l, const int *lam) {

@@ -111,6 +111,7 @@ struct McTerm {
 
 struct PairWave {
     int l = 0;
+    std::vector<double> mult;     // per-term strength multipliers of this wave (empty: 1)
     DBuf<double> v, O, eps, Vt;   // v, O (rows eigenvectors), eps* ascending, Vt = v O^T
     std::vector<double> h_eps;    // host copy of eps*
 };
@@ -208,6 +209,11 @@ struct wpcd_ctx {
     bool has_basis = false;
     int np = 0, nq = 0, ngq = 0, ngx = 0, L = 0, nch = 0;
     int ch_l[wpcd::kMaxCh] = {}, ch_lam[wpcd::kMaxCh] = {};
+    // three nucleons in pair s-waves: 2S (1 or 3; 0 for bosons), the pair
+    // spin and isospin of each channel, and the coefficients g_ab
+    int nuc_two_S = 0;
+    int ch_s[wpcd::kMaxCh] = {}, ch_t[wpcd::kMaxCh] = {};
+    std::vector<double> nuc_g;
     int ch_wave[wpcd::kMaxCh] = {};     // channel -> index into waves
     std::vector<double> p, q;           // host edges
     std::vector<double> gq, wq, gx, wx; // host Gauss tables on [-1, 1]
@@ -284,6 +290,11 @@ void coupling_tables(int L, int nch, const int *l, const int *lam, std::vector<M
                      std::vector<double> &coef);
 void coupling_terms(int L, int nch, const int *l, const int *lam, std::vector<McTerm> &terms,
                     std::vector<int> &first);
+// Three nucleons in pair s-waves: the spin-isospin coefficients g_ab of the
+// permutation kernel (row-major nch x nch) and their degree-0 coupling
+// tables for the multichannel element kernels.
+void nucleon_tables(int two_S, int nch, const int *s, const int *t, std::vector<McPair> &pairs,
+                    std::vector<double> &coef, std::vector<double> &g);
 
 // ---- kernel launchers (defined in the .hip files)
 void launch_potential(wpcd_ctx *c, int wave, double *v_out);

@@ -1,0 +1,144 @@
+"""GPU parity for three nucleons in pair s-waves (Sec. III.B eq.(gal) with
+spin and isospin; Sec. V.A): the library's channel coupling (6j symbols)
+and per-channel pair waves against the oracle's brute-force recoupling.
+
+Bars: structure bit-exact; FP64 P0 blocks and amplitudes within 1e-10
+relative; FP32 P0 blocks within the compensated bound (2e-6 relative plus a
+small absolute floor); mixed amplitudes within 1e-6."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.wpcd as O
+import oracle.nucleons as NU
+from inputs import YUK_RANGES, NUC_DOUBLET, NUC_QUARTET, NUC_SINGLET_MULT
+
+pytestmark = pytest.mark.gpu
+
+FIT = dict(kind="yukawa", strength=[-1.0, -1.0], range=list(YUK_RANGES), fit_e2=-0.1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1508_07441_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle(n, ngx, two_S):
+    p = O.cheb_edges(n, 10.0)
+    s = O.fit_strength(p, YUK_RANGES, -0.1)
+    pot = O.Potential("yukawa", (-s, -s), YUK_RANGES)
+    if two_S == 1:
+        return NU.build_system_nucleons(p, p.copy(), 1, NUC_DOUBLET, 8, ngx, pot,
+                                        [[1.0, 1.0], list(NUC_SINGLET_MULT)])
+    return NU.build_system_nucleons(p, p.copy(), 3, NUC_QUARTET, 8, ngx, pot)
+
+
+def _build(ctx, n, ngx, two_S):
+    if two_S == 1:
+        ctx.build_basis_nucleons(n, n, 10.0, 10.0, 8, ngx, two_S=1, channels=NUC_DOUBLET,
+                                 potential=FIT, mult=[[1.0, 1.0], list(NUC_SINGLET_MULT)])
+    else:
+        ctx.build_basis_nucleons(n, n, 10.0, 10.0, 8, ngx, two_S=3, channels=NUC_QUARTET,
+                                 potential=FIT)
+
+
+@pytest.mark.parametrize("two_S,ngx", [(1, 16), (1, 20), (3, 20)])
+def test_nucleon_p0_blocks(ctx, P, two_S, ngx):
+    n = 26
+    _build(ctx, n, ngx, two_S)
+    sysm = _oracle(n, ngx, two_S)
+    for a in range(len(sysm.chans)):
+        eps, _, _ = ctx.pair_spectrum(a, want_O=False)
+        assert np.max(np.abs(eps - sysm.eps[a])) < 1e-11 * np.abs(sysm.eps[a]).max()
+    say(f"[nucleons 2S={two_S} ngx={ngx}] build_p FP64")
+    nnz = ctx.build_p(P.WPCD_FP64)
+    rp, col, val = ctx.get_p()
+    assert nnz == int(sysm.row_ptr[-1])
+    assert np.array_equal(rp, sysm.row_ptr) and np.array_equal(col, sysm.col)
+    vo = sysm.val
+    scale = np.abs(vo).max()
+    assert np.all(np.abs(val - vo) <= 1e-10 * np.abs(vo) + 1e-13 * scale)
+    say(f"[nucleons 2S={two_S} ngx={ngx}] build_p MIXED")
+    ctx.build_p(P.WPCD_MIXED)
+    _, _, v32 = ctx.get_p()
+    assert np.all(np.abs(v32 - vo) <= 2e-6 * np.abs(vo) + 1e-7 * scale)
+
+
+@pytest.mark.parametrize("two_S", [1, 3])
+def test_nucleon_amplitudes(ctx, P, two_S):
+    n = 24
+    _build(ctx, n, 16, two_S)
+    sysm = _oracle(n, 16, two_S)
+    energies = [-0.07, -0.02, 0.3, 1.5]
+    refs = {}
+    for E in energies:
+        u = O.solve_lu(sysm, E)
+        refs[E] = O.amplitudes(sysm, E, u)
+    ctx.build_p(P.WPCD_FP64)
+    say(f"[nucleons 2S={two_S}] solve FP64")
+    res = ctx.solve(energies, P.WPCD_FP64)
+    for r, E in zip(res, energies):
+        a = refs[E]
+        assert r.status == P.WPCD_OK, (E, P.STATUS_NAMES[r.status])
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
+        if E < 0:
+            assert abs(math.hypot(r.S_re, r.S_im) - 1.0) < 1e-11
+    ctx.build_p(P.WPCD_MIXED)
+    say(f"[nucleons 2S={two_S}] solve MIXED")
+    for r, E in zip(ctx.solve(energies, P.WPCD_MIXED), energies):
+        assert r.status == P.WPCD_OK
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - refs[E].U00) <= 1e-6 * abs(refs[E].U00), (E, U, refs[E].U00)
+
+
+def test_nucleon_breakup_elements(ctx, P):
+    """Breakup pseudostate elements of the doublet above breakup (both
+    channels' pseudostates) against the oracle's."""
+    n = 24
+    _build(ctx, n, 16, 1)
+    sysm = _oracle(n, 16, 1)
+    E = 0.6
+    a = O.amplitudes(sysm, E, O.solve_lu(sysm, E))
+    ctx.build_p(P.WPCD_FP64)
+    res, br = ctx.solve([E], P.WPCD_FP64, want_breakup=True)
+    assert res[0].n_open == len(a.breakup)
+    ref = {(ch, k, j): S for ch, k, j, S in a.breakup}
+    got = {(int(x[0]), int(x[1]), int(x[2])): complex(x[3], x[4]) for x in br[0]}
+    assert set(got) == set(ref) and len(ref) > 0
+    smax = max(abs(S) for S in ref.values())
+    for key, S in ref.items():
+        assert abs(got[key] - S) <= 1e-9 * smax, (key, got[key], S)
+    assert {ch for ch, _, _ in ref} == {0, 1}
+
+
+def test_nucleon_p0_file_signature(ctx, P, tmp_path):
+    """A saved nucleon P0 loads back into the same channel set and is refused
+    by a boson basis on the same grid."""
+    n = 12
+    _build(ctx, n, 16, 1)
+    ctx.build_p(P.WPCD_FP64)
+    _, _, v0 = ctx.get_p()
+    f = str(tmp_path / "p0_nuc.bin")
+    ctx.save_p(f)
+    _build(ctx, n, 16, 1)
+    ctx.load_p(f)
+    assert np.array_equal(ctx.get_p()[2], v0)
+    ctx.build_basis(n, n, 10.0, 10.0, 8, 16, channels=[(0, 0), (0, 0)], L=0, potential=FIT)
+    with pytest.raises(P.WpcdError):
+        ctx.load_p(f)
