@@ -1335,9 +1335,27 @@ static void launch_compacted(wpcd_ctx *c, const ElemTables &T, const NodeTab &N,
 // Element values of the structure (row_ptr, col) into val64 or val32.
 // measure: the launch shape of the s-wave kernel may be timed on first use
 // (otherwise a cached choice or the heuristic one is taken).
+// Nucleon channel blocks from the s-wave values: out[e][p] = g_p v[e]
+// (p = a n_ch + b; the g_p are exact binary fractions).
+struct NucG {
+    double g[kMaxCh * kMaxCh];
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k_spread_g(const T *__restrict__ v, int64_t nnz, int NP,
+                                                  NucG G, T *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nnz * NP) return;
+    const int64_t e = i / NP;
+    out[i] = (T)(G.g[i - e * NP] * (double)v[e]);
+}
+
+static void swave_values(wpcd_ctx *c, const ElemTables &T, bool fp64, const P0Dst &D,
+                         bool measure);
+
 void values_into(wpcd_ctx *c, bool fp64, const int64_t *row_ptr, const int32_t *col,
                  const int32_t *hint, const uint8_t *rstart, int64_t nnz, double *val64,
-                 float *val32, bool measure) {
+                 float *val32, bool measure, bool nuc_spread) {
     ElemTables T{c->d_P2.ptr, c->d_rsd_p.ptr, c->d_rsd_q.ptr, c->d_qnode.ptr, c->d_qwt.ptr,
                  c->d_ux.ptr,  c->d_wx.ptr,    c->d_uxf.ptr,   c->d_wxf.ptr,   c->np,
                  c->ngq,       c->ngx,
@@ -1346,6 +1364,27 @@ void values_into(wpcd_ctx *c, bool fp64, const int64_t *row_ptr, const int32_t *
     const int NP = c->nch * c->nch;
     const P0Dst D{row_ptr, col, nnz, fp64 ? val64 : nullptr, fp64 ? nullptr : val32};
     if (nnz == 0) return;
+    if (c->nuc_two_S && nuc_spread) {
+        // nucleon pair s-waves: every channel block is the s-wave element
+        // times g_ab, so the s-wave kernel computes it once per cell pair
+        // into a scratch array and a spreading pass writes the blocks
+        NucG G{};
+        for (int p = 0; p < NP; ++p) G.g[p] = c->nuc_g[p];
+        const unsigned blocks = (unsigned)((nnz * NP + 255) / 256);
+        if (fp64) {
+            c->d_nuc64.reserve(nnz);
+            swave_values(c, T, true, P0Dst{row_ptr, col, nnz, c->d_nuc64.ptr, nullptr}, measure);
+            hipLaunchKernelGGL(k_spread_g<double>, dim3(blocks), dim3(256), 0, c->stream,
+                               c->d_nuc64.ptr, nnz, NP, G, val64);
+        } else {
+            c->d_nuc32.reserve(nnz);
+            swave_values(c, T, false, P0Dst{row_ptr, col, nnz, nullptr, c->d_nuc32.ptr}, measure);
+            hipLaunchKernelGGL(k_spread_g<float>, dim3(blocks), dim3(256), 0, c->stream,
+                               c->d_nuc32.ptr, nnz, NP, G, val32);
+        }
+        WPCD_HIP(hipGetLastError());
+        return;
+    }
     if (!c->swave) {
         NodeTab N{};
         for (int k = 0; k < c->ngx; ++k) {
@@ -1400,6 +1439,15 @@ void values_into(wpcd_ctx *c, bool fp64, const int64_t *row_ptr, const int32_t *
         WPCD_HIP(hipGetLastError());
         return;
     }
+    swave_values(c, T, fp64, D, measure);
+}
+
+// The s-wave element values of every cell pair into D (one value each).
+static void swave_values(wpcd_ctx *c, const ElemTables &T, bool fp64, const P0Dst &D,
+                         bool measure) {
+    const int64_t nnz = D.nnz;
+    const int64_t *row_ptr = D.row_ptr;
+    const int32_t *col = D.col;
     if (c->ngq == 8) {
         NodeTab N{};
         for (int k = 0; k < c->ngx; ++k) {
@@ -1448,7 +1496,7 @@ void build_values(wpcd_ctx *c, bool fp64) {
     if (fp64) c->d_val64.reserve(nv);
     else c->d_val32.reserve(nv);
     values_into(c, fp64, c->d_rowptr.ptr, c->d_col.ptr, c->d_hint.ptr, c->d_rstart.ptr, c->nnz,
-                c->d_val64.ptr, c->d_val32.ptr, true);
+                c->d_val64.ptr, c->d_val32.ptr, true, true);
 }
 
 }  // namespace wpcd

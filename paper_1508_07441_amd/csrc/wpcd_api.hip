@@ -1293,7 +1293,7 @@ wpcd_status wpcd_build_p_noalloc(wpcd_ctx *c, wpcd_precision prec, int64_t *row_
         structure_fill(c, cnt, tsum, row_ptr, col, hint, rstart, nnz);
         const bool fp64 = prec == WPCD_FP64;
         values_into(c, fp64, row_ptr, col, hint, rstart, nnz, fp64 ? (double *)val : nullptr,
-                    fp64 ? nullptr : (float *)val, false);
+                    fp64 ? nullptr : (float *)val, false, false);
         WPCD_HIP(hipStreamSynchronize(c->stream));
     });
 }
@@ -1845,6 +1845,8 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->d_hint.release();
     c->d_rstart.release();
     c->d_perm.release();
+    c->d_nuc64.release();
+    c->d_nuc32.release();
     c->d_tsum.release();
     c->d_val64.release();
     c->d_val32.release();

@@ -214,6 +214,8 @@ struct wpcd_ctx {
     int nuc_two_S = 0;
     int ch_s[wpcd::kMaxCh] = {}, ch_t[wpcd::kMaxCh] = {};
     std::vector<double> nuc_g;
+    wpcd::DBuf<double> d_nuc64;          // s-wave values before the channel spread
+    wpcd::DBuf<float> d_nuc32;
     int ch_wave[wpcd::kMaxCh] = {};     // channel -> index into waves
     std::vector<double> p, q;           // host edges
     std::vector<double> gq, wq, gx, wx; // host Gauss tables on [-1, 1]
@@ -334,9 +336,12 @@ int64_t structure_rows(wpcd_ctx *c, int32_t *cnt, int64_t *row_ptr, int64_t *tsu
 void structure_count_copy(wpcd_ctx *c);
 void structure_fill(wpcd_ctx *c, const int32_t *cnt, const int64_t *tsum, int64_t *row_ptr,
                     int32_t *col, int32_t *hint, uint8_t *rstart, int64_t cap);
+// nuc_spread: nucleon channels from one s-wave value per cell pair in a
+// scratch array of the context (false: the multichannel kernels, no
+// allocation)
 void values_into(wpcd_ctx *c, bool fp64, const int64_t *row_ptr, const int32_t *col,
                  const int32_t *hint, const uint8_t *rstart, int64_t nnz, double *val64,
-                 float *val32, bool measure);
+                 float *val32, bool measure, bool nuc_spread);
 
 // Pick candidate 0..n_cand-1 for (name, key): forced, cached, heuristic
 // (heur) or measured (measure(i) returns microseconds), by c->tune.mode.
