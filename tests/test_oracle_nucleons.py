@@ -128,3 +128,29 @@ def test_equal_pair_forces_amplitudes_from_boson_solves(E):
         u = W.solve_lu(nuc, E)
         assert W.entrance(nuc, E)[3] == idx
         assert abs(u[idx] - expect) <= 1e-10 * abs(expect)
+
+
+def test_breakup_elements_exact_unitarity_two_pair_waves():
+    """Exact unitarity of the open-channel S-matrix for a random real
+    symmetric operator in place of A (see test_oracle_solve): with the
+    doublet's two channels and their different pair waves, the open
+    pseudostates of both channels enter the flux sum, each at its own
+    pair energies."""
+    p = W.cheb_edges(9, 8.0)
+    pot = _pot(p)
+    sysm = N.build_system_nucleons(p, p.copy(), 1, NUC_DOUBLET, 4, 8, pot,
+                                   [[1.0, 1.0], list(NUC_SINGLET_MULT)])
+    rng = np.random.default_rng(7)
+    M = sysm.M
+    R = rng.normal(size=(M, M))
+    A = 0.2 * (R + R.T) / math.sqrt(M)
+    for E in (0.4, 1.5):
+        G = W.resolvent(sysm, E).ravel()
+        idx = W.entrance(sysm, E)[3]
+        e0 = np.zeros(M)
+        e0[idx] = 1.0
+        u = np.linalg.solve(np.eye(M) - A * G[None, :], A @ e0)
+        a = W.amplitudes(sysm, E, u)
+        total = abs(a.S) ** 2 + sum(abs(s) ** 2 for (_, _, _, s) in a.breakup)
+        assert {c for (c, _, _, _) in a.breakup} == {0, 1}
+        assert abs(total - 1.0) < 1e-12, (E, total)
