@@ -424,11 +424,15 @@ def c4_measure(P, n_var, n_e):
         ctxs.append(c)
     mult, _ = learn_draws(SEED + 9, n_var, 2, 0, 0.0, 1.0)
     E = [-0.05 + 2.05 * k / (n_e - 1) for k in range(n_e)]
-    # first pass: tuning and graph capture for every system, alone and in
-    # lockstep (the lockstep groups are graphs of their own)
-    for c in ctxs:
-        c.solve(E[:min(32, n_e)], P.WPCD_MIXED)
-    P.wpcd_solve_multi([c.h for c in ctxs], [E] * len(ctxs), P.WPCD_MIXED)
+    # first pass (untimed): launch-shape tuning and graph capture for every
+    # batch shape the timed runs meet, alone and in lockstep (a variant can
+    # push an energy below its pair threshold, which changes the batch width)
+    for v in range(n_var):
+        for c in ctxs:
+            c.set_multipliers(mult[v])
+        P.wpcd_solve_multi([c.h for c in ctxs], [E] * len(ctxs), P.WPCD_MIXED)
+        for c in ctxs:
+            c.solve(E, P.WPCD_MIXED)
     t_multi = t_seq = 0.0
     ok = 0
     for v in range(n_var):
