@@ -1050,162 +1050,162 @@ wpcd_status wpcd_create(int device, void *hip_stream, wpcd_ctx **out) {
 // b are not read), else spinless bosons with b's channels.
 static void build_basis_impl(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_potential_desc *pot,
                              const wpcd_nucleon_desc *nuc) {
-        WPCD_REQUIRE(b, WPCD_E_INVALID, "basis descriptor is NULL");
-        WPCD_REQUIRE(pot, WPCD_E_INVALID, "potential descriptor is NULL");
-        WPCD_REQUIRE(b->n_p >= 2 && b->n_p <= 1024 && b->n_q >= 2 && b->n_q <= 1024,
-                     WPCD_E_INVALID, "n_p, n_q must be in 2..1024");
-        WPCD_REQUIRE(b->n_gauss_q >= 1 && b->n_gauss_q <= kMaxGq, WPCD_E_INVALID,
-                     "n_gauss_q must be 1..16");
-        WPCD_REQUIRE(b->n_gauss_x >= 1 && b->n_gauss_x <= kMaxGx, WPCD_E_INVALID,
-                     "n_gauss_x must be 1..64");
-        // channels: (l, lam) per channel, and for nucleons (s, t) and the
-        // pair wave of each channel (its own, with its strength multipliers)
-        int nch, L;
-        std::vector<int> ch_l, ch_lam, ch_s, ch_t;
-        std::vector<int> waves;   // l of each pair wave
-        std::vector<int> ch_wave;
-        if (nuc) {
-            WPCD_REQUIRE(nuc->two_S == 1 || nuc->two_S == 3, WPCD_E_INVALID, "two_S must be 1 or 3");
-            WPCD_REQUIRE(nuc->n_ch >= 1 && nuc->n_ch <= 2, WPCD_E_INVALID,
-                         "nucleon pair s-waves have 1 or 2 channels");
-            WPCD_REQUIRE(nuc->s && nuc->t, WPCD_E_INVALID, "channel arrays NULL");
-            nch = nuc->n_ch;
-            L = 0;
-            for (int a = 0; a < nch; ++a) {
-                const int sa = nuc->s[a], ta = nuc->t[a];
-                WPCD_REQUIRE((sa == 1 && ta == 0) || (sa == 0 && ta == 1), WPCD_E_INVALID,
-                             "pair s-wave channels are (s, t) = (1, 0) or (0, 1)");
-                WPCD_REQUIRE(nuc->two_S == 1 || sa == 1, WPCD_E_INVALID,
-                             "three-body spin 3/2 needs pair spin 1");
-                for (int b2 = 0; b2 < a; ++b2)
-                    WPCD_REQUIRE(nuc->s[b2] != sa, WPCD_E_INVALID, "repeated channel");
-                ch_l.push_back(0);
-                ch_lam.push_back(0);
-                ch_s.push_back(sa);
-                ch_t.push_back(ta);
-                waves.push_back(0);
-                ch_wave.push_back(a);
-            }
-            WPCD_REQUIRE(ch_s[0] == 1, WPCD_E_INVALID,
-                         "channel 0 must be the deuteron channel (s, t) = (1, 0)");
-            WPCD_REQUIRE(!nuc->mult || pot->n_terms >= 1, WPCD_E_INVALID, "bad n_terms");
-            if (nuc->mult)
-                for (int k = 0; k < nch * pot->n_terms; ++k)
-                    WPCD_REQUIRE(std::isfinite(nuc->mult[k]) && nuc->mult[k] >= 0.0, WPCD_E_INVALID,
-                                 "strength multipliers must be finite and >= 0");
-        } else {
-            WPCD_REQUIRE(b->n_ch >= 1 && b->n_ch <= kMaxCh, WPCD_E_INVALID, "n_ch must be 1..8");
-            WPCD_REQUIRE(b->l && b->lam, WPCD_E_INVALID, "channel arrays NULL");
-            WPCD_REQUIRE(b->L >= 0 && b->L <= 8, WPCD_E_INVALID, "L must be 0..8");
-            nch = b->n_ch;
-            L = b->L;
-            for (int a = 0; a < nch; ++a) {
-                const int l = b->l[a], lam = b->lam[a];
-                WPCD_REQUIRE(l >= 0 && l <= 4 && lam >= 0 && lam <= kMaxLam && l % 2 == 0,
-                             WPCD_E_INVALID, "channels need even l <= 4 and lam <= 4");
-                WPCD_REQUIRE(std::abs(l - lam) <= L && L <= l + lam && (l + lam - L) % 2 == 0,
-                             WPCD_E_INVALID, "channel (l, lam) cannot couple to L with parity (-1)^L");
-                if (std::find(waves.begin(), waves.end(), l) == waves.end()) waves.push_back(l);
-                ch_l.push_back(l);
-                ch_lam.push_back(lam);
-                ch_s.push_back(0);
-                ch_t.push_back(0);
-                ch_wave.push_back((int)(std::find(waves.begin(), waves.end(), l) - waves.begin()));
-            }
+    WPCD_REQUIRE(b, WPCD_E_INVALID, "basis descriptor is NULL");
+    WPCD_REQUIRE(pot, WPCD_E_INVALID, "potential descriptor is NULL");
+    WPCD_REQUIRE(b->n_p >= 2 && b->n_p <= 1024 && b->n_q >= 2 && b->n_q <= 1024,
+                 WPCD_E_INVALID, "n_p, n_q must be in 2..1024");
+    WPCD_REQUIRE(b->n_gauss_q >= 1 && b->n_gauss_q <= kMaxGq, WPCD_E_INVALID,
+                 "n_gauss_q must be 1..16");
+    WPCD_REQUIRE(b->n_gauss_x >= 1 && b->n_gauss_x <= kMaxGx, WPCD_E_INVALID,
+                 "n_gauss_x must be 1..64");
+    // channels: (l, lam) per channel, and for nucleons (s, t) and the
+    // pair wave of each channel (its own, with its strength multipliers)
+    int nch, L;
+    std::vector<int> ch_l, ch_lam, ch_s, ch_t;
+    std::vector<int> waves;   // l of each pair wave
+    std::vector<int> ch_wave;
+    if (nuc) {
+        WPCD_REQUIRE(nuc->two_S == 1 || nuc->two_S == 3, WPCD_E_INVALID, "two_S must be 1 or 3");
+        WPCD_REQUIRE(nuc->n_ch >= 1 && nuc->n_ch <= 2, WPCD_E_INVALID,
+                     "nucleon pair s-waves have 1 or 2 channels");
+        WPCD_REQUIRE(nuc->s && nuc->t, WPCD_E_INVALID, "channel arrays NULL");
+        nch = nuc->n_ch;
+        L = 0;
+        for (int a = 0; a < nch; ++a) {
+            const int sa = nuc->s[a], ta = nuc->t[a];
+            WPCD_REQUIRE((sa == 1 && ta == 0) || (sa == 0 && ta == 1), WPCD_E_INVALID,
+                         "pair s-wave channels are (s, t) = (1, 0) or (0, 1)");
+            WPCD_REQUIRE(nuc->two_S == 1 || sa == 1, WPCD_E_INVALID,
+                         "three-body spin 3/2 needs pair spin 1");
+            for (int b2 = 0; b2 < a; ++b2)
+                WPCD_REQUIRE(nuc->s[b2] != sa, WPCD_E_INVALID, "repeated channel");
+            ch_l.push_back(0);
+            ch_lam.push_back(0);
+            ch_s.push_back(sa);
+            ch_t.push_back(ta);
+            waves.push_back(0);
+            ch_wave.push_back(a);
         }
-        WPCD_REQUIRE((int)waves.size() <= kMaxWaves, WPCD_E_INVALID, "too many pair waves");
-        const int two_S = nuc ? nuc->two_S : 0;
-        std::vector<double> p, q;
-        if (b->edge_kind == 0) {
-            WPCD_REQUIRE(b->p_max > 0 && b->q_max > 0 && std::isfinite(b->p_max) &&
-                             std::isfinite(b->q_max),
-                         WPCD_E_INVALID, "p_max, q_max must be positive");
-            p = cheb_edges(b->n_p, b->p_max);
-            q = cheb_edges(b->n_q, b->q_max);
-        } else if (b->edge_kind == 1) {
-            WPCD_REQUIRE(b->p_edges && b->q_edges, WPCD_E_INVALID, "explicit edges NULL");
-            p.assign(b->p_edges, b->p_edges + b->n_p + 1);
-            q.assign(b->q_edges, b->q_edges + b->n_q + 1);
-            WPCD_REQUIRE(p[0] >= 0 && q[0] >= 0, WPCD_E_INVALID, "edges must start >= 0");
-            for (int k = 0; k < b->n_p; ++k)
-                WPCD_REQUIRE(p[k + 1] > p[k] && std::isfinite(p[k + 1]), WPCD_E_INVALID,
-                             "p edges must increase");
-            for (int k = 0; k < b->n_q; ++k)
-                WPCD_REQUIRE(q[k + 1] > q[k] && std::isfinite(q[k + 1]), WPCD_E_INVALID,
-                             "q edges must increase");
-        } else {
-            throw Error{WPCD_E_INVALID, "edge_kind must be 0 or 1"};
+        WPCD_REQUIRE(ch_s[0] == 1, WPCD_E_INVALID,
+                     "channel 0 must be the deuteron channel (s, t) = (1, 0)");
+        WPCD_REQUIRE(!nuc->mult || pot->n_terms >= 1, WPCD_E_INVALID, "bad n_terms");
+        if (nuc->mult)
+            for (int k = 0; k < nch * pot->n_terms; ++k)
+                WPCD_REQUIRE(std::isfinite(nuc->mult[k]) && nuc->mult[k] >= 0.0, WPCD_E_INVALID,
+                             "strength multipliers must be finite and >= 0");
+    } else {
+        WPCD_REQUIRE(b->n_ch >= 1 && b->n_ch <= kMaxCh, WPCD_E_INVALID, "n_ch must be 1..8");
+        WPCD_REQUIRE(b->l && b->lam, WPCD_E_INVALID, "channel arrays NULL");
+        WPCD_REQUIRE(b->L >= 0 && b->L <= 8, WPCD_E_INVALID, "L must be 0..8");
+        nch = b->n_ch;
+        L = b->L;
+        for (int a = 0; a < nch; ++a) {
+            const int l = b->l[a], lam = b->lam[a];
+            WPCD_REQUIRE(l >= 0 && l <= 4 && lam >= 0 && lam <= kMaxLam && l % 2 == 0,
+                         WPCD_E_INVALID, "channels need even l <= 4 and lam <= 4");
+            WPCD_REQUIRE(std::abs(l - lam) <= L && L <= l + lam && (l + lam - L) % 2 == 0,
+                         WPCD_E_INVALID, "channel (l, lam) cannot couple to L with parity (-1)^L");
+            if (std::find(waves.begin(), waves.end(), l) == waves.end()) waves.push_back(l);
+            ch_l.push_back(l);
+            ch_lam.push_back(lam);
+            ch_s.push_back(0);
+            ch_t.push_back(0);
+            ch_wave.push_back((int)(std::find(waves.begin(), waves.end(), l) - waves.begin()));
         }
-        bool same_grid = c->has_basis && c->np == b->n_p && c->nq == b->n_q && c->p == p &&
-                         c->q == q && c->ngq == b->n_gauss_q && c->ngx == b->n_gauss_x &&
-                         c->L == L && c->nch == nch && c->nuc_two_S == two_S;
-        for (int a = 0; same_grid && a < nch; ++a)
-            same_grid = c->ch_l[a] == ch_l[a] && c->ch_lam[a] == ch_lam[a] &&
-                        c->ch_s[a] == ch_s[a] && c->ch_t[a] == ch_t[a];
-        c->has_basis = false;
-        c->learned.release();
-        c->has_pot = false;
-        if (!same_grid) {
-            c->has_p = false;
-            c->has_val64 = false;
-        }
-        c->np = b->n_p;
-        c->nq = b->n_q;
-        c->ngq = b->n_gauss_q;
-        c->ngx = b->n_gauss_x;
-        c->L = L;
-        c->nch = nch;
-        c->nuc_two_S = two_S;
-        c->p = p;
-        c->q = q;
-        gauss_legendre_gw(c->ngq, c->gq, c->wq);
-        gauss_legendre_gw(c->ngx, c->gx, c->wx);
-        c->n_waves = (int)waves.size();
-        for (int w = 0; w < c->n_waves; ++w) {
-            c->waves[w].l = waves[w];
-            c->waves[w].mult.clear();
-            if (nuc && nuc->mult)
-                c->waves[w].mult.assign(nuc->mult + (size_t)w * pot->n_terms,
-                                        nuc->mult + (size_t)(w + 1) * pot->n_terms);
-        }
-        for (int a = 0; a < c->nch; ++a) {
-            c->ch_l[a] = ch_l[a];
-            c->ch_lam[a] = ch_lam[a];
-            c->ch_s[a] = ch_s[a];
-            c->ch_t[a] = ch_t[a];
-            c->ch_wave[a] = ch_wave[a];
-        }
-        upload_tables(c);
-        // s-wave element kernel only for the single boson channel; nucleon
-        // channels take the multichannel kernels with degree-0 couplings g_ab
-        c->swave = !nuc && (c->nch == 1 && c->L == 0 && c->ch_l[0] == 0 && c->ch_lam[0] == 0);
-        // angular coupling: the fitted polynomial for l, lam <= 2 (validated
-        // and fast), the direct bipolar-harmonic terms beyond
-        c->mc_direct = false;
-        for (int a = 0; a < c->nch; ++a)
-            if (c->ch_l[a] > 2 || c->ch_lam[a] > 2) c->mc_direct = true;
-        c->mc_pairs.clear();
-        c->mc_deg = 0;
-        c->nuc_g.clear();
-        if (nuc) {
-            std::vector<double> coef;
-            nucleon_tables(two_S, c->nch, c->ch_s, c->ch_t, c->mc_pairs, coef, c->nuc_g);
-            upload(c->d_mcoef, coef, c->stream);
-        } else if (!c->mc_direct) {
-            std::vector<double> coef;
-            coupling_tables(c->L, c->nch, c->ch_l, c->ch_lam, c->mc_pairs, coef);
-            for (auto &pp : c->mc_pairs) c->mc_deg = std::max(c->mc_deg, pp.d);
-            upload(c->d_mcoef, coef, c->stream);
-        } else {
-            std::vector<McTerm> terms;
-            std::vector<int> first;
-            coupling_terms(c->L, c->nch, c->ch_l, c->ch_lam, terms, first);
-            upload(c->d_mterms, terms, c->stream);
-            upload(c->d_mterm_first, first, c->stream);
-        }
-        WPCD_HIP(hipStreamSynchronize(c->stream));
-        c->has_basis = true;
-        build_pair_waves(c, pot);
+    }
+    WPCD_REQUIRE((int)waves.size() <= kMaxWaves, WPCD_E_INVALID, "too many pair waves");
+    const int two_S = nuc ? nuc->two_S : 0;
+    std::vector<double> p, q;
+    if (b->edge_kind == 0) {
+        WPCD_REQUIRE(b->p_max > 0 && b->q_max > 0 && std::isfinite(b->p_max) &&
+                         std::isfinite(b->q_max),
+                     WPCD_E_INVALID, "p_max, q_max must be positive");
+        p = cheb_edges(b->n_p, b->p_max);
+        q = cheb_edges(b->n_q, b->q_max);
+    } else if (b->edge_kind == 1) {
+        WPCD_REQUIRE(b->p_edges && b->q_edges, WPCD_E_INVALID, "explicit edges NULL");
+        p.assign(b->p_edges, b->p_edges + b->n_p + 1);
+        q.assign(b->q_edges, b->q_edges + b->n_q + 1);
+        WPCD_REQUIRE(p[0] >= 0 && q[0] >= 0, WPCD_E_INVALID, "edges must start >= 0");
+        for (int k = 0; k < b->n_p; ++k)
+            WPCD_REQUIRE(p[k + 1] > p[k] && std::isfinite(p[k + 1]), WPCD_E_INVALID,
+                         "p edges must increase");
+        for (int k = 0; k < b->n_q; ++k)
+            WPCD_REQUIRE(q[k + 1] > q[k] && std::isfinite(q[k + 1]), WPCD_E_INVALID,
+                         "q edges must increase");
+    } else {
+        throw Error{WPCD_E_INVALID, "edge_kind must be 0 or 1"};
+    }
+    bool same_grid = c->has_basis && c->np == b->n_p && c->nq == b->n_q && c->p == p &&
+                     c->q == q && c->ngq == b->n_gauss_q && c->ngx == b->n_gauss_x &&
+                     c->L == L && c->nch == nch && c->nuc_two_S == two_S;
+    for (int a = 0; same_grid && a < nch; ++a)
+        same_grid = c->ch_l[a] == ch_l[a] && c->ch_lam[a] == ch_lam[a] &&
+                    c->ch_s[a] == ch_s[a] && c->ch_t[a] == ch_t[a];
+    c->has_basis = false;
+    c->learned.release();
+    c->has_pot = false;
+    if (!same_grid) {
+        c->has_p = false;
+        c->has_val64 = false;
+    }
+    c->np = b->n_p;
+    c->nq = b->n_q;
+    c->ngq = b->n_gauss_q;
+    c->ngx = b->n_gauss_x;
+    c->L = L;
+    c->nch = nch;
+    c->nuc_two_S = two_S;
+    c->p = p;
+    c->q = q;
+    gauss_legendre_gw(c->ngq, c->gq, c->wq);
+    gauss_legendre_gw(c->ngx, c->gx, c->wx);
+    c->n_waves = (int)waves.size();
+    for (int w = 0; w < c->n_waves; ++w) {
+        c->waves[w].l = waves[w];
+        c->waves[w].mult.clear();
+        if (nuc && nuc->mult)
+            c->waves[w].mult.assign(nuc->mult + (size_t)w * pot->n_terms,
+                                    nuc->mult + (size_t)(w + 1) * pot->n_terms);
+    }
+    for (int a = 0; a < c->nch; ++a) {
+        c->ch_l[a] = ch_l[a];
+        c->ch_lam[a] = ch_lam[a];
+        c->ch_s[a] = ch_s[a];
+        c->ch_t[a] = ch_t[a];
+        c->ch_wave[a] = ch_wave[a];
+    }
+    upload_tables(c);
+    // s-wave element kernel only for the single boson channel; nucleon
+    // channels take the multichannel kernels with degree-0 couplings g_ab
+    c->swave = !nuc && (c->nch == 1 && c->L == 0 && c->ch_l[0] == 0 && c->ch_lam[0] == 0);
+    // angular coupling: the fitted polynomial for l, lam <= 2 (validated
+    // and fast), the direct bipolar-harmonic terms beyond
+    c->mc_direct = false;
+    for (int a = 0; a < c->nch; ++a)
+        if (c->ch_l[a] > 2 || c->ch_lam[a] > 2) c->mc_direct = true;
+    c->mc_pairs.clear();
+    c->mc_deg = 0;
+    c->nuc_g.clear();
+    if (nuc) {
+        std::vector<double> coef;
+        nucleon_tables(two_S, c->nch, c->ch_s, c->ch_t, c->mc_pairs, coef, c->nuc_g);
+        upload(c->d_mcoef, coef, c->stream);
+    } else if (!c->mc_direct) {
+        std::vector<double> coef;
+        coupling_tables(c->L, c->nch, c->ch_l, c->ch_lam, c->mc_pairs, coef);
+        for (auto &pp : c->mc_pairs) c->mc_deg = std::max(c->mc_deg, pp.d);
+        upload(c->d_mcoef, coef, c->stream);
+    } else {
+        std::vector<McTerm> terms;
+        std::vector<int> first;
+        coupling_terms(c->L, c->nch, c->ch_l, c->ch_lam, terms, first);
+        upload(c->d_mterms, terms, c->stream);
+        upload(c->d_mterm_first, first, c->stream);
+    }
+    WPCD_HIP(hipStreamSynchronize(c->stream));
+    c->has_basis = true;
+    build_pair_waves(c, pot);
 }
 
 wpcd_status wpcd_build_basis(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_potential_desc *pot) {
