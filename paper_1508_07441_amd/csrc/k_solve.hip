@@ -309,13 +309,16 @@ __device__ __forceinline__ short bf16_bits(float f) {
     return (short)(u >> 16);
 }
 
-template <bool USE_G, bool SUB, class TI, class TO, class MT>
+// TM = 64: each wavefront owns 32 x 32 outputs (2 x 2 MFMA tiles); TM = 32:
+// 16 x 32 (1 x 2), twice the workgroups for the small products.
+template <bool USE_G, bool SUB, class TI, class TO, class MT, int TM = 64>
 __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, int nq, int W,
                                                           const TI *__restrict__ in,
                                                           const double *__restrict__ G,
                                                           const double *__restrict__ add,
                                                           TO *__restrict__ out) {
-    constexpr int TM = 64, TN = 64, KS = 16;
+    static_assert(TM == 64 || TM == 32, "64- or 32-row tiles");
+    constexpr int TN = 64, KS = 16, UM = TM / 32;   // 16-row MFMA tiles per wavefront
     using V = typename MfmaAcc<MT>::V;
     using L = typename MfmaAcc<MT>::L;
     __shared__ L sA[KS][TM + 1];
@@ -328,9 +331,9 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
     const int64_t ncol = (int64_t)nq * W;
     const double *Mt = mats.p[a];
     const int64_t chbase = (int64_t)a * nq * n;
-    V acc[2][2];
+    V acc[UM][2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < UM; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
 #pragma unroll
@@ -400,29 +403,29 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
         if (k0 + KS < n) fetch(k0 + KS);
         if constexpr (std::is_same<MT, Bf16>::value) {
             // one 16 x 16 x 16 step covers the whole k slab
-            v4s av[2], bv[2];
+            v4s av[UM], bv[2];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
 #pragma unroll
-                for (int u = 0; u < 2; ++u) av[u][q] = bf16_bits(sA[4 * lk + q][wr * 32 + u * 16 + li]);
+                for (int u = 0; u < UM; ++u) av[u][q] = bf16_bits(sA[4 * lk + q][wr * (TM / 2) + u * 16 + li]);
 #pragma unroll
                 for (int v = 0; v < 2; ++v) bv[v][q] = bf16_bits(sB[4 * lk + q][wc * 32 + v * 16 + li]);
             }
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < UM; ++u)
 #pragma unroll
                 for (int v = 0; v < 2; ++v)
                     acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[u], bv[v], acc[u][v], 0, 0, 0);
         } else {
 #pragma unroll
             for (int kb = 0; kb < KS; kb += 4) {
-                MT av[2], bv[2];
+                MT av[UM], bv[2];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) av[u] = sA[kb + lk][wr * 32 + u * 16 + li];
+                for (int u = 0; u < UM; ++u) av[u] = sA[kb + lk][wr * (TM / 2) + u * 16 + li];
 #pragma unroll
                 for (int v = 0; v < 2; ++v) bv[v] = sB[kb + lk][wc * 32 + v * 16 + li];
 #pragma unroll
-                for (int u = 0; u < 2; ++u)
+                for (int u = 0; u < UM; ++u)
 #pragma unroll
                     for (int v = 0; v < 2; ++v) acc[u][v] = MfmaAcc<MT>::step(av[u], bv[v], acc[u][v]);
             }
@@ -430,7 +433,7 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < UM; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
             const int64_t q = q0 + wc * 32 + v * 16 + li;
@@ -439,7 +442,7 @@ __global__ __launch_bounds__(256) void k_block_apply_mfma(ChPtrs mats, int n, in
             const int64_t ob = (chbase + (int64_t)j * n) * W + (q - (int64_t)j * W);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = row0 + wr * 32 + u * 16 + MfmaAcc<MT>::row(lk, r);
+                const int row = row0 + wr * (TM / 2) + u * 16 + MfmaAcc<MT>::row(lk, r);
                 if (row >= n) continue;
                 const int64_t gi = ob + (int64_t)row * W;
                 const double d = (double)acc[u][v][r];
@@ -1301,9 +1304,9 @@ constexpr int kMaxSplit = 64;
 
 // Candidate tile shapes (TM x TN) of the block products; the last one is
 // the FP64 matrix-core kernel (64 x 64 tiles).
-constexpr int kApplyCfg = 5;
-constexpr int kApplyTM[kApplyCfg] = {64, 32, 32, 16, 64};
-constexpr int kApplyTN[kApplyCfg] = {64, 64, 32, 64, 64};
+constexpr int kApplyCfg = 6;
+constexpr int kApplyTM[kApplyCfg] = {64, 32, 32, 16, 64, 32};
+constexpr int kApplyTN[kApplyCfg] = {64, 64, 32, 64, 64, 64};
 constexpr int kNrCand[3] = {1, 2, 4};
 
 int apply_blocks(const wpcd_ctx *c, int W, int cfg) {
@@ -1318,22 +1321,29 @@ void launch_block_apply_t(Batch &b, ChPtrs mats, const TI *in, const double *add
                        mats, c->np, c->nq, b.W, in, b.G, add, out);
 }
 
-template <bool USE_G, bool SUB, class TI, class TO, class MT>
+template <bool USE_G, bool SUB, class TI, class TO, class MT, int TM = 64>
 void launch_block_apply_mfma(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
     wpcd_ctx *c = b.c;
-    dim3 grid(cdiv((int64_t)c->nq * b.W, 64), cdiv(c->np, 64), c->nch);
-    hipLaunchKernelGGL((k_block_apply_mfma<USE_G, SUB, TI, TO, MT>), grid, dim3(256), 0, c->stream,
-                       mats, c->np, c->nq, b.W, in, b.G, add, out);
+    dim3 grid(cdiv((int64_t)c->nq * b.W, 64), cdiv(c->np, TM), c->nch);
+    hipLaunchKernelGGL((k_block_apply_mfma<USE_G, SUB, TI, TO, MT, TM>), grid, dim3(256), 0,
+                       c->stream, mats, c->np, c->nq, b.W, in, b.G, add, out);
 }
 
-// Tile shapes 0-3 on the vector ALUs, 4 on the FP64 matrix cores (all FP64
+// Tile shapes 0-3 on the vector ALUs, 4 and 5 (64- and 32-row tiles) on the FP64 matrix cores (all FP64
 // arithmetic); the inner iterations of the refine tiers (FP32 panels) use the
 // FP32 matrix cores, or the BF16 ones, with FP32 accumulation.
 template <bool USE_G, bool SUB, class TI, class TO>
 void launch_block_apply(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
     if (std::is_same<TI, float>::value || std::is_same<TO, float>::value) {
-        if (b.bf16) launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16>(b, mats, in, add, out);
-        else launch_block_apply_mfma<USE_G, SUB, TI, TO, float>(b, mats, in, add, out);
+        // 32-row tiles when 64-row ones would leave the device under-filled
+        const bool small = apply_blocks(b.c, b.W, 4) < 512;
+        if (b.bf16) {
+            if (small) launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16, 32>(b, mats, in, add, out);
+            else launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16>(b, mats, in, add, out);
+        } else {
+            if (small) launch_block_apply_mfma<USE_G, SUB, TI, TO, float, 32>(b, mats, in, add, out);
+            else launch_block_apply_mfma<USE_G, SUB, TI, TO, float>(b, mats, in, add, out);
+        }
         return;
     }
     switch (b.apply_cfg) {
@@ -1341,7 +1351,8 @@ void launch_block_apply(Batch &b, ChPtrs mats, const TI *in, const double *add, 
         case 1: launch_block_apply_t<USE_G, SUB, 32, 64>(b, mats, in, add, out); break;
         case 2: launch_block_apply_t<USE_G, SUB, 32, 32>(b, mats, in, add, out); break;
         case 3: launch_block_apply_t<USE_G, SUB, 16, 64>(b, mats, in, add, out); break;
-        default: launch_block_apply_mfma<USE_G, SUB, TI, TO, double>(b, mats, in, add, out); break;
+        case 4: launch_block_apply_mfma<USE_G, SUB, TI, TO, double>(b, mats, in, add, out); break;
+        default: launch_block_apply_mfma<USE_G, SUB, TI, TO, double, 32>(b, mats, in, add, out); break;
     }
 }
 
