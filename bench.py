@@ -48,7 +48,7 @@ LEARN_VARIANTS, LEARN_ENERGIES = 16, 32
 # scaled by the counter's reading of a plain device copy of known size
 # (factors 2.0 and 1.0); valid only for the element-kernel source they were
 # taken on (sha256 prefix of csrc/k_p0.hip), reported as null otherwise.
-P0_ELEM_F32_TRAFFIC = {"bytes": 5.2080e+07, "k_p0_sha256": "6f0143c8d6d703fd"}
+P0_ELEM_F32_TRAFFIC = {"bytes": 5.2080e+07, "k_p0_sha256": "60a4f52ddfd1e805"}
 
 # MI355X published peaks used for the roofline fractions
 PEAK_FP32_VECTOR_TFLOPS = 157.3
