@@ -317,13 +317,16 @@ template <int EPL, bool ODD>
 __device__ __forceinline__ void jacobi_round(double (&A)[EPL], double (&B)[EPL], double &nA,
                                              double &nB, int &idA, int &idB, double *mail,
                                              double *mail_n, int *mail_id, int g, int u, int P,
-                                             double tol2, int &any) {
+                                             double tol2, int &any, int &big) {
     double ga = 0.0;
 #pragma unroll
     for (int r = 0; r < EPL; ++r) ga += A[r] * B[r];
     ga = gsum8(ga);
     const bool active = ODD ? g < P - 1 : g < P;
     if (active && ga * ga > tol2 * (nA * nB)) {
+        // an overlap above 1e-8 (relative) may leave more than rounding after
+        // its rotation and the rest of the sweep
+        if (ga * ga > 1e-16 * (nA * nB)) big = 1;
         // The angle only sets how much of the pair's overlap this rotation
         // removes, so it is formed in FP32 (|ze| < 1e17 here: the norms
         // differ by < 1e3 and |ga| > tol |A||B|) with hardware reciprocal
@@ -420,16 +423,21 @@ __global__ __launch_bounds__(768) void k_jacobi_wg(double *__restrict__ W, int n
         }
         nA = gsum8(nA);
         nB = gsum8(nB);
-        int any = 0;
+        int any = 0, big = 0;
         // 2P rounds: even and odd alternate
         for (int rd = 0; rd < P; ++rd) {
             jacobi_round<EPL, false>(A, B, nA, nB, idA, idB, mail, mail_n, mail_id, g, u, P, tol2,
-                                     any);
+                                     any, big);
             jacobi_round<EPL, true>(A, B, nA, nB, idA, idB, mail, mail_n, mail_id, g, u, P, tol2,
-                                    any);
+                                    any, big);
         }
         ++sweep;
-        if (!__syncthreads_or(any)) {
+        // Done when the sweep rotated nothing, or when every overlap it met
+        // was below 1e-8 of the column norms: the one-sided Jacobi then
+        // converges quadratically, so what its rotations leave (and what
+        // they induce in other pairs) is of the order of the squares, below
+        // 1e-16 < tol, and a further sweep would only confirm it.
+        if (!__syncthreads_or(any) || !__syncthreads_or(big)) {
             converged = 1;
             break;
         }
