@@ -142,3 +142,44 @@ def test_nucleon_p0_file_signature(ctx, P, tmp_path):
     ctx.build_basis(n, n, 10.0, 10.0, 8, 16, channels=[(0, 0), (0, 0)], L=0, potential=FIT)
     with pytest.raises(P.WpcdError):
         ctx.load_p(f)
+
+
+def test_nucleon_averaged_resolvent(ctx, P):
+    """The energy-averaged channel resolvent (Sec. II.C) with the two
+    nucleon channels' own pair waves: amplitudes against the oracle's."""
+    n = 24
+    _build(ctx, n, 16, 1)
+    sysm = _oracle(n, 16, 1)
+    ctx.build_p(P.WPCD_FP64)
+    energies = [-0.05, 0.4, 1.2]
+    say("[nucleons] solve FP64, averaged resolvent")
+    res = ctx.solve(energies, P.WPCD_FP64, resolvent=P.WPCD_RESOLVENT_AVERAGED)
+    for r, E in zip(res, energies):
+        u, _, _ = O.solve_gmres(sysm, E, averaged=True)
+        a = O.amplitudes(sysm, E, u, averaged=True)
+        assert r.status == P.WPCD_OK
+        U = complex(r.U_re, r.U_im)
+        assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
+
+
+def test_nucleon_and_boson_systems_in_lockstep(P):
+    """A nucleon doublet, a quartet and a boson system solved together in
+    lockstep give the bits of their one-by-one solves."""
+    cs = [P.Context(0) for _ in range(3)]
+    try:
+        _build(cs[0], 20, 16, 1)
+        _build(cs[1], 24, 16, 3)
+        cs[2].build_basis(22, 22, 10.0, 10.0, 8, 16, potential=FIT)
+        for c in cs:
+            c.build_p(P.WPCD_MIXED)
+        Es = [[-0.05, 0.3, 1.1], [-0.06, 0.5], [0.2, 0.9, 1.7, -0.03]]
+        alone = [c.solve(E, P.WPCD_MIXED) for c, E in zip(cs, Es)]
+        say("[nucleons] lockstep with a boson system")
+        together = P.wpcd_solve_multi([c.h for c in cs], Es, P.WPCD_MIXED)
+        for ra, rt in zip(alone, together):
+            for a, t in zip(ra, rt):
+                assert a.status == t.status == P.WPCD_OK
+                assert (a.U_re, a.U_im) == (t.U_re, t.U_im)
+    finally:
+        for c in cs:
+            c.close()
