@@ -76,6 +76,10 @@ def lib():
 
 
 def _p(a, t):
+    # the C routines index the buffer densely: a strided view would be read
+    # as the wrong values
+    if not a.flags.c_contiguous:
+        raise ValueError("arrays passed to the C oracle must be contiguous")
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
