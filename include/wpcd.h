@@ -311,6 +311,47 @@ wpcd_status wpcd_build_p_noalloc(wpcd_ctx *ctx, wpcd_precision prec, int64_t *ro
  * Errors: WPCD_E_STATE (no P0).                                          */
 wpcd_status wpcd_get_p(wpcd_ctx *ctx, int64_t *row_ptr, int32_t *col, double *val);
 
+/* Feshbach major/minor channel reduction (Sec. V.B): turn `red` into a
+ * reduced system of `full`.  Channels [0, n_major) of full are the major
+ * ones and keep full's lattice; the others are minor and are described on
+ * the coarse lattice of every r_p-th p edge and every r_q-th q edge (bins
+ * that are unions of r_p x r_q fine cells).  The reading: with unit-weight
+ * packets the packet of a union of bins is sum_i sqrt(d_i / D) |x_i>, so
+ * every P0 element involving a coarse cell is that combination of full's
+ * fine elements (exact for the element as an integral over the cells); the
+ * minor channels' pair Hamiltonians are diagonalised on the coarse p bins
+ * with full's potential and their channel resolvent uses the coarse
+ * spectator bins.  wpcd_solve on `red` then solves the coupled reduced
+ * system, whose major components are the solution of the effective-kernel
+ * equation of the major subspace,
+ *   (1 - K_MM - K_Mm (1 - K_mm)^-1 K_mM) u_M = b_M + K_Mm (1 - K_mm)^-1 b_m.
+ * red: a context from wpcd_create on full's device (any basis or P0 it held
+ * is dropped).  full: basis, potential and P0 built (boson channels); if
+ * its P0 is a WPCD_MIXED build, its FP64 values are computed once on the
+ * same structure and kept in full.  The entrance channel (l = 0, lam = L)
+ * must be major.  prec: WPCD_FP64 (solve red with WPCD_FP64) or WPCD_MIXED
+ * (FP32 copies of the reduced values for the mixed tiers; the FP64 ones
+ * are kept as well).  *nnz_out (may be NULL) receives the number of stored
+ * entries.  Layout of red's channel basis (x0, breakup rows): the major
+ * channels as in full, (a n_q + j) n_p + k, then from row n_major n_q n_p
+ * on the minor channels over (a', coarse j, pair state k of the coarse
+ * pair basis); breakup rows carry channel numbers over full's channel
+ * list, with j and k on the coarse lattice for minor channels; breakup_out
+ * needs n_p*n_ch*5 doubles per energy with full's n_p and n_ch.
+ * wpcd_get_p on red copies the reduced P0: row_ptr[R + 1] over the R
+ * reduced cells (n_major n_p n_q fine ones, then (n_ch - n_major)
+ * (n_p/r_p)(n_q/r_q) coarse ones, channel major), columns ascending,
+ * one value per entry.  wpcd_pair_spectrum reports red's major waves.
+ * Not available on red: wpcd_build_p (and _noalloc), wpcd_save_p,
+ * wpcd_load_p, wpcd_set_potential, wpcd_set_multipliers, wpcd_bound_state,
+ * wpcd_learn_train (WPCD_E_STATE); wpcd_build_basis makes red an ordinary
+ * context again.  full may be changed or destroyed afterwards.  The build
+ * keeps each coarse cell's column sets in one workgroup's LDS: lattices up
+ * to about 250,000 fine cells.  Errors: WPCD_E_INVALID (the conditions
+ * above), WPCD_E_STATE, WPCD_E_NOMEM, WPCD_E_DEVICE.                      */
+wpcd_status wpcd_build_reduced(wpcd_ctx *red, wpcd_ctx *full, int32_t n_major, int32_t r_p,
+                               int32_t r_q, wpcd_precision prec, int64_t *nnz_out);
+
 /* Steps 3-4 of Sec. III.C for n_E energies at once: channel resolvent G1
  * (FP64, diagonal in the channel WP basis), the factored kernel
  * K = O P0 V~ G1 (eq.(kernel)) applied on the GPU, and a batched restarted

@@ -50,7 +50,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_
 ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_build_basis_nucleons",
                  "wpcd_set_potential", "wpcd_pair_spectrum",
                  "wpcd_build_p", "wpcd_build_p_noalloc", "wpcd_get_p", "wpcd_save_p",
-                 "wpcd_load_p", "wpcd_solve",
+                 "wpcd_load_p", "wpcd_build_reduced", "wpcd_solve",
                  "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_bound_state", "wpcd_model_fill",
                  "wpcd_set_multipliers",
                  "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_autotune",
@@ -162,6 +162,8 @@ def lib():
                                            ctypes.POINTER(ctypes.c_int64)]
         L.wpcd_get_p.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int32), dp]
+        L.wpcd_build_reduced.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
         L.wpcd_solve.argtypes = [vp, dp, ctypes.c_int32, ctypes.c_int,
                                  ctypes.POINTER(wpcd_solve_opts),
                                  ctypes.POINTER(wpcd_energy_result), dp]
@@ -310,6 +312,16 @@ def wpcd_get_p(ctx, n_cells, nnz, n_ch=1, values=True):
     if values:
         val = val.reshape(nnz, n_ch, n_ch)
     return row_ptr, col, val
+
+
+def wpcd_build_reduced(red, full, n_major, r_p, r_q, precision=WPCD_FP64):
+    """Feshbach reduction: red becomes the reduced system of full (channels
+    [0, n_major) major on full's lattice, the rest on the lattice coarsened
+    by r_p x r_q); returns the number of stored entries of its P0."""
+    n = ctypes.c_int64(0)
+    _check(red, lib().wpcd_build_reduced(red, full, n_major, r_p, r_q, precision,
+                                         ctypes.byref(n)))
+    return n.value
 
 
 def _opts(max_iter=0, krylov_dim=0, tol=0.0, want_breakup=False, warm_start=WPCD_WARM_NONE,
@@ -503,12 +515,14 @@ class Context:
         self.h = wpcd_create(device, stream)
         self.n_p = self.n_q = self.n_ch = 0
         self.nnz = 0
+        self.red_rows = 0   # reduced cells of a reduced system (0: not reduced)
 
     def build_basis(self, n_p, n_q, p_max=10.0, q_max=10.0, n_gauss_q=8, n_gauss_x=16,
                     channels=((0, 0),), L=0, potential=None, p_edges=None, q_edges=None):
         wpcd_build_basis(self.h, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, channels, L,
                          potential, p_edges, q_edges)
         self.n_p, self.n_q, self.n_ch = n_p, n_q, len(channels)
+        self.red_rows = 0
 
     def build_basis_nucleons(self, n_p, n_q, p_max=10.0, q_max=10.0, n_gauss_q=8, n_gauss_x=16,
                              two_S=1, channels=((1, 0), (0, 1)), potential=None, mult=None,
@@ -516,6 +530,7 @@ class Context:
         wpcd_build_basis_nucleons(self.h, n_p, n_q, p_max, q_max, n_gauss_q, n_gauss_x, two_S,
                                   channels, potential, mult, p_edges, q_edges)
         self.n_p, self.n_q, self.n_ch = n_p, n_q, len(channels)
+        self.red_rows = 0
 
     def set_potential(self, potential):
         wpcd_set_potential(self.h, potential)
@@ -527,7 +542,19 @@ class Context:
         self.nnz = wpcd_build_p(self.h, precision)
         return self.nnz
 
+    def build_reduced(self, full, n_major, r_p, r_q, precision=WPCD_FP64):
+        """This context becomes the Feshbach-reduced system of `full` (a
+        Context with basis, potential and P0)."""
+        self.nnz = wpcd_build_reduced(self.h, full.h, n_major, r_p, r_q, precision)
+        self.n_p, self.n_q, self.n_ch = full.n_p, full.n_q, full.n_ch
+        self.red_rows = (n_major * full.n_p * full.n_q +
+                         (full.n_ch - n_major) * (full.n_p // r_p) * (full.n_q // r_q))
+        return self.nnz
+
     def get_p(self, values=True):
+        if self.red_rows:
+            rp, col, val = wpcd_get_p(self.h, self.red_rows, self.nnz, 1, values)
+            return rp, col, (val.reshape(-1) if values else None)
         return wpcd_get_p(self.h, self.n_p * self.n_q, self.nnz, self.n_ch, values)
 
     def solve(self, energies, precision=WPCD_FP64, **kw):

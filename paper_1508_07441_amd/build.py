@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = ["wpcd_api.hip", "wpcd_coupling.hip", "k_pair.hip", "k_p0.hip", "k_solve.hip",
-       "k_mlp.hip", "wpcd_learn.hip", "k_model.hip"]
+       "k_mlp.hip", "wpcd_learn.hip", "k_model.hip", "k_reduce.hip"]
 OUT = os.path.join(HERE, "libwpcd.so")
 # Per-file flags.  The element kernels see only finite tables, so their
 # min/max need no NaN quieting (without this flag every fmax/fmin of a value

@@ -1294,6 +1294,14 @@ struct Batch {
     bool lowp;       // FP32 intermediate panels in the inner iterations
     bool bf16;       // ... with the block products on the BF16 matrix cores
     int spmm_cfg;    // P0 SpMM variant (kSpmmCfg)
+    // Layout.  A reduced system (Feshbach reduction) holds its major
+    // channels in c (fine lattice, rows [0, M_F)) and its minor channels in
+    // cm (coarse lattice, rows [M_F, M)); P0 is then one scalar CSR over
+    // the reduced cells.  Otherwise cm is null and M_F = M.
+    wpcd_ctx *cm;
+    int64_t M_F;
+    int spmm_rows;   // CSR rows of the SpMM: cells (n_p n_q), or the reduced cells
+    int spmm_nch;    // channel block of a CSR entry (1 for the reduced CSR)
     void set_chunks(int nr_) {
         nr = nr_;
         nchunk = (int)((M + (int64_t)nr * (256 / nEp) - 1) / ((int64_t)nr * (256 / nEp)));
@@ -1313,47 +1321,78 @@ int apply_blocks(const wpcd_ctx *c, int W, int cfg) {
     return cdiv((int64_t)c->nq * W, kApplyTN[cfg]) * cdiv(c->np, kApplyTM[cfg]) * c->nch;
 }
 
+// One part of the layout: the geometry (n_p, n_q, channels, pair waves)
+// of a context and the offset of its rows in the batch's vectors.
+struct Part {
+    const wpcd_ctx *g;
+    int64_t off;   // first row of the part
+};
+
+// Per-channel pair-wave matrices of a part: V~ (which 0) or O (which 1).
+ChPtrs wave_mats(const wpcd_ctx *g, int which) {
+    ChPtrs m{};
+    for (int a = 0; a < g->nch; ++a) {
+        const PairWave &w = g->waves[g->ch_wave[a]];
+        m.p[a] = which ? w.O.ptr : w.Vt.ptr;
+    }
+    return m;
+}
+
 template <bool USE_G, bool SUB, int TM, int TN, class TI, class TO>
-void launch_block_apply_t(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
-    wpcd_ctx *c = b.c;
-    dim3 grid(cdiv((int64_t)c->nq * b.W, TN), cdiv(c->np, TM), c->nch);
-    hipLaunchKernelGGL((k_block_apply<USE_G, SUB, TM, TN, TI, TO>), grid, dim3(256), 0, c->stream,
-                       mats, c->np, c->nq, b.W, in, b.G, add, out);
+void launch_block_apply_t(Batch &b, const Part &pt, ChPtrs mats, const TI *in, const double *add,
+                          TO *out) {
+    const wpcd_ctx *g = pt.g;
+    const int64_t o = pt.off * b.W;
+    dim3 grid(cdiv((int64_t)g->nq * b.W, TN), cdiv(g->np, TM), g->nch);
+    hipLaunchKernelGGL((k_block_apply<USE_G, SUB, TM, TN, TI, TO>), grid, dim3(256), 0, b.c->stream,
+                       mats, g->np, g->nq, b.W, in + o, b.G + o, add ? add + o : nullptr, out + o);
 }
 
 template <bool USE_G, bool SUB, class TI, class TO, class MT, int TM = 64>
-void launch_block_apply_mfma(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
-    wpcd_ctx *c = b.c;
-    dim3 grid(cdiv((int64_t)c->nq * b.W, 64), cdiv(c->np, TM), c->nch);
+void launch_block_apply_mfma(Batch &b, const Part &pt, ChPtrs mats, const TI *in, const double *add,
+                             TO *out) {
+    const wpcd_ctx *g = pt.g;
+    const int64_t o = pt.off * b.W;
+    dim3 grid(cdiv((int64_t)g->nq * b.W, 64), cdiv(g->np, TM), g->nch);
     hipLaunchKernelGGL((k_block_apply_mfma<USE_G, SUB, TI, TO, MT, TM>), grid, dim3(256), 0,
-                       c->stream, mats, c->np, c->nq, b.W, in, b.G, add, out);
+                       b.c->stream, mats, g->np, g->nq, b.W, in + o, b.G + o,
+                       add ? add + o : nullptr, out + o);
 }
 
 // Tile shapes 0-3 on the vector ALUs, 4 and 5 (64- and 32-row tiles) on the FP64 matrix cores (all FP64
 // arithmetic); the inner iterations of the refine tiers (FP32 panels) use the
 // FP32 matrix cores, or the BF16 ones, with FP32 accumulation.
 template <bool USE_G, bool SUB, class TI, class TO>
-void launch_block_apply(Batch &b, ChPtrs mats, const TI *in, const double *add, TO *out) {
+void block_apply_part(Batch &b, const Part &pt, ChPtrs mats, const TI *in, const double *add,
+                      TO *out) {
     if (std::is_same<TI, float>::value || std::is_same<TO, float>::value) {
         // 32-row tiles when 64-row ones would leave the device under-filled
-        const bool small = apply_blocks(b.c, b.W, 4) < 512;
+        const bool small = apply_blocks(pt.g, b.W, 4) < 512;
         if (b.bf16) {
-            if (small) launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16, 32>(b, mats, in, add, out);
-            else launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16>(b, mats, in, add, out);
+            if (small) launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16, 32>(b, pt, mats, in, add, out);
+            else launch_block_apply_mfma<USE_G, SUB, TI, TO, Bf16>(b, pt, mats, in, add, out);
         } else {
-            if (small) launch_block_apply_mfma<USE_G, SUB, TI, TO, float, 32>(b, mats, in, add, out);
-            else launch_block_apply_mfma<USE_G, SUB, TI, TO, float>(b, mats, in, add, out);
+            if (small) launch_block_apply_mfma<USE_G, SUB, TI, TO, float, 32>(b, pt, mats, in, add, out);
+            else launch_block_apply_mfma<USE_G, SUB, TI, TO, float>(b, pt, mats, in, add, out);
         }
         return;
     }
     switch (b.apply_cfg) {
-        case 0: launch_block_apply_t<USE_G, SUB, 64, 64>(b, mats, in, add, out); break;
-        case 1: launch_block_apply_t<USE_G, SUB, 32, 64>(b, mats, in, add, out); break;
-        case 2: launch_block_apply_t<USE_G, SUB, 32, 32>(b, mats, in, add, out); break;
-        case 3: launch_block_apply_t<USE_G, SUB, 16, 64>(b, mats, in, add, out); break;
-        case 4: launch_block_apply_mfma<USE_G, SUB, TI, TO, double>(b, mats, in, add, out); break;
-        default: launch_block_apply_mfma<USE_G, SUB, TI, TO, double, 32>(b, mats, in, add, out); break;
+        case 0: launch_block_apply_t<USE_G, SUB, 64, 64>(b, pt, mats, in, add, out); break;
+        case 1: launch_block_apply_t<USE_G, SUB, 32, 64>(b, pt, mats, in, add, out); break;
+        case 2: launch_block_apply_t<USE_G, SUB, 32, 32>(b, pt, mats, in, add, out); break;
+        case 3: launch_block_apply_t<USE_G, SUB, 16, 64>(b, pt, mats, in, add, out); break;
+        case 4: launch_block_apply_mfma<USE_G, SUB, TI, TO, double>(b, pt, mats, in, add, out); break;
+        default: launch_block_apply_mfma<USE_G, SUB, TI, TO, double, 32>(b, pt, mats, in, add, out); break;
     }
+}
+
+// The block products of every part of the layout with its pair waves'
+// V~ (which 0) or O (which 1).
+template <bool USE_G, bool SUB, class TI, class TO>
+void launch_block_apply(Batch &b, int which, const TI *in, const double *add, TO *out) {
+    block_apply_part<USE_G, SUB>(b, Part{b.c, 0}, wave_mats(b.c, which), in, add, out);
+    if (b.cm) block_apply_part<USE_G, SUB>(b, Part{b.cm, b.M_F}, wave_mats(b.cm, which), in, add, out);
 }
 
 // P0 SpMM candidates: 0 plain, 1 XCD-contiguous rows, 2 several nonzeros
@@ -1365,7 +1404,7 @@ constexpr int kSpmmCfg = 7;
 template <class PT, class V, int NCH, bool PERM, bool PIPE>
 void launch_spmm_lds(Batch &b, const V *val, const PT *x, PT *y) {
     wpcd_ctx *c = b.c;
-    const int nrow = c->np * c->nq;
+    const int nrow = b.spmm_rows;
     const int grid = PERM ? c->perm_grid : nrow;
     if (PIPE)
         hipLaunchKernelGGL((k_spmm_pipe<V, NCH, PT, PT, PERM>), dim3(grid), dim3(64), 0,
@@ -1379,7 +1418,7 @@ void launch_spmm_lds(Batch &b, const V *val, const PT *x, PT *y) {
 
 template <class PT, class V, bool PERM, bool PIPE>
 void launch_spmm_lds_n(Batch &b, const V *val, const PT *x, PT *y) {
-    switch (b.c->nch) {
+    switch (b.spmm_nch) {
         case 1: launch_spmm_lds<PT, V, 1, PERM, PIPE>(b, val, x, y); break;
         case 2: launch_spmm_lds<PT, V, 2, PERM, PIPE>(b, val, x, y); break;
         case 3: launch_spmm_lds<PT, V, 3, PERM, PIPE>(b, val, x, y); break;
@@ -1451,12 +1490,12 @@ void ensure_perm(wpcd_ctx *c) {
 template <class PT, class V, bool XCD, int U>
 void launch_spmm_v(Batch &b, const V *val, const PT *x, PT *y) {
     wpcd_ctx *c = b.c;
-    const int nrow = c->np * c->nq;
+    const int nrow = b.spmm_rows;
     const dim3 grid(cdiv(nrow, 4)), blk(256);
     const int64_t *rp = c->d_rowptr.ptr;
     const int32_t *cl = c->d_col.ptr;
     hipStream_t s = c->stream;
-    switch (c->nch) {
+    switch (b.spmm_nch) {
         case 1: hipLaunchKernelGGL((k_spmm<V, PT, PT, XCD>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
         case 2: hipLaunchKernelGGL((k_spmm_bsr<V, 2, PT, PT, XCD, U>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
         case 3: hipLaunchKernelGGL((k_spmm_bsr<V, 3, PT, PT, XCD, U>), grid, blk, 0, s, rp, cl, val, nrow, b.W, b.Wp, x, y); break;
@@ -1497,16 +1536,11 @@ void launch_spmm(Batch &b, const PT *x, PT *y, int cfg) {
 template <class PT>
 void op_apply_t(Batch &b, const double *x, double *out, bool with_g, bool sub) {
     wpcd_ctx *c = b.c;
-    ChPtrs vt{}, oo{};
-    for (int a = 0; a < c->nch; ++a) {
-        vt.p[a] = c->waves[c->ch_wave[a]].Vt.ptr;
-        oo.p[a] = c->waves[c->ch_wave[a]].O.ptr;
-    }
     PT *T1 = (PT *)b.T1, *T2 = (PT *)b.T2;
     {
         TimedLaunch tl(c->timer, c->stream, "apply_vt", WPCD_TIME_SOLVE);
-        if (with_g) launch_block_apply<true, false>(b, vt, x, nullptr, T1);
-        else launch_block_apply<false, false>(b, vt, x, nullptr, T1);
+        if (with_g) launch_block_apply<true, false>(b, 0, x, nullptr, T1);
+        else launch_block_apply<false, false>(b, 0, x, nullptr, T1);
         WPCD_HIP(hipGetLastError());
     }
     {
@@ -1515,8 +1549,8 @@ void op_apply_t(Batch &b, const double *x, double *out, bool with_g, bool sub) {
     }
     {
         TimedLaunch tl(c->timer, c->stream, "apply_o", WPCD_TIME_SOLVE);
-        if (sub) launch_block_apply<false, true>(b, oo, T2, x, out);
-        else launch_block_apply<false, false>(b, oo, T2, nullptr, out);
+        if (sub) launch_block_apply<false, true>(b, 1, T2, x, out);
+        else launch_block_apply<false, false>(b, 1, T2, nullptr, out);
         WPCD_HIP(hipGetLastError());
     }
 }
@@ -1644,10 +1678,15 @@ IterGraphs *graphs_for(Batch &b, double tol, int check_every) {
     uint64_t tb;
     std::memcpy(&tb, &tol, sizeof tb);
     key.push_back(tb);
-    for (int a = 0; a < c->nch; ++a) {
-        key.push_back((uint64_t)c->waves[c->ch_wave[a]].Vt.ptr);
-        key.push_back((uint64_t)c->waves[c->ch_wave[a]].O.ptr);
+    for (const wpcd_ctx *g : {(const wpcd_ctx *)c, (const wpcd_ctx *)b.cm}) {
+        if (!g) continue;
+        key.push_back((uint64_t)g->nch);
+        for (int a = 0; a < g->nch; ++a) {
+            key.push_back((uint64_t)g->waves[g->ch_wave[a]].Vt.ptr);
+            key.push_back((uint64_t)g->waves[g->ch_wave[a]].O.ptr);
+        }
     }
+    key.push_back((uint64_t)b.M_F);
     for (auto &g : c->graphs)
         if (g.key == key) return &g;
     if (c->graphs.size() >= 8) {
@@ -1691,12 +1730,10 @@ void choose_shapes(Batch &b, int m) {
             heur = i;
             break;
         }
-    ChPtrs vt{};
-    for (int a = 0; a < c->nch; ++a) vt.p[a] = c->waves[c->ch_wave[a]].Vt.ptr;
     b.apply_cfg = tune_pick(c, "block_apply", key, kApplyCfg, heur, [&](int i) {
         b.apply_cfg = i;
         return time_launches(c->stream, [&] {
-            launch_block_apply<true, false>(b, vt, (const double *)b.X, nullptr, b.T1);
+            launch_block_apply<true, false>(b, 0, (const double *)b.X, nullptr, b.T1);
             WPCD_HIP(hipGetLastError());
         });
     });
@@ -1729,12 +1766,14 @@ void choose_shapes(Batch &b, int m) {
     });
     b.set_chunks(kNrCand[ch]);
     // P0 SpMM: the variant for the inner iterations' panel type
-    std::snprintf(key, sizeof key, "nnz=%lld nch=%d W=%d %s%s", (long long)c->nnz, c->nch, b.W,
+    std::snprintf(key, sizeof key, "nnz=%lld nch=%d W=%d %s%s", (long long)c->nnz, b.spmm_nch, b.W,
                   b.fp64 ? "f64" : "f32", b.lowp ? " lowp" : "");
-    // candidates: the s-wave kernel has no unrolled form
-    std::vector<int> cand =
-        c->nch > 1 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6} : std::vector<int>{0, 1, 4, 5, 6};
-    ensure_perm(c);   // before any capture
+    // candidates: the s-wave kernel has no unrolled form; the lattice-tile
+    // row order needs one lattice (not the reduced CSR)
+    std::vector<int> cand = b.cm ? std::vector<int>{0, 1, 4, 5}
+                            : c->nch > 1 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6}
+                                         : std::vector<int>{0, 1, 4, 5, 6};
+    if (!b.cm) ensure_perm(c);   // before any capture
     const int pick = tune_pick(c, "spmm", key, (int)cand.size(), 0, [&](int i) {
         return time_launches(c->stream, [&] {
             if (b.lowp) launch_spmm<float>(b, (const float *)b.T1, (float *)b.T2, cand[i]);
@@ -1994,6 +2033,16 @@ void gmres_cycles(std::vector<GmresRun *> &runs) {
     }
 }
 
+// Rows of the batch's vectors and the SpMM's CSR (see Batch).
+void set_layout(Batch &b) {
+    wpcd_ctx *c = b.c;
+    b.cm = c->reduced ? c->minor : nullptr;
+    b.M_F = (int64_t)c->nch * c->nq * c->np;
+    b.M = b.M_F + (b.cm ? (int64_t)b.cm->nch * b.cm->nq * b.cm->np : 0);
+    b.spmm_rows = c->reduced ? (int)c->red_rows : c->np * c->nq;
+    b.spmm_nch = c->reduced ? 1 : c->nch;
+}
+
 void gmres_setup(GmresRun &run, wpcd_ctx *c, const std::vector<double> &E,
                  const std::vector<int64_t> &idx0, int prec, int m, int max_iter, double tol,
                  WarmFill warm, void *warm_user, GmresOut &out, bool err_est,
@@ -2019,7 +2068,7 @@ void gmres_setup(GmresRun &run, wpcd_ctx *c, const std::vector<double> &E,
     while (b.nEp < nE) b.nEp <<= 1;
     b.Wp = 2 * b.nEp;
     b.m = m;
-    b.M = (int64_t)c->nch * c->nq * c->np;
+    set_layout(b);
     b.fp64 = fp64;
     b.lowp = prec == WPCD_MIXED_REFINE || prec == WPCD_MIXED_BF16;
     b.bf16 = prec == WPCD_MIXED_BF16;
@@ -2073,21 +2122,34 @@ void gmres_setup(GmresRun &run, wpcd_ctx *c, const std::vector<double> &E,
     double *dE = c->d_T1.ptr;   // scratch: T1 not yet in use
     WPCD_HIP(hipMemcpyAsync(dE, E.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
     WPCD_HIP(hipMemsetAsync(flag, 0, nE * sizeof(int32_t), s));
-    ChPtrs eps{};
-    for (int a = 0; a < c->nch; ++a) eps.p[a] = c->waves[c->ch_wave[a]].eps.ptr;
     if (ebin) {
         // on-shell energy intervals [E1, E2] per energy (after dE in the scratch)
         double *dB = dE + nE;
         WPCD_HIP(hipMemcpyAsync(dB, ebin->data(), 2 * nE * sizeof(double), hipMemcpyHostToDevice,
                                 s));
         TimedLaunch tl(c->timer, s, "resolvent", WPCD_TIME_SOLVE);
-        hipLaunchKernelGGL(k_resolvent_avg, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s,
-                           c->d_q.ptr, c->np, c->nq, c->nch, nE, dB, eps, b.G);
+        for (const Part &pt : {Part{c, 0}, Part{b.cm, b.M_F}}) {
+            if (!pt.g) continue;
+            const wpcd_ctx *g = pt.g;
+            ChPtrs ep{};
+            for (int a = 0; a < g->nch; ++a) ep.p[a] = g->waves[g->ch_wave[a]].eps.ptr;
+            const int64_t rows = (int64_t)g->nch * g->nq * g->np;
+            hipLaunchKernelGGL(k_resolvent_avg, dim3(cdiv(rows * nE, 256)), dim3(256), 0, s,
+                               g->d_q.ptr, g->np, g->nq, g->nch, nE, dB, ep, b.G + pt.off * b.W);
+        }
         WPCD_HIP(hipGetLastError());
     } else {
         TimedLaunch tl(c->timer, s, "resolvent", WPCD_TIME_SOLVE);
-        hipLaunchKernelGGL(k_resolvent, dim3(cdiv(b.M * nE, 256)), dim3(256), 0, s, c->d_q.ptr,
-                           c->np, c->nq, c->nch, nE, dE, eps, b.G, flag);
+        for (const Part &pt : {Part{c, 0}, Part{b.cm, b.M_F}}) {
+            if (!pt.g) continue;
+            const wpcd_ctx *g = pt.g;
+            ChPtrs ep{};
+            for (int a = 0; a < g->nch; ++a) ep.p[a] = g->waves[g->ch_wave[a]].eps.ptr;
+            const int64_t rows = (int64_t)g->nch * g->nq * g->np;
+            hipLaunchKernelGGL(k_resolvent, dim3(cdiv(rows * nE, 256)), dim3(256), 0, s,
+                               g->d_q.ptr, g->np, g->nq, g->nch, nE, dE, ep,
+                               b.G + pt.off * b.W, flag);
+        }
         WPCD_HIP(hipGetLastError());
     }
     edge_flag.assign(nE, 0);
@@ -2228,7 +2290,7 @@ void arnoldi_kernel(wpcd_ctx *c, double E, int m, std::vector<double> &H, int &s
     b.W = 2;
     b.Wp = 2;
     b.m = m;
-    b.M = (int64_t)c->nch * c->nq * c->np;
+    set_layout(b);
     b.fp64 = fp64;
     b.lowp = false;
     b.bf16 = false;

@@ -386,9 +386,21 @@ struct WarmCtx {
     std::vector<const double *> given;     // given: caller vector per energy
 };
 
+// Rows of the channel basis: for a reduced system its major part (this
+// context's lattice) and then its minor part (the coarse lattice).
+static int64_t basis_rows(const wpcd_ctx *c) {
+    int64_t M = (int64_t)c->nch * c->nq * c->np;
+    if (c->reduced && c->minor) M += (int64_t)c->minor->nch * c->minor->nq * c->minor->np;
+    return M;
+}
+
+static int total_channels(const wpcd_ctx *c) {
+    return c->nch + (c->reduced && c->minor ? c->minor->nch : 0);
+}
+
 static void warm_fill(wpcd_ctx *c, void *user, double *x, int nE) {
     WarmCtx &w = *(WarmCtx *)user;
-    const int64_t M = (int64_t)c->nch * c->nq * c->np;
+    const int64_t M = basis_rows(c);
     if (w.kind == WPCD_WARM_LEARNED) {
         Learned &L = c->learned;
         L.feat.reserve(w.feat.size());
@@ -430,6 +442,7 @@ struct SolveJob {
     int want_breakup = 0, warm_kind = WPCD_WARM_NONE;
     bool err_est = false, averaged = false;
     int64_t M = 0;
+    int64_t bstride = 0;   // doubles per energy in breakup_out
     int a0 = -1;
     double eb = 0.0, qmax = 0.0;
     std::vector<wpcd_energy_result> res;
@@ -486,7 +499,8 @@ struct SolveJob {
         WPCD_REQUIRE(m >= 2 && m <= 128, WPCD_E_INVALID, "krylov_dim must be 2..128");
         WPCD_REQUIRE(warm_kind >= WPCD_WARM_NONE && warm_kind <= WPCD_WARM_GIVEN, WPCD_E_INVALID,
                      "warm_start must be a WPCD_WARM_* value");
-        M = (int64_t)c->nch * c->nq * c->np;
+        M = basis_rows(c);
+        bstride = (int64_t)c->np * total_channels(c) * 5;
         if (warm_kind == WPCD_WARM_GIVEN) WPCD_REQUIRE(opts->x0, WPCD_E_INVALID, "x0 is NULL");
         if (warm_kind == WPCD_WARM_LEARNED)
             WPCD_REQUIRE(c->learned.ready && c->learned.M == M &&
@@ -596,41 +610,63 @@ struct SolveJob {
         }
         // open breakup states: the pseudostate's on-shell bin (resolvent at
         // E, rho = 2/(3 q dq)), or every bin whose shell eps + 3/4 q^2 meets
-        // the on-shell energy interval (averaged, rho = overlap / (D dq))
+        // the on-shell energy interval (averaged, rho = overlap / (D dq)).
+        // A reduced system's minor channels follow its major ones, on their
+        // own (coarse) lattice and with their own pair states.
+        std::vector<int> r_ch, r_k, r_j;
+        std::vector<double> r_eps;
+        for (int t = 0; t < nb; ++t) {
+            r_ch.push_back(-1);
+            r_k.push_back(0);
+            r_j.push_back(0);
+            r_eps.push_back(0.0);
+        }
         for (int t = 0; t < nb; ++t) {
             first_br[t] = (int)rows.size();
             n_br[t] = 0;
-            for (int a = 0; a < c->nch; ++a) {
-                const std::vector<double> &ev = c->waves[c->ch_wave[a]].h_eps;
-                for (int k = 0; k < c->np; ++k) {
-                    if (a == a0 && k == 0) continue;
-                    if (averaged) {
-                        const double e1 = ebin[2 * t], e2 = ebin[2 * t + 1], D = e2 - e1;
-                        const double s1 = e1 - ev[k], s2 = e2 - ev[k];
-                        if (!(s2 > 0.0)) continue;
-                        const double q1 = s1 > 0.0 ? std::sqrt(4.0 * s1 / 3.0) : 0.0;
-                        const double q2 = std::sqrt(4.0 * s2 / 3.0);
-                        int j = (int)(std::upper_bound(c->q.begin(), c->q.end(), q1) - c->q.begin()) - 1;
-                        for (j = std::max(j, 0); j < c->nq && c->q[j] < q2; ++j) {
-                            const double ov = std::min(c->q[j + 1], q2) - std::max(c->q[j], q1);
-                            if (!(ov > 0.0)) continue;
-                            rows.push_back(((int64_t)a * c->nq + j) * c->np + k);
-                            ens.push_back(t);
-                            rho.push_back(ov / (D * (c->q[j + 1] - c->q[j])));
-                            ++n_br[t];
-                        }
-                        continue;
-                    }
-                    if (!(ev[k] < Eb[t])) continue;
-                    const double qk = std::sqrt(4.0 * (Eb[t] - ev[k]) / 3.0);
-                    if (qk >= qmax) continue;
-                    const int jk =
-                        (int)(std::upper_bound(c->q.begin(), c->q.end(), qk) - c->q.begin()) - 1;
-                    rows.push_back(((int64_t)a * c->nq + jk) * c->np + k);
+            int64_t off = 0;
+            int a_base = 0;
+            for (const wpcd_ctx *g : {(const wpcd_ctx *)c, (const wpcd_ctx *)c->minor}) {
+                if (!g) continue;
+                const std::vector<double> &qg = g->q;
+                auto push = [&](int a, int k, int j, double rh, double ek) {
+                    rows.push_back(off + ((int64_t)a * g->nq + j) * g->np + k);
                     ens.push_back(t);
-                    rho.push_back(2.0 / (3.0 * qk * (c->q[jk + 1] - c->q[jk])));
+                    rho.push_back(rh);
+                    r_ch.push_back(a_base + a);
+                    r_k.push_back(k);
+                    r_j.push_back(j);
+                    r_eps.push_back(ek);
                     ++n_br[t];
+                };
+                for (int a = 0; a < g->nch; ++a) {
+                    const std::vector<double> &ev = g->waves[g->ch_wave[a]].h_eps;
+                    for (int k = 0; k < g->np; ++k) {
+                        if (g == c && a == a0 && k == 0) continue;
+                        if (averaged) {
+                            const double e1 = ebin[2 * t], e2 = ebin[2 * t + 1], D = e2 - e1;
+                            const double s1 = e1 - ev[k], s2 = e2 - ev[k];
+                            if (!(s2 > 0.0)) continue;
+                            const double q1 = s1 > 0.0 ? std::sqrt(4.0 * s1 / 3.0) : 0.0;
+                            const double q2 = std::sqrt(4.0 * s2 / 3.0);
+                            int j = (int)(std::upper_bound(qg.begin(), qg.end(), q1) - qg.begin()) - 1;
+                            for (j = std::max(j, 0); j < g->nq && qg[j] < q2; ++j) {
+                                const double ov = std::min(qg[j + 1], q2) - std::max(qg[j], q1);
+                                if (!(ov > 0.0)) continue;
+                                push(a, k, j, ov / (D * (qg[j + 1] - qg[j])), ev[k]);
+                            }
+                            continue;
+                        }
+                        if (!(ev[k] < Eb[t])) continue;
+                        const double qk = std::sqrt(4.0 * (Eb[t] - ev[k]) / 3.0);
+                        if (qk >= qmax) continue;
+                        const int jk =
+                            (int)(std::upper_bound(qg.begin(), qg.end(), qk) - qg.begin()) - 1;
+                        push(a, k, jk, 2.0 / (3.0 * qk * (qg[jk + 1] - qg[jk])), ev[k]);
+                    }
                 }
+                off += (int64_t)g->nch * g->nq * g->np;
+                a_base += g->nch;
             }
         }
         std::vector<double> amp;
@@ -664,39 +700,34 @@ struct SolveJob {
             }
             if (r.status == WPCD_OK) ok.push_back(t);
             if (breakup_out && want_breakup == WPCD_BREAKUP_ELEMENTS) {
-                double *dst = breakup_out + (size_t)e * c->np * c->nch * 5;
+                double *dst = breakup_out + (size_t)e * bstride;
                 for (int u = 0; u < n_br[t]; ++u) {
                     const int row = first_br[t] + u;
-                    const int64_t rr = rows[row];
-                    const int a = (int)(rr / ((int64_t)c->nq * c->np));
-                    const int jk = (int)((rr / c->np) % c->nq);
-                    const int k = (int)(rr % c->np);
-                    dst[5 * u + 0] = a;
-                    dst[5 * u + 1] = k;
-                    dst[5 * u + 2] = jk;
+                    dst[5 * u + 0] = r_ch[row];
+                    dst[5 * u + 1] = r_k[row];
+                    dst[5 * u + 2] = r_j[row];
                     dst[5 * u + 3] = amp[4 * row + 2];
                     dst[5 * u + 4] = amp[4 * row + 3];
                 }
             } else if (want_breakup == WPCD_BREAKUP_DIST) {
                 // one row per pseudostate with open bins, in row order
                 // (channel major, then k): summed |S|^2 over its bins
-                double *dst = breakup_out ? breakup_out + (size_t)e * c->np * c->nch * 5 : nullptr;
+                double *dst = breakup_out ? breakup_out + (size_t)e * bstride : nullptr;
                 int nd = 0;
                 for (int u = 0; u < n_br[t];) {
-                    const int64_t r0 = rows[first_br[t] + u];
-                    const int a = (int)(r0 / ((int64_t)c->nq * c->np)), k = (int)(r0 % c->np);
+                    const int row0 = first_br[t] + u;
+                    const int a = r_ch[row0], k = r_k[row0];
                     double ptot = 0.0;
                     int nbin = 0;
                     for (; u < n_br[t]; ++u, ++nbin) {
                         const int row = first_br[t] + u;
-                        const int64_t rr = rows[row];
-                        if ((int)(rr / ((int64_t)c->nq * c->np)) != a || (int)(rr % c->np) != k) break;
+                        if (r_ch[row] != a || r_k[row] != k) break;
                         ptot += amp[4 * row + 2] * amp[4 * row + 2] + amp[4 * row + 3] * amp[4 * row + 3];
                     }
                     if (dst) {
                         dst[5 * nd + 0] = a;
                         dst[5 * nd + 1] = k;
-                        dst[5 * nd + 2] = c->waves[c->ch_wave[a]].h_eps[k];
+                        dst[5 * nd + 2] = r_eps[row0];
                         dst[5 * nd + 3] = ptot;
                         dst[5 * nd + 4] = nbin;
                     }
@@ -1049,9 +1080,9 @@ wpcd_status wpcd_create(int device, void *hip_stream, wpcd_ctx **out) {
 // three nucleons in pair s-waves (channels from nuc; the channel arrays of
 // b are not read), else spinless bosons with b's channels.
 static void build_basis_impl(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_potential_desc *pot,
-                             const wpcd_nucleon_desc *nuc) {
+                             const wpcd_nucleon_desc *nuc, bool with_waves = true) {
     WPCD_REQUIRE(b, WPCD_E_INVALID, "basis descriptor is NULL");
-    WPCD_REQUIRE(pot, WPCD_E_INVALID, "potential descriptor is NULL");
+    WPCD_REQUIRE(pot || !with_waves, WPCD_E_INVALID, "potential descriptor is NULL");
     WPCD_REQUIRE(b->n_p >= 2 && b->n_p <= 1024 && b->n_q >= 2 && b->n_q <= 1024,
                  WPCD_E_INVALID, "n_p, n_q must be in 2..1024");
     WPCD_REQUIRE(b->n_gauss_q >= 1 && b->n_gauss_q <= kMaxGq, WPCD_E_INVALID,
@@ -1088,6 +1119,7 @@ static void build_basis_impl(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_p
         }
         WPCD_REQUIRE(ch_s[0] == 1, WPCD_E_INVALID,
                      "channel 0 must be the deuteron channel (s, t) = (1, 0)");
+        WPCD_REQUIRE(pot, WPCD_E_INVALID, "potential descriptor is NULL");
         WPCD_REQUIRE(!nuc->mult || pot->n_terms >= 1, WPCD_E_INVALID, "bad n_terms");
         if (nuc->mult)
             for (int k = 0; k < nch * pot->n_terms; ++k)
@@ -1205,11 +1237,136 @@ static void build_basis_impl(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_p
     }
     WPCD_HIP(hipStreamSynchronize(c->stream));
     c->has_basis = true;
-    build_pair_waves(c, pot);
+    if (with_waves) build_pair_waves(c, pot);
 }
 
+// Every device buffer of a context (and of its reduced system's minor
+// part); the context itself and its stream stay.
+static void release_all(wpcd_ctx *c);
+
+// A reduced system becomes an ordinary context again (no P0, no minor part).
+static void drop_reduction(wpcd_ctx *c) {
+    if (!c->reduced && !c->minor) return;
+    if (c->minor) {
+        release_all(c->minor);
+        delete c->minor;
+        c->minor = nullptr;
+    }
+    c->reduced = false;
+    c->red_rows = 0;
+    c->has_p = false;
+    c->has_val64 = false;
+    c->pred_nnz = -1;
+    for (auto &g : c->graphs) g.release();
+    c->graphs.clear();
+    for (auto &g : c->multi_graphs) (void)hipGraphExecDestroy(g.exec);
+    c->multi_graphs.clear();
+}
+
+#define WPCD_NOT_REDUCED(c)                                                                \
+    WPCD_REQUIRE(!(c)->reduced, WPCD_E_STATE,                                             \
+                 "not available on a reduced system (build a basis to reuse the context)")
+
 wpcd_status wpcd_build_basis(wpcd_ctx *c, const wpcd_basis_desc *b, const wpcd_potential_desc *pot) {
-    return guarded(c, [&] { build_basis_impl(c, b, pot, nullptr); });
+    return guarded(c, [&] {
+        drop_reduction(c);
+        build_basis_impl(c, b, pot, nullptr);
+    });
+}
+
+// The potential of `src` (kind, strengths with their multipliers, ranges,
+// fitted scale) on `c`'s pair waves, diagonalised on c's lattice.
+static void copy_potential(const wpcd_ctx *src, wpcd_ctx *c) {
+    c->pot_kind = src->pot_kind;
+    c->pot_s = src->pot_s;
+    c->pot_base = src->pot_base;
+    c->pot_mult = src->pot_mult;
+    c->pot_mu = src->pot_mu;
+    c->pot_scale = src->pot_scale;
+    c->has_pot = false;
+    diagonalise_all(c);
+    c->has_pot = true;
+}
+
+// Feshbach reduction (Sec. V.B): see wpcd_build_reduced in the header.
+static void build_reduced(wpcd_ctx *red, wpcd_ctx *full, int nmaj, int cp, int cq,
+                          wpcd_precision prec) {
+    WPCD_REQUIRE(full && full != red, WPCD_E_INVALID, "full is NULL or the reduced context itself");
+    WPCD_REQUIRE(!full->reduced, WPCD_E_INVALID, "full is itself a reduced system");
+    WPCD_REQUIRE(full->has_basis && full->has_pot && full->has_p, WPCD_E_STATE,
+                 "the full system needs its basis, potential and P0");
+    WPCD_REQUIRE(full->device == red->device, WPCD_E_INVALID, "contexts on different devices");
+    WPCD_REQUIRE(full->nuc_two_S == 0, WPCD_E_INVALID, "the reduction takes boson channel sets");
+    WPCD_REQUIRE(nmaj >= 1 && nmaj < full->nch, WPCD_E_INVALID,
+                 "n_major must leave at least one major and one minor channel");
+    WPCD_REQUIRE(cp >= 1 && cq >= 1 && full->np % cp == 0 && full->nq % cq == 0 &&
+                     full->np / cp >= 2 && full->nq / cq >= 2,
+                 WPCD_E_INVALID, "r_p, r_q must divide n_p, n_q and leave at least 2 bins");
+    WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID,
+                 "precision must be WPCD_FP64 or WPCD_MIXED");
+    bool entrance = false;
+    for (int a = 0; a < nmaj; ++a) entrance |= full->ch_l[a] == 0 && full->ch_lam[a] == full->L;
+    WPCD_REQUIRE(entrance, WPCD_E_INVALID, "the entrance channel (l = 0, lam = L) must be major");
+    // the unreduced values in FP64 (computed once on the existing structure)
+    if (!full->p_fp64 && !full->has_val64) {
+        build_values(full, true);
+        full->has_val64 = true;
+    }
+    WPCD_HIP(hipStreamSynchronize(full->stream));
+    drop_reduction(red);
+    red->learned.release();
+    // major part: this context, the full system's lattice and major channels
+    wpcd_basis_desc bd{};
+    bd.n_p = full->np;
+    bd.n_q = full->nq;
+    bd.edge_kind = 1;
+    bd.p_edges = full->p.data();
+    bd.q_edges = full->q.data();
+    bd.n_gauss_q = full->ngq;
+    bd.n_gauss_x = full->ngx;
+    bd.L = full->L;
+    bd.n_ch = nmaj;
+    bd.l = full->ch_l;
+    bd.lam = full->ch_lam;
+    build_basis_impl(red, &bd, nullptr, nullptr, false);
+    copy_potential(full, red);
+    // minor part: every cp-th p edge and cq-th q edge, the minor channels
+    wpcd_ctx *m = new wpcd_ctx();
+    m->device = red->device;
+    m->stream = red->stream;
+    m->own_stream = false;
+    red->minor = m;
+    std::vector<double> pc, qc;
+    for (int k = 0; k <= full->np; k += cp) pc.push_back(full->p[k]);
+    for (int k = 0; k <= full->nq; k += cq) qc.push_back(full->q[k]);
+    wpcd_basis_desc bm = bd;
+    bm.n_p = full->np / cp;
+    bm.n_q = full->nq / cq;
+    bm.p_edges = pc.data();
+    bm.q_edges = qc.data();
+    bm.n_ch = full->nch - nmaj;
+    bm.l = full->ch_l + nmaj;
+    bm.lam = full->ch_lam + nmaj;
+    build_basis_impl(m, &bm, nullptr, nullptr, false);
+    copy_potential(full, m);
+    // P0 of the reduced cells
+    reduce_p0(full, red, nmaj, cp, cq, full->d_val64.ptr, prec == WPCD_MIXED);
+    red->reduced = true;
+    red->red_cp = cp;
+    red->red_cq = cq;
+    red->red_rows = (int64_t)nmaj * full->np * full->nq + (int64_t)m->nch * m->np * m->nq;
+    red->has_p = true;
+    red->p_fp64 = prec == WPCD_FP64;
+    red->has_val64 = true;
+    red->pred_nnz = -1;
+}
+
+wpcd_status wpcd_build_reduced(wpcd_ctx *red, wpcd_ctx *full, int32_t n_major, int32_t r_p,
+                               int32_t r_q, wpcd_precision prec, int64_t *nnz_out) {
+    return guarded(red, [&] {
+        build_reduced(red, full, n_major, r_p, r_q, prec);
+        if (nnz_out) *nnz_out = red->nnz;
+    });
 }
 
 wpcd_status wpcd_build_basis_nucleons(wpcd_ctx *c, const wpcd_basis_desc *b,
@@ -1217,6 +1374,7 @@ wpcd_status wpcd_build_basis_nucleons(wpcd_ctx *c, const wpcd_basis_desc *b,
                                       const wpcd_nucleon_desc *nuc) {
     return guarded(c, [&] {
         WPCD_REQUIRE(nuc, WPCD_E_INVALID, "nucleon descriptor is NULL");
+        drop_reduction(c);
         build_basis_impl(c, b, pot, nuc);
     });
 }
@@ -1224,6 +1382,7 @@ wpcd_status wpcd_build_basis_nucleons(wpcd_ctx *c, const wpcd_basis_desc *b,
 wpcd_status wpcd_set_potential(wpcd_ctx *c, const wpcd_potential_desc *pot) {
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        WPCD_NOT_REDUCED(c);
         c->has_pot = false;
         build_pair_waves(c, pot);
     });
@@ -1258,6 +1417,7 @@ wpcd_status wpcd_build_p_noalloc(wpcd_ctx *c, wpcd_precision prec, int64_t *row_
                                  int32_t *col, void *val, int64_t cap_nnz, int64_t *nnz_out) {
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        WPCD_NOT_REDUCED(c);
         WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
         WPCD_REQUIRE(row_ptr && col && val && cap_nnz >= 0, WPCD_E_INVALID,
                      "row_ptr, col and val must be device pointers and cap_nnz >= 0");
@@ -1325,6 +1485,7 @@ wpcd_status wpcd_model_fill(wpcd_ctx *c, int32_t kind, int32_t mode, int32_t M, 
 wpcd_status wpcd_build_p(wpcd_ctx *c, wpcd_precision prec, int64_t *nnz_out) {
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        WPCD_NOT_REDUCED(c);
         WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED, WPCD_E_INVALID, "bad precision");
         c->has_p = false;
         c->has_val64 = false;
@@ -1359,8 +1520,9 @@ wpcd_status wpcd_build_p(wpcd_ctx *c, wpcd_precision prec, int64_t *nnz_out) {
 wpcd_status wpcd_get_p(wpcd_ctx *c, int64_t *row_ptr, int32_t *col, double *val) {
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_p, WPCD_E_STATE, "no P0 built");
-        const int64_t nrow = (int64_t)c->np * c->nq;
-        const int64_t nv = c->nnz * c->nch * c->nch;
+        // a reduced system: one value per entry over its reduced cells
+        const int64_t nrow = c->reduced ? c->red_rows : (int64_t)c->np * c->nq;
+        const int64_t nv = c->reduced ? c->nnz : c->nnz * c->nch * c->nch;
         if (row_ptr)
             WPCD_HIP(hipMemcpyAsync(row_ptr, c->d_rowptr.ptr, (nrow + 1) * sizeof(int64_t),
                                     hipMemcpyDeviceToHost, c->stream));
@@ -1475,6 +1637,7 @@ wpcd_status wpcd_bound_state(wpcd_ctx *c, double e_lo, double e_hi, double *e3_o
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_basis && c->has_pot && c->has_p, WPCD_E_STATE,
                      "build_basis and build_p must come first");
+        WPCD_NOT_REDUCED(c);
         WPCD_REQUIRE(e3_out && std::isfinite(e_lo) && std::isfinite(e_hi) && e_lo < e_hi,
                      WPCD_E_INVALID, "need e_lo < e_hi and e3_out");
         double eb = 1e300;
@@ -1563,6 +1726,7 @@ wpcd_status wpcd_save_p(wpcd_ctx *c, const char *path) {
     return guarded(c, [&] {
         WPCD_REQUIRE(path, WPCD_E_INVALID, "path is NULL");
         WPCD_REQUIRE(c->has_p, WPCD_E_STATE, "no P0 built");
+        WPCD_NOT_REDUCED(c);
         const P0Header h = p0_header(c);
         const int64_t nrow = (int64_t)c->np * c->nq, nv = c->nnz * c->nch * c->nch;
         std::vector<int64_t> rp(nrow + 1);
@@ -1591,6 +1755,7 @@ wpcd_status wpcd_load_p(wpcd_ctx *c, const char *path, int64_t *nnz_out) {
     return guarded(c, [&] {
         WPCD_REQUIRE(path, WPCD_E_INVALID, "path is NULL");
         WPCD_REQUIRE(c->has_basis, WPCD_E_STATE, "wpcd_build_basis must come first");
+        WPCD_NOT_REDUCED(c);
         File f(std::fopen(path, "rb"));
         WPCD_REQUIRE(f.f, WPCD_E_INVALID, std::string("cannot open: ") + path);
         P0Header h{};
@@ -1728,12 +1893,16 @@ wpcd_status wpcd_solve_multi(wpcd_ctx *const *ctxs, int32_t n_sys, const double 
 wpcd_status wpcd_set_multipliers(wpcd_ctx *c, const double *mult, int32_t n_mult) {
     return guarded(c, [&] {
         WPCD_REQUIRE(c->has_basis && c->has_pot, WPCD_E_STATE, "no basis/potential");
+        WPCD_NOT_REDUCED(c);
         set_multipliers(c, mult, n_mult);
     });
 }
 
 wpcd_status wpcd_learn_train(wpcd_ctx *c, const wpcd_learn_desc *desc, wpcd_learn_report *report) {
-    return guarded(c, [&] { learn_train(c, desc, report); });
+    return guarded(c, [&] {
+        WPCD_NOT_REDUCED(c);
+        learn_train(c, desc, report);
+    });
 }
 
 wpcd_status wpcd_mlp_eval(wpcd_ctx *c, int32_t n_in, int32_t n_hidden, int32_t n_out,
@@ -1813,10 +1982,12 @@ const char *wpcd_last_error(const wpcd_ctx *c) {
     return c->err.c_str();
 }
 
-void wpcd_destroy(wpcd_ctx *c) {
-    if (!c) return;
-    (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
+static void release_all(wpcd_ctx *c) {
+    if (c->minor) {
+        release_all(c->minor);
+        delete c->minor;
+        c->minor = nullptr;
+    }
     if (c->h_nnz) (void)hipHostFree(c->h_nnz);
     c->h_nnz = nullptr;
     c->timer.release();
@@ -1872,6 +2043,13 @@ void wpcd_destroy(wpcd_ctx *c) {
     c->d_mcoef.release();
     c->d_mterms.release();
     c->d_mterm_first.release();
+}
+
+void wpcd_destroy(wpcd_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    release_all(c);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

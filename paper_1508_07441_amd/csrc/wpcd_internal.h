@@ -274,6 +274,17 @@ struct wpcd_ctx {
     // ---- learned warm start
     wpcd::Learned learned;
 
+    // ---- Feshbach reduction: this context is a reduced system whose major
+    // channels are its own channels (fine lattice) and whose minor channels
+    // live in `minor` (coarse lattice, every red_cp-th p edge and red_cq-th
+    // q edge, the same potential; owned, on this context's stream).  Its P0
+    // (d_rowptr, d_col, d_val64 and, for a mixed build, d_val32) is one
+    // scalar CSR over the red_rows reduced cells.
+    bool reduced = false;
+    wpcd_ctx *minor = nullptr;
+    int red_cp = 1, red_cq = 1;
+    int64_t red_rows = 0;
+
     // ---- launch-shape autotuning, captured iteration graphs
     wpcd::Tuning tune;
     bool use_graphs = true;
@@ -321,6 +332,12 @@ struct ModelResult {
 void model_fill(wpcd_ctx *c, const ModelRequest &r, ModelResult &res);
 
 void build_structure(wpcd_ctx *c);   // a3: counts, scan, fill (sets c->nnz)
+// Feshbach reduction (k_reduce.hip): the reduced P0 of `red` (major
+// channels [0, nmaj) of `full` on its lattice, the rest on the lattice
+// coarsened by cp x cq) from full's structure and FP64 values d_val64, into
+// red->d_rowptr, d_col, d_val64 (and d_val32 with keep32); sets red->nnz.
+void reduce_p0(wpcd_ctx *full, wpcd_ctx *red, int nmaj, int cp, int cq, const double *d_val64,
+               bool keep32);
 void build_values(wpcd_ctx *c, bool fp64);
 // The same into given device buffers: row counts cnt[n_p n_q] and row_ptr
 // [n_p n_q + 1] (returns nnz), columns col[nnz], values val64 or val32
