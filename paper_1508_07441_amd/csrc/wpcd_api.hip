@@ -1288,6 +1288,39 @@ static void copy_potential(const wpcd_ctx *src, wpcd_ctx *c) {
     c->has_pot = true;
 }
 
+// The pair waves of `src` on `c` (the same lattice and potential): each of
+// c's waves copied from src's wave of the same l, no diagonalisation.
+static void copy_waves(const wpcd_ctx *src, wpcd_ctx *c) {
+    const int n = c->np;
+    c->pot_kind = src->pot_kind;
+    c->pot_s = src->pot_s;
+    c->pot_base = src->pot_base;
+    c->pot_mult = src->pot_mult;
+    c->pot_mu = src->pot_mu;
+    c->pot_scale = src->pot_scale;
+    for (int w = 0; w < c->n_waves; ++w) {
+        int ws = -1;
+        for (int k = 0; k < src->n_waves; ++k)
+            if (src->waves[k].l == c->waves[w].l) ws = k;
+        WPCD_REQUIRE(ws >= 0, WPCD_E_STATE, "pair wave missing in the full system");
+        const PairWave &a = src->waves[ws];
+        PairWave &b = c->waves[w];
+        b.v.reserve((size_t)n * n);
+        b.O.reserve((size_t)n * n);
+        b.Vt.reserve((size_t)n * n);
+        b.eps.reserve(n);
+        const size_t nn = (size_t)n * n * sizeof(double);
+        WPCD_HIP(hipMemcpyAsync(b.v.ptr, a.v.ptr, nn, hipMemcpyDeviceToDevice, c->stream));
+        WPCD_HIP(hipMemcpyAsync(b.O.ptr, a.O.ptr, nn, hipMemcpyDeviceToDevice, c->stream));
+        WPCD_HIP(hipMemcpyAsync(b.Vt.ptr, a.Vt.ptr, nn, hipMemcpyDeviceToDevice, c->stream));
+        WPCD_HIP(hipMemcpyAsync(b.eps.ptr, a.eps.ptr, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+        b.h_eps = a.h_eps;
+    }
+    WPCD_HIP(hipStreamSynchronize(c->stream));
+    c->has_pot = true;
+}
+
 // Feshbach reduction (Sec. V.B): see wpcd_build_reduced in the header.
 static void build_reduced(wpcd_ctx *red, wpcd_ctx *full, int nmaj, int cp, int cq,
                           wpcd_precision prec) {
@@ -1329,7 +1362,7 @@ static void build_reduced(wpcd_ctx *red, wpcd_ctx *full, int nmaj, int cp, int c
     bd.l = full->ch_l;
     bd.lam = full->ch_lam;
     build_basis_impl(red, &bd, nullptr, nullptr, false);
-    copy_potential(full, red);
+    copy_waves(full, red);
     // minor part: every cp-th p edge and cq-th q edge, the minor channels
     wpcd_ctx *m = new wpcd_ctx();
     m->device = red->device;
