@@ -1293,7 +1293,7 @@ struct Batch {
     double *out2;    // stage-1 results [nsplit][pairs][2]
     bool lowp;       // FP32 intermediate panels in the inner iterations
     bool bf16;       // ... with the block products on the BF16 matrix cores
-    int spmm_cfg;    // P0 SpMM variant (kSpmmCfg)
+    int spmm_cfg;    // P0 SpMM variant (0..6, see launch_spmm)
     // Layout.  A reduced system (Feshbach reduction) holds its major
     // channels in c (fine lattice, rows [0, M_F)) and its minor channels in
     // cm (coarse lattice, rows [M_F, M)); P0 is then one scalar CSR over
@@ -1399,7 +1399,6 @@ void launch_block_apply(Batch &b, int which, const TI *in, const double *add, TO
 // in flight per lane (block form), 3 both, 4 LDS-staged tiles, 5 LDS-staged
 // tiles with the loads of a tile overlapped (k_spmm_pipe), 6 as 5 with the
 // rows visited in lattice tiles, XCD-contiguous and balanced.
-constexpr int kSpmmCfg = 7;
 
 template <class PT, class V, int NCH, bool PERM, bool PIPE>
 void launch_spmm_lds(Batch &b, const V *val, const PT *x, PT *y) {
@@ -2053,8 +2052,7 @@ void gmres_setup(GmresRun &run, wpcd_ctx *c, const std::vector<double> &E,
     run.err_est = err_est;
     run.idx0 = idx0;
     const bool fp64 = prec == WPCD_FP64;
-    std::vector<int> &iters = out.iters, &edge_flag = out.edge;
-    std::vector<double> &resid = out.resid;
+    std::vector<int> &edge_flag = out.edge;
     const int nE = (int)E.size();
     // the Givens kernel's LDS column stage can exceed the 64 KB default
     WPCD_HIP(hipFuncSetAttribute((const void *)k_norm_givens,

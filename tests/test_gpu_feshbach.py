@@ -162,6 +162,30 @@ def test_reduced_mixed_tiers(P):
         full.close()
 
 
+def test_reduced_spmm_variants(P):
+    """Every SpMM candidate of the reduced system's scalar CSR (plain,
+    XCD-contiguous, LDS-staged, pipelined), forced in turn: the same
+    amplitudes to rounding."""
+    n_p, n_q, pm, qm, ngq, ngx, nmaj, rp, rq = 12, 10, 8.0, 8.0, 8, 12, 1, 2, 2
+    full = _pair(P, n_p, n_q, pm, qm, ngq, ngx, 2.0, P.WPCD_FP64)
+    red = P.Context(0)
+    try:
+        red.build_reduced(full, nmaj, rp, rq, P.WPCD_FP64)
+        E = [0.3, 1.1]
+        red.set_autotune(P.WPCD_TUNE_FORCE)
+        ref = red.solve(E, P.WPCD_FP64)
+        for f in range(1, 6):
+            say(f"[fesh] spmm force {f}")
+            red.set_autotune(P.WPCD_TUNE_FORCE + f)
+            for a, b in zip(ref, red.solve(E, P.WPCD_FP64)):
+                assert a.status == P.WPCD_OK and b.status == P.WPCD_OK
+                Ua, Ub = complex(a.U_re, a.U_im), complex(b.U_re, b.U_im)
+                assert abs(Ua - Ub) <= 1e-12 * abs(Ua), (f, Ua, Ub)
+    finally:
+        red.close()
+        full.close()
+
+
 def test_reduced_sampled_rows_300(P):
     """300 x 300 bins, three L = 2+ channels, the d-wave channels coarsened
     2 x 2: sampled rows of the reduced P0 (fine and coarse) against the
