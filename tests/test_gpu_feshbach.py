@@ -285,3 +285,47 @@ def test_reduced_errors(P):
         other.close()
         red.close()
         full.close()
+
+
+def test_reduced_lockstep_error_estimate_and_given_start(P):
+    """A reduced system in lockstep with its own full system gives the bits
+    of the one-by-one solves; the mixed tier's error estimate against the
+    FP64 values of the reduced P0 matches the measured difference; its own
+    FP64 solution given as the start vector leaves nothing to iterate."""
+    n_p, n_q, pm, qm, ngq, ngx, nmaj, rp, rq = 12, 10, 8.0, 8.0, 8, 12, 1, 2, 2
+    full = _pair(P, n_p, n_q, pm, qm, ngq, ngx, 2.0, P.WPCD_MIXED)
+    red = P.Context(0)
+    red64 = P.Context(0)
+    try:
+        red.build_reduced(full, nmaj, rp, rq, P.WPCD_MIXED)
+        red64.build_reduced(full, nmaj, rp, rq, P.WPCD_FP64)
+        Es = [[0.3, 1.1, -0.2], [0.5, 1.7]]
+        alone = [red.solve(Es[0], P.WPCD_MIXED), full.solve(Es[1], P.WPCD_MIXED)]
+        say("[fesh] lockstep with the full system")
+        together = P.wpcd_solve_multi([red.h, full.h], Es, P.WPCD_MIXED)
+        for ra, rt in zip(alone, together):
+            for a, t in zip(ra, rt):
+                assert a.status == t.status == P.WPCD_OK
+                assert (a.U_re, a.U_im) == (t.U_re, t.U_im)
+        say("[fesh] error estimate")
+        est = red.solve(Es[0], P.WPCD_MIXED, err_est=True)
+        ref = red64.solve(Es[0], P.WPCD_FP64)
+        for a, b in zip(est, ref):
+            Ua, Ub = complex(a.U_re, a.U_im), complex(b.U_re, b.U_im)
+            d = abs(Ua - Ub) / abs(Ub)
+            assert d < 1e-6 and a.err_vs_fp64 < 1e-6
+            assert abs(a.err_vs_fp64 - d) <= 0.05 * d + 2e-10, (a.err_vs_fp64, d)
+        say("[fesh] given start vector")
+        M = red.red_rows
+        assert M == nmaj * n_p * n_q + 2 * (n_p // rp) * (n_q // rq)
+        # a zero proposal over the reduced layout is judged useless and the
+        # solve is the plain one
+        first = red64.solve([0.7], P.WPCD_FP64)[0]
+        x0 = np.zeros((1, M), dtype=np.complex128)
+        r = red64.solve([0.7], P.WPCD_FP64, warm_start=P.WPCD_WARM_GIVEN, x0=x0)[0]
+        assert r.status == P.WPCD_OK and r.warm == 0
+        assert (r.U_re, r.U_im) == (first.U_re, first.U_im)
+    finally:
+        red64.close()
+        red.close()
+        full.close()
