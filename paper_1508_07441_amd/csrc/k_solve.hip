@@ -1004,6 +1004,63 @@ __global__ void k_dots_reduce(const double *__restrict__ out2, int S, int nvec, 
     }
 }
 
+// Both stages at once when the chunks are few (a launch saved per set of
+// dot products): 8 pairs per workgroup, 32 lanes over each pair's chunks
+// (four loads in flight per lane), the 32 lane sums added in lane order and
+// written to h (and H) as k_dots_reduce does.
+constexpr int kFusedChunks = 1024;
+
+__global__ __launch_bounds__(256) void k_dots_final(const double *__restrict__ partial, int nchunk,
+                                                    int nvec, int nE, double *__restrict__ h,
+                                                    double *__restrict__ H, int m, int kcol,
+                                                    int accumulate) {
+    __shared__ double red[32][8][2];
+    const int t = threadIdx.x, pl = t & 7, cl = t >> 3;
+    const int npair = nvec * nE;
+    const int p = blockIdx.x * 8 + pl;
+    double sr = 0.0, si = 0.0;
+    if (p < npair)
+        for (int cb = cl; cb < nchunk; cb += 128) {
+            double xr[4], xi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = cb + 32 * u;
+                xr[u] = c < nchunk ? partial[((int64_t)c * npair + p) * 2] : 0.0;
+                xi[u] = c < nchunk ? partial[((int64_t)c * npair + p) * 2 + 1] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (cb + 32 * u >= nchunk) break;
+                sr += xr[u];
+                si += xi[u];
+            }
+        }
+    red[cl][pl][0] = sr;
+    red[cl][pl][1] = si;
+    __syncthreads();
+    if (t < 8 && p < npair) {
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            ar += red[k][t][0];
+            ai += red[k][t][1];
+        }
+        h[2 * p] = ar;
+        h[2 * p + 1] = ai;
+        if (H) {
+            const int i = p / nE, e = p % nE;
+            double *hh = H + (((int64_t)e * (m + 1) + i) * m + kcol) * 2;
+            if (accumulate) {
+                hh[0] += ar;
+                hh[1] += ai;
+            } else {
+                hh[0] = ar;
+                hh[1] = ai;
+            }
+        }
+    }
+}
+
 // w[row][e] *= scale[e] (scale[e] = 1/norm, or 0 after breakdown)
 __global__ void k_scale(const double *__restrict__ inv, int64_t M, int nE,
                         double *__restrict__ w) {
@@ -1578,6 +1635,12 @@ void reduce_stage1(Batch &b, int npair) {
 void reduce_partials(Batch &b, int nvec, double *h, double *H, int kcol, int accumulate) {
     wpcd_ctx *c = b.c;
     TimedLaunch tl(c->timer, c->stream, "gmres_reduce", WPCD_TIME_SOLVE);
+    if (b.nchunk <= kFusedChunks) {
+        hipLaunchKernelGGL(k_dots_final, dim3(cdiv(nvec * b.nE, 8)), dim3(256), 0, c->stream,
+                           b.partial, b.nchunk, nvec, b.nE, h, H, b.m, kcol, accumulate);
+        WPCD_HIP(hipGetLastError());
+        return;
+    }
     reduce_stage1(b, nvec * b.nE);
     hipLaunchKernelGGL(k_dots_reduce, dim3(cdiv(nvec * b.nE, 256)), dim3(256), 0, c->stream,
                        b.out2, b.nsplit, nvec, b.nE, h, H, b.m, kcol, accumulate);
