@@ -246,7 +246,13 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(const int32_t *__restrict_
     const int64_t per = (n + 1023) / 1024;
     const int64_t r0 = min(n, (int64_t)t * per), r1 = min(n, r0 + per);
     int64_t s = 0;
-    for (int64_t r = r0; r < r1; ++r) s += cnt[r];
+    for (int64_t r = r0; r < r1; r += 8) {   // eight loads in flight
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = r + u < r1 ? cnt[r + u] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
     part[t] = s;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
@@ -256,9 +262,16 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(const int32_t *__restrict_
         __syncthreads();
     }
     s = t ? part[t - 1] : 0;
-    for (int64_t r = r0; r < r1; ++r) {
-        row_ptr[r] = s;
-        s += cnt[r];
+    for (int64_t r = r0; r < r1; r += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = r + u < r1 ? cnt[r + u] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (r + u < r1) {
+                row_ptr[r + u] = s;
+                s += v[u];
+            }
     }
     if (t == 1023) row_ptr[n] = part[1023];
 }
