@@ -110,7 +110,8 @@ typedef struct {
  * operator at the 1e-7 level).  want_breakup:
  * fill breakup_out in wpcd_solve.  warm_start: a WPCD_WARM_* value; x0
  * (WPCD_WARM_GIVEN only): host array [n_E][M][2] of (re, im) doubles in
- * channel-basis order, M = n_ch*n_q*n_p.  err_est: nonzero to fill
+ * channel-basis order, M = n_ch*n_q*n_p (a reduced system: its major and
+ * minor rows, see wpcd_build_reduced).  err_est: nonzero to fill
  * err_vs_fp64 of every result (see wpcd_energy_result); this needs the P0
  * values in FP64 as well, which the first such call computes on the
  * existing structure and keeps (8 B per channel value).

@@ -557,7 +557,15 @@ class Context:
             return rp, col, (val.reshape(-1) if values else None)
         return wpcd_get_p(self.h, self.n_p * self.n_q, self.nnz, self.n_ch, values)
 
+    def basis_rows(self):
+        """M, the rows of the channel basis (a reduced system: its major
+        and minor parts together)."""
+        return self.red_rows if self.red_rows else self.n_ch * self.n_q * self.n_p
+
     def solve(self, energies, precision=WPCD_FP64, **kw):
+        x0 = kw.get("x0")
+        if x0 is not None and np.shape(x0)[-1] != self.basis_rows():
+            raise ValueError(f"x0 rows {np.shape(x0)[-1]} != the basis' {self.basis_rows()}")
         return wpcd_solve(self.h, energies, precision, n_p=self.n_p, n_ch=self.n_ch, **kw)
 
     def bound_state(self, e_lo, e_hi):

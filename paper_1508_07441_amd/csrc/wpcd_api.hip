@@ -1583,6 +1583,7 @@ wpcd_status wpcd_solve(wpcd_ctx *c, const double *E, int32_t n_E, wpcd_precision
     return guarded(c, [&] { solve_impl(c, E, n_E, prec, opts, out, breakup_out, nullptr); });
 }
 
+extern "C++" {  // C++ helpers inside the C-linkage block
 namespace {
 using cd = std::complex<double>;
 
@@ -1665,6 +1666,7 @@ double kernel_top_ritz(wpcd_ctx *c, double E, int m) {
     return best;
 }
 }  // namespace
+}  // extern "C++"
 
 wpcd_status wpcd_bound_state(wpcd_ctx *c, double e_lo, double e_hi, double *e3_out) {
     return guarded(c, [&] {

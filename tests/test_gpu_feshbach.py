@@ -324,6 +324,10 @@ def test_reduced_lockstep_error_estimate_and_given_start(P):
         x0 = np.zeros((1, M), dtype=np.complex128)
         r = red64.solve([0.7], P.WPCD_FP64, warm_start=P.WPCD_WARM_GIVEN, x0=x0)[0]
         assert r.status == P.WPCD_OK and r.warm == 0
+        # a start vector of the unreduced system's length is refused
+        with pytest.raises(ValueError):
+            red64.solve([0.7], P.WPCD_FP64, warm_start=P.WPCD_WARM_GIVEN,
+                        x0=np.zeros((1, 3 * n_p * n_q), dtype=np.complex128))
         assert (r.U_re, r.U_im) == (first.U_re, first.U_im)
     finally:
         red64.close()
