@@ -324,6 +324,21 @@ def feshbach_measure(P, full, nnz_full, r_full, s_full):
                 row["max_rel_amp_err_mixed_vs_fp64"] = max(
                     abs(complex(res[k].U_re, res[k].U_im) - complex(r_red64[k].U_re, r_red64[k].U_im))
                     / abs(complex(r_red64[k].U_re, r_red64[k].U_im)) for k in ok)
+                # the reduced SpMM (scalar CSR over the reduced cells, FP32
+                # values): P0 stream and x panel rows gathered per application
+                red.set_timing(P.WPCD_TIME_SOLVE)
+                red.reset_timing()
+                red.solve(ENERGIES, prec)
+                red.synchronize()
+                sp_ms, sp_n = red.timing()["spmm"]
+                red.set_timing(0)
+                t_sp = sp_ms / sp_n / 1e3
+                p0_bytes = nnz * (4 + 4) + 8 * (red.red_rows + 1)
+                gather = nnz * 2 * len(ENERGIES) * 8
+                row["spmm_mixed"] = {"us_per_launch": 1e6 * t_sp, "p0_stream_bytes": p0_bytes,
+                                     "p0_stream_frac_hbm": p0_bytes / t_sp / 1e9 / PEAK_HBM_GBS,
+                                     "x_gather_bytes": gather,
+                                     "x_gather_GBps": gather / t_sp / 1e9}
         row["basis"] = red.red_rows
         row["entries"] = nnz
         row["entries_unreduced"] = 9 * nnz_full
