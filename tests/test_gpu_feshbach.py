@@ -333,3 +333,34 @@ def test_reduced_lockstep_error_estimate_and_given_start(P):
         red64.close()
         red.close()
         full.close()
+
+
+def test_reduced_two_major_channels_uneven_coarsening(P):
+    """Two major channels ((0,2) and (2,0) on the 12 x 10 lattice) and one
+    minor ((2,2) on bins of 3 x 2 fine bins): FP64 amplitudes and breakup
+    elements against the oracle's effective-kernel solution."""
+    n_p, n_q, pm, qm, ngq, ngx, nmaj, rp, rq = 12, 10, 7.0, 9.0, 5, 9, 2, 3, 2
+    scale = 2.0
+    full = _pair(P, n_p, n_q, pm, qm, ngq, ngx, scale, P.WPCD_FP64)
+    red = P.Context(0)
+    try:
+        red.build_reduced(full, nmaj, rp, rq, P.WPCD_FP64)
+        assert red.red_rows == 2 * n_p * n_q + (n_p // rp) * (n_q // rq)
+        ro = _oracle_red(n_p, n_q, pm, qm, ngq, ngx, scale, nmaj, rp, rq)
+        energies = [ro.major.eps[0][0] + 0.05, 0.6, 1.8]
+        say("[fesh] two major channels")
+        res, brs = red.solve(energies, P.WPCD_FP64, want_breakup=P.WPCD_BREAKUP_ELEMENTS)
+        for r, br, E in zip(res, brs, energies):
+            assert r.status == P.WPCD_OK, (E, P.STATUS_NAMES[r.status])
+            a = F.amplitudes(ro, E, F.solve_effective(ro, E))
+            U = complex(r.U_re, r.U_im)
+            assert abs(U - a.U00) <= 1e-10 * abs(a.U00), (E, U, a.U00)
+            want = {(c, k, j): s for (c, k, j, s) in a.breakup}
+            got = {(int(x[0]), int(x[1]), int(x[2])): complex(x[3], x[4]) for x in br}
+            assert set(want) == set(got), E
+            smax = max([abs(v) for v in want.values()] + [1e-30])
+            for key, v in want.items():
+                assert abs(got[key] - v) <= 1e-10 * smax, (E, key)
+    finally:
+        red.close()
+        full.close()
