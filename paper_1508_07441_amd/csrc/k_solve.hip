@@ -1139,11 +1139,17 @@ __global__ void k_cycle_start(const double *__restrict__ nrm2, int nE, int m, do
 // energy sets H[k+1][k] = ||w|| and inv = 1/||w||, applies the previous
 // Givens rotations to column k, forms the new one and updates the residual
 // estimate.  Dynamic LDS: 256 + nE (m + 1) 2 doubles.
+// With w given (few chunks), every workgroup reduces the norms itself, in
+// the same order (the same bits), and scales its share of w by 1/norm:
+// the basis vector's normalisation without a launch of its own; workgroup
+// 0 alone updates the Hessenberg column and the rotations.
 __global__ __launch_bounds__(256) void k_norm_givens(const double *__restrict__ npart, int nchunk,
                                                      double *__restrict__ H, int nE, int m, int k,
                                                      double tol, GState S,
-                                                     double *__restrict__ inv) {
+                                                     double *__restrict__ inv,
+                                                     double *__restrict__ w, int64_t M) {
     extern __shared__ double sm[];
+    __shared__ double s_inv[64], s_hn[64];
     double *red = sm, *col = sm + 256;
     const int t = threadIdx.x;
     const int G = 256 / nE;
@@ -1164,23 +1170,38 @@ __global__ __launch_bounds__(256) void k_norm_givens(const double *__restrict__ 
             }
         }
     red[t] = acc;
-    for (int idx = t; idx < nE * (k + 1); idx += 256) {
-        const int e = idx / (k + 1), i = idx - e * (k + 1);
-        const double *src = H + (((int64_t)e * (m + 1) + i) * m + k) * 2;
-        col[(e * (m + 1) + i) * 2] = src[0];
-        col[(e * (m + 1) + i) * 2 + 1] = src[1];
+    if (blockIdx.x == 0)
+        for (int idx = t; idx < nE * (k + 1); idx += 256) {
+            const int e = idx / (k + 1), i = idx - e * (k + 1);
+            const double *src = H + (((int64_t)e * (m + 1) + i) * m + k) * 2;
+            col[(e * (m + 1) + i) * 2] = src[0];
+            col[(e * (m + 1) + i) * 2 + 1] = src[1];
+        }
+    __syncthreads();
+    if (t < nE) {
+        double n2 = 0.0;
+        for (int g = 0; g < G; ++g) n2 += red[g * nE + t];
+        const double hn = sqrt(n2);
+        const double beta = S.st[t * kSt];
+        s_hn[t] = hn;
+        s_inv[t] = (hn > 1e-14 * beta && hn > 1e-300) ? 1.0 / hn : 0.0;
     }
     __syncthreads();
+    if (w)
+        for (int64_t idx = (int64_t)blockIdx.x * 256 + t; idx < M * nE;
+             idx += (int64_t)gridDim.x * 256) {
+            const double sc = s_inv[idx % nE];
+            w[2 * idx] *= sc;
+            w[2 * idx + 1] *= sc;
+        }
+    if (blockIdx.x != 0) return;
     const int e = t;
     if (e >= nE) return;
-    double n2 = 0.0;
-    for (int g = 0; g < G; ++g) n2 += red[g * nE + e];
     double *st = S.st + e * kSt;
     double *ce = col + (size_t)e * (m + 1) * 2;
     double *He = H + (int64_t)e * (m + 1) * m * 2;
-    const double hn = sqrt(n2);
-    const double beta = st[0];
-    inv[e] = (hn > 1e-14 * beta && hn > 1e-300) ? 1.0 / hn : 0.0;
+    const double hn = s_hn[e];
+    inv[e] = s_inv[e];
     He[((k + 1) * m + k) * 2] = hn;
     He[((k + 1) * m + k) * 2 + 1] = 0.0;
     if (st[3] != 0.0) return;   // already converged: leave its state alone
@@ -1233,7 +1254,7 @@ __global__ __launch_bounds__(256) void k_norm_givens(const double *__restrict__ 
     const double res = sqrt(g[2 * (k + 1)] * g[2 * (k + 1)] + g[2 * (k + 1) + 1] * g[2 * (k + 1) + 1]);
     st[2] = res;
     st[4] = k + 1;
-    if (res <= tol * st[1] || inv[e] == 0.0) st[3] = 1.0;
+    if (res <= tol * st[1] || s_inv[e] == 0.0) st[3] = 1.0;
 }
 
 // y = R^{-1} g over the first st[4] columns (back substitution).
@@ -1694,10 +1715,18 @@ void iteration(Batch &b, int k, double tol) {
     reduce_partials(b, k + 1, b.h, b.H, k, 1);
     vupdate<false, true>(b, k + 1, w);
     TimedLaunch tl(c->timer, s, "gmres_givens", WPCD_TIME_SOLVE);
-    hipLaunchKernelGGL(k_norm_givens, dim3(1), dim3(256),
-                       (256 + (size_t)b.nE * (b.m + 1) * 2) * sizeof(double), s, b.partial,
-                       b.nchunk, b.H, b.nE, b.m, k, tol, b.S, b.inv);
-    hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * b.nE, 256)), dim3(256), 0, s, b.inv, b.M, b.nE, w);
+    const size_t lds = (256 + (size_t)b.nE * (b.m + 1) * 2) * sizeof(double);
+    if (b.nchunk <= kFusedChunks) {
+        // norms reduced by every workgroup, w scaled in the same launch
+        const int nb = (int)std::min<int64_t>(cdiv(b.M * b.nE, 1024), 512);
+        hipLaunchKernelGGL(k_norm_givens, dim3(nb), dim3(256), lds, s, b.partial, b.nchunk, b.H,
+                           b.nE, b.m, k, tol, b.S, b.inv, w, b.M);
+    } else {
+        hipLaunchKernelGGL(k_norm_givens, dim3(1), dim3(256), lds, s, b.partial, b.nchunk, b.H,
+                           b.nE, b.m, k, tol, b.S, b.inv, nullptr, b.M);
+        hipLaunchKernelGGL(k_scale, dim3(cdiv(b.M * b.nE, 256)), dim3(256), 0, s, b.inv, b.M,
+                           b.nE, w);
+    }
     WPCD_HIP(hipGetLastError());
 }
 
