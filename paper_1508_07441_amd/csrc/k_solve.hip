@@ -1518,9 +1518,27 @@ void launch_spmm_lds_n(Batch &b, const V *val, const PT *x, PT *y) {
 // built for.
 constexpr int kPermTile = 32;
 
+// A reduced system's rows are the cells of its parts: each major channel's
+// fine lattice, then each minor channel's coarse lattice; each part is
+// visited in tiles of its own lattice.
 void ensure_perm(wpcd_ctx *c) {
-    const int nrow = c->np * c->nq;
-    if (c->perm_np == c->np && c->perm_nq == c->nq && c->perm_nnz == c->nnz && c->d_perm.ptr)
+    struct Lat {
+        int64_t off;
+        int np, nq;
+    };
+    std::vector<Lat> parts;
+    if (c->reduced) {
+        const int64_t ncell = (int64_t)c->np * c->nq;
+        for (int a = 0; a < c->nch; ++a) parts.push_back({a * ncell, c->np, c->nq});
+        const wpcd_ctx *m = c->minor;
+        const int64_t ncc = (int64_t)m->np * m->nq;
+        for (int a = 0; a < m->nch; ++a) parts.push_back({c->nch * ncell + a * ncc, m->np, m->nq});
+    } else {
+        parts.push_back({0, c->np, c->nq});
+    }
+    const int nrow = c->reduced ? (int)c->red_rows : c->np * c->nq;
+    if (c->perm_np == c->np && c->perm_nq == c->nq && c->perm_nnz == c->nnz &&
+        c->perm_rows == nrow && c->d_perm.ptr)
         return;
     std::vector<int64_t> rp(nrow + 1);
     WPCD_HIP(hipMemcpyAsync(rp.data(), c->d_rowptr.ptr, rp.size() * sizeof(int64_t),
@@ -1528,11 +1546,12 @@ void ensure_perm(wpcd_ctx *c) {
     WPCD_HIP(hipStreamSynchronize(c->stream));
     std::vector<int32_t> perm;
     perm.reserve((size_t)nrow + 9);
-    for (int tj = 0; tj < c->nq; tj += kPermTile)
-        for (int ti = 0; ti < c->np; ti += kPermTile)
-            for (int j = tj; j < std::min(c->nq, tj + kPermTile); ++j)
-                for (int i = ti; i < std::min(c->np, ti + kPermTile); ++i)
-                    perm.push_back(j * c->np + i);
+    for (const Lat &l : parts)
+        for (int tj = 0; tj < l.nq; tj += kPermTile)
+            for (int ti = 0; ti < l.np; ti += kPermTile)
+                for (int j = tj; j < std::min(l.nq, tj + kPermTile); ++j)
+                    for (int i = ti; i < std::min(l.np, ti + kPermTile); ++i)
+                        perm.push_back((int32_t)(l.off + (int64_t)j * l.np + i));
     const int64_t total = rp[nrow];
     int64_t acc = 0;
     int next = 1, grid = 0, prev = 0;
@@ -1561,6 +1580,7 @@ void ensure_perm(wpcd_ctx *c) {
     c->perm_np = c->np;
     c->perm_nq = c->nq;
     c->perm_nnz = c->nnz;
+    c->perm_rows = nrow;
     c->perm_grid = 8 * std::max(grid, 1);
 }
 
@@ -1778,6 +1798,7 @@ IterGraphs *graphs_for(Batch &b, double tol, int check_every) {
         }
     }
     key.push_back((uint64_t)b.M_F);
+    key.push_back((uint64_t)c->d_perm.ptr);   // the tiled SpMM's row order
     for (auto &g : c->graphs)
         if (g.key == key) return &g;
     if (c->graphs.size() >= 8) {
@@ -1859,12 +1880,12 @@ void choose_shapes(Batch &b, int m) {
     // P0 SpMM: the variant for the inner iterations' panel type
     std::snprintf(key, sizeof key, "nnz=%lld nch=%d W=%d %s%s", (long long)c->nnz, b.spmm_nch, b.W,
                   b.fp64 ? "f64" : "f32", b.lowp ? " lowp" : "");
-    // candidates: the s-wave kernel has no unrolled form; the lattice-tile
-    // row order needs one lattice (not the reduced CSR)
-    std::vector<int> cand = b.cm ? std::vector<int>{0, 1, 4, 5}
+    // candidates: the s-wave kernel and the reduced system's scalar CSR have
+    // no unrolled form
+    std::vector<int> cand = b.cm ? std::vector<int>{0, 1, 4, 5, 6}
                             : c->nch > 1 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6}
                                          : std::vector<int>{0, 1, 4, 5, 6};
-    if (!b.cm) ensure_perm(c);   // before any capture
+    ensure_perm(c);   // before any capture
     const int pick = tune_pick(c, "spmm", key, (int)cand.size(), 0, [&](int i) {
         return time_launches(c->stream, [&] {
             if (b.lowp) launch_spmm<float>(b, (const float *)b.T1, (float *)b.T2, cand[i]);

@@ -260,6 +260,7 @@ struct wpcd_ctx {
     wpcd::DBuf<uint8_t> d_rstart;                // 1 where a nonzero starts its row
     wpcd::DBuf<int32_t> d_perm;                  // SpMM row order in lattice tiles
     int perm_np = 0, perm_nq = 0;                // grid d_perm was built for
+    int perm_rows = 0;                           // rows it orders (reduced cells for a reduced system)
     int64_t perm_nnz = -1;                       // nonzero count it was balanced for
     int perm_grid = 0;                           // workgroups of a tiled SpMM launch
     wpcd::DBuf<double> d_val64;
