@@ -381,6 +381,34 @@ wpcd_status wpcd_solve(wpcd_ctx *ctx, const double *E, int32_t n_E, wpcd_precisi
 wpcd_status wpcd_solve_dev(wpcd_ctx *ctx, const double *E_dev, int32_t n_E, wpcd_precision prec,
                            const wpcd_solve_opts *opts, wpcd_energy_result *out_dev);
 
+/* Energy sweep in batches with a journal of the completed ones, so that an
+ * interrupted sweep resumes from the last completed batch.  P0 does not
+ * depend on the energy (Sec. III.B), so one built (or loaded) P0 serves
+ * the whole sweep.  The energies E[n_E] are solved in batches of `batch`
+ * (the last one shorter; a batch is one wpcd_solve call), in order.
+ * journal: path of the journal file, or NULL for none.  A missing or empty
+ * file is created with a header (the sweep's energies, batch, precision and
+ * a fingerprint of what fixes the results: basis, bin edges, reduction, P0
+ * precision and size, potential and multipliers, solve options, the learned
+ * model's shape and scalings when it proposes the start); a journal of the
+ * same sweep is replayed: its complete batch records (each checked by a
+ * hash) fill out[] and are not solved again, and a torn or damaged tail is
+ * cut off.  Each batch solved here is appended and flushed to disk before
+ * the next one starts.  max_batches > 0 solves at most that many batches
+ * in this call (0: all).  out[n_E]: the results of every energy done (the
+ * first *n_done_out); energies not reached have status WPCD_E_STATE.
+ * *n_resumed_out (may be NULL): energies taken from the journal.  No
+ * breakup rows; opts->want_breakup is ignored; warm_start must not be
+ * WPCD_WARM_GIVEN.  Results equal those of wpcd_solve over the same batches.
+ * A journal is used by one call at a time.
+ * Errors: WPCD_E_INVALID (NULL arrays, batch < 1, WPCD_WARM_GIVEN, a
+ * journal of another sweep or not a journal, the file cannot be created,
+ * trimmed or written), and those of wpcd_solve.                           */
+wpcd_status wpcd_sweep(wpcd_ctx *ctx, const double *E, int32_t n_E, int32_t batch,
+                       wpcd_precision prec, const wpcd_solve_opts *opts, const char *journal,
+                       int32_t max_batches, wpcd_energy_result *out, int32_t *n_done_out,
+                       int32_t *n_resumed_out);
+
 /* Save the built P0 (structure, values in the precision it was built in)
  * with the grid signature (sizes, Gauss orders, channels, bin edges) to a
  * binary file; load it into a context whose basis has the same signature

@@ -51,7 +51,8 @@ ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_build_basis_nucleons",
                  "wpcd_set_potential", "wpcd_pair_spectrum",
                  "wpcd_build_p", "wpcd_build_p_noalloc", "wpcd_get_p", "wpcd_save_p",
                  "wpcd_load_p", "wpcd_build_reduced", "wpcd_solve",
-                 "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_bound_state", "wpcd_model_fill",
+                 "wpcd_solve_dev", "wpcd_solve_multi", "wpcd_sweep", "wpcd_bound_state",
+                 "wpcd_model_fill",
                  "wpcd_set_multipliers",
                  "wpcd_learn_train", "wpcd_mlp_eval", "wpcd_set_autotune",
                  "wpcd_get_autotune", "wpcd_set_graphs", "wpcd_set_timing",
@@ -177,6 +178,10 @@ def lib():
         L.wpcd_load_p.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
         L.wpcd_solve_dev.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int,
                                      ctypes.POINTER(wpcd_solve_opts), vp]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.wpcd_sweep.argtypes = [vp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                 ctypes.POINTER(wpcd_solve_opts), ctypes.c_char_p, ctypes.c_int32,
+                                 ctypes.POINTER(wpcd_energy_result), i32p, i32p]
         L.wpcd_solve_multi.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(dp),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
                                        ctypes.POINTER(wpcd_solve_opts),
@@ -405,6 +410,23 @@ def wpcd_solve_dev(ctx, E_dev_ptr, n_E, out_dev_ptr, precision=WPCD_FP64, **kw):
                                      ctypes.byref(opts), ctypes.c_void_p(out_dev_ptr)))
 
 
+def wpcd_sweep(ctx, energies, batch, precision=WPCD_FP64, journal=None, max_batches=0,
+               max_iter=0, krylov_dim=0, tol=0.0, warm_start=WPCD_WARM_NONE, err_est=False,
+               resolvent=0):
+    """Energy sweep in batches, resumable through the journal file (None:
+    no journal).  Returns (results, n_done, n_resumed): results[k] for
+    every energy, valid for k < n_done; n_resumed were read back from the
+    journal."""
+    E = np.ascontiguousarray(energies, dtype=np.float64)
+    out = (wpcd_energy_result * max(1, E.size))()
+    opts = _opts(max_iter, krylov_dim, tol, False, warm_start, None, err_est, resolvent)
+    n_done, n_res = ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, lib().wpcd_sweep(ctx, _dp(E), E.size, int(batch), precision, ctypes.byref(opts),
+                                 None if journal is None else os.fsencode(journal),
+                                 int(max_batches), out, ctypes.byref(n_done), ctypes.byref(n_res)))
+    return [out[k] for k in range(E.size)], n_done.value, n_res.value
+
+
 def wpcd_solve_multi(ctxs, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0):
     """Solve several systems at once: ctxs[i] (handles) at energies[i]."""
     n = len(ctxs)
@@ -567,6 +589,9 @@ class Context:
         if x0 is not None and np.shape(x0)[-1] != self.basis_rows():
             raise ValueError(f"x0 rows {np.shape(x0)[-1]} != the basis' {self.basis_rows()}")
         return wpcd_solve(self.h, energies, precision, n_p=self.n_p, n_ch=self.n_ch, **kw)
+
+    def sweep(self, energies, batch, precision=WPCD_FP64, journal=None, max_batches=0, **kw):
+        return wpcd_sweep(self.h, energies, batch, precision, journal, max_batches, **kw)
 
     def bound_state(self, e_lo, e_hi):
         return wpcd_bound_state(self.h, e_lo, e_hi)

@@ -14,6 +14,8 @@
 #include <thread>
 #include <vector>
 
+#include <unistd.h>
+
 #include "wpcd_internal.h"
 
 namespace wpcd {
@@ -1850,6 +1852,193 @@ wpcd_status wpcd_load_p(wpcd_ctx *c, const char *path, int64_t *nnz_out) {
         c->has_val64 = c->p_fp64;
         c->has_p = true;
         if (nnz_out) *nnz_out = h.nnz;
+    });
+}
+
+// ---- energy sweep with a journal of completed batches
+extern "C++" {
+namespace {
+constexpr char kSweepMagic[8] = {'W', 'P', 'C', 'D', 'S', 'W', 'P', '\1'};
+
+struct SweepHeader {
+    char magic[8];
+    int32_t version, n_E, batch, prec;
+    uint64_t fingerprint;
+};
+
+struct SweepRecord {
+    int32_t index, count;
+    uint64_t check;   // FNV-1a of the record's results
+};
+
+// 64-bit FNV-1a (offset basis and prime as published for the hash).
+struct Fnv {
+    uint64_t h = 14695981039346656037ull;
+    void bytes(const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t k = 0; k < n; ++k) {
+            h ^= b[k];
+            h *= 1099511628211ull;
+        }
+    }
+    template <class T>
+    void val(T v) {
+        bytes(&v, sizeof v);
+    }
+    template <class T>
+    void vec(const std::vector<T> &v) {
+        val<uint64_t>(v.size());
+        bytes(v.data(), v.size() * sizeof(T));
+    }
+};
+
+// What fixes the results of a sweep: the basis (grid, channels, edges, the
+// reduction), the P0 build (its precision and size), the potential with its
+// multipliers, the solve options, the learned model's shape and scalings
+// when it proposes the start, and the energies.
+uint64_t sweep_fingerprint(const wpcd_ctx *c, wpcd_precision prec, const wpcd_solve_opts &o,
+                           const double *E, int n_E, int batch) {
+    Fnv f;
+    for (const wpcd_ctx *x : {c, (const wpcd_ctx *)c->minor}) {
+        if (!x) continue;
+        const P0Header h = p0_header(x);
+        for (int32_t v : {h.np, h.nq, h.ngq, h.ngx, h.L, h.nch}) f.val(v);
+        for (int a = 0; a < h.nch; ++a) {
+            f.val(h.l[a]);
+            f.val(h.lam[a]);
+        }
+        f.vec(x->p);
+        f.vec(x->q);
+    }
+    f.val<int32_t>(c->p_fp64);
+    f.val(c->nnz);
+    f.val<int32_t>(c->reduced);
+    f.val(c->red_cp);
+    f.val(c->red_cq);
+    f.val(c->pot_kind);
+    f.vec(c->pot_s);
+    f.vec(c->pot_mu);
+    f.val(c->pot_scale);
+    f.val<int32_t>(prec);
+    for (int32_t v : {o.max_iter, o.krylov_dim, o.warm_start, o.err_est, o.resolvent}) f.val(v);
+    f.val(o.tol);
+    if (o.warm_start == WPCD_WARM_LEARNED) {
+        const wpcd::Learned &l = c->learned;
+        f.val<int32_t>(l.ready);
+        f.val(l.K);
+        f.val(l.nfeat);
+        f.val(l.M);
+        f.bytes(l.feat_mu, sizeof l.feat_mu);
+        f.bytes(l.feat_sd, sizeof l.feat_sd);
+        f.val(l.coef_scale);
+    }
+    f.val(n_E);
+    f.val(batch);
+    f.bytes(E, (size_t)n_E * sizeof(double));
+    return f.h;
+}
+
+uint64_t record_check(const wpcd_energy_result *r, int n) {
+    Fnv f;
+    f.bytes(r, (size_t)n * sizeof *r);
+    return f.h;
+}
+
+bool write_all(FILE *f, const void *p, size_t n) { return n == 0 || std::fwrite(p, 1, n, f) == n; }
+
+bool read_all(FILE *f, void *p, size_t n) { return n == 0 || std::fread(p, 1, n, f) == n; }
+
+// Data of the journal on disk before the call returns.
+bool flush_to_disk(FILE *f) { return std::fflush(f) == 0 && fsync(fileno(f)) == 0; }
+}  // namespace
+}  // extern "C++"
+
+wpcd_status wpcd_sweep(wpcd_ctx *c, const double *E, int32_t n_E, int32_t batch,
+                       wpcd_precision prec, const wpcd_solve_opts *opts, const char *journal,
+                       int32_t max_batches, wpcd_energy_result *out, int32_t *n_done_out,
+                       int32_t *n_resumed_out) {
+    return guarded(c, [&] {
+        WPCD_REQUIRE(E && out && n_E >= 0 && batch >= 1, WPCD_E_INVALID,
+                     "E/out NULL, n_E < 0 or batch < 1");
+        batch = std::min(batch, std::max(n_E, 1));
+        wpcd_solve_opts o{};
+        if (opts) o = *opts;
+        WPCD_REQUIRE(o.warm_start != WPCD_WARM_GIVEN && !o.x0, WPCD_E_INVALID,
+                     "a sweep takes no caller-given start vector");
+        o.want_breakup = 0;
+        o.x0 = nullptr;
+        const int nb = (n_E + batch - 1) / batch;
+        auto count_of = [&](int b) { return std::min(batch, n_E - b * batch); };
+        int done = 0;   // batches complete (from the journal, then solved here)
+        File f(nullptr);
+        if (journal) {
+            SweepHeader h{};
+            std::memcpy(h.magic, kSweepMagic, 8);
+            h.version = 1;
+            h.n_E = n_E;
+            h.batch = batch;
+            h.prec = prec;
+            h.fingerprint = sweep_fingerprint(c, prec, o, E, n_E, batch);
+            f.f = std::fopen(journal, "r+b");
+            SweepHeader g{};
+            const bool fresh = !f.f || std::fread(&g, 1, sizeof g, f.f) == 0;
+            if (fresh) {   // a new journal (or an empty file)
+                if (f.f) std::fclose(f.f);
+                f.f = std::fopen(journal, "w+b");
+                WPCD_REQUIRE(f.f, WPCD_E_INVALID, std::string("cannot create journal: ") + journal);
+                WPCD_REQUIRE(write_all(f.f, &h, sizeof h) &&
+                                 write_all(f.f, E, (size_t)n_E * sizeof(double)) && flush_to_disk(f.f),
+                             WPCD_E_INVALID, std::string("journal write failed: ") + journal);
+            } else {
+                WPCD_REQUIRE(std::memcmp(g.magic, kSweepMagic, 8) == 0 && g.version == 1,
+                             WPCD_E_INVALID, "not a sweep journal of this library");
+                std::vector<double> Ej(n_E);
+                WPCD_REQUIRE(g.n_E == n_E && g.batch == batch && g.prec == prec &&
+                                 g.fingerprint == h.fingerprint &&
+                                 read_all(f.f, Ej.data(), Ej.size() * sizeof(double)) &&
+                                 std::memcmp(Ej.data(), E, Ej.size() * sizeof(double)) == 0,
+                             WPCD_E_INVALID,
+                             "the journal belongs to another sweep (energies, batch, precision, "
+                             "basis, potential or options differ)");
+                long good = std::ftell(f.f);
+                // complete records in batch order; a torn or damaged tail
+                // (an interrupted write) ends the replay and is cut off
+                while (done < nb) {
+                    SweepRecord r{};
+                    const int n = count_of(done);
+                    wpcd_energy_result *dst = out + (size_t)done * batch;
+                    if (!read_all(f.f, &r, sizeof r) || r.index != done || r.count != n ||
+                        !read_all(f.f, dst, (size_t)n * sizeof *dst) || record_check(dst, n) != r.check)
+                        break;
+                    ++done;
+                    good = std::ftell(f.f);
+                }
+                WPCD_REQUIRE(good >= 0 && std::fflush(f.f) == 0 && ftruncate(fileno(f.f), good) == 0 &&
+                                 std::fseek(f.f, good, SEEK_SET) == 0,
+                             WPCD_E_INVALID, std::string("cannot trim journal: ") + journal);
+            }
+        }
+        const int resumed = done;
+        const int stop = max_batches > 0 ? std::min(nb, done + max_batches) : nb;
+        for (; done < stop; ++done) {
+            const int n = count_of(done);
+            wpcd_energy_result *dst = out + (size_t)done * batch;
+            solve_impl(c, E + (size_t)done * batch, n, prec, &o, dst, nullptr, nullptr);
+            if (f.f) {
+                const SweepRecord r{done, n, record_check(dst, n)};
+                WPCD_REQUIRE(write_all(f.f, &r, sizeof r) && write_all(f.f, dst, (size_t)n * sizeof *dst) &&
+                                 flush_to_disk(f.f),
+                             WPCD_E_INVALID, std::string("journal write failed: ") + journal);
+            }
+        }
+        const int n_done = std::min(n_E, done * batch);
+        for (int k = n_done; k < n_E; ++k) {   // not reached in this call
+            out[k] = wpcd_energy_result{};
+            out[k].E = E[k];
+            out[k].status = WPCD_E_STATE;
+        }
+        if (n_done_out) *n_done_out = n_done;
+        if (n_resumed_out) *n_resumed_out = std::min(n_E, resumed * batch);
     });
 }
 
