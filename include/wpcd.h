@@ -124,7 +124,16 @@ typedef struct {
  * All energies of one bin then give the same amplitudes (histogram form);
  * the elastic flux factor is 1/D (A = U / D) and every pseudostate bin whose
  * shell eps*_k + 3/4 q^2 meets the interval is an open breakup state with
- * flux factor (its length inside the shell) / (D dq_j).                   */
+ * flux factor (its length inside the shell) / (D dq_j).
+ * fallback_tol (mixed tiers of wpcd_solve, wpcd_solve_dev and wpcd_sweep;
+ * 0 or less: off): after the mixed solve, every energy that did not
+ * converge, or (with err_est) whose err_vs_fp64 is above fallback_tol or
+ * not finite, is solved again on the FP64 P0 values of the same structure
+ * (computed and kept as for err_est) with the FP64 solve's default
+ * tolerance unless tol is given, and its result replaces the mixed one
+ * (result field fallback = 1; err_vs_fp64 then measures the FP64 solve's
+ * remaining error).  With err_est this bounds each returned amplitude's
+ * estimated error by fallback_tol.                                        */
 #define WPCD_RESOLVENT_AT_E 0
 #define WPCD_RESOLVENT_AVERAGED 1
 /* want_breakup values */
@@ -139,6 +148,7 @@ typedef struct {
     const double *x0;
     int32_t err_est;
     int32_t resolvent;
+    double fallback_tol;
 } wpcd_solve_opts;
 
 /* Per-energy result.  status is a wpcd_status value for this energy.
@@ -149,7 +159,8 @@ typedef struct {
  * with WPCD_BREAKUP_ELEMENTS or none asked, pseudostates with open bins with
  * WPCD_BREAKUP_DIST).
  * warm: 1 if a warm start was kept (alpha != 0); r0: relative residual of
- * the initial vector (1 for the zero start).
+ * the initial vector (1 for the zero start).  fallback: 1 if this energy
+ * was solved again in FP64 (opts.fallback_tol).
  * err_vs_fp64 (opts.err_est set, else NaN): |U - U64| / |U|, the relative
  * difference of this amplitude from the FP64 path's (FP64 P0 values, FP64
  * solve), estimated as the on-shell component of the correction d of one
@@ -162,7 +173,7 @@ typedef struct {
     int32_t j0, status, iters, n_open;
     double U_re, U_im, A_re, A_im, S_re, S_im;
     double delta, eta, residual;
-    int32_t warm, pad_;
+    int32_t warm, fallback;
     double r0;
     double err_vs_fp64;
 } wpcd_energy_result;

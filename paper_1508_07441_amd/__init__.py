@@ -88,7 +88,8 @@ class wpcd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("krylov_dim", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("want_breakup", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("x0", ctypes.POINTER(ctypes.c_double)),
-                ("err_est", ctypes.c_int32), ("resolvent", ctypes.c_int32)]
+                ("err_est", ctypes.c_int32), ("resolvent", ctypes.c_int32),
+                ("fallback_tol", ctypes.c_double)]
 
 
 class wpcd_energy_result(ctypes.Structure):
@@ -100,7 +101,7 @@ class wpcd_energy_result(ctypes.Structure):
                 ("S_re", ctypes.c_double), ("S_im", ctypes.c_double),
                 ("delta", ctypes.c_double), ("eta", ctypes.c_double),
                 ("residual", ctypes.c_double), ("warm", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("r0", ctypes.c_double),
+                ("fallback", ctypes.c_int32), ("r0", ctypes.c_double),
                 ("err_vs_fp64", ctypes.c_double)]
 
 
@@ -330,19 +331,20 @@ def wpcd_build_reduced(red, full, n_major, r_p, r_q, precision=WPCD_FP64):
 
 
 def _opts(max_iter=0, krylov_dim=0, tol=0.0, want_breakup=False, warm_start=WPCD_WARM_NONE,
-          x0=None, err_est=False, resolvent=0):
+          x0=None, err_est=False, resolvent=0, fallback_tol=0.0):
     wb = int(want_breakup) if not isinstance(want_breakup, bool) else (1 if want_breakup else 0)
     return wpcd_solve_opts(max_iter, krylov_dim, tol, wb, warm_start, _dp(x0),
-                           1 if err_est else 0, resolvent)
+                           1 if err_est else 0, resolvent, fallback_tol)
 
 
 def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol=0.0,
                want_breakup=False, n_p=0, n_ch=1, warm_start=WPCD_WARM_NONE, x0=None,
-               err_est=False, resolvent=0):
+               err_est=False, resolvent=0, fallback_tol=0.0):
     """want_breakup: False, True / WPCD_BREAKUP_ELEMENTS or WPCD_BREAKUP_DIST
     (returns the rows per energy beside the results); resolvent: a
     WPCD_RESOLVENT_* value; x0 (warm_start=WPCD_WARM_GIVEN): complex array
-    [n_E][M]."""
+    [n_E][M]; fallback_tol > 0: mixed-tier energies that did not converge or
+    whose error estimate exceeds it are solved again in FP64."""
     E = np.ascontiguousarray(energies, dtype=np.float64)
     out = (wpcd_energy_result * max(1, E.size))()
     x0r = None
@@ -351,7 +353,8 @@ def wpcd_solve(ctx, energies, precision=WPCD_FP64, max_iter=0, krylov_dim=0, tol
         if x0c.ndim != 2 or x0c.shape[0] != E.size:
             raise ValueError("x0 must be [n_E][M] complex")
         x0r = x0c.view(np.float64).reshape(-1)
-    opts = _opts(max_iter, krylov_dim, tol, want_breakup, warm_start, x0r, err_est, resolvent)
+    opts = _opts(max_iter, krylov_dim, tol, want_breakup, warm_start, x0r, err_est, resolvent,
+                 fallback_tol)
     br = np.zeros(E.size * max(1, n_p) * n_ch * 5) if want_breakup else None
     _check(ctx, lib().wpcd_solve(ctx, _dp(E), E.size, precision, ctypes.byref(opts), out,
                                  _dp(br)))
@@ -412,14 +415,15 @@ def wpcd_solve_dev(ctx, E_dev_ptr, n_E, out_dev_ptr, precision=WPCD_FP64, **kw):
 
 def wpcd_sweep(ctx, energies, batch, precision=WPCD_FP64, journal=None, max_batches=0,
                max_iter=0, krylov_dim=0, tol=0.0, warm_start=WPCD_WARM_NONE, err_est=False,
-               resolvent=0):
+               resolvent=0, fallback_tol=0.0):
     """Energy sweep in batches, resumable through the journal file (None:
     no journal).  Returns (results, n_done, n_resumed): results[k] for
     every energy, valid for k < n_done; n_resumed were read back from the
     journal."""
     E = np.ascontiguousarray(energies, dtype=np.float64)
     out = (wpcd_energy_result * max(1, E.size))()
-    opts = _opts(max_iter, krylov_dim, tol, False, warm_start, None, err_est, resolvent)
+    opts = _opts(max_iter, krylov_dim, tol, False, warm_start, None, err_est, resolvent,
+                 fallback_tol)
     n_done, n_res = ctypes.c_int32(), ctypes.c_int32()
     _check(ctx, lib().wpcd_sweep(ctx, _dp(E), E.size, int(batch), precision, ctypes.byref(opts),
                                  None if journal is None else os.fsencode(journal),

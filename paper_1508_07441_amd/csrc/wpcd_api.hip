@@ -438,6 +438,7 @@ struct SolveJob {
     wpcd_energy_result *out = nullptr;
     double *breakup_out = nullptr;
     Collect *collect = nullptr;
+    bool values64 = false;   // FP64 tier on the FP64 values kept beside a mixed build
     // plan
     int m = 48, max_iter = 400;
     double tol = 0.0;
@@ -469,7 +470,8 @@ struct SolveJob {
         WPCD_REQUIRE(prec == WPCD_FP64 || prec == WPCD_MIXED || prec == WPCD_MIXED_REFINE ||
                          prec == WPCD_MIXED_BF16,
                      WPCD_E_INVALID, "bad precision");
-        WPCD_REQUIRE(prec != WPCD_FP64 || c->p_fp64, WPCD_E_STATE, "FP64 solve needs an FP64 P0 build");
+        WPCD_REQUIRE(prec != WPCD_FP64 || c->p_fp64 || (values64 && c->has_val64), WPCD_E_STATE,
+                     "FP64 solve needs an FP64 P0 build");
         WPCD_REQUIRE(prec == WPCD_FP64 || !c->p_fp64, WPCD_E_STATE, "mixed solve needs a mixed P0 build");
         m = 48;
         max_iter = 400;
@@ -758,6 +760,17 @@ struct SolveJob {
     }
 };
 
+static void run_job(SolveJob &j) {
+    j.plan();
+    for (size_t t = 0; t < j.n_batches(); ++t) {
+        j.begin_batch(t);
+        std::vector<GmresRun *> one{j.run.get()};
+        gmres_cycles(one);
+        j.end_batch();
+    }
+    j.finish();
+}
+
 static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision prec,
                        const wpcd_solve_opts *opts, wpcd_energy_result *out, double *breakup_out,
                        Collect *collect) {
@@ -770,14 +783,54 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     j.out = out;
     j.breakup_out = breakup_out;
     j.collect = collect;
-    j.plan();
-    for (size_t t = 0; t < j.n_batches(); ++t) {
-        j.begin_batch(t);
-        std::vector<GmresRun *> one{j.run.get()};
-        gmres_cycles(one);
-        j.end_batch();
+    run_job(j);
+    if (!opts || !(opts->fallback_tol > 0.0) || prec == WPCD_FP64 || collect) return;
+    // FP64 fallback: the energies the mixed tier did not converge, or whose
+    // error estimate is above the bound (or not finite), solved again on
+    // the FP64 values of the same structure
+    std::vector<int> redo;
+    for (int e = 0; e < n_E; ++e) {
+        const wpcd_energy_result &r = out[e];
+        if (r.status == WPCD_E_NOT_CONVERGED ||
+            (r.status == WPCD_OK && j.err_est && !(r.err_vs_fp64 <= opts->fallback_tol)))
+            redo.push_back(e);
     }
-    j.finish();
+    if (redo.empty()) return;
+    if (!c->p_fp64 && !c->has_val64) {
+        build_values(c, true);
+        c->has_val64 = true;
+    }
+    const int n2 = (int)redo.size();
+    std::vector<double> E2(n2), x02;
+    for (int k = 0; k < n2; ++k) E2[k] = E[redo[k]];
+    wpcd_solve_opts o2 = *opts;
+    o2.fallback_tol = 0.0;
+    if (o2.warm_start == WPCD_WARM_GIVEN) {   // the chosen energies' rows of x0
+        const size_t row = (size_t)j.M * 2;
+        x02.resize((size_t)n2 * row);
+        for (int k = 0; k < n2; ++k)
+            std::memcpy(x02.data() + k * row, opts->x0 + (size_t)redo[k] * row, row * sizeof(double));
+        o2.x0 = x02.data();
+    }
+    std::vector<wpcd_energy_result> out2(n2);
+    std::vector<double> br2(breakup_out && j.want_breakup ? (size_t)n2 * j.bstride : 0);
+    SolveJob j2;
+    j2.c = c;
+    j2.E = E2.data();
+    j2.n_E = n2;
+    j2.prec = WPCD_FP64;
+    j2.opts = &o2;
+    j2.out = out2.data();
+    j2.breakup_out = br2.empty() ? nullptr : br2.data();
+    j2.values64 = true;
+    run_job(j2);
+    for (int k = 0; k < n2; ++k) {
+        out[redo[k]] = out2[k];
+        out[redo[k]].fallback = 1;
+        if (!br2.empty())
+            std::memcpy(breakup_out + (size_t)redo[k] * j.bstride, br2.data() + (size_t)k * j.bstride,
+                        (size_t)j.bstride * sizeof(double));
+    }
 }
 
 static uint64_t splitmix_next(uint64_t &st) {
@@ -1922,6 +1975,7 @@ uint64_t sweep_fingerprint(const wpcd_ctx *c, wpcd_precision prec, const wpcd_so
     f.val<int32_t>(prec);
     for (int32_t v : {o.max_iter, o.krylov_dim, o.warm_start, o.err_est, o.resolvent}) f.val(v);
     f.val(o.tol);
+    f.val(o.fallback_tol);
     if (o.warm_start == WPCD_WARM_LEARNED) {
         const wpcd::Learned &l = c->learned;
         f.val<int32_t>(l.ready);
