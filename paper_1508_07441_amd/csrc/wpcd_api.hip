@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <chrono>
 #include <complex>
 #include <cmath>
@@ -2033,7 +2034,12 @@ wpcd_status wpcd_sweep(wpcd_ctx *c, const double *E, int32_t n_E, int32_t batch,
             h.batch = batch;
             h.prec = prec;
             h.fingerprint = sweep_fingerprint(c, prec, o, E, n_E, batch);
+            errno = 0;
             f.f = std::fopen(journal, "r+b");
+            // only a missing file is created (one that cannot be opened for
+            // reading and writing is not replaced)
+            WPCD_REQUIRE(f.f || errno == ENOENT, WPCD_E_INVALID,
+                         std::string("cannot open journal: ") + journal);
             SweepHeader g{};
             const bool fresh = !f.f || std::fread(&g, 1, sizeof g, f.f) == 0;
             if (fresh) {   // a new journal (or an empty file)

@@ -364,3 +364,44 @@ def test_reduced_two_major_channels_uneven_coarsening(P):
     finally:
         red.close()
         full.close()
+
+
+def test_reduced_sweep_and_fp64_fallback(P, tmp_path):
+    """The journaled sweep and the mixed tier's FP64 fallback on a reduced
+    system: an interrupted sweep resumes to the bits of the batch-by-batch
+    solves; a fallback bound below the FP32 error gives the amplitudes of
+    the reduced system built in FP64."""
+    full = _pair(P, 12, 10, 8.0, 8.0, 8, 12, 2.0, P.WPCD_MIXED)
+    red = P.Context(0)
+    red64 = P.Context(0)
+    try:
+        red.build_reduced(full, 1, 2, 2, P.WPCD_MIXED)
+        red64.build_reduced(full, 1, 2, 2, P.WPCD_FP64)
+        E = [0.3, 0.7, 1.1, 1.7, -0.2]
+        ref = []
+        for k in range(0, len(E), 2):
+            ref += red.solve(E[k:k + 2], P.WPCD_MIXED)
+        path = str(tmp_path / "red.wj")
+        say("[fesh] sweep, interrupted and resumed")
+        _, n_done, _ = red.sweep(E, 2, P.WPCD_MIXED, journal=path, max_batches=1)
+        assert n_done == 2
+        res, n_done, n_res = red.sweep(E, 2, P.WPCD_MIXED, journal=path)
+        assert (n_done, n_res) == (len(E), 2)
+        for a, b in zip(res, ref):
+            assert (a.status, a.iters, a.U_re, a.U_im) == (b.status, b.iters, b.U_re, b.U_im)
+        say("[fesh] FP64 fallback")
+        fb = red.solve(E, P.WPCD_MIXED, err_est=True, fallback_tol=1e-13)
+        r64 = red64.solve(E, P.WPCD_FP64)
+        n_ok = 0
+        for a, b in zip(fb, r64):
+            assert a.status == b.status
+            if b.status != P.WPCD_OK:
+                continue
+            n_ok += 1
+            Ua, Ub = complex(a.U_re, a.U_im), complex(b.U_re, b.U_im)
+            assert a.fallback == 1 and abs(Ua - Ub) <= 1e-12 * abs(Ub), (Ua, Ub)
+        assert n_ok >= 4
+    finally:
+        red64.close()
+        red.close()
+        full.close()

@@ -166,6 +166,19 @@ def test_sweep_refuses_other_journals(ctx, P, energies, tmp_path):
     with pytest.raises(P.WpcdError) as e:
         ctx.sweep(energies, BATCH, P.WPCD_FP64, journal=junk)
     assert e.value.status == P.WPCD_E_INVALID
+    # a file that cannot be opened for reading and writing, and a folder,
+    # are refused and left as they are
+    locked = tmp_path / "locked.wj"
+    locked.write_bytes(b"x" * 64)
+    os.chmod(locked, 0o200)
+    try:
+        for j in (str(locked), str(tmp_path)):
+            with pytest.raises(P.WpcdError) as e:
+                ctx.sweep(energies, BATCH, P.WPCD_FP64, journal=j)
+            assert e.value.status == P.WPCD_E_INVALID
+    finally:
+        os.chmod(locked, 0o600)
+    assert locked.read_bytes() == b"x" * 64
     with pytest.raises(P.WpcdError) as e:
         ctx.sweep(energies, 0, P.WPCD_FP64)
     assert e.value.status == P.WPCD_E_INVALID
