@@ -40,7 +40,10 @@ typedef enum {
     WPCD_E_NOT_CONVERGED = 4,    /* iterative solve hit max_iter (per energy) */
     WPCD_E_BELOW_THRESHOLD = 5,  /* E at or below the two-body threshold (per energy) */
     WPCD_E_ON_EDGE = 6,          /* an on-shell momentum sits on a bin edge (per energy) */
-    WPCD_E_STATE = 7             /* calls made out of order */
+    WPCD_E_STATE = 7,            /* calls made out of order */
+    WPCD_E_STAGNATED = 8         /* iterative solve stopped: two restart cycles
+                                    without halving the smallest true residual
+                                    (per energy) */
 } wpcd_status;
 
 typedef enum {
@@ -127,7 +130,8 @@ typedef struct {
  * flux factor (its length inside the shell) / (D dq_j).
  * fallback_tol (mixed tiers of wpcd_solve, wpcd_solve_dev and wpcd_sweep;
  * 0 or less: off): after the mixed solve, every energy that did not
- * converge, or (with err_est) whose err_vs_fp64 is above fallback_tol or
+ * converge (WPCD_E_NOT_CONVERGED or WPCD_E_STAGNATED), or (with err_est)
+ * whose err_vs_fp64 is above fallback_tol or
  * not finite, is solved again on the FP64 P0 values of the same structure
  * (computed and kept as for err_est) with the FP64 solve's default
  * tolerance unless tol is given, and its result replaces the mixed one

@@ -24,6 +24,7 @@ WPCD_E_NOT_CONVERGED = 4
 WPCD_E_BELOW_THRESHOLD = 5
 WPCD_E_ON_EDGE = 6
 WPCD_E_STATE = 7
+WPCD_E_STAGNATED = 8
 WPCD_FP64 = 0
 WPCD_MIXED = 1
 WPCD_MIXED_REFINE = 2
@@ -45,7 +46,7 @@ WPCD_TUNE_MEASURE = 1
 WPCD_TUNE_FORCE = 16
 
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_CONVERGED",
-                5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE"}
+                5: "E_BELOW_THRESHOLD", 6: "E_ON_EDGE", 7: "E_STATE", 8: "E_STAGNATED"}
 
 ABI_FUNCTIONS = ("wpcd_create", "wpcd_build_basis", "wpcd_build_basis_nucleons",
                  "wpcd_set_potential", "wpcd_pair_spectrum",

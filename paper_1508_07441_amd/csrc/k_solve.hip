@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <type_traits>
 
 #include "wpcd_internal.h"
@@ -1983,10 +1984,18 @@ void gmres_cycles(std::vector<GmresRun *> &runs) {
     const int m = runs[0]->b.m;
     for (GmresRun *r : runs)
         WPCD_REQUIRE(r->b.m == m, WPCD_E_INVALID, "batches solved together need one krylov_dim");
+    // A batch whose unconverged energies have not halved their smallest
+    // true residual so far in kStagCycles consecutive restart cycles stops
+    // (those energies are marked stagnated): restarted GMRES that gains
+    // that little per cycle, or has reached the rounding floor, would only
+    // spend the remaining iterations.
+    constexpr int kStagCycles = 2;
     struct State {
         GmresRun *r;
         std::vector<double> sth;
+        std::vector<double> best;   // smallest true residual so far, per energy
         int total = 0;
+        int idle = 0;               // consecutive cycles without progress
         bool all_done = false, in_cycle = false, started = false;
         IterGraphs *graphs = nullptr;
     };
@@ -1996,7 +2005,9 @@ void gmres_cycles(std::vector<GmresRun *> &runs) {
         State x;
         x.r = r;
         x.sth.assign((size_t)r->b.nE * kSt, 0.0);
+        x.best.assign(r->b.nE, std::numeric_limits<double>::infinity());
         r->out->iters.assign(r->b.nE, 0);
+        r->out->stag.assign(r->b.nE, 0);
         r->out->resid.assign(r->b.nE, 1.0);
         wpcd_ctx *c = r->b.c;
         graphs_ok &= c->use_graphs && !(c->timer.enabled & WPCD_TIME_SOLVE) &&
@@ -2135,11 +2146,22 @@ void gmres_cycles(std::vector<GmresRun *> &runs) {
             std::vector<int> &iters = x.r->out->iters;
             std::vector<double> &resid = x.r->out->resid;
             x.all_done = true;
+            bool progress = false;
             for (int e = 0; e < nE; ++e) {
                 if (resid[e] > x.r->tol) iters[e] += (int)x.sth[e * kSt + 4];
                 const double bn = x.r->st[e * kSt + 1];
                 resid[e] = bn > 0 ? std::sqrt(x.r->rn[2 * e]) / bn : 0.0;
-                if (resid[e] > x.r->tol) x.all_done = false;
+                if (resid[e] > x.r->tol) {
+                    x.all_done = false;
+                    if (resid[e] < 0.5 * x.best[e]) progress = true;
+                }
+                if (resid[e] < x.best[e]) x.best[e] = resid[e];
+            }
+            x.idle = progress ? 0 : x.idle + 1;
+            if (!x.all_done && x.idle >= kStagCycles) {
+                x.all_done = true;
+                for (int e = 0; e < nE; ++e)
+                    if (resid[e] > x.r->tol) x.r->out->stag[e] = 1;
             }
         }
     }

@@ -688,7 +688,8 @@ struct SolveJob {
                 r.status = WPCD_E_ON_EDGE;
                 continue;
             }
-            if (!(go.resid[t] <= tol * 10.0)) r.status = WPCD_E_NOT_CONVERGED;
+            if (!(go.resid[t] <= tol * 10.0))
+                r.status = go.stag[t] ? WPCD_E_STAGNATED : WPCD_E_NOT_CONVERGED;
             r.U_re = amp[4 * t];
             r.U_im = amp[4 * t + 1];
             r.A_re = rho0[t] * r.U_re;
@@ -792,7 +793,7 @@ static void solve_impl(wpcd_ctx *c, const double *E, int n_E, wpcd_precision pre
     std::vector<int> redo;
     for (int e = 0; e < n_E; ++e) {
         const wpcd_energy_result &r = out[e];
-        if (r.status == WPCD_E_NOT_CONVERGED ||
+        if (r.status == WPCD_E_NOT_CONVERGED || r.status == WPCD_E_STAGNATED ||
             (r.status == WPCD_OK && j.err_est && !(r.err_vs_fp64 <= opts->fallback_tol)))
             redo.push_back(e);
     }

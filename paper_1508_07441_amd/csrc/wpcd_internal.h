@@ -393,6 +393,7 @@ int tune_pick(wpcd_ctx *c, const char *name, const std::string &key, int n_cand,
 // residual, resolvent edge flag, warm start kept, initial relative residual.
 struct GmresOut {
     std::vector<int> iters, edge, warm;
+    std::vector<int> stag;   // stopped on stagnation (see gmres_cycles)
     std::vector<double> resid, r0;
     std::vector<double> U, dU;   // err_est: on-shell x and its FP64 correction, [nE][2]
 };

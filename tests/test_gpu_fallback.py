@@ -125,3 +125,22 @@ def test_iteration_cap_triggers_the_fallback(mixed, P):
 def test_fp64_tier_ignores_the_option(fp64, P):
     res = fp64.solve(ENERGIES, P.WPCD_FP64, err_est=True, fallback_tol=1e-30)
     assert all(r.fallback == 0 for r in res)
+
+
+def test_stagnation_stops_the_solve(mixed, fp64, P):
+    """A tolerance below the rounding floor cannot be met: the solve stops
+    after two restart cycles that do not halve the true residual, instead of
+    spending the whole iteration cap, with the converged amplitudes."""
+    E = [0.05, 0.5, 2.0]
+    say("[stagnation] FP64, tolerance below the rounding floor")
+    ref = fp64.solve(E, P.WPCD_FP64)
+    res = fp64.solve(E, P.WPCD_FP64, tol=1e-30, max_iter=4000)
+    for r, f in zip(res, ref):
+        assert r.status == P.WPCD_E_STAGNATED, P.STATUS_NAMES[r.status]
+        assert r.iters < 400 and r.residual < 1e-13, (r.iters, r.residual)
+        assert abs(_U(r) - _U(f)) <= 1e-11 * abs(_U(f))
+    say("[stagnation] mixed with the FP64 fallback")
+    res = mixed.solve(E, P.WPCD_MIXED, tol=1e-30, max_iter=4000, fallback_tol=1e-6)
+    for r, f in zip(res, ref):
+        assert r.fallback == 1 and r.status == P.WPCD_E_STAGNATED
+        assert abs(_U(r) - _U(f)) <= 1e-11 * abs(_U(f))
