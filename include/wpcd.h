@@ -404,7 +404,8 @@ wpcd_status wpcd_solve_dev(wpcd_ctx *ctx, const double *E_dev, int32_t n_E, wpcd
  * journal: path of the journal file, or NULL for none.  A missing or empty
  * file is created with a header (the sweep's energies, batch, precision and
  * a fingerprint of what fixes the results: basis, bin edges, reduction, P0
- * precision and size, potential and multipliers, solve options, the learned
+ * precision and size, potential and multipliers (also those of each pair
+ * wave of a nucleon basis), solve options, the learned
  * model's shape and scalings when it proposes the start); a journal of the
  * same sweep is replayed: its complete batch records (each checked by a
  * hash) fill out[] and are not solved again, and a torn or damaged tail is

@@ -1974,6 +1974,11 @@ uint64_t sweep_fingerprint(const wpcd_ctx *c, wpcd_precision prec, const wpcd_so
     f.vec(c->pot_s);
     f.vec(c->pot_mu);
     f.val(c->pot_scale);
+    f.val(c->n_waves);
+    for (int w = 0; w < c->n_waves; ++w) {   // per-wave strength multipliers (nucleons)
+        f.val(c->waves[w].l);
+        f.vec(c->waves[w].mult);
+    }
     f.val<int32_t>(prec);
     for (int32_t v : {o.max_iter, o.krylov_dim, o.warm_start, o.err_est, o.resolvent}) f.val(v);
     f.val(o.tol);

@@ -183,3 +183,28 @@ def test_nucleon_and_boson_systems_in_lockstep(P):
     finally:
         for c in cs:
             c.close()
+
+
+def test_nucleon_sweep_journal_tracks_the_singlet_strength(ctx, P, tmp_path):
+    """A resumable sweep on the doublet system: its journal resumes to the
+    batch-by-batch results, and a basis whose 1S0 pair strength differs is
+    refused (the per-wave multipliers are part of the sweep's fingerprint)."""
+    n = 20
+    E = [-0.05, 0.1, 0.6, 1.5]
+    path = str(tmp_path / "nuc.wj")
+    _build(ctx, n, 12, 1)
+    ctx.build_p(P.WPCD_FP64)
+    ref = ctx.solve(E[:2], P.WPCD_FP64) + ctx.solve(E[2:], P.WPCD_FP64)
+    say("[nuc] sweep, interrupted and resumed")
+    ctx.sweep(E, 2, P.WPCD_FP64, journal=path, max_batches=1)
+    res, n_done, n_res = ctx.sweep(E, 2, P.WPCD_FP64, journal=path)
+    assert (n_done, n_res) == (4, 2)
+    for a, b in zip(res, ref):
+        assert (a.status, a.U_re, a.U_im) == (b.status, b.U_re, b.U_im)
+    say("[nuc] other singlet strength")
+    ctx.build_basis_nucleons(n, n, 10.0, 10.0, 8, 12, two_S=1, channels=NUC_DOUBLET,
+                             potential=FIT, mult=[[1.0, 1.0], [0.5, 0.5]])
+    ctx.build_p(P.WPCD_FP64)
+    with pytest.raises(P.WpcdError) as e:
+        ctx.sweep(E, 2, P.WPCD_FP64, journal=path)
+    assert e.value.status == P.WPCD_E_INVALID
