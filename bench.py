@@ -30,6 +30,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -373,6 +374,19 @@ def c5_measure(P, n_var, n_e, sweep):
     t = time.perf_counter()
     learned = ctx.solve(E, P.WPCD_MIXED, warm_start=P.WPCD_WARM_LEARNED)
     t_learned = time.perf_counter() - t
+    # the same sweep through wpcd_sweep with a journal (batches of 32, each
+    # flushed to disk), then its replay from the complete journal
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "sweep.wj")
+        t = time.perf_counter()
+        journaled, n_done, _ = ctx.sweep(E, 32, P.WPCD_MIXED, journal=path)
+        t_journaled = time.perf_counter() - t
+        t = time.perf_counter()
+        _, _, n_replayed = ctx.sweep(E, 32, P.WPCD_MIXED, journal=path)
+        t_replay = time.perf_counter() - t
+    same = n_done == sweep and all(
+        (journaled[k].status, journaled[k].U_re, journaled[k].U_im)
+        == (plain[k].status, plain[k].U_re, plain[k].U_im) for k in range(sweep))
     ok = [k for k in range(sweep) if plain[k].status == P.WPCD_OK]
     err = max(abs(complex(learned[k].U_re, learned[k].U_im) - complex(plain[k].U_re, plain[k].U_im))
               / abs(complex(plain[k].U_re, plain[k].U_im)) for k in ok)
@@ -387,7 +401,10 @@ def c5_measure(P, n_var, n_e, sweep):
                             "learned": sum(learned[k].iters for k in ok)},
             "sweep_s_per_energy": {"plain": t_plain / sweep, "learned": t_learned / sweep},
             "learned_initial_residual_median": r0[len(r0) // 2],
-            "max_rel_amp_diff_learned_vs_plain": err}
+            "max_rel_amp_diff_learned_vs_plain": err,
+            "journaled_sweep": {"batch": 32, "s_per_energy": t_journaled / sweep,
+                                "replay_s": t_replay, "replayed": n_replayed,
+                                "same_results_as_solve": same}}
 
 
 def nucleon_measure(P):
